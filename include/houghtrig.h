@@ -1,0 +1,207 @@
+/*
+ * houghtrig -- Hough-transform track trigger for displaced jets and
+ * black-hole-like vertices on AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Halyo, LeGresley and Lujan, "Massively Parallel
+ * Computing and the Search for Jets and Black Holes at the LHC" (arXiv
+ * 1309.6275):
+ *   - section "Hough Transform Algorithm": every track instance starts with
+ *     zero votes, each hit adds one vote to every instance that would contain
+ *     it, and local maxima of the vote space are track candidates;
+ *   - section "Jet and Black Hole Detection": candidates are refined and a
+ *     second Hough transform over the tracks finds the vertices they share;
+ *     features close to the interaction point are filtered out by a lower
+ *     bound on the radius; the same local-maximum finder serves both
+ *     transforms.
+ *
+ * Conventions shared by every call:
+ *   - All array arguments are DEVICE pointers owned by the caller, except the
+ *     small configuration structs, which are host pointers read during the
+ *     call.  No call allocates device memory; a plan owns its constant
+ *     tables and scratch.
+ *   - Every compute call is asynchronous on `stream` (a hipStream_t; NULL is
+ *     the default stream).  Counts are written to device memory, so the
+ *     caller synchronises only when it reads them.
+ *   - Argument errors are detected on the host before anything is launched
+ *     and return HT_EINVAL (HT_EUNSUPPORTED for sizes beyond the kernels'
+ *     limits); a failing HIP call returns HT_EDEVICE.
+ *   - Invalid hit values (r outside (0, 1e4) cm, |phi| > 4 rad, NaN) are not
+ *     errors: such hits cast no votes and are never associated.
+ *   - Output lists that exceed their capacity are truncated in order; the
+ *     reported count is the full count.
+ *   - A plan's scratch is shared by the calls made with it: calls with one
+ *     plan must be ordered (one stream, or synchronised streams).  Use one
+ *     plan per concurrent stream.
+ */
+#ifndef HOUGHTRIG_H
+#define HOUGHTRIG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HT_OK = 0,
+  HT_EINVAL = -1,        /* bad argument (null pointer, size out of range) */
+  HT_ENOMEM = -2,        /* device allocation failed (plan creation only) */
+  HT_EDEVICE = -3,       /* a HIP runtime call failed */
+  HT_EUNSUPPORTED = -4   /* valid request beyond this build's kernel limits */
+};
+
+#define HT_MAX_LAYERS 16
+
+/* Accumulator grid.  Cells (i, j, k) are phi0 x q/pT x d0 bins at the bin
+ * centres; the accumulator is int32 [n_d0][n_qpt][n_phi] with phi0 fastest,
+ * cell index lin = (k * n_qpt + j) * n_phi + i.  phi0 covers [-pi, pi)
+ * periodically; bins are [lo + n w, lo + (n+1) w).  n_d0 = 1 with
+ * d0_lo = d0_hi = 0 is the prompt ("2D") transform; n_qpt = 1 with
+ * qpt_lo = qpt_hi = 0 is the straight-line transform. */
+typedef struct {
+  int32_t n_phi, n_qpt, n_d0;
+  float qpt_lo, qpt_hi;   /* q/pT [GeV^-1] */
+  float d0_lo, d0_hi;     /* signed transverse impact parameter [cm] */
+  float bfield;           /* solenoid field [T], > 0 */
+} ht_grid;
+
+/* Sizes the plan's scratch is allocated for. */
+typedef struct {
+  int32_t max_hits;        /* hits per call, <= 65535 */
+  int32_t max_peaks;       /* peak-list capacity assoc_cluster accepts, <= 2^26 */
+  int32_t max_member_cap;  /* largest ht_cluster_cfg.member_cap used */
+  int32_t max_tracks;      /* largest track capacity used */
+  int32_t max_vertex_cells;/* largest n_rho * n_theta used */
+  int32_t max_n_rho;       /* largest n_rho used */
+} ht_limits;
+
+typedef struct { int32_t lin, votes; } ht_peak;
+
+/* Candidate refinement and second-transform settings (see assoc_cluster). */
+typedef struct {
+  int32_t win_bins;        /* phi0 bins added to the cell-compatible member window */
+  int32_t min_layers;      /* inlier layers a candidate needs, owned hits a track needs */
+  int32_t seed_k;          /* members per seed layer tried, 1..4 */
+  int32_t member_cap;      /* candidates with more member hits are dropped */
+  float road_sigmas;       /* inlier road half-width in units of sigma_rphi */
+  float box_margin;        /* seed circle must lie in the cell widened by this many bins */
+  float sigma_rphi;        /* hit r-phi resolution [cm] */
+  int32_t fit_iters;       /* Gauss-Newton iterations of the refit */
+  int32_t n_rho, n_theta;  /* vertex accumulator extent, theta fastest */
+  float rho_lo, rho_hi;    /* vertex radius range [cm]; rho_lo is the IP filter */
+  int32_t vtx_min_votes;   /* vertex peak threshold */
+  int32_t bh_min_tracks;   /* black-hole-like: at least this many member tracks */
+  float bh_max_isotropy;   /* ... and |mean member direction| at most this */
+} ht_cluster_cfg;
+
+typedef struct {
+  int32_t peak;            /* index into the peak list */
+  int32_t lin, votes;      /* the peak cell and its votes */
+  int32_t n_layers;        /* layers with a member hit */
+  int32_t n_inliers;       /* layers with a hit on the seed road */
+  int32_t n_owned;         /* inlier hits this track owns */
+  int32_t status;          /* refit: 0 ok, 1 |u| >= 1 on a hit, 2 singular normal matrix */
+  float seed_ss;           /* sum of squared seed distances of the inliers [cm^2] */
+  float phi0, qpt, d0, chi2;  /* refit perigee parameters and chi2 (-1 if status != 0) */
+  float r_first;           /* smallest radius among owned hits [cm] */
+  int32_t hits[HT_MAX_LAYERS]; /* owned hit on each layer, -1 if none */
+} ht_track;
+
+typedef struct {
+  int32_t lin, votes;      /* vertex cell (m * n_theta + t) and its votes */
+  int32_t n_tracks, kind;  /* members; kind 0 displaced jet, 1 black-hole-like */
+  float rho, theta, isotropy; /* cell centre [cm, rad]; |mean member direction| */
+  int32_t member_begin;    /* offset of this object's members in the member list */
+} ht_object;
+
+/* Outputs of assoc_cluster (device pointers; vacc may be NULL). */
+typedef struct {
+  int32_t* hit_owner;      /* [n_hits] track owning the hit, -1 if none */
+  ht_track* tracks;        /* [track_cap] surviving tracks in peak order */
+  int32_t track_cap;
+  ht_object* objects;      /* [object_cap] vertex objects in cell order */
+  int32_t object_cap;
+  int32_t* members;        /* [member_cap] member track indices, object by object */
+  int32_t member_cap;
+  int32_t* vacc;           /* [n_rho * n_theta] vertex accumulator, or NULL */
+  int32_t* counts;         /* [8]: candidates, tracks, objects, members, overflowed, 0,0,0 */
+} ht_cluster_out;
+
+typedef struct ht_plan ht_plan;
+
+/* Create a plan for `grid` on the current HIP device: builds the constant
+ * tables (bin centres computed in float64, rounded once to float32) and
+ * allocates scratch for `limits`.  Host-synchronous; may allocate. */
+int ht_plan_create(const ht_grid* grid, const ht_limits* limits, ht_plan** out);
+void ht_plan_destroy(ht_plan* plan);
+const char* ht_strerror(int status);
+
+/* hough_vote -- the first transform (paper, section "Hough Transform
+ * Algorithm": each datum adds a vote to every instance that would include
+ * it).  For every valid hit and every column (q/pT_j, d0_k) the hit votes
+ * once, for the phi0 bin of
+ *   u = ((KAP_j * r^2 + Q_jk) * (1/r)) * T_jk,   phi0 = phi - asin_f(u)
+ * (no vote unless |u| <= 1), with KAP_j = -0.299792458e-2 B q/pT_j,
+ * Q_jk = KAP_j d0_k^2 + 2 d0_k, T_jk = 0.5 / (1 + KAP_j d0_k): the outgoing
+ * branch of the circle through the perigee (d0, phi0) with curvature KAP_j.
+ * asin_f is Abramowitz & Stegun 4.4.46 in float32; every operation is one
+ * IEEE float32 rounding, no fused multiply-add.
+ *   r, phi   [n_hits] float32 hit radius [cm] and azimuth [rad]
+ *   acc      [n_d0 * n_qpt * n_phi] int32, fully overwritten
+ *   n_votes  device uint64 receiving the total vote count, or NULL
+ * n_hits may be 0 (acc is zeroed).  Returns HT_EUNSUPPORTED when n_hits
+ * exceeds 65535 or the plan's max_hits. */
+int hough_vote(const ht_plan* plan, const float* r, const float* phi, int32_t n_hits,
+               int32_t* acc, unsigned long long* n_votes, void* stream);
+
+/* hough_peaks -- local maxima of the accumulator (paper, section "Hough
+ * Transform Algorithm"; reused for the second transform).  Cell c is a peak
+ * iff acc[c] >= min_votes and for each of its 26 neighbours c+o inside the
+ * q/pT and d0 range (phi0 periodic) acc[c] > acc[c+o] when o = (dk,dj,di) is
+ * lexicographically negative and acc[c] >= acc[c+o] otherwise (a plateau
+ * keeps its first cell).  Peaks are written sorted by lin.
+ *   acc      accumulator of this plan's grid
+ *   out      [capacity] peaks; the first `capacity` in lin order are written
+ *   n_found  device int32 receiving the full peak count */
+int hough_peaks(const ht_plan* plan, const int32_t* acc, int32_t min_votes, ht_peak* out,
+                int32_t capacity, int32_t* n_found, void* stream);
+
+/* assoc_cluster -- candidate refinement, duplicate cleaning, refit and the
+ * second transform (paper, section "Jet and Black Hole Detection").
+ *   members    valid hits whose phi0 coordinate x in the peak's column lies
+ *              within 0.5 + win_bins + INVW (hd0/r + hk r/2) of the cell
+ *              centre (hd0, hk: half column widths in d0 and curvature);
+ *              more than member_cap members drops the candidate;
+ *   seed       over the outer min(n, min_layers) member layers, circles
+ *              through the seed_k nearest-centre members of the innermost,
+ *              middle and outermost of them (through the beam line and two
+ *              hits on the prompt grid), inliers = per layer the member
+ *              within road_sigmas * sigma_rphi of the circle; best seed =
+ *              most inlier layers, then smallest squared distance sum;
+ *              candidates need min_layers inlier layers;
+ *   ownership  each inlier hit goes to the candidate with the most inlier
+ *              layers, then the smallest seed sum (float32), then the lowest
+ *              cell; tracks own at least min_layers of their hits;
+ *   refit      float64 Gauss-Newton of (phi0, kappa, d0) from the seed;
+ *   vertices   each track votes for the (rho, theta) cells its seed circle
+ *              crosses between |d0| and its first hit radius, rho >= rho_lo;
+ *              vertex peaks by the local-maximum rule; members are tracks
+ *              within one cell; black-hole-like when >= bh_min_tracks members
+ *              and |mean perigee direction| <= bh_max_isotropy.
+ *   r, phi, layer  [n_hits] hits (layer index increasing with radius)
+ *   peaks, n_peaks peak list and device count from hough_peaks; entries
+ *                  beyond min(*n_peaks, peak_cap) are ignored
+ *   out            outputs (device pointers) */
+int assoc_cluster(const ht_plan* plan, const float* r, const float* phi, const uint8_t* layer,
+                  int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks,
+                  int32_t peak_cap, const ht_cluster_cfg* cfg, const ht_cluster_out* out,
+                  void* stream);
+
+/* ht_asin_f32 -- the canonical float32 arcsine of hough_vote, elementwise
+ * over n device floats (for checking the formula on the device). */
+int ht_asin_f32(const float* u, float* out, int64_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

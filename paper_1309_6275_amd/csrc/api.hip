@@ -1,0 +1,220 @@
+// C-ABI entry points, argument validation and plan construction.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "ht_internal.h"
+
+namespace {
+
+using ht::Plan;
+
+bool grid_ok(const ht_grid* g) {
+  if (!g) return false;
+  if (g->n_phi < 4 || g->n_qpt < 1 || g->n_d0 < 1) return false;
+  if ((int64_t)g->n_phi * g->n_qpt * g->n_d0 > 0x7fffffffLL) return false;
+  if (!(g->bfield > 0.0f)) return false;
+  if (!(g->qpt_hi >= g->qpt_lo) || !(g->d0_hi >= g->d0_lo)) return false;
+  if (!isfinite(g->qpt_lo) || !isfinite(g->qpt_hi) || !isfinite(g->d0_lo) ||
+      !isfinite(g->d0_hi) || !isfinite(g->bfield))
+    return false;
+  return true;
+}
+
+// Bin-centre constants, float64 then one rounding to float32:
+//   kappa_j = -c_B q/pT_j, d0_k, KAP = kappa_j, Q = kappa_j d0_k^2 + 2 d0_k,
+//   T = 0.5 / (1 + kappa_j d0_k).
+double qpt_centre(const ht_grid& g, int j) {
+  return (double)g.qpt_lo +
+         ((double)j + 0.5) * ((double)g.qpt_hi - (double)g.qpt_lo) / (double)g.n_qpt;
+}
+double kappa_centre(const ht_grid& g, int j) {
+  const double cb = ht::kCLight * (double)g.bfield;
+  return -cb * qpt_centre(g, j);
+}
+double d0_centre(const ht_grid& g, int k) {
+  return (double)g.d0_lo +
+         ((double)k + 0.5) * ((double)g.d0_hi - (double)g.d0_lo) / (double)g.n_d0;
+}
+
+template <typename T>
+int dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc((void**)p, n * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    return HT_ENOMEM;
+  }
+  return HT_OK;
+}
+
+void free_plan(Plan* p) {
+  void* ptrs[] = {p->d_kap,       p->d_q,         p->d_t,        p->d_bits,      p->d_tile_cnt,
+                  p->d_tile_off,  p->d_pbits,     p->d_col_first, p->d_hx,       p->d_hy,
+                  p->d_hq,        p->d_mcount,    p->d_mem,      p->d_madx,      p->d_cstat,
+                  p->d_cgeo,      p->d_chit,      p->d_cnl,      p->d_owner_key, p->d_ctile_cnt,
+                  p->d_ctile_off, p->d_trk_peak,  p->d_arc0,     p->d_arcn,      p->d_vacc,
+                  p->d_obj_cnt,   p->d_obj_off,   p->d_scalars};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ht_strerror(int status) {
+  switch (status) {
+    case HT_OK: return "ok";
+    case HT_EINVAL: return "invalid argument";
+    case HT_ENOMEM: return "device allocation failed";
+    case HT_EDEVICE: return "HIP runtime error";
+    case HT_EUNSUPPORTED: return "unsupported size for this build";
+    default: return "unknown status";
+  }
+}
+
+int ht_plan_create(const ht_grid* grid, const ht_limits* lim, ht_plan** out) {
+  if (!out) return HT_EINVAL;
+  *out = nullptr;
+  if (!grid_ok(grid) || !lim) return HT_EINVAL;
+  if (lim->max_hits < 0 || lim->max_peaks < 0 || lim->max_member_cap < 0 || lim->max_tracks < 0 ||
+      lim->max_vertex_cells < 0 || lim->max_n_rho < 0)
+    return HT_EINVAL;
+  if (lim->max_hits > 65535 || lim->max_peaks > (1 << 26) || grid->n_phi > 1024)
+    return HT_EUNSUPPORTED;
+  int dev = 0;
+  HT_CHECK(hipGetDevice(&dev));
+  ht_plan* p = new (std::nothrow) ht_plan();
+  if (!p) return HT_ENOMEM;
+  memset(static_cast<Plan*>(p), 0, sizeof(Plan));
+  p->grid = *grid;
+  p->lim = *lim;
+  p->device = dev;
+  const ht_grid& g = *grid;
+  p->n_cells = (int64_t)g.n_phi * g.n_qpt * g.n_d0;
+  p->n_tiles = (int32_t)((p->n_cells + 255) / 256);
+  p->phi_lo = (float)(-ht::kPi);
+  p->invw = (float)((double)g.n_phi / (2.0 * ht::kPi));
+
+  const size_t ncol = (size_t)g.n_qpt * g.n_d0;
+  float* hk = new (std::nothrow) float[g.n_qpt];
+  float* hq = new (std::nothrow) float[ncol];
+  float* ht_ = new (std::nothrow) float[ncol];
+  int rc = (hk && hq && ht_) ? HT_OK : HT_ENOMEM;
+  if (rc == HT_OK) {
+    for (int j = 0; j < g.n_qpt; ++j) hk[j] = (float)kappa_centre(g, j);
+    for (int k = 0; k < g.n_d0; ++k) {
+      const double d0 = d0_centre(g, k);
+      for (int j = 0; j < g.n_qpt; ++j) {
+        const double kap = kappa_centre(g, j);
+        hq[(size_t)k * g.n_qpt + j] = (float)(kap * d0 * d0 + 2.0 * d0);
+        ht_[(size_t)k * g.n_qpt + j] = (float)(0.5 / (1.0 + kap * d0));
+      }
+    }
+  }
+  const size_t nh = (size_t)lim->max_hits;
+  const size_t np = (size_t)lim->max_peaks;
+  const size_t words = (size_t)p->n_tiles * 8 + 2;
+  const int64_t ctiles = ((int64_t)np + 255) / 256;
+  if (rc == HT_OK) rc = dalloc(&p->d_kap, (size_t)g.n_qpt);
+  if (rc == HT_OK) rc = dalloc(&p->d_q, ncol);
+  if (rc == HT_OK) rc = dalloc(&p->d_t, ncol);
+  if (rc == HT_OK) rc = dalloc(&p->d_bits, words);
+  if (rc == HT_OK) rc = dalloc(&p->d_tile_cnt, (size_t)p->n_tiles);
+  if (rc == HT_OK) rc = dalloc(&p->d_tile_off, (size_t)p->n_tiles);
+  if (rc == HT_OK) rc = dalloc(&p->d_pbits, words);
+  if (rc == HT_OK) rc = dalloc(&p->d_col_first, ncol);
+  if (rc == HT_OK) rc = dalloc(&p->d_hx, nh);
+  if (rc == HT_OK) rc = dalloc(&p->d_hy, nh);
+  if (rc == HT_OK) rc = dalloc(&p->d_hq, nh);
+  if (rc == HT_OK) rc = dalloc(&p->d_mcount, np);
+  if (rc == HT_OK) rc = dalloc(&p->d_mem, np * (size_t)lim->max_member_cap);
+  if (rc == HT_OK) rc = dalloc(&p->d_madx, np * (size_t)lim->max_member_cap);
+  if (rc == HT_OK) rc = dalloc(&p->d_cstat, np);
+  if (rc == HT_OK) rc = dalloc(&p->d_cgeo, np * 5);
+  if (rc == HT_OK) rc = dalloc(&p->d_chit, np * HT_MAX_LAYERS);
+  if (rc == HT_OK) rc = dalloc(&p->d_cnl, np);
+  if (rc == HT_OK) rc = dalloc(&p->d_owner_key, nh);
+  if (rc == HT_OK) rc = dalloc(&p->d_ctile_cnt, (size_t)ctiles);
+  if (rc == HT_OK) rc = dalloc(&p->d_ctile_off, (size_t)ctiles);
+  if (rc == HT_OK) rc = dalloc(&p->d_trk_peak, (size_t)lim->max_tracks);
+  if (rc == HT_OK) rc = dalloc(&p->d_arc0, (size_t)lim->max_tracks * lim->max_n_rho);
+  if (rc == HT_OK) rc = dalloc(&p->d_arcn, (size_t)lim->max_tracks * lim->max_n_rho);
+  if (rc == HT_OK) rc = dalloc(&p->d_vacc, (size_t)lim->max_vertex_cells);
+  if (rc == HT_OK) rc = dalloc(&p->d_obj_cnt, (size_t)lim->max_vertex_cells);
+  if (rc == HT_OK) rc = dalloc(&p->d_obj_off, (size_t)lim->max_vertex_cells);
+  if (rc == HT_OK) rc = dalloc(&p->d_scalars, 16);
+  if (rc == HT_OK &&
+      (hipMemcpy(p->d_kap, hk, sizeof(float) * g.n_qpt, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(p->d_q, hq, sizeof(float) * ncol, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(p->d_t, ht_, sizeof(float) * ncol, hipMemcpyHostToDevice) != hipSuccess))
+    rc = HT_EDEVICE;
+  if (rc == HT_OK) rc = ht::vote_init(g.n_phi);
+  delete[] hk;
+  delete[] hq;
+  delete[] ht_;
+  if (rc != HT_OK) {
+    free_plan(p);
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return HT_OK;
+}
+
+void ht_plan_destroy(ht_plan* p) {
+  if (!p) return;
+  int cur = 0;
+  if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
+  free_plan(p);
+  if (cur != p->device) (void)hipSetDevice(cur);
+  delete p;
+}
+
+int hough_vote(const ht_plan* p, const float* r, const float* phi, int32_t n_hits, int32_t* acc,
+               unsigned long long* n_votes, void* stream) {
+  if (!p || !acc || n_hits < 0 || (n_hits > 0 && (!r || !phi))) return HT_EINVAL;
+  if (n_hits > 65535 || n_hits > p->lim.max_hits) return HT_EUNSUPPORTED;
+  return ht::launch_vote(*p, r, phi, n_hits, acc, n_votes, (hipStream_t)stream);
+}
+
+int hough_peaks(const ht_plan* p, const int32_t* acc, int32_t min_votes, ht_peak* out,
+                int32_t capacity, int32_t* n_found, void* stream) {
+  if (!p || !acc || !n_found || capacity < 0 || (capacity > 0 && !out)) return HT_EINVAL;
+  return ht::launch_peaks(*p, acc, min_votes, out, capacity, n_found, (hipStream_t)stream);
+}
+
+int assoc_cluster(const ht_plan* p, const float* r, const float* phi, const uint8_t* layer,
+                  int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks, int32_t peak_cap,
+                  const ht_cluster_cfg* cfg, const ht_cluster_out* out, void* stream) {
+  if (!p || !cfg || !out || !n_peaks || n_hits < 0 || peak_cap < 0) return HT_EINVAL;
+  if (n_hits > 0 && (!r || !phi || !layer || !out->hit_owner)) return HT_EINVAL;
+  if (peak_cap > 0 && !peaks) return HT_EINVAL;
+  if (!out->counts || out->track_cap < 0 || out->object_cap < 0 || out->member_cap < 0)
+    return HT_EINVAL;
+  if ((out->track_cap > 0 && !out->tracks) || (out->object_cap > 0 && !out->objects) ||
+      (out->member_cap > 0 && !out->members))
+    return HT_EINVAL;
+  const ht_cluster_cfg& c = *cfg;
+  if (c.win_bins < 0 || c.min_layers < 3 || c.min_layers > HT_MAX_LAYERS || c.seed_k < 1 ||
+      c.member_cap < 1 || !(c.road_sigmas > 0.0f) || !(c.box_margin >= 0.0f) ||
+      c.fit_iters < 0 || c.n_rho < 1 || c.n_theta < 4 || !(c.rho_hi > c.rho_lo) ||
+      !(c.rho_lo > 0.0f) || !(c.sigma_rphi > 0.0f) || !isfinite(c.rho_hi) ||
+      !isfinite(c.bh_max_isotropy) || !isfinite(c.road_sigmas) || !isfinite(c.box_margin))
+    return HT_EINVAL;
+  if (c.seed_k > 4 || n_hits > p->lim.max_hits || peak_cap > p->lim.max_peaks ||
+      c.member_cap > p->lim.max_member_cap || out->track_cap > p->lim.max_tracks ||
+      (int64_t)c.n_rho * c.n_theta > p->lim.max_vertex_cells || c.n_rho > p->lim.max_n_rho)
+    return HT_EUNSUPPORTED;
+  return ht::launch_assoc(*p, r, phi, layer, n_hits, peaks, n_peaks, peak_cap, c, *out,
+                          (hipStream_t)stream);
+}
+
+int ht_asin_f32(const float* u, float* out, int64_t n, void* stream) {
+  if (n < 0 || (n > 0 && (!u || !out))) return HT_EINVAL;
+  return ht::launch_asin(u, out, n, (hipStream_t)stream);
+}
+
+}  // extern "C"

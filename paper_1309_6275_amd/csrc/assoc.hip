@@ -1,0 +1,1192 @@
+// Candidate refinement, duplicate cleaning, refit and the second transform
+// (paper, section "Jet and Black Hole Detection": candidates from the peak
+// finder are refined, then a second Hough transform over the tracks finds
+// the vertices they share, away from the interaction point).
+//
+// Launch sequence (all on the caller's stream, no host synchronisation; the
+// device peak count bounds every per-candidate loop):
+//   prep      per hit: float64 Cartesian coordinates (canonical sincos),
+//             ownership keys cleared;
+//   mark      peak bitmap and the first peak index of every column;
+//   members   a sweep shaped like the vote (workgroup = 64 columns of one
+//             d0, lane = column, hits broadcast through SGPRs) that
+//             re-evaluates each hit's phi0 coordinate and appends it to
+//             every peak of the column whose member window holds it;
+//   refine    one wave per candidate: member layers, seed layers, the
+//             seed_k nearest members of each seed layer by wave argmin, then
+//             one seed combination per lane (<= 64) scored against all
+//             members in LDS; the best lane wins by (inliers, sum, index);
+//   own       per candidate, 64-bit atomicMax of (inliers, -sum, -index) on
+//             each inlier hit;
+//   survive   ordered compaction of the candidates owning >= min_layers
+//             hits into the track list (tile counts, scan, emit);
+//   fit       one thread per track, float64 Gauss-Newton;
+//   vvote     one thread per track: crossing arcs per vertex row, atomic
+//             votes into the vertex accumulator;
+//   vpeaks    one workgroup: vertex local maxima in cell order;
+//   vmembers  one wave per object: member tracks by ballot, written in
+//             order, isotropy summed in track order.
+// Every decision that selects an integer result uses float32 vote
+// arithmetic or float64 arithmetic and square roots in a fixed order, so the
+// results match the CPU reference bit for bit; the refit uses the device
+// asin/atan2 and matches to rounding.
+#include "ht_internal.h"
+
+namespace ht {
+namespace {
+
+constexpr int kSweepWaves = 16;
+constexpr int kSweepThreads = kSweepWaves * kWave;
+constexpr int kRefineWaves = 1;  // one wave per workgroup: barriers are wave-local
+constexpr int kMaxMembers = 256;  // LDS member slots per wave in refine
+constexpr int kGridCap = 8192;    // grid-stride launches use at most this many blocks
+
+enum { S_NP = 0, S_NCAND = 1, S_NOVER = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5 };
+
+__device__ __forceinline__ float bcastf(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ int bcasti(int v, int lane) {
+  return __builtin_amdgcn_readlane(v, lane);
+}
+
+// ---- canonical float64 functions (arithmetic only) ------------------------
+// Cody-Waite reduction by pi/2 (33-bit high part) and Taylor series of sin
+// and cos on |r| <= pi/4; valid for |a| <= 4.
+__device__ void csincos(double a, double* s_out, double* c_out) {
+  const double PIO2_HI = 1.57079632673412561417e+00;
+  const double PIO2_LO = 6.07710050650619224932e-11;
+  double t = a * 0.63661977236758134308;
+  double kf = floor(t + 0.5);
+  double r = a - kf * PIO2_HI;
+  r = r - kf * PIO2_LO;
+  double z = r * r;
+  double ps = -1.0 / 355687428096000.0;
+  ps = ps * z + 1.0 / 1307674368000.0;
+  ps = ps * z - 1.0 / 6227020800.0;
+  ps = ps * z + 1.0 / 39916800.0;
+  ps = ps * z - 1.0 / 362880.0;
+  ps = ps * z + 1.0 / 5040.0;
+  ps = ps * z - 1.0 / 120.0;
+  ps = ps * z + 1.0 / 6.0;
+  double sn = r - r * z * ps;
+  double pc = 1.0 / 20922789888000.0;
+  pc = pc * z - 1.0 / 87178291200.0;
+  pc = pc * z + 1.0 / 479001600.0;
+  pc = pc * z - 1.0 / 3628800.0;
+  pc = pc * z + 1.0 / 40320.0;
+  pc = pc * z - 1.0 / 720.0;
+  pc = pc * z + 1.0 / 24.0;
+  pc = pc * z - 0.5;
+  double cs = 1.0 + z * pc;
+  int q = ((int)kf) & 3;
+  if (q == 0) { *s_out = sn; *c_out = cs; }
+  else if (q == 1) { *s_out = cs; *c_out = -sn; }
+  else if (q == 2) { *s_out = -sn; *c_out = -cs; }
+  else { *s_out = -cs; *c_out = sn; }
+}
+
+// Octant reduction, atan z = pi/6 + atan((sqrt3 z - 1)/(z + sqrt3)) above
+// tan(pi/12), Taylor series of atan to z^35.
+__device__ double catan2(double y, double x) {
+  double ax = fabs(x), ay = fabs(y);
+  bool swap = ay > ax;
+  double num = swap ? ax : ay, den = swap ? ay : ax;
+  if (den == 0.0) return 0.0;
+  double z = num / den;
+  double base = 0.0;
+  const double SQRT3 = 1.73205080756887729353;
+  const double TAN_PI_12 = 0.26794919243112270647;
+  if (z > TAN_PI_12) {
+    z = (z * SQRT3 - 1.0) / (z + SQRT3);
+    base = kPi / 6.0;
+  }
+  double w = z * z;
+  double p = -1.0 / 35.0;
+  p = p * w + 1.0 / 33.0;
+  p = p * w - 1.0 / 31.0;
+  p = p * w + 1.0 / 29.0;
+  p = p * w - 1.0 / 27.0;
+  p = p * w + 1.0 / 25.0;
+  p = p * w - 1.0 / 23.0;
+  p = p * w + 1.0 / 21.0;
+  p = p * w - 1.0 / 19.0;
+  p = p * w + 1.0 / 17.0;
+  p = p * w - 1.0 / 15.0;
+  p = p * w + 1.0 / 13.0;
+  p = p * w - 1.0 / 11.0;
+  p = p * w + 1.0 / 9.0;
+  p = p * w - 1.0 / 7.0;
+  p = p * w + 1.0 / 5.0;
+  p = p * w - 1.0 / 3.0;
+  double a = base + (z + z * w * p);
+  if (swap) a = kPi / 2.0 - a;
+  if (x < 0.0) a = kPi - a;
+  if (y < 0.0) a = -a;
+  return a;
+}
+
+// Circle A(x^2+y^2) + Bx + Cy + D = 0 through P1, P2, P3 (inner to outer),
+// normalised to B^2 + C^2 - 4AD = 1 and oriented so that (-C, B), the
+// direction of motion at the perigee, points from P1 towards P3.
+__device__ bool circle3(double x1, double y1, double x2, double y2, double x3, double y3,
+                        double* A, double* B, double* C, double* D) {
+  double X2 = x2 - x1, Y2 = y2 - y1, X3 = x3 - x1, Y3 = y3 - y1;
+  double q2 = X2 * X2 + Y2 * Y2;
+  double q3 = X3 * X3 + Y3 * Y3;
+  double a = X2 * Y3 - Y2 * X3;
+  double b = Y2 * q3 - q2 * Y3;
+  double c = q2 * X3 - X2 * q3;
+  double nrm2 = b * b + c * c;
+  if (!(nrm2 > 0.0)) return false;
+  double nrm = sqrt(nrm2);
+  double q1 = x1 * x1 + y1 * y1;
+  double AA = a;
+  double BB = b - 2.0 * a * x1;
+  double CC = c - 2.0 * a * y1;
+  double DD = a * q1 - b * x1 - c * y1;
+  AA = AA / nrm;
+  BB = BB / nrm;
+  CC = CC / nrm;
+  DD = DD / nrm;
+  double dir = -CC * (x3 - x1) + BB * (y3 - y1);
+  if (dir == 0.0) return false;
+  if (dir < 0.0) { AA = -AA; BB = -BB; CC = -CC; DD = -DD; }
+  *A = AA; *B = BB; *C = CC; *D = DD;
+  return true;
+}
+
+// signed distance of a point from the normalised circle
+__device__ __forceinline__ double circle_dist(double A, double B, double C, double D, double x,
+                                              double y, double q) {
+  double f = A * q + B * x + C * y + D;
+  double s = 1.0 + 4.0 * A * f;
+  if (s < 0.0) s = 0.0;
+  return 2.0 * f / (1.0 + sqrt(s));
+}
+
+// float32 phi0 coordinate of a hit in a column (the vote formula); false
+// when |u| > 1
+__device__ __forceinline__ bool phi0_coord(float r2, float ir, float ph, float ck, float cq,
+                                           float ct, float phi_lo, float invw, float* x) {
+  const float a = ck * r2;
+  const float b = a + cq;
+  const float c = b * ir;
+  const float u = c * ct;
+  if (!(fabsf(u) <= 1.0f)) return false;
+  const float s = asin_f(u);
+  const float phi0 = ph - s;
+  const float d = phi0 - phi_lo;
+  *x = d * invw;
+  return true;
+}
+
+// |x - (i + 0.5)| on the periodic image of x nearest the cell
+__device__ __forceinline__ float cell_adx(float x, int i, int n_phi) {
+  const float xi = (float)i + 0.5f;
+  const float half_n = 0.5f * (float)n_phi;
+  float dx = x - xi;
+  if (dx > half_n) dx = (x - (float)n_phi) - xi;
+  else if (dx < -half_n) dx = (x + (float)n_phi) - xi;
+  return fabsf(dx);
+}
+
+// member window half-width in bins for a hit at radius r (ir = 1/r)
+__device__ __forceinline__ float member_window(float r, float ir, float wbase, float hd0,
+                                               float hk, float invw) {
+  const float e1 = hd0 * ir;
+  const float e2 = r * 0.5f;
+  const float e3 = hk * e2;
+  const float e4 = e1 + e3;
+  const float e5 = invw * e4;
+  return wbase + e5;
+}
+
+struct AssocArgs {
+  // grid
+  int n_phi, n_qpt, n_d0;
+  int64_t n_cells;
+  float phi_lo, invw;
+  const float* kap;
+  const float* qt;
+  const float* tt;
+  bool origin_seed;
+  double kap_bin, d0_bin;
+  float hk, hd0;
+  double d0_lo, d0_hi, qpt_lo, qpt_hi, bfield;
+  // hits
+  const float* r;
+  const float* phi;
+  const uint8_t* layer;
+  int n_hits;
+  double* hx;
+  double* hy;
+  double* hq;
+  // peaks
+  const ht_peak* peaks;
+  const int32_t* n_peaks;
+  int peak_cap;
+  // cfg
+  ht_cluster_cfg cfg;
+  // scratch
+  uint32_t* pbits;
+  int32_t* col_first;
+  int32_t* mcount;
+  uint16_t* mem;
+  int32_t* cstat;
+  int32_t* cnl;
+  double* cgeo;
+  int32_t* chit;
+  unsigned long long* owner_key;
+  int32_t* ctile_cnt;
+  int32_t* ctile_off;
+  int32_t* trk_peak;
+  int32_t* arc0;
+  int32_t* arcn;
+  int32_t* vacc;
+  int32_t* obj_cnt;
+  int32_t* sc;  // device scalars
+  // outputs
+  ht_cluster_out out;
+};
+
+__device__ __forceinline__ int n_cands(const AssocArgs& A) { return A.sc[S_NP]; }
+
+// ---- prep ------------------------------------------------------------------
+__global__ void init_kernel(AssocArgs A, int words) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (tid < 16) A.sc[tid] = 0;
+  if (tid == 0) {
+    int np = *A.n_peaks;
+    np = np < 0 ? 0 : (np > A.peak_cap ? A.peak_cap : np);
+    A.sc[S_NP] = np;
+  }
+  for (int64_t w = tid; w < words; w += stride) A.pbits[w] = 0u;
+  for (int64_t h = tid; h < A.n_hits; h += stride) {
+    const float r = A.r[h], ph = A.phi[h];
+    const bool ok = hit_ok(r, ph);
+    double s, c;
+    csincos(ok ? (double)ph : 0.0, &s, &c);
+    const double rr = (double)r;
+    const double x = rr * c;
+    const double y = rr * s;
+    A.hx[h] = x;
+    A.hy[h] = y;
+    A.hq[h] = x * x + y * y;
+    A.owner_key[h] = 0ull;
+    A.out.hit_owner[h] = -1;
+  }
+  const int ncell_v = A.cfg.n_rho * A.cfg.n_theta;
+  for (int64_t v = tid; v < ncell_v; v += stride) A.vacc[v] = 0;
+}
+
+__global__ void mark_kernel(AssocArgs A) {
+  const int np = n_cands(A);
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
+    A.mcount[p] = 0;
+    const int lin = A.peaks[p].lin;
+    if (lin < 0 || lin >= A.n_cells) continue;
+    atomicOr(&A.pbits[lin >> 5], 1u << (lin & 31));
+    const int col = lin / A.n_phi;
+    bool first = p == 0;
+    if (!first) {
+      const int pl = A.peaks[p - 1].lin;
+      first = pl < 0 || pl >= A.n_cells || pl / A.n_phi != col;
+    }
+    if (first) A.col_first[col] = p;
+  }
+}
+
+// ---- member sweep -----------------------------------------------------------
+// LDS per column: the column's peak bits (starting at bit i = 0) and the
+// number of peaks before each 32-bit word.
+constexpr int kMaxPhiWords = 32;  // n_phi <= 1024
+
+__global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
+  __shared__ uint32_t cbits[kWave][kMaxPhiWords + 1];
+  __shared__ int32_t cpre[kWave][kMaxPhiWords + 1];
+  __shared__ int any_peak;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x >> 6;
+  const int j0 = blockIdx.x * kWave;
+  const int k = blockIdx.y;
+  const int n_phi = A.n_phi;
+  const int nwords = (n_phi + 31) >> 5;
+  if (threadIdx.x == 0) any_peak = 0;
+  __syncthreads();
+  // gather the column bitmaps (column bits are not word aligned in general)
+  for (int e = threadIdx.x; e < kWave * nwords; e += kSweepThreads) {
+    const int cl = e / nwords, w = e - cl * nwords;
+    const int j = j0 + cl;
+    uint32_t v = 0;
+    if (j < A.n_qpt) {
+      const int64_t bit0 = ((int64_t)k * A.n_qpt + j) * n_phi + (int64_t)w * 32;
+      const int nb = min(32, n_phi - w * 32);
+      const int64_t wi = bit0 >> 5;
+      const int sh = (int)(bit0 & 31);
+      uint64_t two = (uint64_t)A.pbits[wi];
+      if (sh + nb > 32) two |= (uint64_t)A.pbits[wi + 1] << 32;
+      v = (uint32_t)(two >> sh);
+      if (nb < 32) v &= (1u << nb) - 1u;
+    }
+    cbits[cl][w] = v;
+    if (v) any_peak = 1;
+  }
+  __syncthreads();
+  if (!any_peak) return;
+  if (threadIdx.x < kWave) {
+    int s = 0;
+    for (int w = 0; w < nwords; ++w) {
+      cpre[threadIdx.x][w] = s;
+      s += __popc(cbits[threadIdx.x][w]);
+    }
+  }
+  __syncthreads();
+
+  const int j = j0 + lane;
+  const bool col_ok = j < A.n_qpt;
+  float ck = 0.0f, cq = 0.0f, ct = 0.0f;
+  int cfirst = 0;
+  bool has = false;
+  if (col_ok) {
+    ck = A.kap[j];
+    cq = A.qt[(size_t)k * A.n_qpt + j];
+    ct = A.tt[(size_t)k * A.n_qpt + j];
+    for (int w = 0; w < nwords; ++w) has |= cbits[lane][w] != 0u;
+    if (has) cfirst = A.col_first[(size_t)k * A.n_qpt + j];
+  }
+  const float wbase = 0.5f + (float)A.cfg.win_bins;
+  const int cap = A.cfg.member_cap;
+  const int np = n_cands(A);
+  for (int base = wave * kWave; base < A.n_hits; base += kSweepThreads) {
+    const int h = base + lane;
+    float hr = 1.0f, hp = 0.0f;
+    bool hv = false;
+    if (h < A.n_hits) {
+      hr = A.r[h];
+      hp = A.phi[h];
+      hv = hit_ok(hr, hp) && A.layer[h] < HT_MAX_LAYERS;
+    }
+    const float hr2 = hr * hr;
+    const float hir = 1.0f / hr;
+    const float hw = member_window(hr, hir, wbase, A.hd0, A.hk, A.invw);
+    uint64_t todo = __ballot(hv);
+    while (todo) {
+      const int src = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const float r2 = bcastf(hr2, src);
+      const float ir = bcastf(hir, src);
+      const float ph = bcastf(hp, src);
+      const float w = bcastf(hw, src);
+      const int hh = base + src;
+      float x;
+      if (!has || !phi0_coord(r2, ir, ph, ck, cq, ct, A.phi_lo, A.invw, &x)) continue;
+      // candidate cells: a conservative integer range (at most one pass over
+      // the column), then the exact test of the reference
+      int ilo = 0, ihi = n_phi - 1;
+      if (w < 0.5f * (float)n_phi) {
+        const int lo = (int)floorf(x - w - 0.5f) - 1;
+        const int hi = (int)floorf(x + w - 0.5f) + 1;
+        if (hi - lo + 1 < n_phi) { ilo = lo; ihi = hi; }
+      }
+      int i = ilo;
+      while (i <= ihi) {
+        int iw = i % n_phi;
+        if (iw < 0) iw += n_phi;
+        const int wi = iw >> 5, bit = iw & 31;
+        int span = 32 - bit;
+        span = min(span, ihi - i + 1);
+        span = min(span, n_phi - iw);
+        uint32_t bits = cbits[lane][wi] >> bit;
+        if (span < 32) bits &= (1u << span) - 1u;
+        while (bits) {
+          const int b = __builtin_ctz(bits);
+          bits &= bits - 1u;
+          const int ic = iw + b;
+          const float adx = cell_adx(x, ic, n_phi);
+          if (!(adx <= w)) continue;
+          const uint32_t below = cbits[lane][wi] & ((1u << (bit + b)) - 1u);
+          const int p = cfirst + cpre[lane][wi] + __popc(below);
+          if (p < 0 || p >= np) continue;  // only for peak lists not sorted by cell
+          const int slot = atomicAdd(&A.mcount[p], 1);
+          if (slot < cap) A.mem[(size_t)p * cap + slot] = (uint16_t)hh;
+        }
+        i += span;
+      }
+    }
+  }
+}
+
+// ---- refine: one wave per candidate ------------------------------------------
+struct WaveMem {
+  int32_t h[kMaxMembers];
+  int8_t L[kMaxMembers];
+  float adx[kMaxMembers];
+  double x[kMaxMembers];
+  double y[kMaxMembers];
+  double q[kMaxMembers];
+  int32_t order[kMaxMembers];   // members grouped by layer
+  int32_t lstart[HT_MAX_LAYERS + 1];
+};
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(v, off);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ int wave_max_i32(int v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+  for (int off = 32; off > 0; off >>= 1) v |= __shfl_xor(v, off);
+  return v;
+}
+
+// index of the n-th (0-based) set bit of a 16-bit mask
+__device__ __forceinline__ int nth_set_bit(unsigned mask, int n) {
+  for (int L = 0; L < HT_MAX_LAYERS; ++L) {
+    if ((mask >> L) & 1u) {
+      if (n == 0) return L;
+      --n;
+    }
+  }
+  return HT_MAX_LAYERS - 1;
+}
+
+__global__ __launch_bounds__(kRefineWaves* kWave) void refine_kernel(AssocArgs A) {
+  __shared__ WaveMem wm_all[kRefineWaves];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x >> 6;
+  WaveMem& M = wm_all[wave];
+  const int np = n_cands(A);
+  const ht_cluster_cfg& cfg = A.cfg;
+  const int cap = cfg.member_cap;
+  for (int p = blockIdx.x * kRefineWaves + wave; p < np; p += gridDim.x * kRefineWaves) {
+    const int lin = A.peaks[p].lin;
+    const int n = A.mcount[p];
+    if (lin < 0 || lin >= A.n_cells) {
+      if (lane == 0) { A.cstat[p] = -1; A.cnl[p] = 0; }
+      continue;
+    }
+    if (n > cap) {
+      if (lane == 0) { A.cstat[p] = -2; A.cnl[p] = 0; atomicAdd(&A.sc[S_NOVER], 1); }
+      continue;
+    }
+    const int i = lin % A.n_phi;
+    const int col = lin / A.n_phi;
+    const int j = col % A.n_qpt;
+    const int k = col / A.n_qpt;
+    const float ck = A.kap[j], cq = A.qt[col], ct = A.tt[col];
+    // load members
+    unsigned lmask = 0;
+    for (int m = lane; m < n; m += kWave) {
+      const int h = A.mem[(size_t)p * cap + m];
+      const int L = A.layer[h];
+      const float r = A.r[h];
+      float x = 0.0f;
+      phi0_coord(r * r, 1.0f / r, A.phi[h], ck, cq, ct, A.phi_lo, A.invw, &x);
+      M.h[m] = h;
+      M.L[m] = (int8_t)L;
+      M.adx[m] = cell_adx(x, i, A.n_phi);
+      M.x[m] = A.hx[h];
+      M.y[m] = A.hy[h];
+      M.q[m] = A.hq[h];
+      lmask |= 1u << L;
+    }
+    lmask = wave_or(lmask);
+    const int nS = __popc(lmask);
+    if (nS < cfg.min_layers || nS < 3) {
+      if (lane == 0) { A.cstat[p] = -1; A.cnl[p] = nS; }
+      continue;
+    }
+    // group members by layer (stable order is not needed: ties break on h)
+    if (lane == 0) {
+      int s = 0;
+      for (int L = 0; L < HT_MAX_LAYERS; ++L) {
+        M.lstart[L] = s;
+        for (int m = 0; m < n; ++m)
+          if (M.L[m] == L) M.order[s++] = m;
+      }
+      M.lstart[HT_MAX_LAYERS] = s;
+    }
+    __syncthreads();
+    // seed layers: innermost, middle and outermost of the outer min(nS, min_layers)
+    const int span = nS < cfg.min_layers ? nS : cfg.min_layers;
+    const int Ls0 = nth_set_bit(lmask, nS - span);
+    const int Ls1 = nth_set_bit(lmask, nS - span + (span - 1) / 2);
+    const int Ls2 = nth_set_bit(lmask, nS - 1);
+    // seed_k nearest members per seed layer: repeated wave argmin on (adx, h)
+    int seedm[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    int ns[3] = {0, 0, 0};
+    const int kk = cfg.seed_k;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const int Lsel = s == 0 ? Ls0 : (s == 1 ? Ls1 : Ls2);
+      unsigned long long prev = 0ull;
+      bool have_prev = false, done = false;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t >= kk || done) continue;
+        unsigned long long best = ~0ull;
+        for (int m = lane; m < n; m += kWave) {
+          if (M.L[m] != Lsel) continue;
+          const unsigned long long key =
+              ((unsigned long long)__float_as_uint(M.adx[m]) << 32) | (unsigned)M.h[m];
+          if (have_prev && key <= prev) continue;
+          best = key < best ? key : best;
+        }
+        best = wave_min_u64(best);
+        if (best == ~0ull) { done = true; continue; }
+        // recover the member slot of that hit
+        int slot = -1;
+        for (int m = lane; m < n; m += kWave)
+          if (M.L[m] == Lsel && (unsigned)M.h[m] == (unsigned)(best & 0xffffffffu)) slot = m;
+        slot = wave_max_i32(slot);
+        seedm[s][t] = slot;
+        ns[s] = t + 1;
+        prev = best;
+        have_prev = true;
+      }
+    }
+    if (A.origin_seed) ns[0] = 1;
+    const int nc = ns[0] * ns[1] * ns[2];
+    // one combination per lane
+    int n_in = -1;
+    double ss = 0.0;
+    double cA = 0.0, cB = 0.0, cC = 0.0, cD = 0.0;
+    int hitL[HT_MAX_LAYERS];
+#pragma unroll
+    for (int L = 0; L < HT_MAX_LAYERS; ++L) hitL[L] = -1;
+    const double road = (double)cfg.road_sigmas * (double)cfg.sigma_rphi;
+    if (lane < nc) {
+      const int a = lane / (ns[1] * ns[2]);
+      const int b = (lane / ns[2]) % ns[1];
+      const int c = lane % ns[2];
+      int ma = 0, mb = 0, mc = 0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t == a) ma = seedm[0][t];
+        if (t == b) mb = seedm[1][t];
+        if (t == c) mc = seedm[2][t];
+      }
+      double xa = 0.0, ya = 0.0;
+      if (!A.origin_seed) { xa = M.x[ma]; ya = M.y[ma]; }
+      bool ok = circle3(xa, ya, M.x[mb], M.y[mb], M.x[mc], M.y[mc], &cA, &cB, &cC, &cD);
+      if (ok) {
+        const double kapc = -(kCLight * A.bfield) *
+                            (A.qpt_lo + ((double)j + 0.5) * (A.qpt_hi - A.qpt_lo) / (double)A.n_qpt);
+        const double d0c = A.d0_lo + ((double)k + 0.5) * (A.d0_hi - A.d0_lo) / (double)A.n_d0;
+        double ktol = (0.5 + (double)cfg.box_margin) * A.kap_bin;
+        if (ktol < 1e-6) ktol = 1e-6;
+        const double dtol = (0.5 + (double)cfg.box_margin) * A.d0_bin + road;
+        const double kap = 2.0 * cA;
+        const double sq = sqrt(cB * cB + cC * cC);
+        const double d0 = 2.0 * cD / (1.0 + sq);
+        ok = (fabs(kap - kapc) <= ktol) && (fabs(d0 - d0c) <= dtol);
+      }
+      if (ok) {
+        n_in = 0;
+        int remaining = nS;
+#pragma unroll
+        for (int L = 0; L < HT_MAX_LAYERS; ++L) {
+          if (!((lmask >> L) & 1u)) continue;
+          --remaining;
+          if (n_in + remaining + 1 < cfg.min_layers) { n_in = -2; break; }
+          double bd = 0.0;
+          int bh = -1;
+          for (int e = M.lstart[L]; e < M.lstart[L + 1]; ++e) {
+            const int m = M.order[e];
+            const double dist = fabs(circle_dist(cA, cB, cC, cD, M.x[m], M.y[m], M.q[m]));
+            if (!(dist <= road)) continue;
+            if (bh < 0 || dist < bd || (dist == bd && M.h[m] < bh)) { bh = M.h[m]; bd = dist; }
+          }
+          hitL[L] = bh;
+          if (bh >= 0) { ++n_in; ss += bd * bd; }
+        }
+      }
+    }
+    // best lane: most inliers, then smallest sum, then lowest combination index
+    const int best_n = wave_max_i32(n_in);
+    if (best_n < cfg.min_layers) {
+      if (lane == 0) { A.cstat[p] = -1; A.cnl[p] = nS; }
+      __syncthreads();
+      continue;
+    }
+    unsigned long long key = ~0ull;
+    if (n_in == best_n) key = (unsigned long long)__double_as_longlong(ss);
+    const unsigned long long best_ss = wave_min_u64(key);
+    const unsigned long long ballot = __ballot(n_in == best_n && key == best_ss);
+    const int win = __builtin_ctzll(ballot);
+    if (lane == win) {
+      A.cstat[p] = best_n;
+      A.cnl[p] = nS;
+      double* g = A.cgeo + (size_t)p * 5;
+      g[0] = ss; g[1] = cA; g[2] = cB; g[3] = cC; g[4] = cD;
+#pragma unroll
+      for (int L = 0; L < HT_MAX_LAYERS; ++L) A.chit[(size_t)p * HT_MAX_LAYERS + L] = hitL[L];
+      atomicAdd(&A.sc[S_NCAND], 1);
+    }
+    __syncthreads();
+  }
+}
+
+// ---- ownership -----------------------------------------------------------------
+__device__ __forceinline__ unsigned long long own_key(int n_in, double ss, int p) {
+  const uint32_t sb = __float_as_uint((float)ss);
+  return ((unsigned long long)n_in << 58) | ((unsigned long long)(0xffffffffu - sb) << 26) |
+         (unsigned long long)(0x3ffffff - p);
+}
+
+__global__ void own_kernel(AssocArgs A) {
+  const int np = n_cands(A);
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
+    const int st = A.cstat[p];
+    if (st < 0) continue;
+    const unsigned long long key = own_key(st, A.cgeo[(size_t)p * 5], p);
+    for (int L = 0; L < HT_MAX_LAYERS; ++L) {
+      const int h = A.chit[(size_t)p * HT_MAX_LAYERS + L];
+      if (h >= 0) atomicMax(&A.owner_key[h], key);
+    }
+  }
+}
+
+__device__ __forceinline__ int owned_count(const AssocArgs& A, int p) {
+  int own = 0;
+  for (int L = 0; L < HT_MAX_LAYERS; ++L) {
+    const int h = A.chit[(size_t)p * HT_MAX_LAYERS + L];
+    if (h >= 0 && (int)(0x3ffffff - (A.owner_key[h] & 0x3ffffffull)) == p) ++own;
+  }
+  return own;
+}
+
+__device__ __forceinline__ bool survives(const AssocArgs& A, int p, int* own) {
+  if (A.cstat[p] < 0) return false;
+  *own = owned_count(A, p);
+  return *own >= A.cfg.min_layers;
+}
+
+// survivor counts per 256-candidate tile
+__global__ __launch_bounds__(256) void surv_count_kernel(AssocArgs A, int tiles) {
+  __shared__ int32_t wc[4];
+  const int np = n_cands(A);
+  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int p = tile * 256 + threadIdx.x;
+    int own = 0;
+    const bool s = p < np && survives(A, p, &own);
+    const uint64_t m = __ballot(s);
+    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) A.ctile_cnt[tile] = wc[0] + wc[1] + wc[2] + wc[3];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(1024) void scan_kernel(const int32_t* __restrict__ cnt,
+                                                    int32_t* __restrict__ off, int n,
+                                                    int32_t* __restrict__ total) {
+  __shared__ long long part[1024];
+  const int t = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int b = t * per, e = min(n, b + per);
+  long long s = 0;
+  for (int x = b; x < e; ++x) s += cnt[x];
+  part[t] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    long long v = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  long long run = part[t] - s;
+  for (int x = b; x < e; ++x) {
+    off[x] = run > 0x7fffffffLL ? 0x7fffffff : (int32_t)run;
+    run += cnt[x];
+  }
+  if (t == 1023) *total = part[t] > 0x7fffffffLL ? 0x7fffffff : (int32_t)part[t];
+}
+
+__global__ __launch_bounds__(256) void surv_emit_kernel(AssocArgs A, int tiles) {
+  __shared__ int32_t wc[4];
+  const int np = n_cands(A);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int p = tile * 256 + threadIdx.x;
+    int own = 0;
+    const bool s = p < np && survives(A, p, &own);
+    const uint64_t m = __ballot(s);
+    if (lane == 0) wc[wave] = __popcll(m);
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += wc[w];
+    if (s) {
+      const uint64_t lower = lane ? (m & ((1ull << lane) - 1ull)) : 0ull;
+      const int t = A.ctile_off[tile] + before + __popcll(lower);
+      if (t < A.out.track_cap) {
+        ht_track tr;
+        tr.peak = p;
+        tr.lin = A.peaks[p].lin;
+        tr.votes = A.peaks[p].votes;
+        tr.n_layers = A.cnl[p];
+        tr.n_inliers = A.cstat[p];
+        tr.n_owned = own;
+        tr.status = 0;
+        tr.seed_ss = (float)A.cgeo[(size_t)p * 5];
+        tr.phi0 = tr.qpt = tr.d0 = tr.chi2 = 0.0f;
+        float rf = __builtin_inff();
+        for (int L = 0; L < HT_MAX_LAYERS; ++L) {
+          int h = A.chit[(size_t)p * HT_MAX_LAYERS + L];
+          if (h >= 0 && (int)(0x3ffffff - (A.owner_key[h] & 0x3ffffffull)) != p) h = -1;
+          tr.hits[L] = h;
+          if (h >= 0) {
+            if (A.r[h] < rf) rf = A.r[h];
+            A.out.hit_owner[h] = t;
+          }
+        }
+        tr.r_first = rf;
+        A.out.tracks[t] = tr;
+        A.trk_peak[t] = p;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- refit ----------------------------------------------------------------------
+__device__ __forceinline__ double wrap_pi(double a) {
+  return a - 2.0 * kPi * floor((a + kPi) / (2.0 * kPi));
+}
+
+__global__ void fit_kernel(AssocArgs A) {
+  const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntrk; t += gridDim.x * blockDim.x) {
+    ht_track& tr = A.out.tracks[t];
+    const int p = A.trk_peak[t];
+    const double* g = A.cgeo + (size_t)p * 5;
+    const double gA = g[1], gB = g[2], gC = g[3], gD = g[4];
+    const int lin = tr.lin;
+    const int i = lin % A.n_phi, col = lin / A.n_phi, j = col % A.n_qpt, k = col / A.n_qpt;
+    const double cb = kCLight * A.bfield;
+    const double kap_c = -cb * (A.qpt_lo + ((double)j + 0.5) * (A.qpt_hi - A.qpt_lo) / (double)A.n_qpt);
+    const double d0_c = A.d0_lo + ((double)k + 0.5) * (A.d0_hi - A.d0_lo) / (double)A.n_d0;
+    const double sq0 = sqrt(gB * gB + gC * gC);
+    double p3[3];
+    p3[0] = atan2(gB, -gC);
+    p3[1] = A.n_qpt > 1 ? 2.0 * gA : kap_c;
+    p3[2] = A.n_d0 > 1 ? 2.0 * gD / (1.0 + sq0) : d0_c;
+    int idx[3], nfree = 0;
+    idx[nfree++] = 0;
+    if (A.n_qpt > 1) idx[nfree++] = 1;
+    if (A.n_d0 > 1) idx[nfree++] = 2;
+    int status = 0;
+    for (int it = 0; it < A.cfg.fit_iters && status == 0; ++it) {
+      double Am[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, gv[3] = {0, 0, 0};
+      for (int L = 0; L < HT_MAX_LAYERS; ++L) {
+        const int h = tr.hits[L];
+        if (h < 0) continue;
+        const double rr = (double)A.r[h], ph = (double)A.phi[h];
+        const double kap = p3[1], d0 = p3[2];
+        const double den = 1.0 + kap * d0;
+        const double u = (kap * (rr * rr + d0 * d0) + 2.0 * d0) / (2.0 * rr * den);
+        if (!(fabs(u) < 1.0)) { status = 1; break; }
+        const double sq = sqrt(1.0 - u * u);
+        const double res = wrap_pi(ph - (p3[0] + asin(u)));
+        double jac[3];
+        jac[0] = 1.0;
+        jac[1] = (rr * rr - d0 * d0) / (2.0 * rr * den * den) / sq;
+        jac[2] = (den * den + 1.0 - kap * kap * rr * rr) / (2.0 * rr * den * den) / sq;
+        const double w = rr * rr;
+        for (int a = 0; a < nfree; ++a) {
+          gv[a] += w * jac[idx[a]] * res;
+          for (int b = 0; b < nfree; ++b) Am[a][b] += w * jac[idx[a]] * jac[idx[b]];
+        }
+      }
+      if (status) break;
+      double Lm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      for (int a = 0; a < nfree && !status; ++a) {
+        for (int b = 0; b <= a; ++b) {
+          double s = Am[a][b];
+          for (int c = 0; c < b; ++c) s -= Lm[a][c] * Lm[b][c];
+          if (a == b) {
+            if (!(s > 0.0)) { status = 2; break; }
+            Lm[a][a] = sqrt(s);
+          } else {
+            Lm[a][b] = s / Lm[b][b];
+          }
+        }
+      }
+      if (status) break;
+      double y[3], d[3];
+      for (int a = 0; a < nfree; ++a) {
+        double s = gv[a];
+        for (int c = 0; c < a; ++c) s -= Lm[a][c] * y[c];
+        y[a] = s / Lm[a][a];
+      }
+      for (int a = nfree - 1; a >= 0; --a) {
+        double s = y[a];
+        for (int c = a + 1; c < nfree; ++c) s -= Lm[c][a] * d[c];
+        d[a] = s / Lm[a][a];
+      }
+      for (int a = 0; a < nfree; ++a) p3[idx[a]] += d[a];
+    }
+    double chi2 = 0.0;
+    if (status == 0) {
+      for (int L = 0; L < HT_MAX_LAYERS; ++L) {
+        const int h = tr.hits[L];
+        if (h < 0) continue;
+        const double rr = (double)A.r[h], ph = (double)A.phi[h];
+        const double kap = p3[1], d0 = p3[2];
+        const double den = 1.0 + kap * d0;
+        const double u = (kap * (rr * rr + d0 * d0) + 2.0 * d0) / (2.0 * rr * den);
+        if (!(fabs(u) < 1.0)) { status = 1; break; }
+        const double res = wrap_pi(ph - (p3[0] + asin(u)));
+        const double z = rr * res / (double)A.cfg.sigma_rphi;
+        chi2 += z * z;
+      }
+    }
+    if (status != 0) {
+      p3[0] = -kPi + ((double)i + 0.5) * (2.0 * kPi / (double)A.n_phi);
+      p3[1] = kap_c;
+      p3[2] = d0_c;
+      chi2 = -1.0;
+    }
+    tr.status = status;
+    tr.phi0 = (float)wrap_pi(p3[0]);
+    tr.qpt = (float)(-p3[1] / cb);
+    tr.d0 = (float)p3[2];
+    tr.chi2 = (float)chi2;
+  }
+}
+
+// ---- second transform --------------------------------------------------------------
+__device__ __forceinline__ double crossing_theta(double cA, double cB, double cC, double cD,
+                                                 double sn, double rho) {
+  const double c0 = -(cA * rho * rho + cD);
+  const double dl = c0 / sn;
+  const double hh = (rho - dl) * (rho + dl);
+  const double h = hh > 0.0 ? sqrt(hh) : 0.0;
+  const double px = (dl / sn) * cB + (h / sn) * (-cC);
+  const double py = (dl / sn) * cC + (h / sn) * cB;
+  return catan2(py, px);
+}
+
+__device__ __forceinline__ int theta_bin(double th, int nt) {
+  int t = (int)floor((th + kPi) / (2.0 * kPi / (double)nt));
+  t %= nt;
+  return t < 0 ? t + nt : t;
+}
+
+__global__ void vvote_kernel(AssocArgs A) {
+  const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
+  const int nm = A.cfg.n_rho, nt = A.cfg.n_theta;
+  const double rw = ((double)A.cfg.rho_hi - (double)A.cfg.rho_lo) / (double)nm;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntrk; t += gridDim.x * blockDim.x) {
+    const int p = A.trk_peak[t];
+    const double* g = A.cgeo + (size_t)p * 5;
+    const double cA = g[1], cB = g[2], cC = g[3], cD = g[4];
+    const double sn = sqrt(cB * cB + cC * cC);
+    const double pca = fabs(2.0 * cD / (1.0 + sn));
+    const double rf = (double)A.out.tracks[t].r_first;
+    for (int m = 0; m < nm; ++m) {
+      int start = 0, len = 0;
+      const double e0 = (double)A.cfg.rho_lo + (double)m * rw;
+      const double e1 = (double)A.cfg.rho_lo + (double)(m + 1) * rw;
+      const double ra = e0 > pca ? e0 : pca;
+      const double rb = e1 < rf ? e1 : rf;
+      if (ra < rb) {
+        const int ta = theta_bin(crossing_theta(cA, cB, cC, cD, sn, ra), nt);
+        const int tb = theta_bin(crossing_theta(cA, cB, cC, cD, sn, rb), nt);
+        int d = (tb - ta) % nt;
+        if (d < 0) d += nt;
+        if (d <= nt / 2) { start = ta; len = d + 1; }
+        else { start = tb; len = nt - d + 1; }
+        for (int q = 0; q < len; ++q) {
+          int c = start + q;
+          if (c >= nt) c -= nt;
+          atomicAdd(&A.vacc[m * nt + c], 1);
+        }
+      }
+      A.arc0[(size_t)t * nm + m] = start;
+      A.arcn[(size_t)t * nm + m] = len;
+    }
+  }
+}
+
+// vertex peaks in cell order, by one workgroup
+__global__ __launch_bounds__(1024) void vpeaks_kernel(AssocArgs A) {
+  __shared__ int32_t wc[16];
+  __shared__ int32_t run;
+  const int nm = A.cfg.n_rho, nt = A.cfg.n_theta;
+  const int ncell = nm * nt;
+  const int thr = A.cfg.vtx_min_votes;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double rw = ((double)A.cfg.rho_hi - (double)A.cfg.rho_lo) / (double)nm;
+  if (threadIdx.x == 0) run = 0;
+  __syncthreads();
+  for (int base = 0; base < ncell; base += 1024) {
+    const int c = base + threadIdx.x;
+    bool pk = false;
+    if (c < ncell) {
+      const int m = c / nt, ti = c - m * nt;
+      const int v = A.vacc[c];
+      pk = v >= thr;
+      for (int dm = -1; dm <= 1 && pk; ++dm) {
+        const int mm = m + dm;
+        if (mm < 0 || mm >= nm) continue;
+        for (int dt = -1; dt <= 1; ++dt) {
+          if (dm == 0 && dt == 0) continue;
+          int tt = ti + dt;
+          tt = tt < 0 ? tt + nt : (tt >= nt ? tt - nt : tt);
+          const int w = A.vacc[mm * nt + tt];
+          const bool neg = dm < 0 || (dm == 0 && dt < 0);
+          if (neg ? !(v > w) : !(v >= w)) { pk = false; break; }
+        }
+      }
+    }
+    const uint64_t msk = __ballot(pk);
+    if (lane == 0) wc[wave] = __popcll(msk);
+    __syncthreads();
+    int before = run;
+    for (int w = 0; w < wave; ++w) before += wc[w];
+    if (pk) {
+      const uint64_t lower = lane ? (msk & ((1ull << lane) - 1ull)) : 0ull;
+      const int o = before + __popcll(lower);
+      if (o < A.out.object_cap) {
+        const int m = c / nt, ti = c - m * nt;
+        ht_object ob;
+        ob.lin = c;
+        ob.votes = A.vacc[c];
+        ob.n_tracks = 0;
+        ob.kind = 0;
+        ob.rho = (float)((double)A.cfg.rho_lo + ((double)m + 0.5) * rw);
+        ob.theta = (float)(-kPi + ((double)ti + 0.5) * (2.0 * kPi / (double)nt));
+        ob.isotropy = 0.0f;
+        ob.member_begin = 0;
+        A.out.objects[o] = ob;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int s = 0;
+      for (int w = 0; w < 16; ++w) s += wc[w];
+      run += s;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) A.sc[S_NOBJ] = run;
+}
+
+__device__ __forceinline__ bool is_member(const AssocArgs& A, int t, int m, int ti) {
+  const int nm = A.cfg.n_rho, nt = A.cfg.n_theta;
+  for (int dm = -1; dm <= 1; ++dm) {
+    const int mm = m + dm;
+    if (mm < 0 || mm >= nm) continue;
+    const int len = A.arcn[(size_t)t * nm + mm];
+    if (len == 0) continue;
+    const int st = A.arc0[(size_t)t * nm + mm];
+    int off = (ti - st + 1) % nt;
+    if (off < 0) off += nt;
+    if (off < len + 2) return true;
+  }
+  return false;
+}
+
+// pass 1: member count per object (one wave per object)
+__global__ __launch_bounds__(256) void vcount_kernel(AssocArgs A) {
+  const int nobj = min(A.sc[S_NOBJ], A.out.object_cap);
+  const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int o = blockIdx.x * 4 + wave; o < nobj; o += gridDim.x * 4) {
+    const int c = A.out.objects[o].lin;
+    const int m = c / A.cfg.n_theta, ti = c % A.cfg.n_theta;
+    int cnt = 0;
+    for (int t0 = 0; t0 < ntrk; t0 += 64) {
+      const int t = t0 + lane;
+      cnt += __popcll(__ballot(t < ntrk && is_member(A, t, m, ti)));
+    }
+    if (lane == 0) A.obj_cnt[o] = cnt;
+  }
+}
+
+// pass 2: members in track order, isotropy summed sequentially in that order
+__global__ __launch_bounds__(256) void vmembers_kernel(AssocArgs A, const int32_t* obj_off) {
+  const int nobj = min(A.sc[S_NOBJ], A.out.object_cap);
+  const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int o = blockIdx.x * 4 + wave; o < nobj; o += gridDim.x * 4) {
+    ht_object& ob = A.out.objects[o];
+    const int c = ob.lin;
+    const int m = c / A.cfg.n_theta, ti = c % A.cfg.n_theta;
+    const int begin = obj_off[o];
+    int cnt = 0;
+    double sx = 0.0, sy = 0.0;
+    for (int t0 = 0; t0 < ntrk; t0 += 64) {
+      const int t = t0 + lane;
+      const bool mem = t < ntrk && is_member(A, t, m, ti);
+      const uint64_t msk = __ballot(mem);
+      if (mem) {
+        const uint64_t lower = lane ? (msk & ((1ull << lane) - 1ull)) : 0ull;
+        const int idx = begin + cnt + __popcll(lower);
+        if (idx < A.out.member_cap) A.out.members[idx] = t;
+      }
+      if (lane == 0) {
+        uint64_t b = msk;
+        while (b) {
+          const int l = __builtin_ctzll(b);
+          b &= b - 1;
+          const double* g = A.cgeo + (size_t)A.trk_peak[t0 + l] * 5;
+          const double sn = sqrt(g[2] * g[2] + g[3] * g[3]);
+          sx += -g[3] / sn;
+          sy += g[2] / sn;
+        }
+      }
+      cnt += __popcll(msk);
+    }
+    if (lane == 0) {
+      const double R = cnt > 0 ? sqrt(sx * sx + sy * sy) / (double)cnt : 0.0;
+      ob.n_tracks = cnt;
+      ob.member_begin = begin;
+      ob.isotropy = (float)R;
+      ob.kind = (cnt >= A.cfg.bh_min_tracks && R <= (double)A.cfg.bh_max_isotropy) ? 1 : 0;
+    }
+  }
+}
+
+__global__ void counts_kernel(AssocArgs A) {
+  int32_t* c = A.out.counts;
+  c[0] = A.sc[S_NCAND];
+  c[1] = A.sc[S_NTRK];
+  c[2] = A.sc[S_NOBJ];
+  c[3] = A.sc[S_NMEM];
+  c[4] = A.sc[S_NOVER];
+  c[5] = 0;
+  c[6] = 0;
+  c[7] = 0;
+}
+
+// zero the member-count prefix input when there are no objects
+__global__ void zero_i32_kernel(int32_t* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+int blocks_for(int64_t n, int per) {
+  int64_t b = (n + per - 1) / per;
+  if (b < 1) b = 1;
+  if (b > kGridCap) b = kGridCap;
+  return (int)b;
+}
+
+}  // namespace
+
+int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t* layer,
+                 int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks, int32_t peak_cap,
+                 const ht_cluster_cfg& cfg, const ht_cluster_out& out, hipStream_t s) {
+  const ht_grid& g = P.grid;
+  AssocArgs A;
+  A.n_phi = g.n_phi;
+  A.n_qpt = g.n_qpt;
+  A.n_d0 = g.n_d0;
+  A.n_cells = P.n_cells;
+  A.phi_lo = P.phi_lo;
+  A.invw = P.invw;
+  A.kap = P.d_kap;
+  A.qt = P.d_q;
+  A.tt = P.d_t;
+  A.origin_seed = (g.n_d0 == 1 && g.d0_lo == 0.0f && g.d0_hi == 0.0f);
+  const double cb = kCLight * (double)g.bfield;
+  A.kap_bin = cb * ((double)g.qpt_hi - (double)g.qpt_lo) / (double)g.n_qpt;
+  A.d0_bin = ((double)g.d0_hi - (double)g.d0_lo) / (double)g.n_d0;
+  A.hk = (float)(0.5 * A.kap_bin);
+  A.hd0 = (float)(0.5 * A.d0_bin);
+  A.d0_lo = (double)g.d0_lo;
+  A.d0_hi = (double)g.d0_hi;
+  A.qpt_lo = (double)g.qpt_lo;
+  A.qpt_hi = (double)g.qpt_hi;
+  A.bfield = (double)g.bfield;
+  A.r = r;
+  A.phi = phi;
+  A.layer = layer;
+  A.n_hits = n_hits;
+  A.hx = P.d_hx;
+  A.hy = P.d_hy;
+  A.hq = P.d_hq;
+  A.peaks = peaks;
+  A.n_peaks = n_peaks;
+  A.peak_cap = peak_cap;
+  A.cfg = cfg;
+  A.pbits = P.d_pbits;
+  A.col_first = P.d_col_first;
+  A.mcount = P.d_mcount;
+  A.mem = reinterpret_cast<uint16_t*>(P.d_mem);
+  A.cstat = P.d_cstat;
+  A.cnl = P.d_cnl;
+  A.cgeo = P.d_cgeo;
+  A.chit = P.d_chit;
+  A.owner_key = P.d_owner_key;
+  A.ctile_cnt = P.d_ctile_cnt;
+  A.ctile_off = P.d_ctile_off;
+  A.trk_peak = P.d_trk_peak;
+  A.arc0 = P.d_arc0;
+  A.arcn = P.d_arcn;
+  A.vacc = out.vacc ? out.vacc : P.d_vacc;
+  A.obj_cnt = P.d_obj_cnt;
+  A.sc = P.d_scalars;
+  A.out = out;
+  if (cfg.member_cap > kMaxMembers) return HT_EUNSUPPORTED;
+
+  const int words = P.n_tiles * 8 + 2;
+  const int64_t init_n = words > n_hits ? words : n_hits;
+  init_kernel<<<blocks_for(init_n, 256), 256, 0, s>>>(A, words);
+  HT_CHECK(hipGetLastError());
+  mark_kernel<<<blocks_for(peak_cap, 256), 256, 0, s>>>(A);
+  HT_CHECK(hipGetLastError());
+  dim3 sweep((g.n_qpt + kWave - 1) / kWave, g.n_d0);
+  member_kernel<<<sweep, kSweepThreads, 0, s>>>(A);
+  HT_CHECK(hipGetLastError());
+  refine_kernel<<<blocks_for(peak_cap, kRefineWaves), kRefineWaves * kWave, 0, s>>>(A);
+  HT_CHECK(hipGetLastError());
+  own_kernel<<<blocks_for(peak_cap, 256), 256, 0, s>>>(A);
+  HT_CHECK(hipGetLastError());
+  const int tiles = (peak_cap + 255) / 256 > 0 ? (peak_cap + 255) / 256 : 1;
+  surv_count_kernel<<<blocks_for(tiles, 1), 256, 0, s>>>(A, tiles);
+  HT_CHECK(hipGetLastError());
+  scan_kernel<<<1, 1024, 0, s>>>(P.d_ctile_cnt, P.d_ctile_off, tiles, P.d_scalars + S_NTRK);
+  HT_CHECK(hipGetLastError());
+  surv_emit_kernel<<<blocks_for(tiles, 1), 256, 0, s>>>(A, tiles);
+  HT_CHECK(hipGetLastError());
+  const int tcap = out.track_cap > 0 ? out.track_cap : 1;
+  if (out.track_cap > 0) {
+    fit_kernel<<<blocks_for(tcap, 64), 64, 0, s>>>(A);
+    HT_CHECK(hipGetLastError());
+    vvote_kernel<<<blocks_for(tcap, 64), 64, 0, s>>>(A);
+    HT_CHECK(hipGetLastError());
+  }
+  vpeaks_kernel<<<1, 1024, 0, s>>>(A);
+  HT_CHECK(hipGetLastError());
+  const int ocap = out.object_cap > 0 ? out.object_cap : 1;
+  const int ozero = ocap < P.lim.max_vertex_cells ? ocap : P.lim.max_vertex_cells;
+  zero_i32_kernel<<<blocks_for(ozero, 256), 256, 0, s>>>(P.d_obj_cnt, ozero);
+  HT_CHECK(hipGetLastError());
+  if (out.object_cap > 0) {
+    vcount_kernel<<<blocks_for(ocap, 4), 256, 0, s>>>(A);
+    HT_CHECK(hipGetLastError());
+  }
+  // object member offsets, then members and isotropy
+  const int oscan = ocap < P.lim.max_vertex_cells ? ocap : P.lim.max_vertex_cells;
+  scan_kernel<<<1, 1024, 0, s>>>(P.d_obj_cnt, P.d_obj_off, oscan > 0 ? oscan : 1,
+                                 P.d_scalars + S_NMEM);
+  HT_CHECK(hipGetLastError());
+  if (out.object_cap > 0) {
+    vmembers_kernel<<<blocks_for(ocap, 4), 256, 0, s>>>(A, P.d_obj_off);
+    HT_CHECK(hipGetLastError());
+  }
+  counts_kernel<<<1, 1, 0, s>>>(A);
+  HT_CHECK(hipGetLastError());
+  return HT_OK;
+}
+
+}  // namespace ht

@@ -1,0 +1,156 @@
+// First Hough transform: every valid hit votes once in every (q/pT, d0)
+// column, for the phi0 bin of the outgoing circle branch through it (paper,
+// section "Hough Transform Algorithm").
+//
+// gfx950 mapping.  One workgroup owns a tile of 64 consecutive q/pT columns
+// at one d0 (lane = column), so a tile's accumulator rows are one contiguous
+// block of the output.  The tile's counters live in LDS as packed 16-bit
+// pairs (a column holds at most n_hits <= 65535 votes per bin, so a
+// ds_add_u32 of 1 or 1 << 16 never carries across the pair); the row stride
+// is odd in dwords so neighbouring columns fall in different banks.  Waves of
+// the workgroup split the hits: each wave loads 64 hits with one coalesced
+// load, keeps them in VGPRs and broadcasts them one at a time through SGPRs
+// (v_readlane), so the per-evaluation work is pure VALU with scalar hit
+// operands plus one LDS atomic.  The tile is written to HBM once, by
+// contiguous stores, so no clearing pass is needed.  No MFMA: the vote is a
+// scatter, not a contraction.
+#include "ht_internal.h"
+
+namespace ht {
+namespace {
+
+constexpr int kVoteWaves = 16;
+constexpr int kVoteThreads = kVoteWaves * kWave;
+
+__device__ __forceinline__ float bcast(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+__global__ __launch_bounds__(kVoteThreads) void vote_kernel(
+    const float* __restrict__ r, const float* __restrict__ phi, int n_hits,
+    const float* __restrict__ kap, const float* __restrict__ qt, const float* __restrict__ tt,
+    int n_phi, int n_qpt, float phi_lo, float invw, int stride, int32_t* __restrict__ acc,
+    unsigned long long* __restrict__ n_votes) {
+  extern __shared__ uint32_t lds[];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x >> 6;
+  const int j0 = blockIdx.x * kWave;
+  const int k = blockIdx.y;
+  const int j = j0 + lane;
+  const bool col_ok = j < n_qpt;
+
+  for (int w = threadIdx.x; w < kWave * stride; w += kVoteThreads) lds[w] = 0u;
+  float ck = 0.0f, cq = 0.0f, ct = 0.0f;
+  if (col_ok) {
+    ck = kap[j];
+    cq = qt[(size_t)k * n_qpt + j];
+    ct = tt[(size_t)k * n_qpt + j];
+  }
+  __syncthreads();
+
+  uint32_t* col = lds + lane * stride;
+  uint32_t votes = 0;
+  for (int base = wave * kWave; base < n_hits; base += kVoteThreads) {
+    const int h = base + lane;
+    float hr = 1.0f, hp = 0.0f;
+    bool hv = false;
+    if (h < n_hits) {
+      hr = r[h];
+      hp = phi[h];
+      hv = hit_ok(hr, hp);
+    }
+    const float hr2 = hr * hr;
+    const float hir = 1.0f / hr;
+    uint64_t todo = __ballot(hv);
+    while (todo) {
+      const int src = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const float r2 = bcast(hr2, src);
+      const float ir = bcast(hir, src);
+      const float ph = bcast(hp, src);
+      const float a = ck * r2;
+      const float b = a + cq;
+      const float c = b * ir;
+      const float u = c * ct;
+      const bool ok = col_ok && (fabsf(u) <= 1.0f);
+      const float s = asin_f(u);
+      const float phi0 = ph - s;
+      const float d = phi0 - phi_lo;
+      const float x = d * invw;
+      int i = (int)floorf(x);
+      i = i < 0 ? i + n_phi : i;
+      i = i >= n_phi ? i - n_phi : i;
+      if (ok) {
+        atomicAdd(&col[i >> 1], (i & 1) ? 65536u : 1u);
+        ++votes;
+      }
+    }
+  }
+  __syncthreads();
+
+  // write the tile: rows j0 .. j0+ncol-1 of plane k are contiguous
+  const int ncol = min(kWave, n_qpt - j0);
+  int32_t* out = acc + ((size_t)k * n_qpt + j0) * n_phi;
+  const int total = ncol * n_phi;
+  for (int e = threadIdx.x; e < total; e += kVoteThreads) {
+    const int cj = e / n_phi;
+    const int i = e - cj * n_phi;
+    const uint32_t w = lds[cj * stride + (i >> 1)];
+    out[e] = (int32_t)((i & 1) ? (w >> 16) : (w & 0xFFFFu));
+  }
+
+  if (n_votes) {
+    unsigned long long v = votes;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0 && v) atomicAdd(n_votes, v);
+  }
+}
+
+__global__ void asin_kernel(const float* __restrict__ u, float* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = asin_f(u[i]);
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
+
+int vote_stride(int n_phi) {
+  int words = (n_phi + 1) / 2;
+  return words | 1;  // odd dword stride
+}
+
+}  // namespace
+
+int vote_init(int n_phi) {
+  const int bytes = kWave * vote_stride(n_phi) * 4;
+  HT_CHECK(hipFuncSetAttribute((const void*)vote_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  return HT_OK;
+}
+
+int launch_vote(const Plan& p, const float* r, const float* phi, int32_t n_hits, int32_t* acc,
+                unsigned long long* n_votes, hipStream_t s) {
+  const ht_grid& g = p.grid;
+  const int stride = vote_stride(g.n_phi);
+  const size_t lds_bytes = (size_t)kWave * stride * 4;
+  if (n_votes) {
+    zero_u64_kernel<<<1, 1, 0, s>>>(n_votes);
+    HT_CHECK(hipGetLastError());
+  }
+  dim3 grid((g.n_qpt + kWave - 1) / kWave, g.n_d0);
+  vote_kernel<<<grid, kVoteThreads, lds_bytes, s>>>(r, phi, n_hits, p.d_kap, p.d_q, p.d_t,
+                                                      g.n_phi, g.n_qpt, p.phi_lo, p.invw, stride,
+                                                      acc, n_votes);
+  HT_CHECK(hipGetLastError());
+  return HT_OK;
+}
+
+int launch_asin(const float* u, float* out, int64_t n, hipStream_t s) {
+  if (n == 0) return HT_OK;
+  const int threads = 256;
+  const int64_t blocks = (n + threads - 1) / threads;
+  asin_kernel<<<(unsigned)blocks, threads, 0, s>>>(u, out, n);
+  HT_CHECK(hipGetLastError());
+  return HT_OK;
+}
+
+}  // namespace ht

@@ -1,0 +1,268 @@
+"""Thin ctypes binding of libhoughtrig.so (the gfx950 Hough trigger library).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Tensors must be contiguous device tensors of the stated dtype; the
+calls are asynchronous on the current torch stream.  There is no fallback:
+if the library is missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhoughtrig.so")
+MAX_LAYERS = 16
+
+HT_OK, HT_EINVAL, HT_ENOMEM, HT_EDEVICE, HT_EUNSUPPORTED = 0, -1, -2, -3, -4
+
+PEAK_DTYPE = np.dtype([("lin", "<i4"), ("votes", "<i4")])
+TRACK_DTYPE = np.dtype([
+    ("peak", "<i4"), ("lin", "<i4"), ("votes", "<i4"), ("n_layers", "<i4"),
+    ("n_inliers", "<i4"), ("n_owned", "<i4"), ("status", "<i4"), ("seed_ss", "<f4"),
+    ("phi0", "<f4"), ("qpt", "<f4"), ("d0", "<f4"), ("chi2", "<f4"), ("r_first", "<f4"),
+    ("hits", "<i4", (MAX_LAYERS,)),
+])
+OBJECT_DTYPE = np.dtype([
+    ("lin", "<i4"), ("votes", "<i4"), ("n_tracks", "<i4"), ("kind", "<i4"),
+    ("rho", "<f4"), ("theta", "<f4"), ("isotropy", "<f4"), ("member_begin", "<i4"),
+])
+
+
+class HoughError(RuntimeError):
+    def __init__(self, what, code):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("n_phi", C.c_int32), ("n_qpt", C.c_int32), ("n_d0", C.c_int32),
+                ("qpt_lo", C.c_float), ("qpt_hi", C.c_float),
+                ("d0_lo", C.c_float), ("d0_hi", C.c_float), ("bfield", C.c_float)]
+
+
+class Limits(C.Structure):
+    _fields_ = [("max_hits", C.c_int32), ("max_peaks", C.c_int32),
+                ("max_member_cap", C.c_int32), ("max_tracks", C.c_int32),
+                ("max_vertex_cells", C.c_int32), ("max_n_rho", C.c_int32)]
+
+
+class ClusterCfg(C.Structure):
+    _fields_ = [("win_bins", C.c_int32), ("min_layers", C.c_int32), ("seed_k", C.c_int32),
+                ("member_cap", C.c_int32), ("road_sigmas", C.c_float),
+                ("box_margin", C.c_float), ("sigma_rphi", C.c_float),
+                ("fit_iters", C.c_int32), ("n_rho", C.c_int32), ("n_theta", C.c_int32),
+                ("rho_lo", C.c_float), ("rho_hi", C.c_float),
+                ("vtx_min_votes", C.c_int32), ("bh_min_tracks", C.c_int32),
+                ("bh_max_isotropy", C.c_float)]
+
+
+class ClusterOut(C.Structure):
+    _fields_ = [("hit_owner", C.c_void_p), ("tracks", C.c_void_p), ("track_cap", C.c_int32),
+                ("objects", C.c_void_p), ("object_cap", C.c_int32),
+                ("members", C.c_void_p), ("member_cap", C.c_int32),
+                ("vacc", C.c_void_p), ("counts", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhoughtrig.so (built by ``paper_1309_6275_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_1309_6275_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.ht_strerror.argtypes = [C.c_int]
+        L.ht_strerror.restype = C.c_char_p
+        L.ht_plan_create.argtypes = [vp, vp, vp]
+        L.ht_plan_destroy.argtypes = [vp]
+        L.ht_plan_destroy.restype = None
+        L.hough_vote.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+        L.hough_peaks.argtypes = [vp, vp, i32, vp, i32, vp, vp]
+        L.assoc_cluster.argtypes = [vp, vp, vp, vp, i32, vp, vp, i32, vp, vp, vp]
+        L.ht_asin_f32.argtypes = [vp, vp, i64, vp]
+        for f in ("ht_plan_create", "hough_vote", "hough_peaks", "assoc_cluster", "ht_asin_f32"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().ht_strerror(int(code)).decode()
+    except Exception:  # library not loadable: still report the code
+        return "error"
+
+
+def _check(rc, what):
+    if rc != HT_OK:
+        raise HoughError(what, rc)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("houghtrig needs a ROCm GPU; none is available")
+    return torch
+
+
+def _ptr(t, dtype, what):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{what} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous {dtype} tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def grid_struct(g: dict) -> Grid:
+    return Grid(int(g["n_phi"]), int(g["n_qpt"]), int(g["n_d0"]), float(g["qpt_lo"]),
+                float(g["qpt_hi"]), float(g["d0_lo"]), float(g["d0_hi"]), float(g["bfield"]))
+
+
+def cluster_struct(c: dict) -> ClusterCfg:
+    return ClusterCfg(int(c["win_bins"]), int(c["min_layers"]), int(c["seed_k"]),
+                      int(c["member_cap"]), float(c["road_sigmas"]), float(c["box_margin"]),
+                      float(c["sigma_rphi"]), int(c["fit_iters"]), int(c["n_rho"]),
+                      int(c["n_theta"]), float(c["rho_lo"]), float(c["rho_hi"]),
+                      int(c["vtx_min_votes"]), int(c["bh_min_tracks"]),
+                      float(c["bh_max_isotropy"]))
+
+
+class Plan:
+    """Owns an ht_plan (constant tables + scratch) for one grid on the
+    current device."""
+
+    def __init__(self, grid: dict, max_hits=65535, max_peaks=1 << 20, max_member_cap=256,
+                 max_tracks=1 << 16, max_vertex_cells=64 * 256, max_n_rho=64):
+        _torch()
+        self.grid = dict(grid)
+        self._g = grid_struct(grid)
+        self._lim = Limits(int(max_hits), int(max_peaks), int(max_member_cap), int(max_tracks),
+                           int(max_vertex_cells), int(max_n_rho))
+        h = C.c_void_p()
+        _check(lib().ht_plan_create(C.byref(self._g), C.byref(self._lim), C.byref(h)),
+               "ht_plan_create")
+        self._h = h
+        self.limits = dict(max_hits=max_hits, max_peaks=max_peaks, max_member_cap=max_member_cap,
+                           max_tracks=max_tracks, max_vertex_cells=max_vertex_cells,
+                           max_n_rho=max_n_rho)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def acc_shape(self):
+        return (self.grid["n_d0"], self.grid["n_qpt"], self.grid["n_phi"])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ht_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hough_vote(plan: Plan, r, phi, acc, n_votes=None, stream=None):
+    """acc[n_d0, n_qpt, n_phi] int32 <- votes of hits (r, phi) (float32)."""
+    torch = _torch()
+    n = int(r.numel())
+    if phi.numel() != n or tuple(acc.shape) != plan.acc_shape:
+        raise ValueError("shape mismatch")
+    _check(lib().hough_vote(plan.handle, _ptr(r, torch.float32, "r"),
+                            _ptr(phi, torch.float32, "phi"), n,
+                            _ptr(acc, torch.int32, "acc"),
+                            _ptr(n_votes, torch.int64, "n_votes"), _stream(stream)),
+           "hough_vote")
+
+
+def hough_peaks(plan: Plan, acc, min_votes: int, out, n_found, stream=None):
+    """out: int32 [capacity, 2] (lin, votes) rows; n_found: int32 [1]."""
+    torch = _torch()
+    if tuple(acc.shape) != plan.acc_shape or out.dim() != 2 or out.shape[1] != 2:
+        raise ValueError("shape mismatch")
+    _check(lib().hough_peaks(plan.handle, _ptr(acc, torch.int32, "acc"), int(min_votes),
+                             _ptr(out, torch.int32, "out"), int(out.shape[0]),
+                             _ptr(n_found, torch.int32, "n_found"), _stream(stream)),
+           "hough_peaks")
+
+
+class ClusterBuffers:
+    """Device outputs of assoc_cluster."""
+
+    def __init__(self, n_hits_max, track_cap, object_cap, member_cap, n_rho, n_theta,
+                 device="cuda"):
+        torch = _torch()
+        self.hit_owner = torch.empty(max(n_hits_max, 1), dtype=torch.int32, device=device)
+        self.tracks = torch.zeros((max(track_cap, 1), TRACK_DTYPE.itemsize // 4),
+                                  dtype=torch.int32, device=device)
+        self.objects = torch.zeros((max(object_cap, 1), OBJECT_DTYPE.itemsize // 4),
+                                   dtype=torch.int32, device=device)
+        self.members = torch.zeros(max(member_cap, 1), dtype=torch.int32, device=device)
+        self.vacc = torch.zeros((n_rho, n_theta), dtype=torch.int32, device=device)
+        self.counts = torch.zeros(8, dtype=torch.int32, device=device)
+        self.track_cap, self.object_cap, self.member_cap = track_cap, object_cap, member_cap
+
+    def struct(self, with_vacc=True) -> ClusterOut:
+        return ClusterOut(self.hit_owner.data_ptr(), self.tracks.data_ptr(), self.track_cap,
+                          self.objects.data_ptr(), self.object_cap, self.members.data_ptr(),
+                          self.member_cap, self.vacc.data_ptr() if with_vacc else None,
+                          self.counts.data_ptr())
+
+    def to_host(self, n_hits):
+        """Copy back as numpy (structured track/object arrays), trimmed."""
+        counts = self.counts.cpu().numpy()
+        nt = min(int(counts[1]), self.track_cap)
+        no = min(int(counts[2]), self.object_cap)
+        nm = min(int(counts[3]), self.member_cap)
+        tr = self.tracks.cpu().numpy().view(TRACK_DTYPE).reshape(-1)[:nt].copy()
+        ob = self.objects.cpu().numpy().view(OBJECT_DTYPE).reshape(-1)[:no].copy()
+        return dict(hit_owner=self.hit_owner[:n_hits].cpu().numpy(), tracks=tr, objects=ob,
+                    members=self.members[:nm].cpu().numpy(), vacc=self.vacc.cpu().numpy(),
+                    counts=counts)
+
+
+def assoc_cluster(plan: Plan, r, phi, layer, peaks, n_peaks, cfg: dict, bufs: ClusterBuffers,
+                  with_vacc=True, stream=None):
+    """peaks: int32 [cap, 2] from hough_peaks; n_peaks: int32 [1] device."""
+    torch = _torch()
+    n = int(r.numel())
+    if phi.numel() != n or layer.numel() != n:
+        raise ValueError("shape mismatch")
+    c = cluster_struct(cfg)
+    o = bufs.struct(with_vacc)
+    _check(lib().assoc_cluster(plan.handle, _ptr(r, torch.float32, "r"),
+                               _ptr(phi, torch.float32, "phi"),
+                               _ptr(layer, torch.uint8, "layer"), n,
+                               _ptr(peaks, torch.int32, "peaks"),
+                               _ptr(n_peaks, torch.int32, "n_peaks"), int(peaks.shape[0]),
+                               C.byref(c), C.byref(o), _stream(stream)),
+           "assoc_cluster")
+
+
+def asin_f32(u, out, stream=None):
+    torch = _torch()
+    _check(lib().ht_asin_f32(_ptr(u, torch.float32, "u"), _ptr(out, torch.float32, "out"),
+                             int(u.numel()), _stream(stream)), "ht_asin_f32")
+
+
+EXPORTS = ("ht_plan_create", "ht_plan_destroy", "ht_strerror", "hough_vote", "hough_peaks",
+           "assoc_cluster", "ht_asin_f32")

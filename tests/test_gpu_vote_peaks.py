@@ -1,0 +1,186 @@
+"""GPU parity of hough_vote, hough_peaks and the canonical arcsine against the
+CPU oracle, through the C-ABI library.  Integer outputs must be bit-exact."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1309_6275_amd import configs as CF
+from paper_1309_6275_amd import eventgen as G
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+@pytest.fixture(scope="module")
+def ht(torch):
+    from paper_1309_6275_amd import houghtrig
+    houghtrig.lib()
+    return houghtrig
+
+
+_plans = {}
+
+
+def plan_for(ht, grid):
+    key = tuple(sorted(grid.items()))
+    if key not in _plans:
+        _plans[key] = ht.Plan(grid, max_peaks=1 << 21)
+    return _plans[key]
+
+
+def gpu_vote(torch, ht, grid, r, phi):
+    plan = plan_for(ht, grid)
+    rd = torch.from_numpy(np.ascontiguousarray(r, np.float32)).cuda()
+    pd = torch.from_numpy(np.ascontiguousarray(phi, np.float32)).cuda()
+    acc = torch.full(plan.acc_shape, -7, dtype=torch.int32, device="cuda")
+    nv = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ht.hough_vote(plan, rd, pd, acc, nv)
+    torch.cuda.synchronize()
+    return acc, int(nv.item())
+
+
+def gpu_peaks(torch, ht, grid, acc_d, thr, capacity):
+    plan = plan_for(ht, grid)
+    out = torch.full((max(capacity, 1), 2), -1, dtype=torch.int32, device="cuda")
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ht.hough_peaks(plan, acc_d, thr, out[:capacity] if capacity else out[:0], nf)
+    torch.cuda.synchronize()
+    n = int(nf.item())
+    return out[:min(n, capacity)].cpu().numpy(), n
+
+
+def test_asin_exhaustive_bitwise(torch, ht, oracle):
+    """Every float32 in [-1, 1]: the device arcsine equals the oracle's bit for
+    bit (this covers the correctly rounded square root as well)."""
+    top = 0x3F800000
+    step = 1 << 26
+    for lo in range(0, top + 1, step):
+        hi = min(lo + step, top + 1)
+        bits = np.arange(lo, hi, dtype=np.uint32)
+        for sign in (0, 0x80000000):
+            u = (bits | np.uint32(sign)).view(np.float32)
+            ud = torch.from_numpy(u).cuda()
+            od = torch.empty_like(ud)
+            ht.asin_f32(ud, od)
+            got = od.cpu().numpy().view(np.uint32)
+            want = oracle.asin_f(u).view(np.uint32)
+            bad = np.flatnonzero(got != want)
+            assert bad.size == 0, (u[bad[:5]], got[bad[:5]], want[bad[:5]])
+
+
+@pytest.mark.parametrize("cfg,seeds", [(1, range(6)), (2, range(3)), (3, range(1))])
+def test_vote_parity_workloads(torch, ht, oracle, cfg, seeds):
+    W = CF.WORKLOADS[cfg]
+    g = W["grid"]
+    for s in seeds:
+        ev = G.make_event(cfg, W["seed0"] + s)
+        print(f"cfg{cfg} seed {W['seed0'] + s} hits {ev.n_hits}", flush=True)
+        acc_d, nv = gpu_vote(torch, ht, g, ev.r, ev.phi)
+        want, nv_w = oracle.hough_vote(g, ev.r, ev.phi)
+        got = acc_d.cpu().numpy()
+        assert nv == nv_w
+        if not np.array_equal(got, want):
+            bad = np.argwhere(got != want)
+            raise AssertionError(f"{bad.shape[0]} cells differ, first {bad[:5].tolist()}")
+        pk_w, n_w = oracle.hough_peaks(g, want, W["min_votes"])
+        cap = n_w + 16
+        pk, n = gpu_peaks(torch, ht, g, acc_d, W["min_votes"], cap)
+        assert n == n_w
+        assert np.array_equal(pk[:, 0], pk_w["lin"]) and np.array_equal(pk[:, 1], pk_w["votes"])
+
+
+ODD_GRIDS = [
+    dict(n_phi=37, n_qpt=100, n_d0=3, qpt_lo=-1.0, qpt_hi=1.0, d0_lo=-5.0, d0_hi=5.0,
+         bfield=3.8),
+    dict(n_phi=1024, n_qpt=65, n_d0=2, qpt_lo=-0.5, qpt_hi=1.0, d0_lo=-20.0, d0_hi=20.0,
+         bfield=2.0),
+    dict(n_phi=512, n_qpt=1, n_d0=64, qpt_lo=0.0, qpt_hi=0.0, d0_lo=-20.0, d0_hi=20.0,
+         bfield=3.8),
+    dict(n_phi=4, n_qpt=7, n_d0=1, qpt_lo=-1.0, qpt_hi=1.0, d0_lo=0.0, d0_hi=0.0, bfield=3.8),
+]
+
+
+@pytest.mark.parametrize("gi", range(len(ODD_GRIDS)))
+@pytest.mark.parametrize("n_hits", [0, 1, 63, 65, 1000])
+def test_vote_parity_odd_grids(torch, ht, oracle, gi, n_hits):
+    g = ODD_GRIDS[gi]
+    r, phi, _ = G.random_hits(n_hits, seed=100 + gi * 7 + n_hits, r_lo=0.5, r_hi=120.0,
+                              bad_fraction=0.05)
+    acc_d, nv = gpu_vote(torch, ht, g, r, phi)
+    want, nv_w = oracle.hough_vote(g, r, phi)
+    assert nv == nv_w
+    assert np.array_equal(acc_d.cpu().numpy(), want)
+    pk_w, n_w = oracle.hough_peaks(g, want, 2)
+    pk, n = gpu_peaks(torch, ht, g, acc_d, 2, n_w + 3)
+    assert n == n_w and np.array_equal(pk[:, 0], pk_w["lin"])
+
+
+def test_vote_max_hits(torch, ht, oracle):
+    """The largest supported event: 65535 hits (16-bit LDS counters are
+    exact up to there)."""
+    g = dict(n_phi=256, n_qpt=64, n_d0=4, qpt_lo=-1.0, qpt_hi=1.0, d0_lo=-2.0, d0_hi=2.0,
+             bfield=3.8)
+    r = np.full(65535, 50.0, np.float32)
+    phi = np.full(65535, 0.25, np.float32)  # every hit in the same bins
+    acc_d, nv = gpu_vote(torch, ht, g, r, phi)
+    want, nv_w = oracle.hough_vote(g, r, phi)
+    assert nv == nv_w and np.array_equal(acc_d.cpu().numpy(), want)
+    assert want.max() == 65535
+
+
+def test_vote_rejects_too_many_hits(torch, ht):
+    g = CF.GRID_2D
+    plan = plan_for(ht, g)
+    r = torch.ones(65536, dtype=torch.float32, device="cuda")
+    acc = torch.empty(plan.acc_shape, dtype=torch.int32, device="cuda")
+    with pytest.raises(ht.HoughError) as e:
+        ht.hough_vote(plan, r, r, acc)
+    assert e.value.code == ht.HT_EUNSUPPORTED
+
+
+def test_peaks_golden_on_device(torch, ht):
+    with open(os.path.join(HERE, "golden", "peaks_cases.json")) as f:
+        cases = json.load(f)["cases"]
+    for case in cases:
+        nd, nq, np_ = case["dims"]
+        acc = np.zeros((nd, nq, np_), np.int32)
+        for k, j, i, v in case["cells"]:
+            acc[k, j, i] = v
+        g = dict(n_phi=np_, n_qpt=nq, n_d0=nd, qpt_lo=-1.0, qpt_hi=1.0,
+                 d0_lo=-20.0 if nd > 1 else 0.0, d0_hi=20.0 if nd > 1 else 0.0, bfield=3.8)
+        acc_d = torch.from_numpy(acc).cuda()
+        pk, n = gpu_peaks(torch, ht, g, acc_d, case["threshold"], 16)
+        assert pk.tolist() == case["expected"], case["name"]
+        assert n == len(case["expected"])
+
+
+def test_peaks_capacity_and_random_ties(torch, ht, oracle):
+    rng = np.random.default_rng(21)
+    g = dict(n_phi=512, n_qpt=256, n_d0=8, qpt_lo=-1.0, qpt_hi=1.0, d0_lo=-20.0, d0_hi=20.0,
+             bfield=3.8)
+    acc = rng.poisson(5.5, size=(8, 256, 512)).astype(np.int32)
+    acc_d = torch.from_numpy(acc).cuda()
+    want, n_w = oracle.hough_peaks(g, acc, 7)
+    for cap in (0, 1, 1000, n_w, n_w + 5):
+        pk, n = gpu_peaks(torch, ht, g, acc_d, 7, cap)
+        assert n == n_w
+        k = min(cap, n_w)
+        assert np.array_equal(pk[:k, 0], want["lin"][:k])
+        assert np.array_equal(pk[:k, 1], want["votes"][:k])
+
+
+def test_vote_deterministic(torch, ht):
+    ev = G.make_event(2, 2_000_011)
+    a1, n1 = gpu_vote(torch, ht, CF.GRID_3D, ev.r, ev.phi)
+    a2, n2 = gpu_vote(torch, ht, CF.GRID_3D, ev.r, ev.phi)
+    assert n1 == n2 and torch.equal(a1, a2)
