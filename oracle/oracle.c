@@ -504,6 +504,13 @@ static void refine(const or_grid* g, const tables* tb, const window_t* wd, const
                    const float* r, const float* phi, const uint8_t* layer, int32_t n_hits,
                    int32_t lin, const or_cluster_cfg* cfg, member_t* mem, cand_t* out) {
   const int np = g->n_phi, nq = g->n_qpt;
+  out->status = 1;
+  out->n_layers = 0;
+  out->n_inliers = 0;
+  out->ss = 0.0;
+  for (int L = 0; L < OR_MAX_LAYERS; ++L) out->hit[L] = -1;
+  /* a cell index outside the grid is not a candidate */
+  if (lin < 0 || (int64_t)lin >= (int64_t)np * nq * g->n_d0) return;
   int i = lin % np, col = lin / np, j = col % nq, k = col / nq;
   float xi = (float)i + 0.5f;
   float half_n = 0.5f * (float)np;
@@ -812,10 +819,6 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
     return -1;
   tables tb;
   if (make_tables(g, &tb)) { free_tables(&tb); return -2; }
-  const int np = g->n_phi, nq = g->n_qpt;
-  int64_t ncells = (int64_t)np * nq * g->n_d0;
-  for (int32_t p = 0; p < n_peaks; ++p)
-    if (peaks[p].lin < 0 || peaks[p].lin >= ncells) { free_tables(&tb); return -1; }
 
   /* 0. hit Cartesian coordinates (canonical sincos, float64) */
   hitxy_t hx;

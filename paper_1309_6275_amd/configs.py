@@ -33,6 +33,8 @@ CLUSTER_2D = dict(win_bins=1, min_layers=8, seed_k=4, member_cap=256, road_sigma
                   rho_lo=4.0, rho_hi=68.0, vtx_min_votes=5, bh_min_tracks=20,
                   bh_max_isotropy=0.75)
 CLUSTER_3D = dict(CLUSTER_2D, min_layers=7)
+# ~55k hits: about 700 hits fall in a cell's member window
+CLUSTER_3D_DENSE = dict(CLUSTER_3D, member_cap=1024)
 
 WORKLOADS = {
     1: dict(name="2D Hough, 20 prompt tracks + 50 noise hits, 256x256", grid=GRID_2D,
@@ -40,5 +42,5 @@ WORKLOADS = {
     2: dict(name="displaced-jet event, 3D Hough 512x256x64, ~3.6k hits", grid=GRID_3D,
             min_votes=7, cluster=CLUSTER_3D, seed0=2_000_000),
     3: dict(name="high-pileup event, 3D Hough 512x256x64, ~55k hits", grid=GRID_3D,
-            min_votes=7, cluster=CLUSTER_3D, seed0=3_000_000),
+            min_votes=7, cluster=CLUSTER_3D_DENSE, seed0=3_000_000),
 }

@@ -38,7 +38,7 @@ namespace {
 constexpr int kSweepWaves = 16;
 constexpr int kSweepThreads = kSweepWaves * kWave;
 constexpr int kRefineWaves = 1;  // one wave per workgroup: barriers are wave-local
-constexpr int kMaxMembers = 256;  // LDS member slots per wave in refine
+constexpr int kMaxMembers = 1024; // largest member_cap (LDS slots per wave in refine)
 constexpr int kGridCap = 8192;    // grid-stride launches use at most this many blocks
 
 enum { S_NP = 0, S_NCAND = 1, S_NOVER = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5 };
@@ -419,14 +419,15 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
 }
 
 // ---- refine: one wave per candidate ------------------------------------------
+template <int CAP>
 struct WaveMem {
-  int32_t h[kMaxMembers];
-  int8_t L[kMaxMembers];
-  float adx[kMaxMembers];
-  double x[kMaxMembers];
-  double y[kMaxMembers];
-  double q[kMaxMembers];
-  int32_t order[kMaxMembers];   // members grouped by layer
+  double x[CAP];
+  double y[CAP];
+  double q[CAP];
+  int32_t h[CAP];
+  float adx[CAP];
+  int16_t order[CAP];  // members grouped by layer
+  int8_t L[CAP];
   int32_t lstart[HT_MAX_LAYERS + 1];
 };
 
@@ -457,11 +458,12 @@ __device__ __forceinline__ int nth_set_bit(unsigned mask, int n) {
   return HT_MAX_LAYERS - 1;
 }
 
+template <int CAP>
 __global__ __launch_bounds__(kRefineWaves* kWave) void refine_kernel(AssocArgs A) {
-  __shared__ WaveMem wm_all[kRefineWaves];
+  __shared__ WaveMem<CAP> wm_all[kRefineWaves];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x >> 6;
-  WaveMem& M = wm_all[wave];
+  WaveMem<CAP>& M = wm_all[wave];
   const int np = n_cands(A);
   const ht_cluster_cfg& cfg = A.cfg;
   const int cap = cfg.member_cap;
@@ -509,7 +511,7 @@ __global__ __launch_bounds__(kRefineWaves* kWave) void refine_kernel(AssocArgs A
       for (int L = 0; L < HT_MAX_LAYERS; ++L) {
         M.lstart[L] = s;
         for (int m = 0; m < n; ++m)
-          if (M.L[m] == L) M.order[s++] = m;
+          if (M.L[m] == L) M.order[s++] = (int16_t)m;
       }
       M.lstart[HT_MAX_LAYERS] = s;
     }
@@ -1147,7 +1149,11 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   dim3 sweep((g.n_qpt + kWave - 1) / kWave, g.n_d0);
   member_kernel<<<sweep, kSweepThreads, 0, s>>>(A);
   HT_CHECK(hipGetLastError());
-  refine_kernel<<<blocks_for(peak_cap, kRefineWaves), kRefineWaves * kWave, 0, s>>>(A);
+  if (cfg.member_cap <= 256)
+    refine_kernel<256><<<blocks_for(peak_cap, kRefineWaves), kRefineWaves * kWave, 0, s>>>(A);
+  else
+    refine_kernel<kMaxMembers>
+        <<<blocks_for(peak_cap, kRefineWaves), kRefineWaves * kWave, 0, s>>>(A);
   HT_CHECK(hipGetLastError());
   own_kernel<<<blocks_for(peak_cap, 256), 256, 0, s>>>(A);
   HT_CHECK(hipGetLastError());
