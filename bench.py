@@ -1,0 +1,255 @@
+"""Throughput of the Hough trigger path on one MI355X.
+
+A step is one pass of the whole path -- hough_vote, hough_peaks and
+assoc_cluster (refinement, ownership, refit, vertex transform) -- over a batch
+of synthetic displaced-jet events (512 phi0 x 256 q/pT x 64 d0 accumulator,
+~3.6k hits each), inputs resident in HBM before the timed region.  Prints
+one JSON line: whole-job Hough votes/s (value), events/s, p50/p99 event
+latency, track efficiency and fake rate of the outputs, the roofline of the
+vote kernel measured live with HIP events, and the CPU oracle timed on a
+bounded sample on the host cores.
+
+    python bench.py [--steps K] [--warmup W] [--batch B] [--workload 1|2|3]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Hough votes/s + events/s at >=95% track eff; p50/p99 event latency (ms)"
+# fp32 operations of the canonical vote formula per (hit, column) evaluation:
+# u = ((KAP*r2 + Q)*ir)*T (4), |u| <= 1 (1); then for a vote: 1 - |u|, sqrt,
+# 7 multiplies + 7 adds of the polynomial, s*p, pi/2 - sp (18), phi - asin,
+# - PHI_LO, * INVW, floor (4)
+OPS_PER_EVAL = 5
+OPS_PER_VOTE = 22
+# single-issue fp32 VALU rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--cpu-sample", type=int, default=2,
+                    help="events of the CPU oracle baseline (0 skips it)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (read + write) 5 times, the "
+                         "reference for scaling HBM byte counters")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 64 << 20  # 64 Mi float32 = 256 MiB
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("vote.hip", "ht_internal.h"):
+        with open(os.path.join(ROOT, "paper_1309_6275_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload):
+    """HBM bytes per vote launch from the committed rocprofv3 counter summary,
+    if it was taken on the current vote kernel source."""
+    path = os.path.join(ROOT, "profiles", f"vote_cfg{workload}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"```json\n(.*?)\n```", txt, re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return float(d["hbm_bytes_per_launch"])
+
+
+def cpu_baseline(W, events, votes_per_event):
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    total_votes = 0
+    for ev in events:
+        acc, nv = O.hough_vote(W["grid"], ev.r, ev.phi)
+        pk, n = O.hough_peaks(W["grid"], acc, W["min_votes"])
+        O.assoc_cluster(W["grid"], ev.r, ev.phi, ev.layer, pk, W["cluster"])
+        total_votes += nv
+    dt = time.perf_counter() - t0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    return {"value": total_votes / dt, "unit": "votes/s", "cores": min(cores, threads),
+            "kind": "oracle",
+            "sample": f"{len(events)} events of the same workload, full path (vote, peaks, "
+                      f"refinement, vertex transform), {dt:.1f} s, "
+                      f"{len(events) / dt:.3f} events/s"}
+
+
+def main():
+    args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+              "(events are independent: scale by running one process per GPU)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_1309_6275_amd import build as hip_build
+    if not os.path.exists(hip_build.LIB):
+        hip_build.build()
+    from paper_1309_6275_amd import configs as CF
+    from paper_1309_6275_amd import eventgen as G
+    from paper_1309_6275_amd import houghtrig as H
+    from paper_1309_6275_amd import metrics as M
+
+    W = CF.WORKLOADS[args.workload]
+    g, cl = W["grid"], W["cluster"]
+    torch.cuda.set_device(0)
+    B = args.batch
+    events = [G.make_event(args.workload, W["seed0"] + 100 + e) for e in range(B)]
+    peak_cap = 1 << 19 if args.workload < 3 else 1 << 21
+    plan = H.Plan(g, max_hits=65535, max_peaks=peak_cap, max_member_cap=cl["member_cap"],
+                  max_tracks=1 << 14)
+    dev = []
+    for ev in events:
+        dev.append(dict(r=torch.from_numpy(ev.r).cuda(), phi=torch.from_numpy(ev.phi).cuda(),
+                        layer=torch.from_numpy(ev.layer).cuda(), n=ev.n_hits))
+    acc = torch.empty(plan.acc_shape, dtype=torch.int32, device="cuda")
+    peaks = torch.empty((peak_cap, 2), dtype=torch.int32, device="cuda")
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nv = torch.zeros(1, dtype=torch.int64, device="cuda")
+    bufs = [H.ClusterBuffers(ev.n_hits, 1 << 14, 1024, 1 << 16, cl["n_rho"], cl["n_theta"])
+            for ev in events]
+
+    # per-event vote counts and evaluations (deterministic), outside timing
+    votes, evals = [], []
+    ncol = g["n_qpt"] * g["n_d0"]
+    for d, ev in zip(dev, events):
+        H.hough_vote(plan, d["r"], d["phi"], acc, nv)
+        torch.cuda.synchronize()
+        votes.append(int(nv.item()))
+        ok = (ev.r > 0) & (ev.r < 1e4) & (np.abs(ev.phi) <= 4)
+        evals.append(int(ok.sum()) * ncol)
+
+    stream = torch.cuda.current_stream()
+    ev_a = [torch.cuda.Event(enable_timing=True) for _ in range(B)]
+    ev_b = [torch.cuda.Event(enable_timing=True) for _ in range(B)]
+    ev_c = [torch.cuda.Event(enable_timing=True) for _ in range(B)]
+
+    def step(record):
+        for e, d in enumerate(dev):
+            if record:
+                ev_a[e].record(stream)
+            H.hough_vote(plan, d["r"], d["phi"], acc)
+            if record:
+                ev_b[e].record(stream)
+            H.hough_peaks(plan, acc, W["min_votes"], peaks, nf)
+            H.assoc_cluster(plan, d["r"], d["phi"], d["layer"], peaks, nf, cl, bufs[e],
+                            with_vacc=False)
+            if record:
+                ev_c[e].record(stream)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    vote_ms, lat_ms = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+        torch.cuda.synchronize()  # per-step sync so the events of this step can be read
+        for e in range(B):
+            vote_ms.append(ev_a[e].elapsed_time(ev_b[e]))
+            lat_ms.append(ev_a[e].elapsed_time(ev_c[e]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    n_events = args.steps * B
+    total_votes = args.steps * sum(votes)
+    ms_per_step = wall * 1e3 / args.steps
+    vote_ms = np.array(vote_ms)
+    lat_ms = np.array(lat_ms)
+    # roofline of the vote kernel: algorithmic fp32 operations per launch
+    ops_per_launch = np.mean([OPS_PER_EVAL * E + OPS_PER_VOTE * V for E, V in zip(evals, votes)])
+    vote_avg_s = float(vote_ms.mean()) / 1e3
+    achieved = ops_per_launch / vote_avg_s / 1e12
+    traffic = traffic_from_profile(args.workload)
+
+    # physics of the outputs (last step), outside the timed region
+    effs, fakes, n_trk = [], [], 0
+    for ev, b in zip(events, bufs):
+        out = b.to_host(ev.n_hits)
+        tm = M.track_metrics(ev, g, cl["min_layers"], out["tracks"]["hits"])
+        effs.append((tm["n_found"], tm["n_truth_acc"]))
+        fakes.append((tm["n_fake"], tm["n_tracks"]))
+        n_trk += tm["n_tracks"]
+    eff = sum(a for a, _ in effs) / max(1, sum(b for _, b in effs))
+    fake = sum(a for a, _ in fakes) / max(1, sum(b for _, b in fakes))
+
+    cpu = None
+    if args.cpu_sample > 0:
+        cpu = cpu_baseline(W, events[:args.cpu_sample], votes[:args.cpu_sample])
+
+    line = {
+        "metric": METRIC,
+        "value": total_votes / wall,
+        "unit": "votes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": W["name"], "events_per_step": B,
+                   "grid": f"{g['n_phi']}x{g['n_qpt']}x{g['n_d0']}",
+                   "mean_hits": float(np.mean([ev.n_hits for ev in events])),
+                   "parallelism": "single GPU, events back to back on one stream"},
+        "events_per_s": n_events / wall,
+        "p50_ms": float(np.percentile(lat_ms, 50)),
+        "p99_ms": float(np.percentile(lat_ms, 99)),
+        "track_efficiency": eff,
+        "fake_rate": fake,
+        "tracks_per_event": n_trk / B,
+        "vote_kernel_votes_per_s": float(np.mean(votes)) / vote_avg_s,
+        "vote_kernel_ms": float(vote_ms.mean()),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS,
+                     "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TOPS,
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

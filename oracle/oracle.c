@@ -165,18 +165,25 @@ static int hit_valid(float r, float phi) {
  *   no vote unless |u| <= 1
  *   phi0 = phi - asin_f(u); x = (phi0 - PHI_LO) * INVW.
  * Returns 0 (no vote) or 1 and the unfloored coordinate x. */
-static int phi0_coord(float r2, float ir, float phi, float kap, float q, float t,
-                      float phi_lo, float invw, float* x_out) {
+static int phi0_coord_u(float r2, float ir, float phi, float kap, float q, float t,
+                        float phi_lo, float invw, float* x_out, float* u_out) {
   float a = kap * r2;
   float b = a + q;
   float c = b * ir;
   float u = c * t;
+  *u_out = u;
   if (!(fabsf(u) <= 1.0f)) return 0;
   float s = oracle_asin_f(u);
   float phi0 = phi - s;
   float d = phi0 - phi_lo;
   *x_out = d * invw;
   return 1;
+}
+
+static int phi0_coord(float r2, float ir, float phi, float kap, float q, float t,
+                      float phi_lo, float invw, float* x_out) {
+  float u;
+  return phi0_coord_u(r2, ir, phi, kap, q, t, phi_lo, invw, x_out, &u);
 }
 
 /* floor of x, then periodic wrap into [0, n) */
@@ -412,11 +419,14 @@ void oracle_sincos_array(const double* a, double* s, double* c, int64_t n) {
  * least-squares fit).  Reading used, per peak cell (i, j, k):
  *
  *  members   valid hits whose coordinate x in column (j, k), on the periodic
- *            image nearest the cell, satisfies |x - (i + 0.5)| <= w(r) with
- *            w(r) = 0.5 + win_bins + INVW (hd0 / r + hk r / 2): the cell
- *            itself widened by the first-order phi0 spread of a hit across
- *            the column's d0 half-width hd0 and curvature half-width hk.
- *            More than member_cap members drops the candidate.
+ *            image nearest the cell, satisfies |x - (i + 0.5)| <= w with
+ *            w = 0.5 + win_bins + 1.5 INVW (hd0 / r + hk r / 2) / (1 - u^2):
+ *            the cell widened by the phi0 spread of a hit across the
+ *            column's d0 half-width hd0 and curvature half-width hk, to first
+ *            order (du/dd0 ~ 1/r, du/dkappa ~ r/2), with 1/(1 - u^2) bounding
+ *            the arcsine slope 1/sqrt(1 - u^2) and 1.5 covering the (1 +
+ *            kappa d0) factors of the exact derivatives.  More than
+ *            member_cap members drops the candidate.
  *  seed      among the layers with members (ascending layer index = radius),
  *            take the outer min(n, min_layers) of them; the seed layers are
  *            the innermost, middle and outermost of that span.  For every
@@ -527,8 +537,9 @@ static void refine(const or_grid* g, const tables* tb, const window_t* wd, const
     if (L >= OR_MAX_LAYERS) continue;
     float r2 = r[h] * r[h];
     float ir = 1.0f / r[h];
-    float x;
-    if (!phi0_coord(r2, ir, phi[h], tb->kap[j], tb->q[col], tb->t[col], tb->phi_lo, tb->invw, &x))
+    float x, u;
+    if (!phi0_coord_u(r2, ir, phi[h], tb->kap[j], tb->q[col], tb->t[col], tb->phi_lo, tb->invw,
+                      &x, &u))
       continue;
     float dx = x - xi;
     if (dx > half_n) dx = (x - (float)np) - xi;
@@ -538,7 +549,11 @@ static void refine(const or_grid* g, const tables* tb, const window_t* wd, const
     float e3 = wd->hk * e2;
     float e4 = e1 + e3;
     float e5 = tb->invw * e4;
-    float w = wbase + e5;
+    float uu = u * u;
+    float gg = 1.0f - uu;
+    float e6 = e5 * 1.5f;
+    float e7 = e6 / gg;
+    float w = wbase + e7;
     float adx = fabsf(dx);
     if (!(adx <= w)) continue;
     if (nm >= cfg->member_cap) { out->status = 2; return; }

@@ -168,11 +168,13 @@ __device__ __forceinline__ double circle_dist(double A, double B, double C, doub
 // float32 phi0 coordinate of a hit in a column (the vote formula); false
 // when |u| > 1
 __device__ __forceinline__ bool phi0_coord(float r2, float ir, float ph, float ck, float cq,
-                                           float ct, float phi_lo, float invw, float* x) {
+                                           float ct, float phi_lo, float invw, float* x,
+                                           float* u_out) {
   const float a = ck * r2;
   const float b = a + cq;
   const float c = b * ir;
   const float u = c * ct;
+  *u_out = u;
   if (!(fabsf(u) <= 1.0f)) return false;
   const float s = asin_f(u);
   const float phi0 = ph - s;
@@ -191,15 +193,21 @@ __device__ __forceinline__ float cell_adx(float x, int i, int n_phi) {
   return fabsf(dx);
 }
 
-// member window half-width in bins for a hit at radius r (ir = 1/r)
-__device__ __forceinline__ float member_window(float r, float ir, float wbase, float hd0,
-                                               float hk, float invw) {
+// member window half-width in bins: the column-width part depends on the
+// hit only (e5), the arcsine slope bound 1.5 / (1 - u^2) on the column too
+__device__ __forceinline__ float member_e5(float r, float ir, float hd0, float hk, float invw) {
   const float e1 = hd0 * ir;
   const float e2 = r * 0.5f;
   const float e3 = hk * e2;
   const float e4 = e1 + e3;
-  const float e5 = invw * e4;
-  return wbase + e5;
+  return invw * e4;
+}
+__device__ __forceinline__ float member_window(float e5, float u, float wbase) {
+  const float uu = u * u;
+  const float gg = 1.0f - uu;
+  const float e6 = e5 * 1.5f;
+  const float e7 = e6 / gg;
+  return wbase + e7;
 }
 
 struct AssocArgs {
@@ -370,7 +378,7 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
     }
     const float hr2 = hr * hr;
     const float hir = 1.0f / hr;
-    const float hw = member_window(hr, hir, wbase, A.hd0, A.hk, A.invw);
+    const float he5 = member_e5(hr, hir, A.hd0, A.hk, A.invw);
     uint64_t todo = __ballot(hv);
     while (todo) {
       const int src = __builtin_ctzll(todo);
@@ -378,10 +386,11 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
       const float r2 = bcastf(hr2, src);
       const float ir = bcastf(hir, src);
       const float ph = bcastf(hp, src);
-      const float w = bcastf(hw, src);
+      const float e5 = bcastf(he5, src);
       const int hh = base + src;
-      float x;
-      if (!has || !phi0_coord(r2, ir, ph, ck, cq, ct, A.phi_lo, A.invw, &x)) continue;
+      float x, u;
+      if (!has || !phi0_coord(r2, ir, ph, ck, cq, ct, A.phi_lo, A.invw, &x, &u)) continue;
+      const float w = member_window(e5, u, wbase);
       // candidate cells: a conservative integer range (at most one pass over
       // the column), then the exact test of the reference
       int ilo = 0, ihi = n_phi - 1;
@@ -489,8 +498,8 @@ __global__ __launch_bounds__(kRefineWaves* kWave) void refine_kernel(AssocArgs A
       const int h = A.mem[(size_t)p * cap + m];
       const int L = A.layer[h];
       const float r = A.r[h];
-      float x = 0.0f;
-      phi0_coord(r * r, 1.0f / r, A.phi[h], ck, cq, ct, A.phi_lo, A.invw, &x);
+      float x = 0.0f, u;
+      phi0_coord(r * r, 1.0f / r, A.phi[h], ck, cq, ct, A.phi_lo, A.invw, &x, &u);
       M.h[m] = h;
       M.L[m] = (int8_t)L;
       M.adx[m] = cell_adx(x, i, A.n_phi);

@@ -64,8 +64,7 @@ struct Plan {
   double* d_hy;
   double* d_hq;
   int32_t* d_mcount;     // [max_peaks] member counts
-  int32_t* d_mem;        // [max_peaks * max_member_cap] member hit indices
-  float* d_madx;         // [max_peaks * max_member_cap] |x - centre| of each member
+  int32_t* d_mem;        // [max_peaks * max_member_cap / 2] member hit indices (uint16)
   int32_t* d_cstat;      // [max_peaks] candidate status / inlier count
   double* d_cgeo;        // [max_peaks * 5] seed ss, A, B, C, D
   int32_t* d_chit;       // [max_peaks * HT_MAX_LAYERS] inlier hit per layer

@@ -404,3 +404,54 @@ def test_generator_hits_on_track_circle():
         for li, x, y, _ in G.crossings(vx, vy, psi, kap):
             assert abs(np.hypot(x, y) - G.RADII[li]) < 1e-9
             assert abs(np.hypot(x - cx, y - cy) - 1 / abs(kap)) < 1e-9
+
+
+def test_member_window_holds_tracks_anywhere_in_the_cell(oracle):
+    """A noiseless track whose (q/pT, d0) sit at any corner of the peak cell's
+    column box, and whose phi0 is anywhere in the cell, has every hit among
+    the cell's members (the window's d0 and curvature terms are what make
+    this hold at small and large radii respectively; the one-bin margin
+    covers the first-order approximation for |d0| up to 5 cm)."""
+    g = CF.GRID_3D
+    cl = dict(CF.CLUSTER_3D)
+    rng = np.random.default_rng(17)
+    wq = (g["qpt_hi"] - g["qpt_lo"]) / g["n_qpt"]
+    wd = (g["d0_hi"] - g["d0_lo"]) / g["n_d0"]
+    wp = 2 * np.pi / g["n_phi"]
+    checked = 0
+    for _ in range(40):
+        i, j, k = int(rng.integers(0, 512)), int(rng.integers(40, 216)), int(rng.integers(24, 40))
+        phi0c, qptc, d0c = _bin_centre_track(g, i, j, k)
+        fq, fd, fp = rng.choice([-0.49, 0.49]), rng.choice([-0.49, 0.49]), rng.uniform(-0.45, 0.45)
+        ev = G.make_tracks_event([(phi0c + fp * wp, qptc + fq * wq, d0c + fd * wd)], smear=0.0)
+        if ev.n_hits < 7:
+            continue
+        lin = (k * g["n_qpt"] + j) * g["n_phi"] + i
+        rr = oracle.refine_one(g, ev.r, ev.phi, ev.layer, lin, cl)
+        assert rr["n_layers"] == ev.n_hits, (i, j, k, fq, fd, rr["n_layers"], ev.n_hits)
+        checked += 1
+    assert checked > 20
+
+
+def test_vertex_isotropy_matches_truth(oracle):
+    """The object's isotropy is the length of the mean unit perigee direction
+    of its members; for noiseless tracks that is the generator's value."""
+    W = CF.WORKLOADS[2]
+    g, cl = W["grid"], dict(W["cluster"], member_cap=512)
+    rng = np.random.default_rng(18)
+    rho, theta = 9.0, 0.4
+    psis = theta + rng.uniform(-1.2, 1.2, 30)
+    qpts = rng.choice([-1, 1], 30) * rng.uniform(0.3, 0.9, 30)
+    ev = G.make_vertex_event(rho, theta, psis, qpts, smear=0.0)
+    acc, _ = oracle.hough_vote(g, ev.r, ev.phi)
+    pk, _ = oracle.hough_peaks(g, acc, W["min_votes"])
+    res = oracle.assoc_cluster(g, ev.r, ev.phi, ev.layer, pk, cl)
+    obj = res["objects"]
+    best = obj[np.argmax(obj["n_tracks"])]
+    mem = res["members"][best["member_begin"]:best["member_begin"] + best["n_tracks"]]
+    from paper_1309_6275_amd import metrics as M
+    truth = M.match_tracks(res["tracks"]["hits"], ev.hit_track, cl["min_layers"])[mem]
+    assert (truth >= 0).all()
+    phi0 = ev.trk_phi0[truth]
+    want = np.hypot(np.cos(phi0).sum(), np.sin(phi0).sum()) / phi0.size
+    assert abs(best["isotropy"] - want) < 1e-4
