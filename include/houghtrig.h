@@ -169,8 +169,9 @@ int hough_peaks(const ht_plan* plan, const int32_t* acc, int32_t min_votes, ht_p
 /* assoc_cluster -- candidate refinement, duplicate cleaning, refit and the
  * second transform (paper, section "Jet and Black Hole Detection").
  *   members    valid hits whose phi0 coordinate x in the peak's column lies
- *              within 0.5 + win_bins + INVW (hd0/r + hk r/2) of the cell
- *              centre (hd0, hk: half column widths in d0 and curvature);
+ *              within 0.5 + win_bins + 1.5 INVW (hd0/r + hk r/2) / sqrt(1-u^2)
+ *              bins of the cell centre (hd0, hk: half column widths in d0
+ *              and curvature; u as in hough_vote);
  *              more than member_cap members drops the candidate;
  *   seed       over the outer min(n, min_layers) member layers, circles
  *              through the seed_k nearest-centre members of the innermost,

@@ -420,13 +420,13 @@ void oracle_sincos_array(const double* a, double* s, double* c, int64_t n) {
  *
  *  members   valid hits whose coordinate x in column (j, k), on the periodic
  *            image nearest the cell, satisfies |x - (i + 0.5)| <= w with
- *            w = 0.5 + win_bins + 1.5 INVW (hd0 / r + hk r / 2) / (1 - u^2):
+ *            w = 0.5 + win_bins + 1.5 INVW (hd0 / r + hk r / 2) / sqrt(1 - u^2):
  *            the cell widened by the phi0 spread of a hit across the
  *            column's d0 half-width hd0 and curvature half-width hk, to first
- *            order (du/dd0 ~ 1/r, du/dkappa ~ r/2), with 1/(1 - u^2) bounding
- *            the arcsine slope 1/sqrt(1 - u^2) and 1.5 covering the (1 +
- *            kappa d0) factors of the exact derivatives.  More than
- *            member_cap members drops the candidate.
+ *            order (du/dd0 ~ 1/r, du/dkappa ~ r/2, arcsine slope
+ *            1/sqrt(1 - u^2)), with 1.5 covering the (1 + kappa d0) factors
+ *            of the exact derivatives.  More than member_cap members drops
+ *            the candidate.
  *  seed      among the layers with members (ascending layer index = radius),
  *            take the outer min(n, min_layers) of them; the seed layers are
  *            the innermost, middle and outermost of that span.  For every
@@ -551,8 +551,9 @@ static void refine(const or_grid* g, const tables* tb, const window_t* wd, const
     float e5 = tb->invw * e4;
     float uu = u * u;
     float gg = 1.0f - uu;
+    float sg = sqrtf(gg);
     float e6 = e5 * 1.5f;
-    float e7 = e6 / gg;
+    float e7 = e6 / sg;
     float w = wbase + e7;
     float adx = fabsf(dx);
     if (!(adx <= w)) continue;

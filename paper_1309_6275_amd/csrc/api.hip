@@ -52,7 +52,7 @@ int dalloc(T** p, size_t n) {
 void free_plan(Plan* p) {
   void* ptrs[] = {p->d_kap,       p->d_q,         p->d_t,        p->d_bits,      p->d_tile_cnt,
                   p->d_tile_off,  p->d_pbits,     p->d_col_first, p->d_hx,       p->d_hy,
-                  p->d_hq,        p->d_mcount,    p->d_mem,      p->d_cstat,
+                  p->d_hq,        p->d_mcount,    p->d_mcur,      p->d_moff,    p->d_mem,      p->d_cstat,
                   p->d_cgeo,      p->d_chit,      p->d_cnl,      p->d_owner_key, p->d_ctile_cnt,
                   p->d_ctile_off, p->d_trk_peak,  p->d_arc0,     p->d_arcn,      p->d_vacc,
                   p->d_obj_cnt,   p->d_obj_off,   p->d_scalars};
@@ -130,6 +130,8 @@ int ht_plan_create(const ht_grid* grid, const ht_limits* lim, ht_plan** out) {
   if (rc == HT_OK) rc = dalloc(&p->d_hy, nh);
   if (rc == HT_OK) rc = dalloc(&p->d_hq, nh);
   if (rc == HT_OK) rc = dalloc(&p->d_mcount, np);
+  if (rc == HT_OK) rc = dalloc(&p->d_mcur, np);
+  if (rc == HT_OK) rc = dalloc(&p->d_moff, np);
   if (rc == HT_OK) rc = dalloc(&p->d_mem, (np * (size_t)lim->max_member_cap + 1) / 2);
   if (rc == HT_OK) rc = dalloc(&p->d_cstat, np);
   if (rc == HT_OK) rc = dalloc(&p->d_cgeo, np * 5);

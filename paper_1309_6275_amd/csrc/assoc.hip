@@ -37,11 +37,10 @@ namespace {
 
 constexpr int kSweepWaves = 16;
 constexpr int kSweepThreads = kSweepWaves * kWave;
-constexpr int kRefineWaves = 1;  // one wave per workgroup: barriers are wave-local
 constexpr int kMaxMembers = 1024; // largest member_cap (LDS slots per wave in refine)
 constexpr int kGridCap = 8192;    // grid-stride launches use at most this many blocks
 
-enum { S_NP = 0, S_NCAND = 1, S_NOVER = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5 };
+enum { S_NP = 0, S_NCAND = 1, S_NOVER = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5, S_POOL = 6 };
 
 __device__ __forceinline__ float bcastf(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -194,7 +193,7 @@ __device__ __forceinline__ float cell_adx(float x, int i, int n_phi) {
 }
 
 // member window half-width in bins: the column-width part depends on the
-// hit only (e5), the arcsine slope bound 1.5 / (1 - u^2) on the column too
+// hit only (e5), the arcsine slope 1 / sqrt(1 - u^2) on the column too
 __device__ __forceinline__ float member_e5(float r, float ir, float hd0, float hk, float invw) {
   const float e1 = hd0 * ir;
   const float e2 = r * 0.5f;
@@ -204,9 +203,10 @@ __device__ __forceinline__ float member_e5(float r, float ir, float hd0, float h
 }
 __device__ __forceinline__ float member_window(float e5, float u, float wbase) {
   const float uu = u * u;
-  const float gg = 1.0f - uu;
+  const float gg = 1.0f - uu;  // 0 or >= 2^-24: the square root below is exact
+  const float sg = sqrt_unit(gg);
   const float e6 = e5 * 1.5f;
-  const float e7 = e6 / gg;
+  const float e7 = e6 / sg;
   return wbase + e7;
 }
 
@@ -240,7 +240,9 @@ struct AssocArgs {
   uint32_t* pbits;
   int32_t* col_first;
   int32_t* mcount;
-  uint16_t* mem;
+  int32_t* mcur;
+  int32_t* moff;
+  uint16_t* pool;
   int32_t* cstat;
   int32_t* cnl;
   double* cgeo;
@@ -308,65 +310,47 @@ __global__ void mark_kernel(AssocArgs A) {
 
 // ---- member sweep -----------------------------------------------------------
 // LDS per column: the column's peak bits (starting at bit i = 0) and the
-// number of peaks before each 32-bit word.
+// number of peaks before each 32-bit word.  The workgroup owns the peaks of
+// its 64 columns, which are consecutive in the (cell-ordered) peak list, so
+// it can count their members in LDS, give each candidate a compact slice of
+// one global pool, and fill the slices in a second sweep: the member lists of
+// a workgroup then occupy one contiguous region instead of member_cap-strided
+// slots, and no global atomic is needed per member.
 constexpr int kMaxPhiWords = 32;  // n_phi <= 1024
+constexpr int kMaxWgPeaks = 8192; // LDS counters; more peaks fall back to global counters
 
-__global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
-  __shared__ uint32_t cbits[kWave][kMaxPhiWords + 1];
-  __shared__ int32_t cpre[kWave][kMaxPhiWords + 1];
-  __shared__ int any_peak;
+struct SweepShared {
+  uint32_t cbits[kWave][kMaxPhiWords + 1];
+  int32_t cpre[kWave][kMaxPhiWords + 1];
+  int32_t ccnt[kWave];
+  int32_t cnt[kMaxWgPeaks];   // member counts, then fill cursors
+  int32_t off[kMaxWgPeaks];   // slice offsets within the workgroup region, -1 = overflow
+  int32_t wsum[kSweepWaves];
+  int32_t any, np_wg, p_lo, base;
+};
+
+// One pass over the workgroup's (hit, column) pairs; for every member
+// (candidate q = p - p_lo, hit h) call fn(q, h).
+template <typename F>
+__device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S, int k, int j0,
+                                              F fn) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x >> 6;
-  const int j0 = blockIdx.x * kWave;
-  const int k = blockIdx.y;
   const int n_phi = A.n_phi;
   const int nwords = (n_phi + 31) >> 5;
-  if (threadIdx.x == 0) any_peak = 0;
-  __syncthreads();
-  // gather the column bitmaps (column bits are not word aligned in general)
-  for (int e = threadIdx.x; e < kWave * nwords; e += kSweepThreads) {
-    const int cl = e / nwords, w = e - cl * nwords;
-    const int j = j0 + cl;
-    uint32_t v = 0;
-    if (j < A.n_qpt) {
-      const int64_t bit0 = ((int64_t)k * A.n_qpt + j) * n_phi + (int64_t)w * 32;
-      const int nb = min(32, n_phi - w * 32);
-      const int64_t wi = bit0 >> 5;
-      const int sh = (int)(bit0 & 31);
-      uint64_t two = (uint64_t)A.pbits[wi];
-      if (sh + nb > 32) two |= (uint64_t)A.pbits[wi + 1] << 32;
-      v = (uint32_t)(two >> sh);
-      if (nb < 32) v &= (1u << nb) - 1u;
-    }
-    cbits[cl][w] = v;
-    if (v) any_peak = 1;
-  }
-  __syncthreads();
-  if (!any_peak) return;
-  if (threadIdx.x < kWave) {
-    int s = 0;
-    for (int w = 0; w < nwords; ++w) {
-      cpre[threadIdx.x][w] = s;
-      s += __popc(cbits[threadIdx.x][w]);
-    }
-  }
-  __syncthreads();
-
   const int j = j0 + lane;
   const bool col_ok = j < A.n_qpt;
   float ck = 0.0f, cq = 0.0f, ct = 0.0f;
   int cfirst = 0;
-  bool has = false;
+  const bool has = col_ok && S.ccnt[lane] > 0;
   if (col_ok) {
     ck = A.kap[j];
     cq = A.qt[(size_t)k * A.n_qpt + j];
     ct = A.tt[(size_t)k * A.n_qpt + j];
-    for (int w = 0; w < nwords; ++w) has |= cbits[lane][w] != 0u;
-    if (has) cfirst = A.col_first[(size_t)k * A.n_qpt + j];
+    if (has) cfirst = A.col_first[(size_t)k * A.n_qpt + j] - S.p_lo;
   }
   const float wbase = 0.5f + (float)A.cfg.win_bins;
-  const int cap = A.cfg.member_cap;
-  const int np = n_cands(A);
+  const int np_wg = S.np_wg;
   for (int base = wave * kWave; base < A.n_hits; base += kSweepThreads) {
     const int h = base + lane;
     float hr = 1.0f, hp = 0.0f;
@@ -390,36 +374,39 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
       const int hh = base + src;
       float x, u;
       if (!has || !phi0_coord(r2, ir, ph, ck, cq, ct, A.phi_lo, A.invw, &x, &u)) continue;
-      const float w = member_window(e5, u, wbase);
-      // candidate cells: a conservative integer range (at most one pass over
-      // the column), then the exact test of the reference
+      // upper bound of the window with the hardware reciprocal square root
+      // (1 ulp) and a 0.1% margin; the exact window is computed only if a
+      // peak is in reach
+      const float gg = 1.0f - u * u;
+      const float w_hi = wbase + e5 * 1.5f * __builtin_amdgcn_rsqf(gg) * 1.001f;
       int ilo = 0, ihi = n_phi - 1;
-      if (w < 0.5f * (float)n_phi) {
-        const int lo = (int)floorf(x - w - 0.5f) - 1;
-        const int hi = (int)floorf(x + w - 0.5f) + 1;
+      if (w_hi < 0.5f * (float)n_phi) {
+        const int lo = (int)floorf(x - w_hi - 0.5f) - 1;
+        const int hi = (int)floorf(x + w_hi - 0.5f) + 1;
         if (hi - lo + 1 < n_phi) { ilo = lo; ihi = hi; }
       }
+      float w = -1.0f;
       int i = ilo;
       while (i <= ihi) {
-        int iw = i % n_phi;
-        if (iw < 0) iw += n_phi;
+        // i lies in (-n_phi, 2 n_phi): one period of correction
+        const int iw = i < 0 ? i + n_phi : (i >= n_phi ? i - n_phi : i);
         const int wi = iw >> 5, bit = iw & 31;
         int span = 32 - bit;
         span = min(span, ihi - i + 1);
         span = min(span, n_phi - iw);
-        uint32_t bits = cbits[lane][wi] >> bit;
+        uint32_t bits = S.cbits[lane][wi] >> bit;
         if (span < 32) bits &= (1u << span) - 1u;
         while (bits) {
           const int b = __builtin_ctz(bits);
           bits &= bits - 1u;
+          if (w < 0.0f) w = member_window(e5, u, wbase);
           const int ic = iw + b;
           const float adx = cell_adx(x, ic, n_phi);
           if (!(adx <= w)) continue;
-          const uint32_t below = cbits[lane][wi] & ((1u << (bit + b)) - 1u);
-          const int p = cfirst + cpre[lane][wi] + __popc(below);
-          if (p < 0 || p >= np) continue;  // only for peak lists not sorted by cell
-          const int slot = atomicAdd(&A.mcount[p], 1);
-          if (slot < cap) A.mem[(size_t)p * cap + slot] = (uint16_t)hh;
+          const uint32_t below = S.cbits[lane][wi] & ((1u << (bit + b)) - 1u);
+          const int q = cfirst + S.cpre[lane][wi] + __popc(below);
+          if (q < 0 || q >= np_wg) continue;  // only for peak lists not sorted by cell
+          fn(q, hh);
         }
         i += span;
       }
@@ -427,17 +414,154 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
   }
 }
 
+__device__ __forceinline__ int wg_scan_excl(int v, int32_t* wsum, int* total) {
+  // exclusive scan across the workgroup (kSweepThreads), returns v's offset
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x >> 6;
+  int incl = v;
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int o = __shfl_up(incl, d);
+    if (lane >= d) incl += o;
+  }
+  if (lane == kWave - 1) wsum[wave] = incl;
+  __syncthreads();
+  int before = 0, tot = 0;
+  for (int w = 0; w < kSweepWaves; ++w) {
+    if (w < wave) before += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return before + incl - v;
+}
+
+__global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
+  __shared__ SweepShared S;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int j0 = blockIdx.x * kWave;
+  const int k = blockIdx.y;
+  const int n_phi = A.n_phi;
+  const int nwords = (n_phi + 31) >> 5;
+  const int cap = A.cfg.member_cap;
+  // gather the column bitmaps (column bits are not word aligned in general)
+  for (int e = threadIdx.x; e < kWave * nwords; e += kSweepThreads) {
+    const int cl = e / nwords, w = e - cl * nwords;
+    const int j = j0 + cl;
+    uint32_t v = 0;
+    if (j < A.n_qpt) {
+      const int64_t bit0 = ((int64_t)k * A.n_qpt + j) * n_phi + (int64_t)w * 32;
+      const int nb = min(32, n_phi - w * 32);
+      const int64_t wi = bit0 >> 5;
+      const int sh = (int)(bit0 & 31);
+      uint64_t two = (uint64_t)A.pbits[wi];
+      if (sh + nb > 32) two |= (uint64_t)A.pbits[wi + 1] << 32;
+      v = (uint32_t)(two >> sh);
+      if (nb < 32) v &= (1u << nb) - 1u;
+    }
+    S.cbits[cl][w] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    int s = 0;
+    for (int w = 0; w < nwords; ++w) {
+      S.cpre[threadIdx.x][w] = s;
+      s += __popc(S.cbits[threadIdx.x][w]);
+    }
+    S.ccnt[threadIdx.x] = s;
+    // first column with peaks gives the workgroup's first peak index
+    const uint64_t hasm = __ballot(s > 0);
+    int tot = s;
+    for (int d = 32; d > 0; d >>= 1) tot += __shfl_xor(tot, d);
+    if (threadIdx.x == 0) {
+      S.np_wg = tot;
+      S.p_lo = 0;
+      if (hasm) {
+        const int c0 = __builtin_ctzll(hasm);
+        S.p_lo = A.col_first[(size_t)k * A.n_qpt + j0 + c0];
+      }
+    }
+  }
+  __syncthreads();
+  const int np_wg = S.np_wg;
+  const int p_lo = S.p_lo;
+  // a cell-ordered peak list gives p_lo + np_wg <= n_peaks; anything else is
+  // a malformed list, whose candidates in these columns then get no members
+  if (np_wg == 0 || p_lo < 0 || p_lo + np_wg > n_cands(A)) return;
+  const bool in_lds = np_wg <= kMaxWgPeaks;
+  int32_t* cnt = in_lds ? S.cnt : A.mcur + p_lo;    // counts, zeroed
+  for (int q = threadIdx.x; q < np_wg; q += kSweepThreads) {
+    if (in_lds) S.cnt[q] = 0;
+    else A.mcur[p_lo + q] = 0;
+  }
+  __syncthreads();
+  // pass 1: count members
+  sweep_members(A, S, k, j0, [&](int q, int) { atomicAdd(&cnt[q], 1); });
+  __syncthreads();
+  // slices: overflowed candidates (count > cap) get none
+  int run = 0;
+  for (int q0 = 0; q0 < np_wg; q0 += kSweepThreads) {
+    const int q = q0 + threadIdx.x;
+    const int c = q < np_wg ? cnt[q] : 0;
+    const int sz = c <= cap ? c : 0;
+    int tot = 0;
+    const int ex = wg_scan_excl(sz, S.wsum, &tot);
+    if (q < np_wg) {
+      A.mcount[p_lo + q] = c;
+      const int o = c <= cap ? run + ex : -1;
+      if (in_lds) S.off[q] = o;
+      else A.moff[p_lo + q] = o;
+    }
+    run += tot;
+  }
+  if (threadIdx.x == 0) S.base = atomicAdd(&A.sc[S_POOL], run);
+  __syncthreads();
+  const int base = S.base;
+  for (int q = threadIdx.x; q < np_wg; q += kSweepThreads) {
+    if (in_lds) {
+      const int o = S.off[q];
+      A.moff[p_lo + q] = o >= 0 ? base + o : -1;
+      S.cnt[q] = 0;
+    } else {
+      const int o = A.moff[p_lo + q];
+      A.moff[p_lo + q] = o >= 0 ? base + o : -1;
+      A.mcur[p_lo + q] = 0;
+    }
+  }
+  __syncthreads();
+  // pass 2: fill the slices
+  if (in_lds) {
+    sweep_members(A, S, k, j0, [&](int q, int hh) {
+      const int o = S.off[q];
+      if (o < 0) return;
+      const int slot = atomicAdd(&S.cnt[q], 1);
+      A.pool[(size_t)base + o + slot] = (uint16_t)hh;
+    });
+  } else {
+    sweep_members(A, S, k, j0, [&](int q, int hh) {
+      const int o = A.moff[p_lo + q];
+      if (o < 0) return;
+      const int slot = atomicAdd(&A.mcur[p_lo + q], 1);
+      A.pool[(size_t)o + slot] = (uint16_t)hh;
+    });
+  }
+  (void)lane;
+}
+
 // ---- refine: one wave per candidate ------------------------------------------
+// Members in LDS as float32 coordinates for a conservative pre-filter; the
+// float64 coordinates of the few members that pass are read from global
+// memory (the hit arrays stay in L2).
 template <int CAP>
 struct WaveMem {
-  double x[CAP];
-  double y[CAP];
-  double q[CAP];
+  float xf[CAP];
+  float yf[CAP];
+  float qf[CAP];
   int32_t h[CAP];
   float adx[CAP];
   int16_t order[CAP];  // members grouped by layer
   int8_t L[CAP];
   int32_t lstart[HT_MAX_LAYERS + 1];
+  int32_t seed[3][4];
 };
 
 __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
@@ -468,15 +592,15 @@ __device__ __forceinline__ int nth_set_bit(unsigned mask, int n) {
 }
 
 template <int CAP>
-__global__ __launch_bounds__(kRefineWaves* kWave) void refine_kernel(AssocArgs A) {
-  __shared__ WaveMem<CAP> wm_all[kRefineWaves];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x >> 6;
-  WaveMem<CAP>& M = wm_all[wave];
+__global__ __launch_bounds__(kWave) void refine_kernel(AssocArgs A) {
+  __shared__ WaveMem<CAP> M;
+  const int lane = threadIdx.x;
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
   const int np = n_cands(A);
   const ht_cluster_cfg& cfg = A.cfg;
   const int cap = cfg.member_cap;
-  for (int p = blockIdx.x * kRefineWaves + wave; p < np; p += gridDim.x * kRefineWaves) {
+  const double road = (double)cfg.road_sigmas * (double)cfg.sigma_rphi;
+  for (int p = blockIdx.x; p < np; p += gridDim.x) {
     const int lin = A.peaks[p].lin;
     const int n = A.mcount[p];
     if (lin < 0 || lin >= A.n_cells) {
@@ -492,10 +616,11 @@ __global__ __launch_bounds__(kRefineWaves* kWave) void refine_kernel(AssocArgs A
     const int j = col % A.n_qpt;
     const int k = col / A.n_qpt;
     const float ck = A.kap[j], cq = A.qt[col], ct = A.tt[col];
+    const int moff = A.moff[p];
     // load members
     unsigned lmask = 0;
     for (int m = lane; m < n; m += kWave) {
-      const int h = A.mem[(size_t)p * cap + m];
+      const int h = A.pool[(size_t)moff + m];
       const int L = A.layer[h];
       const float r = A.r[h];
       float x = 0.0f, u;
@@ -503,66 +628,63 @@ __global__ __launch_bounds__(kRefineWaves* kWave) void refine_kernel(AssocArgs A
       M.h[m] = h;
       M.L[m] = (int8_t)L;
       M.adx[m] = cell_adx(x, i, A.n_phi);
-      M.x[m] = A.hx[h];
-      M.y[m] = A.hy[h];
-      M.q[m] = A.hq[h];
+      M.xf[m] = (float)A.hx[h];
+      M.yf[m] = (float)A.hy[h];
+      M.qf[m] = (float)A.hq[h];
       lmask |= 1u << L;
     }
     lmask = wave_or(lmask);
     const int nS = __popc(lmask);
     if (nS < cfg.min_layers || nS < 3) {
       if (lane == 0) { A.cstat[p] = -1; A.cnl[p] = nS; }
+      __syncthreads();
       continue;
     }
-    // group members by layer (stable order is not needed: ties break on h)
-    if (lane == 0) {
-      int s = 0;
+    __syncthreads();
+    // group members by layer: ballot + popcount scatter (order within a
+    // layer does not matter, every selection breaks ties on the hit index)
+    {
+      int base = 0;
       for (int L = 0; L < HT_MAX_LAYERS; ++L) {
-        M.lstart[L] = s;
-        for (int m = 0; m < n; ++m)
-          if (M.L[m] == L) M.order[s++] = (int16_t)m;
+        if (lane == 0) M.lstart[L] = base;
+        if (!((lmask >> L) & 1u)) continue;
+        for (int m0 = 0; m0 < n; m0 += kWave) {
+          const int m = m0 + lane;
+          const bool pr = m < n && M.L[m] == L;
+          const uint64_t b = __ballot(pr);
+          if (pr) M.order[base + __popcll(b & lt_mask)] = (int16_t)m;
+          base += __popcll(b);
+        }
       }
-      M.lstart[HT_MAX_LAYERS] = s;
+      if (lane == 0) M.lstart[HT_MAX_LAYERS] = base;
     }
     __syncthreads();
     // seed layers: innermost, middle and outermost of the outer min(nS, min_layers)
     const int span = nS < cfg.min_layers ? nS : cfg.min_layers;
-    const int Ls0 = nth_set_bit(lmask, nS - span);
-    const int Ls1 = nth_set_bit(lmask, nS - span + (span - 1) / 2);
-    const int Ls2 = nth_set_bit(lmask, nS - 1);
-    // seed_k nearest members per seed layer: repeated wave argmin on (adx, h)
-    int seedm[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-    int ns[3] = {0, 0, 0};
+    const int Ls[3] = {nth_set_bit(lmask, nS - span),
+                       nth_set_bit(lmask, nS - span + (span - 1) / 2), nth_set_bit(lmask, nS - 1)};
+    // seed_k nearest members per seed layer, by rank of (adx, h)
     const int kk = cfg.seed_k;
+    int ns[3];
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-      const int Lsel = s == 0 ? Ls0 : (s == 1 ? Ls1 : Ls2);
-      unsigned long long prev = 0ull;
-      bool have_prev = false, done = false;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (t >= kk || done) continue;
-        unsigned long long best = ~0ull;
-        for (int m = lane; m < n; m += kWave) {
-          if (M.L[m] != Lsel) continue;
-          const unsigned long long key =
-              ((unsigned long long)__float_as_uint(M.adx[m]) << 32) | (unsigned)M.h[m];
-          if (have_prev && key <= prev) continue;
-          best = key < best ? key : best;
+      const int st = M.lstart[Ls[s]], en = M.lstart[Ls[s] + 1];
+      ns[s] = en - st < kk ? en - st : kk;
+      for (int e = st + lane; e < en; e += kWave) {
+        const int m = M.order[e];
+        const unsigned long long key =
+            ((unsigned long long)__float_as_uint(M.adx[m]) << 32) | (unsigned)M.h[m];
+        int rank = 0;
+        for (int e2 = st; e2 < en; ++e2) {
+          const int m2 = M.order[e2];
+          const unsigned long long k2 =
+              ((unsigned long long)__float_as_uint(M.adx[m2]) << 32) | (unsigned)M.h[m2];
+          rank += k2 < key;
         }
-        best = wave_min_u64(best);
-        if (best == ~0ull) { done = true; continue; }
-        // recover the member slot of that hit
-        int slot = -1;
-        for (int m = lane; m < n; m += kWave)
-          if (M.L[m] == Lsel && (unsigned)M.h[m] == (unsigned)(best & 0xffffffffu)) slot = m;
-        slot = wave_max_i32(slot);
-        seedm[s][t] = slot;
-        ns[s] = t + 1;
-        prev = best;
-        have_prev = true;
+        if (rank < kk) M.seed[s][rank] = m;
       }
     }
+    __syncthreads();
     if (A.origin_seed) ns[0] = 1;
     const int nc = ns[0] * ns[1] * ns[2];
     // one combination per lane
@@ -572,21 +694,14 @@ __global__ __launch_bounds__(kRefineWaves* kWave) void refine_kernel(AssocArgs A
     int hitL[HT_MAX_LAYERS];
 #pragma unroll
     for (int L = 0; L < HT_MAX_LAYERS; ++L) hitL[L] = -1;
-    const double road = (double)cfg.road_sigmas * (double)cfg.sigma_rphi;
     if (lane < nc) {
       const int a = lane / (ns[1] * ns[2]);
       const int b = (lane / ns[2]) % ns[1];
       const int c = lane % ns[2];
-      int ma = 0, mb = 0, mc = 0;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (t == a) ma = seedm[0][t];
-        if (t == b) mb = seedm[1][t];
-        if (t == c) mc = seedm[2][t];
-      }
+      const int ha = M.h[M.seed[0][a]], hb = M.h[M.seed[1][b]], hc = M.h[M.seed[2][c]];
       double xa = 0.0, ya = 0.0;
-      if (!A.origin_seed) { xa = M.x[ma]; ya = M.y[ma]; }
-      bool ok = circle3(xa, ya, M.x[mb], M.y[mb], M.x[mc], M.y[mc], &cA, &cB, &cC, &cD);
+      if (!A.origin_seed) { xa = A.hx[ha]; ya = A.hy[ha]; }
+      bool ok = circle3(xa, ya, A.hx[hb], A.hy[hb], A.hx[hc], A.hy[hc], &cA, &cB, &cC, &cD);
       if (ok) {
         const double kapc = -(kCLight * A.bfield) *
                             (A.qpt_lo + ((double)j + 0.5) * (A.qpt_hi - A.qpt_lo) / (double)A.n_qpt);
@@ -600,6 +715,15 @@ __global__ __launch_bounds__(kRefineWaves* kWave) void refine_kernel(AssocArgs A
         ok = (fabs(kap - kapc) <= ktol) && (fabs(d0 - d0c) <= dtol);
       }
       if (ok) {
+        // |dist| >= |f| / (1 + |A||f|): a member with |f| > road / (1 -
+        // road |A|) cannot be within the road.  The test runs in float32
+        // with a margin of 1e-6 of the sum of the terms' magnitudes, far
+        // above float32 rounding of f (< 4e-7 of it), so it never drops a
+        // member the float64 test would keep.
+        const double ra = road * fabs(cA);
+        const float pre = ra < 0.5 ? (float)(road / (1.0 - ra) * 1.000001) : __builtin_inff();
+        const float Af = (float)cA, Bf = (float)cB, Cf = (float)cC, Df = (float)cD;
+        const float aA = fabsf(Af), aB = fabsf(Bf), aC = fabsf(Cf), aD = fabsf(Df);
         n_in = 0;
         int remaining = nS;
 #pragma unroll
@@ -609,11 +733,20 @@ __global__ __launch_bounds__(kRefineWaves* kWave) void refine_kernel(AssocArgs A
           if (n_in + remaining + 1 < cfg.min_layers) { n_in = -2; break; }
           double bd = 0.0;
           int bh = -1;
-          for (int e = M.lstart[L]; e < M.lstart[L + 1]; ++e) {
+          const int en = M.lstart[L + 1];
+          for (int e = M.lstart[L]; e < en; ++e) {
             const int m = M.order[e];
-            const double dist = fabs(circle_dist(cA, cB, cC, cD, M.x[m], M.y[m], M.q[m]));
+            const float xf = M.xf[m], yf = M.yf[m], qf = M.qf[m];
+            const float f32 = Af * qf + Bf * xf + Cf * yf + Df;
+            const float mag = aA * qf + aB * fabsf(xf) + aC * fabsf(yf) + aD;
+            if (!(fabsf(f32) <= pre + mag * 1e-6f)) continue;
+            const int hh = M.h[m];
+            const double f = cA * A.hq[hh] + cB * A.hx[hh] + cC * A.hy[hh] + cD;
+            double sarg = 1.0 + 4.0 * cA * f;
+            if (sarg < 0.0) sarg = 0.0;
+            const double dist = fabs(2.0 * f / (1.0 + sqrt(sarg)));
             if (!(dist <= road)) continue;
-            if (bh < 0 || dist < bd || (dist == bd && M.h[m] < bh)) { bh = M.h[m]; bd = dist; }
+            if (bh < 0 || dist < bd || (dist == bd && hh < bh)) { bh = hh; bd = dist; }
           }
           hitL[L] = bh;
           if (bh >= 0) { ++n_in; ss += bd * bd; }
@@ -696,31 +829,6 @@ __global__ __launch_bounds__(256) void surv_count_kernel(AssocArgs A, int tiles)
   }
 }
 
-__global__ __launch_bounds__(1024) void scan_kernel(const int32_t* __restrict__ cnt,
-                                                    int32_t* __restrict__ off, int n,
-                                                    int32_t* __restrict__ total) {
-  __shared__ long long part[1024];
-  const int t = threadIdx.x;
-  const int per = (n + 1023) / 1024;
-  const int b = t * per, e = min(n, b + per);
-  long long s = 0;
-  for (int x = b; x < e; ++x) s += cnt[x];
-  part[t] = s;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    long long v = t >= d ? part[t - d] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  long long run = part[t] - s;
-  for (int x = b; x < e; ++x) {
-    off[x] = run > 0x7fffffffLL ? 0x7fffffff : (int32_t)run;
-    run += cnt[x];
-  }
-  if (t == 1023) *total = part[t] > 0x7fffffffLL ? 0x7fffffff : (int32_t)part[t];
-}
-
 __global__ __launch_bounds__(256) void surv_emit_kernel(AssocArgs A, int tiles) {
   __shared__ int32_t wc[4];
   const int np = n_cands(A);
@@ -772,9 +880,23 @@ __device__ __forceinline__ double wrap_pi(double a) {
   return a - 2.0 * kPi * floor((a + kPi) / (2.0 * kPi));
 }
 
-__global__ void fit_kernel(AssocArgs A) {
+// wave sum, then lane 0's value everywhere (the butterfly rounds differently
+// on each lane; the solve below must see one value so control stays uniform)
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return __shfl(v, 0);
+}
+
+// One wave per track, lane = layer: each lane forms its hit's residual and
+// Jacobian row, the normal equations are summed across the wave and every
+// lane solves the same (at most 3x3) system by Cholesky.  Fixed parameters
+// (one bin in q/pT or d0) get a zero Jacobian column and a unit diagonal, so
+// their step is exactly zero.
+__global__ __launch_bounds__(256) void fit_kernel(AssocArgs A) {
+  const int lane = threadIdx.x & 63;
   const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntrk; t += gridDim.x * blockDim.x) {
+  const bool fk = A.n_qpt > 1, fd = A.n_d0 > 1;
+  for (int t = blockIdx.x * 4 + (threadIdx.x >> 6); t < ntrk; t += gridDim.x * 4) {
     ht_track& tr = A.out.tracks[t];
     const int p = A.trk_peak[t];
     const double* g = A.cgeo + (size_t)p * 5;
@@ -782,94 +904,89 @@ __global__ void fit_kernel(AssocArgs A) {
     const int lin = tr.lin;
     const int i = lin % A.n_phi, col = lin / A.n_phi, j = col % A.n_qpt, k = col / A.n_qpt;
     const double cb = kCLight * A.bfield;
-    const double kap_c = -cb * (A.qpt_lo + ((double)j + 0.5) * (A.qpt_hi - A.qpt_lo) / (double)A.n_qpt);
+    const double kap_c =
+        -cb * (A.qpt_lo + ((double)j + 0.5) * (A.qpt_hi - A.qpt_lo) / (double)A.n_qpt);
     const double d0_c = A.d0_lo + ((double)k + 0.5) * (A.d0_hi - A.d0_lo) / (double)A.n_d0;
     const double sq0 = sqrt(gB * gB + gC * gC);
-    double p3[3];
-    p3[0] = atan2(gB, -gC);
-    p3[1] = A.n_qpt > 1 ? 2.0 * gA : kap_c;
-    p3[2] = A.n_d0 > 1 ? 2.0 * gD / (1.0 + sq0) : d0_c;
-    int idx[3], nfree = 0;
-    idx[nfree++] = 0;
-    if (A.n_qpt > 1) idx[nfree++] = 1;
-    if (A.n_d0 > 1) idx[nfree++] = 2;
+    double p0 = atan2(gB, -gC);
+    double p1 = fk ? 2.0 * gA : kap_c;
+    double p2 = fd ? 2.0 * gD / (1.0 + sq0) : d0_c;
+    const int h = lane < HT_MAX_LAYERS ? tr.hits[lane] : -1;
+    const double rr = h >= 0 ? (double)A.r[h] : 1.0;
+    const double ph = h >= 0 ? (double)A.phi[h] : 0.0;
     int status = 0;
     for (int it = 0; it < A.cfg.fit_iters && status == 0; ++it) {
-      double Am[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, gv[3] = {0, 0, 0};
-      for (int L = 0; L < HT_MAX_LAYERS; ++L) {
-        const int h = tr.hits[L];
-        if (h < 0) continue;
-        const double rr = (double)A.r[h], ph = (double)A.phi[h];
-        const double kap = p3[1], d0 = p3[2];
-        const double den = 1.0 + kap * d0;
-        const double u = (kap * (rr * rr + d0 * d0) + 2.0 * d0) / (2.0 * rr * den);
-        if (!(fabs(u) < 1.0)) { status = 1; break; }
-        const double sq = sqrt(1.0 - u * u);
-        const double res = wrap_pi(ph - (p3[0] + asin(u)));
-        double jac[3];
-        jac[0] = 1.0;
-        jac[1] = (rr * rr - d0 * d0) / (2.0 * rr * den * den) / sq;
-        jac[2] = (den * den + 1.0 - kap * kap * rr * rr) / (2.0 * rr * den * den) / sq;
-        const double w = rr * rr;
-        for (int a = 0; a < nfree; ++a) {
-          gv[a] += w * jac[idx[a]] * res;
-          for (int b = 0; b < nfree; ++b) Am[a][b] += w * jac[idx[a]] * jac[idx[b]];
+      double j0 = 0.0, j1 = 0.0, j2 = 0.0, res = 0.0, w = 0.0;
+      int bad = 0;
+      if (h >= 0) {
+        const double den = 1.0 + p1 * p2;
+        const double u = (p1 * (rr * rr + p2 * p2) + 2.0 * p2) / (2.0 * rr * den);
+        if (!(fabs(u) < 1.0)) {
+          bad = 1;
+        } else {
+          const double sq = sqrt(1.0 - u * u);
+          res = wrap_pi(ph - (p0 + asin(u)));
+          j0 = 1.0;
+          j1 = fk ? (rr * rr - p2 * p2) / (2.0 * rr * den * den) / sq : 0.0;
+          j2 = fd ? (den * den + 1.0 - p1 * p1 * rr * rr) / (2.0 * rr * den * den) / sq : 0.0;
+          w = rr * rr;
         }
       }
-      if (status) break;
-      double Lm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-      for (int a = 0; a < nfree && !status; ++a) {
-        for (int b = 0; b <= a; ++b) {
-          double s = Am[a][b];
-          for (int c = 0; c < b; ++c) s -= Lm[a][c] * Lm[b][c];
-          if (a == b) {
-            if (!(s > 0.0)) { status = 2; break; }
-            Lm[a][a] = sqrt(s);
-          } else {
-            Lm[a][b] = s / Lm[b][b];
-          }
-        }
-      }
-      if (status) break;
-      double y[3], d[3];
-      for (int a = 0; a < nfree; ++a) {
-        double s = gv[a];
-        for (int c = 0; c < a; ++c) s -= Lm[a][c] * y[c];
-        y[a] = s / Lm[a][a];
-      }
-      for (int a = nfree - 1; a >= 0; --a) {
-        double s = y[a];
-        for (int c = a + 1; c < nfree; ++c) s -= Lm[c][a] * d[c];
-        d[a] = s / Lm[a][a];
-      }
-      for (int a = 0; a < nfree; ++a) p3[idx[a]] += d[a];
+      if (__ballot(bad)) { status = 1; break; }
+      const double a00 = wave_sum_d(w * j0 * j0), a01 = wave_sum_d(w * j0 * j1);
+      const double a02 = wave_sum_d(w * j0 * j2), a11 = wave_sum_d(w * j1 * j1);
+      const double a12 = wave_sum_d(w * j1 * j2), a22 = wave_sum_d(w * j2 * j2);
+      const double g0 = wave_sum_d(w * j0 * res), g1 = wave_sum_d(w * j1 * res);
+      const double g2 = wave_sum_d(w * j2 * res);
+      // Cholesky of the 3x3 system with unit diagonal for fixed parameters
+      const double m11 = fk ? a11 : 1.0, m22 = fd ? a22 : 1.0;
+      if (!(a00 > 0.0)) { status = 2; break; }
+      const double l00 = sqrt(a00);
+      const double l10 = a01 / l00, l20 = a02 / l00;
+      const double d1 = m11 - l10 * l10;
+      if (!(d1 > 0.0)) { status = 2; break; }
+      const double l11 = sqrt(d1);
+      const double l21 = (a12 - l20 * l10) / l11;
+      const double d2 = m22 - l20 * l20 - l21 * l21;
+      if (!(d2 > 0.0)) { status = 2; break; }
+      const double l22 = sqrt(d2);
+      const double y0 = g0 / l00, y1 = (g1 - l10 * y0) / l11, y2 = (g2 - l20 * y0 - l21 * y1) / l22;
+      const double x2 = y2 / l22, x1 = (y1 - l21 * x2) / l11, x0 = (y0 - l10 * x1 - l20 * x2) / l00;
+      p0 += x0;
+      if (fk) p1 += x1;
+      if (fd) p2 += x2;
     }
     double chi2 = 0.0;
     if (status == 0) {
-      for (int L = 0; L < HT_MAX_LAYERS; ++L) {
-        const int h = tr.hits[L];
-        if (h < 0) continue;
-        const double rr = (double)A.r[h], ph = (double)A.phi[h];
-        const double kap = p3[1], d0 = p3[2];
-        const double den = 1.0 + kap * d0;
-        const double u = (kap * (rr * rr + d0 * d0) + 2.0 * d0) / (2.0 * rr * den);
-        if (!(fabs(u) < 1.0)) { status = 1; break; }
-        const double res = wrap_pi(ph - (p3[0] + asin(u)));
-        const double z = rr * res / (double)A.cfg.sigma_rphi;
-        chi2 += z * z;
+      double z2 = 0.0;
+      int bad = 0;
+      if (h >= 0) {
+        const double den = 1.0 + p1 * p2;
+        const double u = (p1 * (rr * rr + p2 * p2) + 2.0 * p2) / (2.0 * rr * den);
+        if (!(fabs(u) < 1.0)) {
+          bad = 1;
+        } else {
+          const double res = wrap_pi(ph - (p0 + asin(u)));
+          const double z = rr * res / (double)A.cfg.sigma_rphi;
+          z2 = z * z;
+        }
       }
+      if (__ballot(bad)) status = 1;
+      chi2 = wave_sum_d(z2);
     }
     if (status != 0) {
-      p3[0] = -kPi + ((double)i + 0.5) * (2.0 * kPi / (double)A.n_phi);
-      p3[1] = kap_c;
-      p3[2] = d0_c;
+      p0 = -kPi + ((double)i + 0.5) * (2.0 * kPi / (double)A.n_phi);
+      p1 = kap_c;
+      p2 = d0_c;
       chi2 = -1.0;
     }
-    tr.status = status;
-    tr.phi0 = (float)wrap_pi(p3[0]);
-    tr.qpt = (float)(-p3[1] / cb);
-    tr.d0 = (float)p3[2];
-    tr.chi2 = (float)chi2;
+    if (lane == 0) {
+      tr.status = status;
+      tr.phi0 = (float)wrap_pi(p0);
+      tr.qpt = (float)(-p1 / cb);
+      tr.d0 = (float)p2;
+      tr.chi2 = (float)chi2;
+    }
   }
 }
 
@@ -1132,7 +1249,9 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   A.pbits = P.d_pbits;
   A.col_first = P.d_col_first;
   A.mcount = P.d_mcount;
-  A.mem = reinterpret_cast<uint16_t*>(P.d_mem);
+  A.mcur = P.d_mcur;
+  A.moff = P.d_moff;
+  A.pool = reinterpret_cast<uint16_t*>(P.d_mem);
   A.cstat = P.d_cstat;
   A.cnl = P.d_cnl;
   A.cgeo = P.d_cgeo;
@@ -1158,24 +1277,26 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   dim3 sweep((g.n_qpt + kWave - 1) / kWave, g.n_d0);
   member_kernel<<<sweep, kSweepThreads, 0, s>>>(A);
   HT_CHECK(hipGetLastError());
+  const int rblocks = blocks_for(peak_cap, 1) > 16384 ? 16384 : blocks_for(peak_cap, 1);
   if (cfg.member_cap <= 256)
-    refine_kernel<256><<<blocks_for(peak_cap, kRefineWaves), kRefineWaves * kWave, 0, s>>>(A);
+    refine_kernel<256><<<rblocks, kWave, 0, s>>>(A);
+  else if (cfg.member_cap <= 512)
+    refine_kernel<512><<<rblocks, kWave, 0, s>>>(A);
   else
-    refine_kernel<kMaxMembers>
-        <<<blocks_for(peak_cap, kRefineWaves), kRefineWaves * kWave, 0, s>>>(A);
+    refine_kernel<kMaxMembers><<<rblocks, kWave, 0, s>>>(A);
   HT_CHECK(hipGetLastError());
   own_kernel<<<blocks_for(peak_cap, 256), 256, 0, s>>>(A);
   HT_CHECK(hipGetLastError());
   const int tiles = (peak_cap + 255) / 256 > 0 ? (peak_cap + 255) / 256 : 1;
   surv_count_kernel<<<blocks_for(tiles, 1), 256, 0, s>>>(A, tiles);
   HT_CHECK(hipGetLastError());
-  scan_kernel<<<1, 1024, 0, s>>>(P.d_ctile_cnt, P.d_ctile_off, tiles, P.d_scalars + S_NTRK);
-  HT_CHECK(hipGetLastError());
+  int rc = launch_scan(P.d_ctile_cnt, P.d_ctile_off, tiles, P.d_scalars + S_NTRK, s);
+  if (rc != HT_OK) return rc;
   surv_emit_kernel<<<blocks_for(tiles, 1), 256, 0, s>>>(A, tiles);
   HT_CHECK(hipGetLastError());
   const int tcap = out.track_cap > 0 ? out.track_cap : 1;
   if (out.track_cap > 0) {
-    fit_kernel<<<blocks_for(tcap, 64), 64, 0, s>>>(A);
+    fit_kernel<<<blocks_for(tcap, 4), 256, 0, s>>>(A);
     HT_CHECK(hipGetLastError());
     vvote_kernel<<<blocks_for(tcap, 64), 64, 0, s>>>(A);
     HT_CHECK(hipGetLastError());
@@ -1192,9 +1313,8 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   }
   // object member offsets, then members and isotropy
   const int oscan = ocap < P.lim.max_vertex_cells ? ocap : P.lim.max_vertex_cells;
-  scan_kernel<<<1, 1024, 0, s>>>(P.d_obj_cnt, P.d_obj_off, oscan > 0 ? oscan : 1,
-                                 P.d_scalars + S_NMEM);
-  HT_CHECK(hipGetLastError());
+  rc = launch_scan(P.d_obj_cnt, P.d_obj_off, oscan > 0 ? oscan : 1, P.d_scalars + S_NMEM, s);
+  if (rc != HT_OK) return rc;
   if (out.object_cap > 0) {
     vmembers_kernel<<<blocks_for(ocap, 4), 256, 0, s>>>(A, P.d_obj_off);
     HT_CHECK(hipGetLastError());

@@ -22,6 +22,26 @@ __device__ __forceinline__ bool hit_ok(float r, float phi) {
   return r > 0.0f && r < 1.0e4f && fabsf(phi) <= 4.0f;
 }
 
+// Correctly rounded square root for x = 0 or 2^-24 <= x <= 1 (the arguments
+// 1 - |u| of the arcsine and 1 - u*u of the member window never lie below
+// 2^-24 unless they are 0).  The
+// hardware v_sqrt_f32 is within one ulp; the neighbours s -/+ 1 ulp are
+// tested by the exact residuals x - s_dn*s and x - s_up*s (one fused
+// rounding each), which decide round-to-nearest because no float x lies
+// strictly between s_dn*s and the squared midpoint.  At x = 0 both tests
+// fail and 0 is returned.  (Inputs here are never denormal, so the general
+// expansion's rescaling and class checks are not needed.)
+__device__ __forceinline__ float sqrt_unit(float x) {
+  const float s = __builtin_amdgcn_sqrtf(x);
+  const float s_dn = __int_as_float(__float_as_int(s) - 1);
+  const float s_up = __int_as_float(__float_as_int(s) + 1);
+  const float r_dn = __builtin_fmaf(-s_dn, s, x);
+  const float r_up = __builtin_fmaf(-s_up, s, x);
+  float t = r_dn <= 0.0f ? s_dn : s;
+  t = r_up > 0.0f ? s_up : t;
+  return t;
+}
+
 // Canonical arcsine: Abramowitz & Stegun 4.4.46,
 //   asin a = pi/2 - sqrt(1 - a) (a0 + a1 a + ... + a7 a^7),  0 <= a <= 1,
 // Horner with separate multiply and add, correctly rounded square root,
@@ -36,7 +56,7 @@ __device__ __forceinline__ float asin_f(float u) {
   p = p * a; p = p + 0.0889789874f;
   p = p * a; p = p + -0.2145988016f;
   p = p * a; p = p + 1.5707963050f;
-  const float s = __builtin_sqrtf(1.0f - a);
+  const float s = sqrt_unit(1.0f - a);
   const float r = 1.57079632679489661923f - s * p;
   return copysignf(r, u);
 }
@@ -64,7 +84,9 @@ struct Plan {
   double* d_hy;
   double* d_hq;
   int32_t* d_mcount;     // [max_peaks] member counts
-  int32_t* d_mem;        // [max_peaks * max_member_cap / 2] member hit indices (uint16)
+  int32_t* d_mcur;       // [max_peaks] fill cursors (workgroups with many peaks)
+  int32_t* d_moff;       // [max_peaks] offset of each member list in the pool, -1 = overflow
+  int32_t* d_mem;        // member pool: uint16 hit indices, max_peaks * max_member_cap of them
   int32_t* d_cstat;      // [max_peaks] candidate status / inlier count
   double* d_cgeo;        // [max_peaks * 5] seed ss, A, B, C, D
   int32_t* d_chit;       // [max_peaks * HT_MAX_LAYERS] inlier hit per layer
@@ -95,6 +117,7 @@ int launch_assoc(const Plan& p, const float* r, const float* phi, const uint8_t*
                  int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks, int32_t peak_cap,
                  const ht_cluster_cfg& cfg, const ht_cluster_out& out, hipStream_t s);
 int launch_asin(const float* u, float* out, int64_t n, hipStream_t s);
+int launch_scan(const int32_t* cnt, int32_t* off, int n, int32_t* total, hipStream_t s);
 int vote_init(int n_phi);
 }  // namespace ht
 

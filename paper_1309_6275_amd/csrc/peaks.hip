@@ -78,38 +78,6 @@ __global__ __launch_bounds__(kTile) void flag_kernel(const int32_t* __restrict__
   }
 }
 
-// Exclusive scan of n int32 counts by one workgroup of 1024 threads; the
-// total goes to *total (clamped to INT32_MAX).
-constexpr int kScanThreads = 1024;
-__global__ __launch_bounds__(kScanThreads) void scan_kernel(const int32_t* __restrict__ cnt,
-                                                            int32_t* __restrict__ off, int n,
-                                                            int32_t* __restrict__ total) {
-  __shared__ long long part[kScanThreads];
-  const int t = threadIdx.x;
-  const int per = (n + kScanThreads - 1) / kScanThreads;
-  const int b = t * per, e = min(n, b + per);
-  long long s = 0;
-  for (int x = b; x < e; ++x) s += cnt[x];
-  part[t] = s;
-  __syncthreads();
-  // Hillis-Steele inclusive scan over the 1024 partial sums
-  for (int d = 1; d < kScanThreads; d <<= 1) {
-    long long v = t >= d ? part[t - d] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  long long run = part[t] - s;
-  for (int x = b; x < e; ++x) {
-    off[x] = run > 0x7fffffffLL ? 0x7fffffff : (int32_t)run;
-    run += cnt[x];
-  }
-  if (t == kScanThreads - 1 && total) {
-    const long long tot = part[t];
-    *total = tot > 0x7fffffffLL ? 0x7fffffff : (int32_t)tot;
-  }
-}
-
 __global__ __launch_bounds__(kTile) void emit_kernel(const int32_t* __restrict__ acc,
                                                      const uint32_t* __restrict__ bits,
                                                      const int32_t* __restrict__ tile_off,
@@ -147,8 +115,8 @@ int launch_peaks(const Plan& p, const int32_t* acc, int32_t min_votes, ht_peak* 
   flag_kernel<<<tiles, kTile, 0, s>>>(acc, g.n_phi, g.n_qpt, g.n_d0, p.n_cells, min_votes,
                                       p.d_bits, p.d_tile_cnt);
   HT_CHECK(hipGetLastError());
-  scan_kernel<<<1, kScanThreads, 0, s>>>(p.d_tile_cnt, p.d_tile_off, tiles, n_found);
-  HT_CHECK(hipGetLastError());
+  const int rc = launch_scan(p.d_tile_cnt, p.d_tile_off, tiles, n_found, s);
+  if (rc != HT_OK) return rc;
   if (capacity > 0) {
     emit_kernel<<<tiles, kTile, 0, s>>>(acc, p.d_bits, p.d_tile_off, p.n_cells, out, capacity);
     HT_CHECK(hipGetLastError());

@@ -4,10 +4,11 @@
 //
 // gfx950 mapping.  One workgroup owns a tile of 64 consecutive q/pT columns
 // at one d0 (lane = column), so a tile's accumulator rows are one contiguous
-// block of the output.  The tile's counters live in LDS as packed 16-bit
-// pairs (a column holds at most n_hits <= 65535 votes per bin, so a
-// ds_add_u32 of 1 or 1 << 16 never carries across the pair); the row stride
-// is odd in dwords so neighbouring columns fall in different banks.  Waves of
+// block of the output.  The tile's counters live in LDS: 32-bit counters
+// when 64 rows fit in the 160 KiB of a gfx950 CU (n_phi <= 639), otherwise
+// packed 16-bit pairs (a column holds at most n_hits <= 65535 votes per bin,
+// so a ds_add_u32 of 1 or 1 << 16 never carries across the pair).  The row
+// stride is odd in dwords so neighbouring columns fall in different banks.  Waves of
 // the workgroup split the hits: each wave loads 64 hits with one coalesced
 // load, keeps them in VGPRs and broadcasts them one at a time through SGPRs
 // (v_readlane), so the per-evaluation work is pure VALU with scalar hit
@@ -26,6 +27,7 @@ __device__ __forceinline__ float bcast(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+template <bool POW2, bool WIDE>
 __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
     const float* __restrict__ r, const float* __restrict__ phi, int n_hits,
     const float* __restrict__ kap, const float* __restrict__ qt, const float* __restrict__ tt,
@@ -77,11 +79,20 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
       const float phi0 = ph - s;
       const float d = phi0 - phi_lo;
       const float x = d * invw;
+      // x lies in [-n_phi, 2 n_phi) (|phi| <= 4, |asin| <= pi/2): one
+      // period of correction is enough; a power of two wraps with a mask
       int i = (int)floorf(x);
-      i = i < 0 ? i + n_phi : i;
-      i = i >= n_phi ? i - n_phi : i;
+      if (POW2) {
+        i &= n_phi - 1;
+      } else {
+        i = i < 0 ? i + n_phi : i;
+        i = i >= n_phi ? i - n_phi : i;
+      }
       if (ok) {
-        atomicAdd(&col[i >> 1], (i & 1) ? 65536u : 1u);
+        if (WIDE)
+          atomicAdd(&col[i], 1u);
+        else
+          atomicAdd(&col[i >> 1], (i & 1) ? 65536u : 1u);
         ++votes;
       }
     }
@@ -95,8 +106,12 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
   for (int e = threadIdx.x; e < total; e += kVoteThreads) {
     const int cj = e / n_phi;
     const int i = e - cj * n_phi;
-    const uint32_t w = lds[cj * stride + (i >> 1)];
-    out[e] = (int32_t)((i & 1) ? (w >> 16) : (w & 0xFFFFu));
+    if (WIDE) {
+      out[e] = (int32_t)lds[cj * stride + i];
+    } else {
+      const uint32_t w = lds[cj * stride + (i >> 1)];
+      out[e] = (int32_t)((i & 1) ? (w >> 16) : (w & 0xFFFFu));
+    }
   }
 
   if (n_votes) {
@@ -113,8 +128,10 @@ __global__ void asin_kernel(const float* __restrict__ u, float* __restrict__ out
 
 __global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
 
+constexpr int kLdsBytes = 160 * 1024;
+bool vote_wide(int n_phi) { return (size_t)kWave * (size_t)(n_phi | 1) * 4 <= (size_t)kLdsBytes; }
 int vote_stride(int n_phi) {
-  int words = (n_phi + 1) / 2;
+  const int words = vote_wide(n_phi) ? n_phi : (n_phi + 1) / 2;
   return words | 1;  // odd dword stride
 }
 
@@ -122,8 +139,11 @@ int vote_stride(int n_phi) {
 
 int vote_init(int n_phi) {
   const int bytes = kWave * vote_stride(n_phi) * 4;
-  HT_CHECK(hipFuncSetAttribute((const void*)vote_kernel,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
+  HT_CHECK(hipFuncSetAttribute((const void*)vote_kernel<true, true>, at, bytes));
+  HT_CHECK(hipFuncSetAttribute((const void*)vote_kernel<false, true>, at, bytes));
+  HT_CHECK(hipFuncSetAttribute((const void*)vote_kernel<true, false>, at, bytes));
+  HT_CHECK(hipFuncSetAttribute((const void*)vote_kernel<false, false>, at, bytes));
   return HT_OK;
 }
 
@@ -137,9 +157,12 @@ int launch_vote(const Plan& p, const float* r, const float* phi, int32_t n_hits,
     HT_CHECK(hipGetLastError());
   }
   dim3 grid((g.n_qpt + kWave - 1) / kWave, g.n_d0);
-  vote_kernel<<<grid, kVoteThreads, lds_bytes, s>>>(r, phi, n_hits, p.d_kap, p.d_q, p.d_t,
-                                                      g.n_phi, g.n_qpt, p.phi_lo, p.invw, stride,
-                                                      acc, n_votes);
+  const bool pow2 = (g.n_phi & (g.n_phi - 1)) == 0;
+  const bool wide = vote_wide(g.n_phi);
+  auto kern = pow2 ? (wide ? vote_kernel<true, true> : vote_kernel<true, false>)
+                   : (wide ? vote_kernel<false, true> : vote_kernel<false, false>);
+  kern<<<grid, kVoteThreads, lds_bytes, s>>>(r, phi, n_hits, p.d_kap, p.d_q, p.d_t, g.n_phi,
+                                             g.n_qpt, p.phi_lo, p.invw, stride, acc, n_votes);
   HT_CHECK(hipGetLastError());
   return HT_OK;
 }
