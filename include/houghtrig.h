@@ -124,7 +124,8 @@ typedef struct {
   int32_t* members;        /* [member_cap] member track indices, object by object */
   int32_t member_cap;
   int32_t* vacc;           /* [n_rho * n_theta] vertex accumulator, or NULL */
-  int32_t* counts;         /* [8]: candidates, tracks, objects, members, overflowed, 0,0,0 */
+  int32_t* counts;         /* [8]: candidates, tracks, objects, object members, candidates
+                              over member_cap, (candidate, member) pairs of the others, 0, 0 */
 } ht_cluster_out;
 
 typedef struct ht_plan ht_plan;
@@ -190,8 +191,11 @@ int hough_peaks(const ht_plan* plan, const int32_t* acc, int32_t min_votes, ht_p
  *              within one cell; black-hole-like when >= bh_min_tracks members
  *              and |mean perigee direction| <= bh_max_isotropy.
  *   r, phi, layer  [n_hits] hits (layer index increasing with radius)
- *   peaks, n_peaks peak list and device count from hough_peaks; entries
- *                  beyond min(*n_peaks, peak_cap) are ignored
+ *   peaks, n_peaks peak list and device count from hough_peaks (sorted by
+ *                  lin, no cell twice); entries beyond min(*n_peaks,
+ *                  peak_cap) are ignored; entries with lin outside the grid
+ *                  are no candidates; any other list gives unspecified
+ *                  results (memory accesses stay in bounds)
  *   out            outputs (device pointers) */
 int assoc_cluster(const ht_plan* plan, const float* r, const float* phi, const uint8_t* layer,
                   int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks,

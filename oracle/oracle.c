@@ -446,6 +446,7 @@ void oracle_sincos_array(const double* a, double* s, double* c, int64_t n) {
  * in a fixed order, so every decision is reproducible bit for bit. */
 typedef struct {
   int32_t n_layers, n_inliers, status; /* status 0 ok, 1 too few layers/inliers, 2 member overflow */
+  int32_t n_members;
   int32_t hit[OR_MAX_LAYERS];          /* inlier hit per layer */
   double ss;                           /* sum of squared inlier distances */
   double A, B, C, D;                   /* seed circle */
@@ -526,6 +527,7 @@ static void refine(const or_grid* g, const tables* tb, const window_t* wd, const
   float half_n = 0.5f * (float)np;
   float wbase = 0.5f + (float)cfg->win_bins;
   int nm = 0;
+  out->n_members = 0;
   out->status = 1;
   out->n_layers = 0;
   out->n_inliers = 0;
@@ -557,12 +559,13 @@ static void refine(const or_grid* g, const tables* tb, const window_t* wd, const
     float w = wbase + e7;
     float adx = fabsf(dx);
     if (!(adx <= w)) continue;
-    if (nm >= cfg->member_cap) { out->status = 2; return; }
+    if (nm >= cfg->member_cap) { out->status = 2; out->n_members = 0; return; }
     mem[nm].h = h;
     mem[nm].layer = L;
     mem[nm].adx = adx;
     ++nm;
   }
+  out->n_members = nm;
   /* member layers */
   int cntL[OR_MAX_LAYERS] = {0};
   for (int m = 0; m < nm; ++m) cntL[mem[m].layer]++;
@@ -872,7 +875,9 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
   int32_t* owner = (int32_t*)malloc(sizeof(int32_t) * nh1);
   for (int32_t h = 0; h < n_hits; ++h) owner[h] = -1;
   int32_t n_cand = 0, n_over = 0;
+  int64_t n_pairs = 0;
   for (int32_t p = 0; p < n_peaks; ++p) {
+    n_pairs += cd[p].n_members;
     if (cd[p].status == 2) ++n_over;
     if (cd[p].status != 0) continue;
     ++n_cand;
@@ -1012,6 +1017,7 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
   counts[2] = n_obj;
   counts[3] = (int32_t)n_mem;
   counts[4] = n_over;
+  counts[5] = (int32_t)(n_pairs > 0x7fffffff ? 0x7fffffff : n_pairs);
 
   free(cd);
   free(owner);

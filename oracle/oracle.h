@@ -105,7 +105,8 @@ int oracle_refine_one(const or_grid* g, const float* r, const float* phi, const 
 
 /* counts[0] candidates (seed with >= min_layers inlier layers), counts[1]
  * surviving tracks, counts[2] vertex objects, counts[3] object members,
- * counts[4] candidates dropped for exceeding member_cap.  vacc (may be NULL)
+ * counts[4] candidates dropped for exceeding member_cap, counts[5] (candidate,
+ * member) pairs of the other candidates.  vacc (may be NULL)
  * receives the vertex accumulator [n_rho][n_theta]. */
 int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
                          const uint8_t* layer, int32_t n_hits, const or_peak* peaks,

@@ -32,7 +32,7 @@ CLUSTER_2D = dict(win_bins=1, min_layers=8, seed_k=4, member_cap=256, road_sigma
                   box_margin=16.0, sigma_rphi=20e-4, fit_iters=3, n_rho=64, n_theta=256,
                   rho_lo=4.0, rho_hi=68.0, vtx_min_votes=5, bh_min_tracks=20,
                   bh_max_isotropy=0.75)
-CLUSTER_3D = dict(CLUSTER_2D, min_layers=7, member_cap=512)
+CLUSTER_3D = dict(CLUSTER_2D, min_layers=7, member_cap=128)
 # ~55k hits: about 700 hits fall in a cell's member window
 CLUSTER_3D_DENSE = dict(CLUSTER_3D, member_cap=1024)
 

@@ -52,7 +52,7 @@ int dalloc(T** p, size_t n) {
 void free_plan(Plan* p) {
   void* ptrs[] = {p->d_kap,       p->d_q,         p->d_t,        p->d_bits,      p->d_tile_cnt,
                   p->d_tile_off,  p->d_pbits,     p->d_col_first, p->d_hx,       p->d_hy,
-                  p->d_hq,        p->d_mcount,    p->d_mcur,      p->d_moff,    p->d_mem,      p->d_cstat,
+                  p->d_hq,        p->d_hitA,      p->d_hitB,      p->d_mcount,    p->d_mem,      p->d_cstat,
                   p->d_cgeo,      p->d_chit,      p->d_cnl,      p->d_owner_key, p->d_ctile_cnt,
                   p->d_ctile_off, p->d_trk_peak,  p->d_arc0,     p->d_arcn,      p->d_vacc,
                   p->d_obj_cnt,   p->d_obj_off,   p->d_scalars};
@@ -129,9 +129,9 @@ int ht_plan_create(const ht_grid* grid, const ht_limits* lim, ht_plan** out) {
   if (rc == HT_OK) rc = dalloc(&p->d_hx, nh);
   if (rc == HT_OK) rc = dalloc(&p->d_hy, nh);
   if (rc == HT_OK) rc = dalloc(&p->d_hq, nh);
+  if (rc == HT_OK) rc = dalloc(&p->d_hitA, nh);
+  if (rc == HT_OK) rc = dalloc(&p->d_hitB, nh);
   if (rc == HT_OK) rc = dalloc(&p->d_mcount, np);
-  if (rc == HT_OK) rc = dalloc(&p->d_mcur, np);
-  if (rc == HT_OK) rc = dalloc(&p->d_moff, np);
   if (rc == HT_OK) rc = dalloc(&p->d_mem, (np * (size_t)lim->max_member_cap + 1) / 2);
   if (rc == HT_OK) rc = dalloc(&p->d_cstat, np);
   if (rc == HT_OK) rc = dalloc(&p->d_cgeo, np * 5);
@@ -153,6 +153,7 @@ int ht_plan_create(const ht_grid* grid, const ht_limits* lim, ht_plan** out) {
        hipMemcpy(p->d_t, ht_, sizeof(float) * ncol, hipMemcpyHostToDevice) != hipSuccess))
     rc = HT_EDEVICE;
   if (rc == HT_OK) rc = ht::vote_init(g.n_phi);
+  if (rc == HT_OK) rc = ht::peaks_init(g.n_phi);
   delete[] hk;
   delete[] hq;
   delete[] ht_;

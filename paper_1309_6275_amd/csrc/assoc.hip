@@ -40,7 +40,8 @@ constexpr int kSweepThreads = kSweepWaves * kWave;
 constexpr int kMaxMembers = 1024; // largest member_cap (LDS slots per wave in refine)
 constexpr int kGridCap = 8192;    // grid-stride launches use at most this many blocks
 
-enum { S_NP = 0, S_NCAND = 1, S_NOVER = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5, S_POOL = 6 };
+// S_PAIRS is a 64-bit counter over slots 6 and 7 (8-byte aligned)
+enum { S_NP = 0, S_NCAND = 1, S_NOVER = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5, S_PAIRS = 6 };
 
 __device__ __forceinline__ float bcastf(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -230,6 +231,8 @@ struct AssocArgs {
   double* hx;
   double* hy;
   double* hq;
+  float4* hitA;  // r, phi, r*r, 1/r
+  float4* hitB;  // x, y, x^2+y^2 (float32), layer
   // peaks
   const ht_peak* peaks;
   const int32_t* n_peaks;
@@ -240,8 +243,6 @@ struct AssocArgs {
   uint32_t* pbits;
   int32_t* col_first;
   int32_t* mcount;
-  int32_t* mcur;
-  int32_t* moff;
   uint16_t* pool;
   int32_t* cstat;
   int32_t* cnl;
@@ -281,9 +282,12 @@ __global__ void init_kernel(AssocArgs A, int words) {
     const double rr = (double)r;
     const double x = rr * c;
     const double y = rr * s;
+    const double q = x * x + y * y;
     A.hx[h] = x;
     A.hy[h] = y;
-    A.hq[h] = x * x + y * y;
+    A.hq[h] = q;
+    A.hitA[h] = make_float4(r, ph, r * r, 1.0f / r);
+    A.hitB[h] = make_float4((float)x, (float)y, (float)q, (float)A.layer[h]);
     A.owner_key[h] = 0ull;
     A.out.hit_owner[h] = -1;
   }
@@ -312,10 +316,9 @@ __global__ void mark_kernel(AssocArgs A) {
 // LDS per column: the column's peak bits (starting at bit i = 0) and the
 // number of peaks before each 32-bit word.  The workgroup owns the peaks of
 // its 64 columns, which are consecutive in the (cell-ordered) peak list, so
-// it can count their members in LDS, give each candidate a compact slice of
-// one global pool, and fill the slices in a second sweep: the member lists of
-// a workgroup then occupy one contiguous region instead of member_cap-strided
-// slots, and no global atomic is needed per member.
+// it counts their members with LDS atomics and writes each member straight
+// into its candidate's member_cap slots of the pool: one sweep, and the
+// workgroup's member lists form one contiguous region of the pool.
 constexpr int kMaxPhiWords = 32;  // n_phi <= 1024
 constexpr int kMaxWgPeaks = 8192; // LDS counters; more peaks fall back to global counters
 
@@ -323,10 +326,8 @@ struct SweepShared {
   uint32_t cbits[kWave][kMaxPhiWords + 1];
   int32_t cpre[kWave][kMaxPhiWords + 1];
   int32_t ccnt[kWave];
-  int32_t cnt[kMaxWgPeaks];   // member counts, then fill cursors
-  int32_t off[kMaxWgPeaks];   // slice offsets within the workgroup region, -1 = overflow
-  int32_t wsum[kSweepWaves];
-  int32_t any, np_wg, p_lo, base;
+  int32_t cnt[kMaxWgPeaks];   // member counts = next free slot of each candidate
+  int32_t np_wg, p_lo;
 };
 
 // One pass over the workgroup's (hit, column) pairs; for every member
@@ -351,6 +352,7 @@ __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S
   }
   const float wbase = 0.5f + (float)A.cfg.win_bins;
   const int np_wg = S.np_wg;
+  const bool fast_bits = (n_phi & 31) == 0;
   for (int base = wave * kWave; base < A.n_hits; base += kSweepThreads) {
     const int h = base + lane;
     float hr = 1.0f, hp = 0.0f;
@@ -385,11 +387,38 @@ __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S
         const int hi = (int)floorf(x + w_hi - 0.5f) + 1;
         if (hi - lo + 1 < n_phi) { ilo = lo; ihi = hi; }
       }
+      const int len = ihi - ilo + 1;
+      if (fast_bits && len <= 32) {
+        // common case: the range fits in 64 bits starting at ilo's word
+        // (n_phi is a multiple of 32, so the column bits are cyclic by word)
+        const int iw0 = ilo < 0 ? ilo + n_phi : (ilo >= n_phi ? ilo - n_phi : ilo);
+        const int w0 = iw0 >> 5;
+        const int w1 = w0 + 1 == nwords ? 0 : w0 + 1;
+        const uint64_t two = (uint64_t)S.cbits[lane][w0] | ((uint64_t)S.cbits[lane][w1] << 32);
+        uint64_t bits = (two >> (iw0 & 31)) & ((1ull << len) - 1ull);
+        if (!bits) continue;
+        const float w = member_window(e5, u, wbase);
+        while (bits) {
+          const int b = __builtin_ctzll(bits);
+          bits &= bits - 1ull;
+          int ic = iw0 + b;
+          if (ic >= n_phi) ic -= n_phi;
+          const float adx = cell_adx(x, ic, n_phi);
+          if (!(adx <= w)) continue;
+          const int wi = ic >> 5;
+          const uint32_t below = S.cbits[lane][wi] & ((1u << (ic & 31)) - 1u);
+          const int q = cfirst + S.cpre[lane][wi] + __popc(below);
+          if (q < 0 || q >= np_wg) continue;  // only for peak lists not sorted by cell
+          fn(q, hh);
+        }
+        continue;
+      }
       float w = -1.0f;
       int i = ilo;
       while (i <= ihi) {
-        // i lies in (-n_phi, 2 n_phi): one period of correction
-        const int iw = i < 0 ? i + n_phi : (i >= n_phi ? i - n_phi : i);
+        // i lies in (-n_phi, 2 n_phi) for n_phi >= 14; smaller grids take the modulo
+        int iw = i < 0 ? i + n_phi : (i >= n_phi ? i - n_phi : i);
+        if (iw < 0 || iw >= n_phi) iw = ((i % n_phi) + n_phi) % n_phi;
         const int wi = iw >> 5, bit = iw & 31;
         int span = 32 - bit;
         span = min(span, ihi - i + 1);
@@ -414,30 +443,17 @@ __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S
   }
 }
 
-__device__ __forceinline__ int wg_scan_excl(int v, int32_t* wsum, int* total) {
-  // exclusive scan across the workgroup (kSweepThreads), returns v's offset
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x >> 6;
-  int incl = v;
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int o = __shfl_up(incl, d);
-    if (lane >= d) incl += o;
-  }
-  if (lane == kWave - 1) wsum[wave] = incl;
-  __syncthreads();
-  int before = 0, tot = 0;
-  for (int w = 0; w < kSweepWaves; ++w) {
-    if (w < wave) before += wsum[w];
-    tot += wsum[w];
-  }
-  __syncthreads();
-  *total = tot;
-  return before + incl - v;
+// adds the (candidate, member) pairs of the wave's candidates within
+// member_cap (each <= member_cap) to the 64-bit device total
+__device__ __forceinline__ void wg_add_pairs(const AssocArgs& A, int pairs) {
+  unsigned long long v = (unsigned long long)pairs;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & (kWave - 1)) == 0 && v)
+    atomicAdd(reinterpret_cast<unsigned long long*>(A.sc + S_PAIRS), v);
 }
 
 __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
   __shared__ SweepShared S;
-  const int lane = threadIdx.x & (kWave - 1);
   const int j0 = blockIdx.x * kWave;
   const int k = blockIdx.y;
   const int n_phi = A.n_phi;
@@ -468,7 +484,7 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
       s += __popc(S.cbits[threadIdx.x][w]);
     }
     S.ccnt[threadIdx.x] = s;
-    // first column with peaks gives the workgroup's first peak index
+    // the first column with peaks gives the workgroup's first peak index
     const uint64_t hasm = __ballot(s > 0);
     int tot = s;
     for (int d = 32; d > 0; d >>= 1) tot += __shfl_xor(tot, d);
@@ -487,80 +503,73 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
   // a cell-ordered peak list gives p_lo + np_wg <= n_peaks; anything else is
   // a malformed list, whose candidates in these columns then get no members
   if (np_wg == 0 || p_lo < 0 || p_lo + np_wg > n_cands(A)) return;
-  const bool in_lds = np_wg <= kMaxWgPeaks;
-  int32_t* cnt = in_lds ? S.cnt : A.mcur + p_lo;    // counts, zeroed
-  for (int q = threadIdx.x; q < np_wg; q += kSweepThreads) {
-    if (in_lds) S.cnt[q] = 0;
-    else A.mcur[p_lo + q] = 0;
-  }
-  __syncthreads();
-  // pass 1: count members
-  sweep_members(A, S, k, j0, [&](int q, int) { atomicAdd(&cnt[q], 1); });
-  __syncthreads();
-  // slices: overflowed candidates (count > cap) get none
-  int run = 0;
-  for (int q0 = 0; q0 < np_wg; q0 += kSweepThreads) {
-    const int q = q0 + threadIdx.x;
-    const int c = q < np_wg ? cnt[q] : 0;
-    const int sz = c <= cap ? c : 0;
-    int tot = 0;
-    const int ex = wg_scan_excl(sz, S.wsum, &tot);
-    if (q < np_wg) {
-      A.mcount[p_lo + q] = c;
-      const int o = c <= cap ? run + ex : -1;
-      if (in_lds) S.off[q] = o;
-      else A.moff[p_lo + q] = o;
-    }
-    run += tot;
-  }
-  if (threadIdx.x == 0) S.base = atomicAdd(&A.sc[S_POOL], run);
-  __syncthreads();
-  const int base = S.base;
-  for (int q = threadIdx.x; q < np_wg; q += kSweepThreads) {
-    if (in_lds) {
-      const int o = S.off[q];
-      A.moff[p_lo + q] = o >= 0 ? base + o : -1;
-      S.cnt[q] = 0;
-    } else {
-      const int o = A.moff[p_lo + q];
-      A.moff[p_lo + q] = o >= 0 ? base + o : -1;
-      A.mcur[p_lo + q] = 0;
-    }
-  }
-  __syncthreads();
-  // pass 2: fill the slices
-  if (in_lds) {
+  uint16_t* pool = A.pool + (size_t)p_lo * cap;
+  if (np_wg <= kMaxWgPeaks) {
+    for (int q = threadIdx.x; q < np_wg; q += kSweepThreads) S.cnt[q] = 0;
+    __syncthreads();
     sweep_members(A, S, k, j0, [&](int q, int hh) {
-      const int o = S.off[q];
-      if (o < 0) return;
       const int slot = atomicAdd(&S.cnt[q], 1);
-      A.pool[(size_t)base + o + slot] = (uint16_t)hh;
+      if (slot < cap) pool[(size_t)q * cap + slot] = (uint16_t)hh;
     });
+    __syncthreads();
+    int pairs = 0;
+    for (int q = threadIdx.x; q < np_wg; q += kSweepThreads) {
+      const int c = S.cnt[q];
+      A.mcount[p_lo + q] = c;
+      pairs += c <= cap ? c : 0;
+    }
+    wg_add_pairs(A, pairs);
   } else {
+    // counters in global memory (zeroed by mark_kernel)
+    int32_t* cnt = A.mcount + p_lo;
     sweep_members(A, S, k, j0, [&](int q, int hh) {
-      const int o = A.moff[p_lo + q];
-      if (o < 0) return;
-      const int slot = atomicAdd(&A.mcur[p_lo + q], 1);
-      A.pool[(size_t)o + slot] = (uint16_t)hh;
+      const int slot = atomicAdd(&cnt[q], 1);
+      if (slot < cap) pool[(size_t)q * cap + slot] = (uint16_t)hh;
     });
+    __syncthreads();
+    int pairs = 0;
+    for (int q = threadIdx.x; q < np_wg; q += kSweepThreads) {
+      const int c = atomicAdd(&cnt[q], 0);  // read back at the device scope
+      pairs += c <= cap ? c : 0;
+    }
+    wg_add_pairs(A, pairs);
   }
-  (void)lane;
 }
 
 // ---- refine: one wave per candidate ------------------------------------------
-// Members in LDS as float32 coordinates for a conservative pre-filter; the
-// float64 coordinates of the few members that pass are read from global
-// memory (the hit arrays stay in L2).
+// Members are grouped by layer in LDS as (x, y, x^2+y^2) in float32 plus the
+// hit index, one 16-byte record each, for a conservative float32 pre-filter;
+// the float64 coordinates of the seeds and of the few members that pass are
+// read from global memory (the hit arrays stay in L2).  Lanes are seed
+// combinations.  They visit the layers that are not seed layers first, so a
+// combination that can no longer reach min_layers inlier layers drops out
+// early, and the wave leaves the candidate as soon as every lane has dropped
+// out.  The seed sum of squares is a float64 sum over layers in increasing
+// layer order; the lanes that tie for the most inlier layers recompute it in
+// that order at the end.
+struct alignas(16) Mem4 {
+  float x, y, q;
+  int32_t h;
+};
+
+template <int CAP>
+struct RawMembers {  // members in pool order, before grouping
+  Mem4 mem[CAP];
+  float adx[CAP];
+  int16_t slot[CAP];
+  int8_t L[CAP];
+};
+
 template <int CAP>
 struct WaveMem {
-  float xf[CAP];
-  float yf[CAP];
-  float qf[CAP];
-  int32_t h[CAP];
-  float adx[CAP];
-  int16_t order[CAP];  // members grouped by layer
-  int8_t L[CAP];
+  Mem4 mem[CAP];   // grouped by layer
+  float adx[CAP];  // |x - cell centre| of the grouped members
+  union {
+    RawMembers<CAP> raw;
+    int32_t hit[kWave][HT_MAX_LAYERS + 1];  // each lane's inlier per layer
+  } u;
   int32_t lstart[HT_MAX_LAYERS + 1];
+  int32_t lcnt[HT_MAX_LAYERS + 1];
   int32_t seed[3][4];
 };
 
@@ -595,7 +604,6 @@ template <int CAP>
 __global__ __launch_bounds__(kWave) void refine_kernel(AssocArgs A) {
   __shared__ WaveMem<CAP> M;
   const int lane = threadIdx.x;
-  const uint64_t lt_mask = (1ull << lane) - 1ull;
   const int np = n_cands(A);
   const ht_cluster_cfg& cfg = A.cfg;
   const int cap = cfg.member_cap;
@@ -616,47 +624,61 @@ __global__ __launch_bounds__(kWave) void refine_kernel(AssocArgs A) {
     const int j = col % A.n_qpt;
     const int k = col / A.n_qpt;
     const float ck = A.kap[j], cq = A.qt[col], ct = A.tt[col];
-    const int moff = A.moff[p];
-    // load members
+    const size_t moff = (size_t)p * cap;
+    // load members in pool order
     unsigned lmask = 0;
+    float qmax = 0.0f;
     for (int m = lane; m < n; m += kWave) {
-      const int h = A.pool[(size_t)moff + m];
-      const int L = A.layer[h];
-      const float r = A.r[h];
+      const int h = A.pool[moff + m];
+      const float4 ha = A.hitA[h];
+      const float4 hb = A.hitB[h];
+      const int L = (int)hb.w;
       float x = 0.0f, u;
-      phi0_coord(r * r, 1.0f / r, A.phi[h], ck, cq, ct, A.phi_lo, A.invw, &x, &u);
-      M.h[m] = h;
-      M.L[m] = (int8_t)L;
-      M.adx[m] = cell_adx(x, i, A.n_phi);
-      M.xf[m] = (float)A.hx[h];
-      M.yf[m] = (float)A.hy[h];
-      M.qf[m] = (float)A.hq[h];
+      phi0_coord(ha.z, ha.w, ha.y, ck, cq, ct, A.phi_lo, A.invw, &x, &u);
+      Mem4 rec;
+      rec.x = hb.x;
+      rec.y = hb.y;
+      rec.q = hb.z;
+      rec.h = h;
+      M.u.raw.mem[m] = rec;
+      M.u.raw.adx[m] = cell_adx(x, i, A.n_phi);
+      M.u.raw.L[m] = (int8_t)L;
       lmask |= 1u << L;
+      qmax = fmaxf(qmax, hb.z);
     }
-    lmask = wave_or(lmask);
+    lmask = __builtin_amdgcn_readfirstlane(wave_or(lmask));
+    for (int off = 32; off > 0; off >>= 1) qmax = fmaxf(qmax, __shfl_xor(qmax, off));
+    const float rmax = __builtin_sqrtf(qmax) * 1.0001f;
     const int nS = __popc(lmask);
     if (nS < cfg.min_layers || nS < 3) {
       if (lane == 0) { A.cstat[p] = -1; A.cnl[p] = nS; }
       __syncthreads();
       continue;
     }
-    __syncthreads();
-    // group members by layer: ballot + popcount scatter (order within a
+    // group members by layer: counting sort with LDS atomics (order within a
     // layer does not matter, every selection breaks ties on the hit index)
+    if (lane <= HT_MAX_LAYERS) M.lcnt[lane] = 0;
+    __syncthreads();
+    for (int m = lane; m < n; m += kWave)
+      M.u.raw.slot[m] = (int16_t)atomicAdd(&M.lcnt[M.u.raw.L[m]], 1);
+    __syncthreads();
+    // layer starts: exclusive scan over lanes 0..16 (lane 16 holds n)
+    int ls;
     {
-      int base = 0;
-      for (int L = 0; L < HT_MAX_LAYERS; ++L) {
-        if (lane == 0) M.lstart[L] = base;
-        if (!((lmask >> L) & 1u)) continue;
-        for (int m0 = 0; m0 < n; m0 += kWave) {
-          const int m = m0 + lane;
-          const bool pr = m < n && M.L[m] == L;
-          const uint64_t b = __ballot(pr);
-          if (pr) M.order[base + __popcll(b & lt_mask)] = (int16_t)m;
-          base += __popcll(b);
-        }
+      const int c = lane < HT_MAX_LAYERS ? M.lcnt[lane] : 0;
+      int incl = c;
+      for (int d = 1; d <= HT_MAX_LAYERS; d <<= 1) {
+        const int t = __shfl_up(incl, d);
+        if (lane >= d) incl += t;
       }
-      if (lane == 0) M.lstart[HT_MAX_LAYERS] = base;
+      ls = incl - c;
+      if (lane <= HT_MAX_LAYERS) M.lstart[lane] = ls;
+    }
+    __syncthreads();
+    for (int m = lane; m < n; m += kWave) {
+      const int e = M.lstart[M.u.raw.L[m]] + M.u.raw.slot[m];
+      M.mem[e] = M.u.raw.mem[m];
+      M.adx[e] = M.u.raw.adx[m];
     }
     __syncthreads();
     // seed layers: innermost, middle and outermost of the outer min(nS, min_layers)
@@ -668,40 +690,40 @@ __global__ __launch_bounds__(kWave) void refine_kernel(AssocArgs A) {
     int ns[3];
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-      const int st = M.lstart[Ls[s]], en = M.lstart[Ls[s] + 1];
+      const int st = __builtin_amdgcn_readlane(ls, Ls[s]);
+      const int en = __builtin_amdgcn_readlane(ls, Ls[s] + 1);
       ns[s] = en - st < kk ? en - st : kk;
       for (int e = st + lane; e < en; e += kWave) {
-        const int m = M.order[e];
         const unsigned long long key =
-            ((unsigned long long)__float_as_uint(M.adx[m]) << 32) | (unsigned)M.h[m];
+            ((unsigned long long)__float_as_uint(M.adx[e]) << 32) | (unsigned)M.mem[e].h;
         int rank = 0;
         for (int e2 = st; e2 < en; ++e2) {
-          const int m2 = M.order[e2];
           const unsigned long long k2 =
-              ((unsigned long long)__float_as_uint(M.adx[m2]) << 32) | (unsigned)M.h[m2];
+              ((unsigned long long)__float_as_uint(M.adx[e2]) << 32) | (unsigned)M.mem[e2].h;
           rank += k2 < key;
         }
-        if (rank < kk) M.seed[s][rank] = m;
+        if (rank < kk) M.seed[s][rank] = e;
       }
     }
+    // the grouped raw records are dead from here on; the union holds the
+    // per-lane inlier rows
+    int32_t* hitL = M.u.hit[lane];
+    for (int L = 0; L < HT_MAX_LAYERS; ++L) hitL[L] = -1;
     __syncthreads();
     if (A.origin_seed) ns[0] = 1;
     const int nc = ns[0] * ns[1] * ns[2];
     // one combination per lane
-    int n_in = -1;
-    double ss = 0.0;
     double cA = 0.0, cB = 0.0, cC = 0.0, cD = 0.0;
-    int hitL[HT_MAX_LAYERS];
-#pragma unroll
-    for (int L = 0; L < HT_MAX_LAYERS; ++L) hitL[L] = -1;
+    bool ok = false;
     if (lane < nc) {
       const int a = lane / (ns[1] * ns[2]);
       const int b = (lane / ns[2]) % ns[1];
       const int c = lane % ns[2];
-      const int ha = M.h[M.seed[0][a]], hb = M.h[M.seed[1][b]], hc = M.h[M.seed[2][c]];
+      const int ha = M.mem[M.seed[0][a]].h, hb = M.mem[M.seed[1][b]].h;
+      const int hc = M.mem[M.seed[2][c]].h;
       double xa = 0.0, ya = 0.0;
       if (!A.origin_seed) { xa = A.hx[ha]; ya = A.hy[ha]; }
-      bool ok = circle3(xa, ya, A.hx[hb], A.hy[hb], A.hx[hc], A.hy[hc], &cA, &cB, &cC, &cD);
+      ok = circle3(xa, ya, A.hx[hb], A.hy[hb], A.hx[hc], A.hy[hc], &cA, &cB, &cC, &cD);
       if (ok) {
         const double kapc = -(kCLight * A.bfield) *
                             (A.qpt_lo + ((double)j + 0.5) * (A.qpt_hi - A.qpt_lo) / (double)A.n_qpt);
@@ -714,43 +736,56 @@ __global__ __launch_bounds__(kWave) void refine_kernel(AssocArgs A) {
         const double d0 = 2.0 * cD / (1.0 + sq);
         ok = (fabs(kap - kapc) <= ktol) && (fabs(d0 - d0c) <= dtol);
       }
-      if (ok) {
-        // |dist| >= |f| / (1 + |A||f|): a member with |f| > road / (1 -
-        // road |A|) cannot be within the road.  The test runs in float32
-        // with a margin of 1e-6 of the sum of the terms' magnitudes, far
-        // above float32 rounding of f (< 4e-7 of it), so it never drops a
-        // member the float64 test would keep.
-        const double ra = road * fabs(cA);
-        const float pre = ra < 0.5 ? (float)(road / (1.0 - ra) * 1.000001) : __builtin_inff();
-        const float Af = (float)cA, Bf = (float)cB, Cf = (float)cC, Df = (float)cD;
-        const float aA = fabsf(Af), aB = fabsf(Bf), aC = fabsf(Cf), aD = fabsf(Df);
-        n_in = 0;
-        int remaining = nS;
-#pragma unroll
-        for (int L = 0; L < HT_MAX_LAYERS; ++L) {
-          if (!((lmask >> L) & 1u)) continue;
-          --remaining;
-          if (n_in + remaining + 1 < cfg.min_layers) { n_in = -2; break; }
-          double bd = 0.0;
-          int bh = -1;
-          const int en = M.lstart[L + 1];
-          for (int e = M.lstart[L]; e < en; ++e) {
-            const int m = M.order[e];
-            const float xf = M.xf[m], yf = M.yf[m], qf = M.qf[m];
-            const float f32 = Af * qf + Bf * xf + Cf * yf + Df;
-            const float mag = aA * qf + aB * fabsf(xf) + aC * fabsf(yf) + aD;
-            if (!(fabsf(f32) <= pre + mag * 1e-6f)) continue;
-            const int hh = M.h[m];
-            const double f = cA * A.hq[hh] + cB * A.hx[hh] + cC * A.hy[hh] + cD;
-            double sarg = 1.0 + 4.0 * cA * f;
-            if (sarg < 0.0) sarg = 0.0;
-            const double dist = fabs(2.0 * f / (1.0 + sqrt(sarg)));
-            if (!(dist <= road)) continue;
-            if (bh < 0 || dist < bd || (dist == bd && hh < bh)) { bh = hh; bd = dist; }
-          }
-          hitL[L] = bh;
-          if (bh >= 0) { ++n_in; ss += bd * bd; }
-        }
+    }
+    // |dist| >= |f| / (1 + |A||f|): a member with |f| > road / (1 - road |A|)
+    // cannot be within the road.  The float32 test allows a margin of 1e-6
+    // of a bound on the magnitudes of the terms and partial sums over all
+    // members (|x|, |y| <= rmax, q <= qmax), far above what the rounding of
+    // the coefficients, of the coordinates and of three fused multiply-adds
+    // can move f (< 5e-7 of that bound), so it never drops a member the
+    // float64 test keeps.
+    float Af = 0.0f, Bf = 0.0f, Cf = 0.0f, Df = 0.0f, thr = -1.0f;
+    if (ok) {
+      const double ra = road * fabs(cA);
+      const float pre = ra < 0.5 ? (float)(road / (1.0 - ra) * 1.000001) : __builtin_inff();
+      Af = (float)cA;
+      Bf = (float)cB;
+      Cf = (float)cC;
+      Df = (float)cD;
+      const float mag = fabsf(Af) * qmax + (fabsf(Bf) + fabsf(Cf)) * rmax + fabsf(Df);
+      thr = pre + mag * 1e-6f;
+    }
+    int n_in = ok ? 0 : -1;
+    bool active = ok;
+    // visiting order: layers that are not seed layers, then the seed layers
+    const unsigned smask = (1u << Ls[0]) | (1u << Ls[1]) | (1u << Ls[2]);
+    unsigned seq = (lmask & ~smask) | (smask << HT_MAX_LAYERS);
+    int remaining = nS;
+    while (seq) {
+      const int L = __builtin_ctz(seq) & (HT_MAX_LAYERS - 1);
+      seq &= seq - 1u;
+      --remaining;
+      if (active && n_in + remaining + 1 < cfg.min_layers) {
+        active = false;
+        n_in = -2;
+      }
+      if (__ballot(active) == 0ull) break;
+      const int st = __builtin_amdgcn_readlane(ls, L);
+      const int en = __builtin_amdgcn_readlane(ls, L + 1);
+      double bd = 0.0;
+      int bh = -1;
+      for (int e = st; e < en; ++e) {
+        const Mem4 v = M.mem[e];
+        const float f32 = __builtin_fmaf(Af, v.q, __builtin_fmaf(Bf, v.x, __builtin_fmaf(Cf, v.y, Df)));
+        if (!(active && fabsf(f32) <= thr)) continue;
+        const int hh = v.h;
+        const double dist = fabs(circle_dist(cA, cB, cC, cD, A.hx[hh], A.hy[hh], A.hq[hh]));
+        if (!(dist <= road)) continue;
+        if (bh < 0 || dist < bd || (dist == bd && hh < bh)) { bh = hh; bd = dist; }
+      }
+      if (active) {
+        hitL[L] = bh;
+        if (bh >= 0) ++n_in;
       }
     }
     // best lane: most inliers, then smallest sum, then lowest combination index
@@ -759,6 +794,15 @@ __global__ __launch_bounds__(kWave) void refine_kernel(AssocArgs A) {
       if (lane == 0) { A.cstat[p] = -1; A.cnl[p] = nS; }
       __syncthreads();
       continue;
+    }
+    double ss = 0.0;
+    if (n_in == best_n) {
+      for (unsigned lm = lmask; lm; lm &= lm - 1u) {
+        const int hh = hitL[__builtin_ctz(lm)];
+        if (hh < 0) continue;
+        const double d = fabs(circle_dist(cA, cB, cC, cD, A.hx[hh], A.hy[hh], A.hq[hh]));
+        ss += d * d;
+      }
     }
     unsigned long long key = ~0ull;
     if (n_in == best_n) key = (unsigned long long)__double_as_longlong(ss);
@@ -770,10 +814,10 @@ __global__ __launch_bounds__(kWave) void refine_kernel(AssocArgs A) {
       A.cnl[p] = nS;
       double* g = A.cgeo + (size_t)p * 5;
       g[0] = ss; g[1] = cA; g[2] = cB; g[3] = cC; g[4] = cD;
-#pragma unroll
-      for (int L = 0; L < HT_MAX_LAYERS; ++L) A.chit[(size_t)p * HT_MAX_LAYERS + L] = hitL[L];
       atomicAdd(&A.sc[S_NCAND], 1);
     }
+    __syncthreads();
+    if (lane < HT_MAX_LAYERS) A.chit[(size_t)p * HT_MAX_LAYERS + lane] = M.u.hit[win][lane];
     __syncthreads();
   }
 }
@@ -1191,7 +1235,8 @@ __global__ void counts_kernel(AssocArgs A) {
   c[2] = A.sc[S_NOBJ];
   c[3] = A.sc[S_NMEM];
   c[4] = A.sc[S_NOVER];
-  c[5] = 0;
+  const unsigned long long pairs = *reinterpret_cast<const unsigned long long*>(A.sc + S_PAIRS);
+  c[5] = pairs > 0x7fffffffull ? 0x7fffffff : (int32_t)pairs;
   c[6] = 0;
   c[7] = 0;
 }
@@ -1242,6 +1287,8 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   A.hx = P.d_hx;
   A.hy = P.d_hy;
   A.hq = P.d_hq;
+  A.hitA = P.d_hitA;
+  A.hitB = P.d_hitB;
   A.peaks = peaks;
   A.n_peaks = n_peaks;
   A.peak_cap = peak_cap;
@@ -1249,8 +1296,6 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   A.pbits = P.d_pbits;
   A.col_first = P.d_col_first;
   A.mcount = P.d_mcount;
-  A.mcur = P.d_mcur;
-  A.moff = P.d_moff;
   A.pool = reinterpret_cast<uint16_t*>(P.d_mem);
   A.cstat = P.d_cstat;
   A.cnl = P.d_cnl;
@@ -1278,7 +1323,9 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   member_kernel<<<sweep, kSweepThreads, 0, s>>>(A);
   HT_CHECK(hipGetLastError());
   const int rblocks = blocks_for(peak_cap, 1) > 16384 ? 16384 : blocks_for(peak_cap, 1);
-  if (cfg.member_cap <= 256)
+  if (cfg.member_cap <= 128)
+    refine_kernel<128><<<rblocks, kWave, 0, s>>>(A);
+  else if (cfg.member_cap <= 256)
     refine_kernel<256><<<rblocks, kWave, 0, s>>>(A);
   else if (cfg.member_cap <= 512)
     refine_kernel<512><<<rblocks, kWave, 0, s>>>(A);

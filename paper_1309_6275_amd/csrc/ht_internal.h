@@ -83,10 +83,10 @@ struct Plan {
   double* d_hx;          // [max_hits] hit x, y, x^2+y^2
   double* d_hy;
   double* d_hq;
+  float4* d_hitA;        // [max_hits] r, phi, r*r, 1/r
+  float4* d_hitB;        // [max_hits] x, y, x^2+y^2 (float32), layer
   int32_t* d_mcount;     // [max_peaks] member counts
-  int32_t* d_mcur;       // [max_peaks] fill cursors (workgroups with many peaks)
-  int32_t* d_moff;       // [max_peaks] offset of each member list in the pool, -1 = overflow
-  int32_t* d_mem;        // member pool: uint16 hit indices, max_peaks * max_member_cap of them
+  int32_t* d_mem;        // member pool: uint16 hit indices, member_cap slots per candidate
   int32_t* d_cstat;      // [max_peaks] candidate status / inlier count
   double* d_cgeo;        // [max_peaks * 5] seed ss, A, B, C, D
   int32_t* d_chit;       // [max_peaks * HT_MAX_LAYERS] inlier hit per layer
@@ -119,6 +119,7 @@ int launch_assoc(const Plan& p, const float* r, const float* phi, const uint8_t*
 int launch_asin(const float* u, float* out, int64_t n, hipStream_t s);
 int launch_scan(const int32_t* cnt, int32_t* off, int n, int32_t* total, hipStream_t s);
 int vote_init(int n_phi);
+int peaks_init(int n_phi);
 }  // namespace ht
 
 #define HT_CHECK(x)                              \

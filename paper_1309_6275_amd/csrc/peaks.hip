@@ -108,6 +108,8 @@ __global__ __launch_bounds__(kTile) void emit_kernel(const int32_t* __restrict__
 
 }  // namespace
 
+int peaks_init(int) { return HT_OK; }
+
 int launch_peaks(const Plan& p, const int32_t* acc, int32_t min_votes, ht_peak* out,
                  int32_t capacity, int32_t* n_found, hipStream_t s) {
   const ht_grid& g = p.grid;

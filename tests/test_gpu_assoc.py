@@ -74,7 +74,7 @@ def run_oracle(oracle, grid, ev, acc, pk_gpu, cfg, track_cap=4096, object_cap=51
 
 
 def compare(got, want, label=""):
-    assert np.array_equal(got["counts"][:5], want["counts"][:5]), (label, got["counts"],
+    assert np.array_equal(got["counts"][:6], want["counts"][:6]), (label, got["counts"],
                                                                    want["counts"])
     assert np.array_equal(got["hit_owner"], want["hit_owner"]), label
     gt, wt = got["tracks"], want["tracks"]
