@@ -6,8 +6,9 @@ of synthetic displaced-jet events (512 phi0 x 256 q/pT x 64 d0 accumulator,
 ~3.6k hits each), inputs resident in HBM before the timed region.  Prints
 one JSON line: whole-job Hough votes/s (value), events/s, p50/p99 event
 latency, track efficiency and fake rate of the outputs, the roofline of the
-vote kernel measured live with HIP events, and the CPU oracle timed on a
-bounded sample on the host cores.
+dominant kernel (the seed search of the refinement) and of the vote kernel,
+both from the library's HIP-event stage timers on the launch stream, and the
+CPU oracle timed on a bounded sample on the host cores.
 
     python bench.py [--steps K] [--warmup W] [--batch B] [--workload 1|2|3]
 """
@@ -33,6 +34,10 @@ METRIC = "Hough votes/s + events/s at >=95% track eff; p50/p99 event latency (ms
 # - PHI_LO, * INVW, floor (4)
 OPS_PER_EVAL = 5
 OPS_PER_VOTE = 22
+# float64 operations of one road test of the seed search, the distance of a
+# member from a seed circle: f = A q + B x + C y + D (3 multiplies, 3 adds),
+# s = 1 + 4 A f (2, 1), sqrt, 1 + sqrt, 2 f, the division
+OPS_PER_TEST = 13
 # single-issue fp32 VALU rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
@@ -64,18 +69,23 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
 
 
-def kernel_source_sha():
+# the sources a kernel's code comes from (plan and launch code excluded)
+KERNEL_SOURCES = {"vote": ("vote.hip", "ht_device.h"),
+                  "refine": ("assoc.hip", "ht_device.h")}
+
+
+def kernel_source_sha(kernel):
     h = hashlib.sha256()
-    for f in ("vote.hip", "ht_internal.h"):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1309_6275_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload):
-    """HBM bytes per vote launch from the committed rocprofv3 counter summary,
-    if it was taken on the current vote kernel source."""
-    path = os.path.join(ROOT, "profiles", f"vote_cfg{workload}_hbm_counters.md")
+def traffic_from_profile(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current source of that kernel."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_cfg{workload}_hbm_counters.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -83,7 +93,7 @@ def traffic_from_profile(workload):
     if not m:
         return None
     d = json.loads(m.group(1))
-    if d.get("kernel_source_sha") != kernel_source_sha():
+    if d.get("kernel_source_sha") != kernel_source_sha(kernel):
         return None
     return float(d["hbm_bytes_per_launch"])
 
@@ -162,7 +172,6 @@ def main():
 
     stream = torch.cuda.current_stream()
     ev_a = [torch.cuda.Event(enable_timing=True) for _ in range(B)]
-    ev_b = [torch.cuda.Event(enable_timing=True) for _ in range(B)]
     ev_c = [torch.cuda.Event(enable_timing=True) for _ in range(B)]
 
     def step(record):
@@ -170,8 +179,6 @@ def main():
             if record:
                 ev_a[e].record(stream)
             H.hough_vote(plan, d["r"], d["phi"], acc)
-            if record:
-                ev_b[e].record(stream)
             H.hough_peaks(plan, acc, W["min_votes"], peaks, nf)
             H.assoc_cluster(plan, d["r"], d["phi"], d["layer"], peaks, nf, cl, bufs[e],
                             with_vacc=False)
@@ -181,27 +188,47 @@ def main():
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
-    vote_ms, lat_ms = [], []
+    # stage timers: HIP events the library records around its kernels on the
+    # launch stream, read after each step
+    H.profile_begin(plan, depth=2 * B)
+    stages = {}
+    lat_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step(True)
         torch.cuda.synchronize()  # per-step sync so the events of this step can be read
         for e in range(B):
-            vote_ms.append(ev_a[e].elapsed_time(ev_b[e]))
             lat_ms.append(ev_a[e].elapsed_time(ev_c[e]))
+        H.profile_read(plan, stages)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    H.profile_end(plan)
 
     n_events = args.steps * B
     total_votes = args.steps * sum(votes)
     ms_per_step = wall * 1e3 / args.steps
-    vote_ms = np.array(vote_ms)
     lat_ms = np.array(lat_ms)
-    # roofline of the vote kernel: algorithmic fp32 operations per launch
-    ops_per_launch = np.mean([OPS_PER_EVAL * E + OPS_PER_VOTE * V for E, V in zip(evals, votes)])
-    vote_avg_s = float(vote_ms.mean()) / 1e3
-    achieved = ops_per_launch / vote_avg_s / 1e12
-    traffic = traffic_from_profile(args.workload)
+    avg_ms = {k: (v[0] / v[1] if v[1] else float("nan")) for k, v in stages.items()}
+    # algorithmic work per launch: the vote's fp32 operations; the seed
+    # search's float64 road tests as the method defines them (every member
+    # against every admissible seed circle, counts[6] of each event)
+    tests = []
+    for ev, b in zip(events, bufs):
+        tests.append(int(b.to_host(ev.n_hits)["counts"][6]))
+    work = {"vote": np.mean([OPS_PER_EVAL * E + OPS_PER_VOTE * V for E, V in zip(evals, votes)]),
+            "refine": OPS_PER_TEST * float(np.mean(tests))}
+
+    def roofline(kernel):
+        achieved = work[kernel] / (avg_ms[kernel] / 1e3) / 1e12
+        return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
+                "frac": achieved / ALU_PEAK_TOPS,
+                "traffic": traffic_from_profile(kernel, args.workload),
+                "kernel": f"{kernel}_kernel", "avg_launch_ms": avg_ms[kernel]}
+
+    # the dominant kernel by measured time among the timed kernels
+    dominant = max(("vote", "refine", "members"), key=lambda k: avg_ms.get(k, 0.0))
+    if dominant == "members":  # no algorithmic figure of its own: report the next
+        dominant = max(("vote", "refine"), key=lambda k: avg_ms.get(k, 0.0))
 
     # physics of the outputs (last step), outside the timed region
     effs, fakes, n_trk = [], [], 0
@@ -229,7 +256,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": W["name"], "events_per_step": B,
                    "grid": f"{g['n_phi']}x{g['n_qpt']}x{g['n_d0']}",
@@ -241,11 +268,10 @@ def main():
         "track_efficiency": eff,
         "fake_rate": fake,
         "tracks_per_event": n_trk / B,
-        "vote_kernel_votes_per_s": float(np.mean(votes)) / vote_avg_s,
-        "vote_kernel_ms": float(vote_ms.mean()),
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TOPS,
-                     "traffic": traffic},
+        "vote_kernel_votes_per_s": float(np.mean(votes)) / (avg_ms["vote"] / 1e3),
+        "stage_ms": {k: avg_ms[k] for k in ("vote", "peaks", "members", "refine", "assoc")},
+        "roofline": roofline(dominant),
+        "roofline_vote": roofline("vote"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

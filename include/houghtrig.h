@@ -125,7 +125,9 @@ typedef struct {
   int32_t member_cap;
   int32_t* vacc;           /* [n_rho * n_theta] vertex accumulator, or NULL */
   int32_t* counts;         /* [8]: candidates, tracks, objects, object members, candidates
-                              over member_cap, (candidate, member) pairs of the others, 0, 0 */
+                              over member_cap, (candidate, member) pairs of the others,
+                              road tests of the seed search ((admissible seed circle,
+                              member) pairs), 0; a count above INT32_MAX reads INT32_MAX */
 } ht_cluster_out;
 
 typedef struct ht_plan ht_plan;
@@ -201,6 +203,26 @@ int assoc_cluster(const ht_plan* plan, const float* r, const float* phi, const u
                   int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks,
                   int32_t peak_cap, const ht_cluster_cfg* cfg, const ht_cluster_out* out,
                   void* stream);
+
+/* Stage timing, for measurement.  After ht_profile_begin, each later call
+ * on the plan records HIP events on its stream around its stages:
+ *   HT_STAGE_VOTE     the vote kernel of hough_vote,
+ *   HT_STAGE_PEAKS    the kernels of hough_peaks,
+ *   HT_STAGE_ASSOC    all of assoc_cluster,
+ *   HT_STAGE_MEMBERS  its member sweep (inside HT_STAGE_ASSOC),
+ *   HT_STAGE_REFINE   its seed search (inside HT_STAGE_ASSOC).
+ * At most `depth` launches per stage are recorded between two reads; later
+ * ones are not timed.  ht_profile_read waits for the recorded events, ADDS
+ * each stage's total milliseconds to ms[HT_STAGES] and its timed launches to
+ * launches[HT_STAGES], and starts a new interval.  ht_profile_end stops
+ * timing and frees the events.  Host calls; ht_profile_begin creates
+ * 2 * depth * HT_STAGES events (HT_ENOMEM if that fails), the compute calls
+ * still allocate nothing.  depth is 1..65536. */
+enum { HT_STAGE_VOTE = 0, HT_STAGE_PEAKS = 1, HT_STAGE_ASSOC = 2, HT_STAGE_MEMBERS = 3,
+       HT_STAGE_REFINE = 4, HT_STAGES = 5 };
+int ht_profile_begin(ht_plan* plan, int32_t depth);
+int ht_profile_read(ht_plan* plan, double* ms, int64_t* launches);
+int ht_profile_end(ht_plan* plan);
 
 /* ht_asin_f32 -- the canonical float32 arcsine of hough_vote, elementwise
  * over n device floats (for checking the formula on the device). */

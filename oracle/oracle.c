@@ -447,6 +447,7 @@ void oracle_sincos_array(const double* a, double* s, double* c, int64_t n) {
 typedef struct {
   int32_t n_layers, n_inliers, status; /* status 0 ok, 1 too few layers/inliers, 2 member overflow */
   int32_t n_members;
+  int64_t n_tests;                     /* (admissible seed circle, member) road tests */
   int32_t hit[OR_MAX_LAYERS];          /* inlier hit per layer */
   double ss;                           /* sum of squared inlier distances */
   double A, B, C, D;                   /* seed circle */
@@ -528,6 +529,7 @@ static void refine(const or_grid* g, const tables* tb, const window_t* wd, const
   float wbase = 0.5f + (float)cfg->win_bins;
   int nm = 0;
   out->n_members = 0;
+  out->n_tests = 0;
   out->status = 1;
   out->n_layers = 0;
   out->n_inliers = 0;
@@ -623,6 +625,7 @@ static void refine(const or_grid* g, const tables* tb, const window_t* wd, const
         double sq = sqrt(B * B + C * C);
         double d0 = 2.0 * D / (1.0 + sq);
         if (!(fabs(kap - kap_c) <= ktol) || !(fabs(d0 - d0_c) <= dtol)) continue;
+        out->n_tests += nm;
         int n_in = 0;
         double ss = 0.0;
         int hit[OR_MAX_LAYERS];
@@ -875,9 +878,10 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
   int32_t* owner = (int32_t*)malloc(sizeof(int32_t) * nh1);
   for (int32_t h = 0; h < n_hits; ++h) owner[h] = -1;
   int32_t n_cand = 0, n_over = 0;
-  int64_t n_pairs = 0;
+  int64_t n_pairs = 0, n_tests = 0;
   for (int32_t p = 0; p < n_peaks; ++p) {
     n_pairs += cd[p].n_members;
+    n_tests += cd[p].n_tests;
     if (cd[p].status == 2) ++n_over;
     if (cd[p].status != 0) continue;
     ++n_cand;
@@ -1018,6 +1022,8 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
   counts[3] = (int32_t)n_mem;
   counts[4] = n_over;
   counts[5] = (int32_t)(n_pairs > 0x7fffffff ? 0x7fffffff : n_pairs);
+  counts[6] = (int32_t)(n_tests > 0x7fffffff ? 0x7fffffff : n_tests);
+  counts[7] = 0;
 
   free(cd);
   free(owner);

@@ -106,7 +106,9 @@ int oracle_refine_one(const or_grid* g, const float* r, const float* phi, const 
 /* counts[0] candidates (seed with >= min_layers inlier layers), counts[1]
  * surviving tracks, counts[2] vertex objects, counts[3] object members,
  * counts[4] candidates dropped for exceeding member_cap, counts[5] (candidate,
- * member) pairs of the other candidates.  vacc (may be NULL)
+ * member) pairs of the other candidates, counts[6] road tests of the seed
+ * search: (admissible seed circle, member) pairs, summed over candidates,
+ * counts[7] 0.  Counts above INT32_MAX read INT32_MAX.  vacc (may be NULL)
  * receives the vertex accumulator [n_rho][n_theta]. */
 int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
                          const uint8_t* layer, int32_t n_hits, const or_peak* peaks,

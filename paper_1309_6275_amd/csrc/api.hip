@@ -50,9 +50,9 @@ int dalloc(T** p, size_t n) {
 }
 
 void free_plan(Plan* p) {
-  void* ptrs[] = {p->d_kap,       p->d_q,         p->d_t,        p->d_bits,      p->d_tile_cnt,
+  void* ptrs[] = {p->d_kap,       p->d_kapc,      p->d_d0c,       p->d_q,         p->d_t,        p->d_bits,      p->d_tile_cnt,
                   p->d_tile_off,  p->d_pbits,     p->d_col_first, p->d_hx,       p->d_hy,
-                  p->d_hq,        p->d_hitA,      p->d_hitB,      p->d_mcount,    p->d_mem,      p->d_cstat,
+                  p->d_hq,        p->d_hitB,      p->d_mcount,    p->d_mem,      p->d_cstat,
                   p->d_cgeo,      p->d_chit,      p->d_cnl,      p->d_owner_key, p->d_ctile_cnt,
                   p->d_ctile_off, p->d_trk_peak,  p->d_arc0,     p->d_arcn,      p->d_vacc,
                   p->d_obj_cnt,   p->d_obj_off,   p->d_scalars};
@@ -102,8 +102,12 @@ int ht_plan_create(const ht_grid* grid, const ht_limits* lim, ht_plan** out) {
   float* hk = new (std::nothrow) float[g.n_qpt];
   float* hq = new (std::nothrow) float[ncol];
   float* ht_ = new (std::nothrow) float[ncol];
-  int rc = (hk && hq && ht_) ? HT_OK : HT_ENOMEM;
+  double* hkc = new (std::nothrow) double[g.n_qpt];
+  double* hdc = new (std::nothrow) double[g.n_d0];
+  int rc = (hk && hq && ht_ && hkc && hdc) ? HT_OK : HT_ENOMEM;
   if (rc == HT_OK) {
+    for (int j = 0; j < g.n_qpt; ++j) hkc[j] = kappa_centre(g, j);
+    for (int k = 0; k < g.n_d0; ++k) hdc[k] = d0_centre(g, k);
     for (int j = 0; j < g.n_qpt; ++j) hk[j] = (float)kappa_centre(g, j);
     for (int k = 0; k < g.n_d0; ++k) {
       const double d0 = d0_centre(g, k);
@@ -119,9 +123,12 @@ int ht_plan_create(const ht_grid* grid, const ht_limits* lim, ht_plan** out) {
   const size_t words = (size_t)p->n_tiles * 8 + 2;
   const int64_t ctiles = ((int64_t)np + 255) / 256;
   if (rc == HT_OK) rc = dalloc(&p->d_kap, (size_t)g.n_qpt);
+  if (rc == HT_OK) rc = dalloc(&p->d_kapc, (size_t)g.n_qpt);
+  if (rc == HT_OK) rc = dalloc(&p->d_d0c, (size_t)g.n_d0);
   if (rc == HT_OK) rc = dalloc(&p->d_q, ncol);
   if (rc == HT_OK) rc = dalloc(&p->d_t, ncol);
-  if (rc == HT_OK) rc = dalloc(&p->d_bits, words);
+  // peak ballots: 256 bits per 256-cell tile, or per 1024-cell tile of four-cell lanes
+  if (rc == HT_OK) rc = dalloc(&p->d_bits, (size_t)((p->n_tiles + 3) / 4) * 32 + 2);
   if (rc == HT_OK) rc = dalloc(&p->d_tile_cnt, (size_t)p->n_tiles);
   if (rc == HT_OK) rc = dalloc(&p->d_tile_off, (size_t)p->n_tiles);
   if (rc == HT_OK) rc = dalloc(&p->d_pbits, words);
@@ -129,10 +136,9 @@ int ht_plan_create(const ht_grid* grid, const ht_limits* lim, ht_plan** out) {
   if (rc == HT_OK) rc = dalloc(&p->d_hx, nh);
   if (rc == HT_OK) rc = dalloc(&p->d_hy, nh);
   if (rc == HT_OK) rc = dalloc(&p->d_hq, nh);
-  if (rc == HT_OK) rc = dalloc(&p->d_hitA, nh);
   if (rc == HT_OK) rc = dalloc(&p->d_hitB, nh);
   if (rc == HT_OK) rc = dalloc(&p->d_mcount, np);
-  if (rc == HT_OK) rc = dalloc(&p->d_mem, (np * (size_t)lim->max_member_cap + 1) / 2);
+  if (rc == HT_OK) rc = dalloc(&p->d_mem, np * (size_t)lim->max_member_cap);
   if (rc == HT_OK) rc = dalloc(&p->d_cstat, np);
   if (rc == HT_OK) rc = dalloc(&p->d_cgeo, np * 5);
   if (rc == HT_OK) rc = dalloc(&p->d_chit, np * HT_MAX_LAYERS);
@@ -150,13 +156,17 @@ int ht_plan_create(const ht_grid* grid, const ht_limits* lim, ht_plan** out) {
   if (rc == HT_OK &&
       (hipMemcpy(p->d_kap, hk, sizeof(float) * g.n_qpt, hipMemcpyHostToDevice) != hipSuccess ||
        hipMemcpy(p->d_q, hq, sizeof(float) * ncol, hipMemcpyHostToDevice) != hipSuccess ||
-       hipMemcpy(p->d_t, ht_, sizeof(float) * ncol, hipMemcpyHostToDevice) != hipSuccess))
+       hipMemcpy(p->d_t, ht_, sizeof(float) * ncol, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(p->d_kapc, hkc, sizeof(double) * g.n_qpt, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(p->d_d0c, hdc, sizeof(double) * g.n_d0, hipMemcpyHostToDevice) != hipSuccess))
     rc = HT_EDEVICE;
   if (rc == HT_OK) rc = ht::vote_init(g.n_phi);
   if (rc == HT_OK) rc = ht::peaks_init(g.n_phi);
   delete[] hk;
   delete[] hq;
   delete[] ht_;
+  delete[] hkc;
+  delete[] hdc;
   if (rc != HT_OK) {
     free_plan(p);
     delete p;
@@ -170,6 +180,7 @@ void ht_plan_destroy(ht_plan* p) {
   if (!p) return;
   int cur = 0;
   if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
+  (void)ht_profile_end(p);
   free_plan(p);
   if (cur != p->device) (void)hipSetDevice(cur);
   delete p;
@@ -217,6 +228,61 @@ int assoc_cluster(const ht_plan* p, const float* r, const float* phi, const uint
 int ht_asin_f32(const float* u, float* out, int64_t n, void* stream) {
   if (n < 0 || (n > 0 && (!u || !out))) return HT_EINVAL;
   return ht::launch_asin(u, out, n, (hipStream_t)stream);
+}
+
+int ht_profile_begin(ht_plan* p, int32_t depth) {
+  if (!p || depth < 1 || depth > 65536) return HT_EINVAL;
+  int rc = ht_profile_end(p);
+  if (rc != HT_OK) return rc;
+  const size_t n = (size_t)HT_STAGES * depth * 2;
+  hipEvent_t* ev = new (std::nothrow) hipEvent_t[n];
+  if (!ev) return HT_ENOMEM;
+  for (size_t e = 0; e < n; ++e) {
+    if (hipEventCreate(&ev[e]) != hipSuccess) {
+      for (size_t f = 0; f < e; ++f) (void)hipEventDestroy(ev[f]);
+      delete[] ev;
+      return HT_ENOMEM;
+    }
+  }
+  p->prof_ev = ev;
+  for (int st = 0; st < HT_STAGES; ++st) p->prof_used[st] = 0;
+  p->prof_depth = depth;
+  return HT_OK;
+}
+
+int ht_profile_read(ht_plan* p, double* ms, int64_t* launches) {
+  if (!p || !ms || !launches) return HT_EINVAL;
+  if (p->prof_depth == 0) return HT_OK;
+  int rc = HT_OK;
+  for (int st = 0; st < HT_STAGES; ++st) {
+    for (int u = 0; u < p->prof_used[st]; ++u) {
+      hipEvent_t* pair = p->prof_ev + ((size_t)st * p->prof_depth + u) * 2;
+      float t = 0.0f;
+      if (hipEventSynchronize(pair[1]) != hipSuccess ||
+          hipEventElapsedTime(&t, pair[0], pair[1]) != hipSuccess) {
+        rc = HT_EDEVICE;
+        continue;
+      }
+      ms[st] += (double)t;
+      launches[st] += 1;
+    }
+    p->prof_used[st] = 0;
+  }
+  return rc;
+}
+
+int ht_profile_end(ht_plan* p) {
+  if (!p) return HT_EINVAL;
+  if (p->prof_ev) {
+    if (hipDeviceSynchronize() != hipSuccess) return HT_EDEVICE;
+    const size_t n = (size_t)HT_STAGES * p->prof_depth * 2;
+    for (size_t e = 0; e < n; ++e) (void)hipEventDestroy(p->prof_ev[e]);
+    delete[] p->prof_ev;
+  }
+  p->prof_ev = nullptr;
+  p->prof_depth = 0;
+  for (int st = 0; st < HT_STAGES; ++st) p->prof_used[st] = 0;
+  return HT_OK;
 }
 
 }  // extern "C"

@@ -30,6 +30,8 @@
 // arithmetic or float64 arithmetic and square roots in a fixed order, so the
 // results match the CPU reference bit for bit; the refit uses the device
 // asin/atan2 and matches to rounding.
+#include <type_traits>
+
 #include "ht_internal.h"
 
 namespace ht {
@@ -40,8 +42,9 @@ constexpr int kSweepThreads = kSweepWaves * kWave;
 constexpr int kMaxMembers = 1024; // largest member_cap (LDS slots per wave in refine)
 constexpr int kGridCap = 8192;    // grid-stride launches use at most this many blocks
 
-// S_PAIRS is a 64-bit counter over slots 6 and 7 (8-byte aligned)
-enum { S_NP = 0, S_NCAND = 1, S_NOVER = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5, S_PAIRS = 6 };
+// S_PAIRS and S_TESTS are 64-bit counters over slots 6-7 and 8-9 (8-byte aligned)
+enum { S_NP = 0, S_NCAND = 1, S_NOVER = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5, S_PAIRS = 6,
+       S_TESTS = 8 };
 
 __device__ __forceinline__ float bcastf(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -219,10 +222,12 @@ struct AssocArgs {
   const float* kap;
   const float* qt;
   const float* tt;
+  const double* kapc;  // column-centre curvature and plane-centre d0, float64
+  const double* d0c;
   bool origin_seed;
   double kap_bin, d0_bin;
   float hk, hd0;
-  double d0_lo, d0_hi, qpt_lo, qpt_hi, bfield;
+  double cb;  // 0.299792458e-2 B: curvature per unit q/pT
   // hits
   const float* r;
   const float* phi;
@@ -231,7 +236,6 @@ struct AssocArgs {
   double* hx;
   double* hy;
   double* hq;
-  float4* hitA;  // r, phi, r*r, 1/r
   float4* hitB;  // x, y, x^2+y^2 (float32), layer
   // peaks
   const ht_peak* peaks;
@@ -243,7 +247,7 @@ struct AssocArgs {
   uint32_t* pbits;
   int32_t* col_first;
   int32_t* mcount;
-  uint16_t* pool;
+  uint2* pool;   // member_cap slots per candidate: hit, |x - cell centre| bits
   int32_t* cstat;
   int32_t* cnl;
   double* cgeo;
@@ -286,7 +290,6 @@ __global__ void init_kernel(AssocArgs A, int words) {
     A.hx[h] = x;
     A.hy[h] = y;
     A.hq[h] = q;
-    A.hitA[h] = make_float4(r, ph, r * r, 1.0f / r);
     A.hitB[h] = make_float4((float)x, (float)y, (float)q, (float)A.layer[h]);
     A.owner_key[h] = 0ull;
     A.out.hit_owner[h] = -1;
@@ -320,39 +323,81 @@ __global__ void mark_kernel(AssocArgs A) {
 // into its candidate's member_cap slots of the pool: one sweep, and the
 // workgroup's member lists form one contiguous region of the pool.
 constexpr int kMaxPhiWords = 32;  // n_phi <= 1024
-constexpr int kMaxWgPeaks = 8192; // LDS counters; more peaks fall back to global counters
+constexpr int kMaxWgPeaks = 4096; // LDS counters; more peaks fall back to global counters
+constexpr int kQueue = 2 * kWave; // per-wave queue of (hit, column) pairs with a peak in reach
 
 struct SweepShared {
   uint32_t cbits[kWave][kMaxPhiWords + 1];
   int32_t cpre[kWave][kMaxPhiWords + 1];
   int32_t ccnt[kWave];
+  int32_t cfirst[kWave];      // first peak of each column, relative to p_lo
   int32_t cnt[kMaxWgPeaks];   // member counts = next free slot of each candidate
+  // Pairs whose window range holds a peak bit wait here until a full wave of
+  // them can be resolved at once: x, u, the window's hit part e5, the peak
+  // bits in range, and hit | column lane << 16 | first cell of the range << 22.
+  float qx[kSweepWaves][kQueue];
+  float qu[kSweepWaves][kQueue];
+  float qe[kSweepWaves][kQueue];
+  uint32_t qbits[kSweepWaves][kQueue];
+  uint32_t qmeta[kSweepWaves][kQueue];
   int32_t np_wg, p_lo;
 };
 
 // One pass over the workgroup's (hit, column) pairs; for every member
-// (candidate q = p - p_lo, hit h) call fn(q, h).
+// (candidate q = p - p_lo, hit h, |x - cell centre| adx) call fn(q, h, adx).  A lane (column) first
+// bounds the window from above with cheap arithmetic and reads the peak bits
+// it covers; the rare pairs with a peak bit in range are queued and resolved
+// (exact window, candidate index, fn) a wave at a time, so the exact test
+// does not run with most lanes idle.
 template <typename F>
 __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S, int k, int j0,
                                               F fn) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x >> 6;
   const int n_phi = A.n_phi;
-  const int nwords = (n_phi + 31) >> 5;
   const int j = j0 + lane;
   const bool col_ok = j < A.n_qpt;
   float ck = 0.0f, cq = 0.0f, ct = 0.0f;
-  int cfirst = 0;
   const bool has = col_ok && S.ccnt[lane] > 0;
   if (col_ok) {
     ck = A.kap[j];
     cq = A.qt[(size_t)k * A.n_qpt + j];
     ct = A.tt[(size_t)k * A.n_qpt + j];
-    if (has) cfirst = A.col_first[(size_t)k * A.n_qpt + j] - S.p_lo;
   }
+  const int cfirst = S.cfirst[lane];
   const float wbase = 0.5f + (float)A.cfg.win_bins;
   const int np_wg = S.np_wg;
+  const int nwords = (n_phi + 31) >> 5;
   const bool fast_bits = (n_phi & 31) == 0;
+  int head = 0, tail = 0;  // queue positions, uniform over the wave
+  auto drain = [&](int nproc) {
+    if (lane < nproc) {
+      const int slot = (head + lane) & (kQueue - 1);
+      const float x = S.qx[wave][slot];
+      const float u = S.qu[wave][slot];
+      const float e5 = S.qe[wave][slot];
+      uint32_t bits = S.qbits[wave][slot];
+      const uint32_t meta = S.qmeta[wave][slot];
+      const int hh = (int)(meta & 0xffffu);
+      const int cl = (int)((meta >> 16) & 63u);
+      const int iw0 = (int)(meta >> 22);
+      const float w = member_window(e5, u, wbase);
+      while (bits) {
+        const int b = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        int ic = iw0 + b;
+        if (ic >= n_phi) ic -= n_phi;
+        const float adx = cell_adx(x, ic, n_phi);
+        if (!(adx <= w)) continue;
+        const int wi = ic >> 5;
+        const uint32_t below = S.cbits[cl][wi] & ((1u << (ic & 31)) - 1u);
+        const int q = S.cfirst[cl] + S.cpre[cl][wi] + __popc(below);
+        if (q < 0 || q >= np_wg) continue;  // only for peak lists not sorted by cell
+        fn(q, hh, adx);
+      }
+    }
+    head += nproc;
+  };
   for (int base = wave * kWave; base < A.n_hits; base += kSweepThreads) {
     const int h = base + lane;
     float hr = 1.0f, hp = 0.0f;
@@ -374,73 +419,82 @@ __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S
       const float ph = bcastf(hp, src);
       const float e5 = bcastf(he5, src);
       const int hh = base + src;
-      float x, u;
-      if (!has || !phi0_coord(r2, ir, ph, ck, cq, ct, A.phi_lo, A.invw, &x, &u)) continue;
-      // upper bound of the window with the hardware reciprocal square root
-      // (1 ulp) and a 0.1% margin; the exact window is computed only if a
-      // peak is in reach
-      const float gg = 1.0f - u * u;
-      const float w_hi = wbase + e5 * 1.5f * __builtin_amdgcn_rsqf(gg) * 1.001f;
-      int ilo = 0, ihi = n_phi - 1;
-      if (w_hi < 0.5f * (float)n_phi) {
-        const int lo = (int)floorf(x - w_hi - 0.5f) - 1;
-        const int hi = (int)floorf(x + w_hi - 0.5f) + 1;
-        if (hi - lo + 1 < n_phi) { ilo = lo; ihi = hi; }
-      }
-      const int len = ihi - ilo + 1;
-      if (fast_bits && len <= 32) {
-        // common case: the range fits in 64 bits starting at ilo's word
-        // (n_phi is a multiple of 32, so the column bits are cyclic by word)
-        const int iw0 = ilo < 0 ? ilo + n_phi : (ilo >= n_phi ? ilo - n_phi : ilo);
-        const int w0 = iw0 >> 5;
-        const int w1 = w0 + 1 == nwords ? 0 : w0 + 1;
-        const uint64_t two = (uint64_t)S.cbits[lane][w0] | ((uint64_t)S.cbits[lane][w1] << 32);
-        uint64_t bits = (two >> (iw0 & 31)) & ((1ull << len) - 1ull);
-        if (!bits) continue;
-        const float w = member_window(e5, u, wbase);
-        while (bits) {
-          const int b = __builtin_ctzll(bits);
-          bits &= bits - 1ull;
-          int ic = iw0 + b;
-          if (ic >= n_phi) ic -= n_phi;
-          const float adx = cell_adx(x, ic, n_phi);
-          if (!(adx <= w)) continue;
-          const int wi = ic >> 5;
-          const uint32_t below = S.cbits[lane][wi] & ((1u << (ic & 31)) - 1u);
-          const int q = cfirst + S.cpre[lane][wi] + __popc(below);
-          if (q < 0 || q >= np_wg) continue;  // only for peak lists not sorted by cell
-          fn(q, hh);
+      float x = 0.0f, u = 0.0f;
+      uint32_t bits = 0u;
+      int iw0 = 0, ilo = 0, ihi = -1;
+      bool slow = false;
+      if (has && phi0_coord(r2, ir, ph, ck, cq, ct, A.phi_lo, A.invw, &x, &u)) {
+        // upper bound of the window with the hardware reciprocal square root
+        // (1 ulp) and a 0.1% margin
+        const float gg = 1.0f - u * u;
+        const float w_hi = wbase + e5 * 1.5f * __builtin_amdgcn_rsqf(gg) * 1.001f;
+        ilo = 0;
+        ihi = n_phi - 1;
+        if (w_hi < 0.5f * (float)n_phi) {
+          const int lo = (int)floorf(x - w_hi - 0.5f) - 1;
+          const int hi = (int)floorf(x + w_hi - 0.5f) + 1;
+          if (hi - lo + 1 < n_phi) { ilo = lo; ihi = hi; }
         }
-        continue;
-      }
-      float w = -1.0f;
-      int i = ilo;
-      while (i <= ihi) {
-        // i lies in (-n_phi, 2 n_phi) for n_phi >= 14; smaller grids take the modulo
-        int iw = i < 0 ? i + n_phi : (i >= n_phi ? i - n_phi : i);
-        if (iw < 0 || iw >= n_phi) iw = ((i % n_phi) + n_phi) % n_phi;
-        const int wi = iw >> 5, bit = iw & 31;
-        int span = 32 - bit;
-        span = min(span, ihi - i + 1);
-        span = min(span, n_phi - iw);
-        uint32_t bits = S.cbits[lane][wi] >> bit;
-        if (span < 32) bits &= (1u << span) - 1u;
-        while (bits) {
-          const int b = __builtin_ctz(bits);
-          bits &= bits - 1u;
-          if (w < 0.0f) w = member_window(e5, u, wbase);
-          const int ic = iw + b;
-          const float adx = cell_adx(x, ic, n_phi);
-          if (!(adx <= w)) continue;
-          const uint32_t below = S.cbits[lane][wi] & ((1u << (bit + b)) - 1u);
-          const int q = cfirst + S.cpre[lane][wi] + __popc(below);
-          if (q < 0 || q >= np_wg) continue;  // only for peak lists not sorted by cell
-          fn(q, hh);
+        const int len = ihi - ilo + 1;
+        if (fast_bits && len <= 32) {
+          // the range fits in 64 bits starting at ilo's word (n_phi is a
+          // multiple of 32, so the column bits are cyclic by word)
+          iw0 = ilo < 0 ? ilo + n_phi : (ilo >= n_phi ? ilo - n_phi : ilo);
+          const int w0 = iw0 >> 5;
+          const int w1 = w0 + 1 == nwords ? 0 : w0 + 1;
+          const uint64_t two = (uint64_t)S.cbits[lane][w0] | ((uint64_t)S.cbits[lane][w1] << 32);
+          bits = (uint32_t)((two >> (iw0 & 31)) & ((1ull << len) - 1ull));
+        } else {
+          slow = true;
         }
-        i += span;
+      }
+      const bool push = bits != 0u;
+      const uint64_t pm = __ballot(push);
+      if (pm) {
+        if (push) {
+          const uint64_t lower = lane ? (pm & ((1ull << lane) - 1ull)) : 0ull;
+          const int slot = (tail + __popcll(lower)) & (kQueue - 1);
+          S.qx[wave][slot] = x;
+          S.qu[wave][slot] = u;
+          S.qe[wave][slot] = e5;
+          S.qbits[wave][slot] = bits;
+          S.qmeta[wave][slot] = (uint32_t)hh | ((uint32_t)lane << 16) | ((uint32_t)iw0 << 22);
+        }
+        tail += __popcll(pm);
+        if (tail - head >= kWave) drain(kWave);
+      }
+      if (slow) {
+        // general range: word by word over the cyclic column
+        float w = -1.0f;
+        int i = ilo;
+        while (i <= ihi) {
+          // i lies in (-n_phi, 2 n_phi) for n_phi >= 14; smaller grids take the modulo
+          int iw = i < 0 ? i + n_phi : (i >= n_phi ? i - n_phi : i);
+          if (iw < 0 || iw >= n_phi) iw = ((i % n_phi) + n_phi) % n_phi;
+          const int wi = iw >> 5, bit = iw & 31;
+          int span = 32 - bit;
+          span = min(span, ihi - i + 1);
+          span = min(span, n_phi - iw);
+          uint32_t wbits = S.cbits[lane][wi] >> bit;
+          if (span < 32) wbits &= (1u << span) - 1u;
+          while (wbits) {
+            const int b = __builtin_ctz(wbits);
+            wbits &= wbits - 1u;
+            if (w < 0.0f) w = member_window(e5, u, wbase);
+            const int ic = iw + b;
+            const float adx = cell_adx(x, ic, n_phi);
+            if (!(adx <= w)) continue;
+            const uint32_t below = S.cbits[lane][wi] & ((1u << (bit + b)) - 1u);
+            const int q = cfirst + S.cpre[lane][wi] + __popc(below);
+            if (q < 0 || q >= np_wg) continue;  // only for peak lists not sorted by cell
+            fn(q, hh, adx);
+          }
+          i += span;
+        }
       }
     }
   }
+  while (tail > head) drain(min(kWave, tail - head));
 }
 
 // adds the (candidate, member) pairs of the wave's candidates within
@@ -503,13 +557,19 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
   // a cell-ordered peak list gives p_lo + np_wg <= n_peaks; anything else is
   // a malformed list, whose candidates in these columns then get no members
   if (np_wg == 0 || p_lo < 0 || p_lo + np_wg > n_cands(A)) return;
-  uint16_t* pool = A.pool + (size_t)p_lo * cap;
+  if (threadIdx.x < kWave) {
+    const int j = j0 + threadIdx.x;
+    S.cfirst[threadIdx.x] =
+        (j < A.n_qpt && S.ccnt[threadIdx.x] > 0) ? A.col_first[(size_t)k * A.n_qpt + j] - p_lo : 0;
+  }
+  __syncthreads();
+  uint2* pool = A.pool + (size_t)p_lo * cap;
   if (np_wg <= kMaxWgPeaks) {
     for (int q = threadIdx.x; q < np_wg; q += kSweepThreads) S.cnt[q] = 0;
     __syncthreads();
-    sweep_members(A, S, k, j0, [&](int q, int hh) {
+    sweep_members(A, S, k, j0, [&](int q, int hh, float adx) {
       const int slot = atomicAdd(&S.cnt[q], 1);
-      if (slot < cap) pool[(size_t)q * cap + slot] = (uint16_t)hh;
+      if (slot < cap) pool[(size_t)q * cap + slot] = make_uint2((unsigned)hh, __float_as_uint(adx));
     });
     __syncthreads();
     int pairs = 0;
@@ -522,9 +582,9 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
   } else {
     // counters in global memory (zeroed by mark_kernel)
     int32_t* cnt = A.mcount + p_lo;
-    sweep_members(A, S, k, j0, [&](int q, int hh) {
+    sweep_members(A, S, k, j0, [&](int q, int hh, float adx) {
       const int slot = atomicAdd(&cnt[q], 1);
-      if (slot < cap) pool[(size_t)q * cap + slot] = (uint16_t)hh;
+      if (slot < cap) pool[(size_t)q * cap + slot] = make_uint2((unsigned)hh, __float_as_uint(adx));
     });
     __syncthreads();
     int pairs = 0;
@@ -547,6 +607,9 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
 // out.  The seed sum of squares is a float64 sum over layers in increasing
 // layer order; the lanes that tie for the most inlier layers recompute it in
 // that order at the end.
+// hit indices are < 65535 (at most 65535 hits), so 0xffff marks "no hit"
+constexpr uint16_t kNoHit = 0xffff;
+
 struct alignas(16) Mem4 {
   float x, y, q;
   int32_t h;
@@ -566,26 +629,91 @@ struct WaveMem {
   float adx[CAP];  // |x - cell centre| of the grouped members
   union {
     RawMembers<CAP> raw;
-    int32_t hit[kWave][HT_MAX_LAYERS + 1];  // each lane's inlier per layer
+    uint16_t hit[kWave][HT_MAX_LAYERS + 2];  // each lane's inlier per layer, kNoHit if none
   } u;
   int32_t lstart[HT_MAX_LAYERS + 1];
   int32_t lcnt[HT_MAX_LAYERS + 1];
   int32_t seed[3][4];
 };
 
-__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
-  for (int off = 32; off > 0; off >>= 1) {
-    const unsigned long long o = __shfl_xor(v, off);
-    v = o < v ? o : v;
-  }
-  return v;
+// Waves of a refine workgroup work on different candidates and share
+// nothing; each has its own LDS area, as many as the LDS of a CU allows at
+// good occupancy.  Ordering of a wave's own LDS accesses needs only a
+// wave-scope fence.
+template <int CAP>
+struct RefineShape {
+  static constexpr int kWaves = CAP <= 128 ? 4 : (CAP <= 256 ? 2 : 1);
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// Wave reductions with DPP: within each row of 16 lanes, xor-1 and xor-2
+// quad permutes, then the half-row and row mirrors leave the row's result in
+// every lane; the four row results are read into scalars.  No LDS round
+// trips.  Called with all 64 lanes active.
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+constexpr int kQuadXor1 = 0xb1;   // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4e;   // quad_perm [2,3,0,1]
+constexpr int kRowHalfMirror = 0x141;
+constexpr int kRowMirror = 0x140;
+
+template <typename Op>
+__device__ __forceinline__ int wave_reduce_i32(int v, Op op) {
+  v = op(v, dpp<kQuadXor1>(v));
+  v = op(v, dpp<kQuadXor2>(v));
+  v = op(v, dpp<kRowHalfMirror>(v));
+  v = op(v, dpp<kRowMirror>(v));
+  const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+  const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+  return op(op(r0, r1), op(r2, r3));
+}
+
 __device__ __forceinline__ int wave_max_i32(int v) {
-  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
-  return v;
+  return wave_reduce_i32(v, [](int a, int b) { return a > b ? a : b; });
 }
 __device__ __forceinline__ unsigned wave_or(unsigned v) {
-  for (int off = 32; off > 0; off >>= 1) v |= __shfl_xor(v, off);
+  return (unsigned)wave_reduce_i32((int)v, [](int a, int b) { return a | b; });
+}
+// maximum of non-negative floats (their bit patterns order like the values)
+__device__ __forceinline__ float wave_max_nonneg(float v) {
+  return __int_as_float(wave_max_i32(__float_as_int(v)));
+}
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+  auto step = [](unsigned long long x, unsigned long long o) { return o < x ? o : x; };
+  auto perm = [](unsigned long long x, auto tag) {
+    constexpr int C = decltype(tag)::value;
+    const unsigned lo = (unsigned)dpp<C>((int)(unsigned)x);
+    const unsigned hi = (unsigned)dpp<C>((int)(unsigned)(x >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+  };
+  v = step(v, perm(v, std::integral_constant<int, kQuadXor1>{}));
+  v = step(v, perm(v, std::integral_constant<int, kQuadXor2>{}));
+  v = step(v, perm(v, std::integral_constant<int, kRowHalfMirror>{}));
+  v = step(v, perm(v, std::integral_constant<int, kRowMirror>{}));
+  unsigned long long r = ~0ull;
+#pragma unroll
+  for (int row = 0; row < 4; ++row) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, row * 16);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), row * 16);
+    r = step(r, ((unsigned long long)hi << 32) | lo);
+  }
+  return r;
+}
+
+// inclusive prefix sum within each row of 16 lanes (row_shr with zero fill)
+__device__ __forceinline__ int row_scan_incl(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
   return v;
 }
 
@@ -601,14 +729,18 @@ __device__ __forceinline__ int nth_set_bit(unsigned mask, int n) {
 }
 
 template <int CAP>
-__global__ __launch_bounds__(kWave) void refine_kernel(AssocArgs A) {
-  __shared__ WaveMem<CAP> M;
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kernel(AssocArgs A) {
+  constexpr int W = RefineShape<CAP>::kWaves;
+  __shared__ WaveMem<CAP> MW[W];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x >> 6;
+  WaveMem<CAP>& M = MW[wave];
   const int np = n_cands(A);
   const ht_cluster_cfg& cfg = A.cfg;
   const int cap = cfg.member_cap;
   const double road = (double)cfg.road_sigmas * (double)cfg.sigma_rphi;
-  for (int p = blockIdx.x; p < np; p += gridDim.x) {
+  unsigned long long tests = 0;
+  for (int p = blockIdx.x * W + wave; p < np; p += gridDim.x * W) {
     const int lin = A.peaks[p].lin;
     const int n = A.mcount[p];
     if (lin < 0 || lin >= A.n_cells) {
@@ -619,97 +751,119 @@ __global__ __launch_bounds__(kWave) void refine_kernel(AssocArgs A) {
       if (lane == 0) { A.cstat[p] = -2; A.cnl[p] = 0; atomicAdd(&A.sc[S_NOVER], 1); }
       continue;
     }
-    const int i = lin % A.n_phi;
     const int col = lin / A.n_phi;
     const int j = col % A.n_qpt;
     const int k = col / A.n_qpt;
-    const float ck = A.kap[j], cq = A.qt[col], ct = A.tt[col];
+    const double kapc = A.kapc[j], d0c = A.d0c[k];  // issued early, used by the box check
     const size_t moff = (size_t)p * cap;
     // load members in pool order
     unsigned lmask = 0;
     float qmax = 0.0f;
     for (int m = lane; m < n; m += kWave) {
-      const int h = A.pool[moff + m];
-      const float4 ha = A.hitA[h];
+      const uint2 pe = A.pool[moff + m];
+      const int h = (int)pe.x;
       const float4 hb = A.hitB[h];
       const int L = (int)hb.w;
-      float x = 0.0f, u;
-      phi0_coord(ha.z, ha.w, ha.y, ck, cq, ct, A.phi_lo, A.invw, &x, &u);
       Mem4 rec;
       rec.x = hb.x;
       rec.y = hb.y;
       rec.q = hb.z;
       rec.h = h;
       M.u.raw.mem[m] = rec;
-      M.u.raw.adx[m] = cell_adx(x, i, A.n_phi);
+      M.u.raw.adx[m] = __uint_as_float(pe.y);
       M.u.raw.L[m] = (int8_t)L;
       lmask |= 1u << L;
       qmax = fmaxf(qmax, hb.z);
     }
-    lmask = __builtin_amdgcn_readfirstlane(wave_or(lmask));
-    for (int off = 32; off > 0; off >>= 1) qmax = fmaxf(qmax, __shfl_xor(qmax, off));
+    lmask = wave_or(lmask);
+    qmax = wave_max_nonneg(qmax);
     const float rmax = __builtin_sqrtf(qmax) * 1.0001f;
     const int nS = __popc(lmask);
     if (nS < cfg.min_layers || nS < 3) {
       if (lane == 0) { A.cstat[p] = -1; A.cnl[p] = nS; }
-      __syncthreads();
+      wave_sync();
       continue;
     }
     // group members by layer: counting sort with LDS atomics (order within a
     // layer does not matter, every selection breaks ties on the hit index)
     if (lane <= HT_MAX_LAYERS) M.lcnt[lane] = 0;
-    __syncthreads();
+    wave_sync();
     for (int m = lane; m < n; m += kWave)
       M.u.raw.slot[m] = (int16_t)atomicAdd(&M.lcnt[M.u.raw.L[m]], 1);
-    __syncthreads();
-    // layer starts: exclusive scan over lanes 0..16 (lane 16 holds n)
+    wave_sync();
+    // layer starts: exclusive scan of the 16 layer counts in the first row
+    // of lanes; lane 16 holds the total
     int ls;
     {
       const int c = lane < HT_MAX_LAYERS ? M.lcnt[lane] : 0;
-      int incl = c;
-      for (int d = 1; d <= HT_MAX_LAYERS; d <<= 1) {
-        const int t = __shfl_up(incl, d);
-        if (lane >= d) incl += t;
-      }
-      ls = incl - c;
+      const int incl = row_scan_incl(c);
+      const int total = __builtin_amdgcn_readlane(incl, HT_MAX_LAYERS - 1);
+      ls = lane < HT_MAX_LAYERS ? incl - c : total;
       if (lane <= HT_MAX_LAYERS) M.lstart[lane] = ls;
     }
-    __syncthreads();
+    wave_sync();
     for (int m = lane; m < n; m += kWave) {
       const int e = M.lstart[M.u.raw.L[m]] + M.u.raw.slot[m];
       M.mem[e] = M.u.raw.mem[m];
       M.adx[e] = M.u.raw.adx[m];
     }
-    __syncthreads();
+    wave_sync();
     // seed layers: innermost, middle and outermost of the outer min(nS, min_layers)
     const int span = nS < cfg.min_layers ? nS : cfg.min_layers;
     const int Ls[3] = {nth_set_bit(lmask, nS - span),
                        nth_set_bit(lmask, nS - span + (span - 1) / 2), nth_set_bit(lmask, nS - 1)};
     // seed_k nearest members per seed layer, by rank of (adx, h)
     const int kk = cfg.seed_k;
-    int ns[3];
+    int ns[3], sst[3], sen[3];
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-      const int st = __builtin_amdgcn_readlane(ls, Ls[s]);
-      const int en = __builtin_amdgcn_readlane(ls, Ls[s] + 1);
-      ns[s] = en - st < kk ? en - st : kk;
-      for (int e = st + lane; e < en; e += kWave) {
-        const unsigned long long key =
-            ((unsigned long long)__float_as_uint(M.adx[e]) << 32) | (unsigned)M.mem[e].h;
-        int rank = 0;
-        for (int e2 = st; e2 < en; ++e2) {
+      sst[s] = __builtin_amdgcn_readlane(ls, Ls[s]);
+      sen[s] = __builtin_amdgcn_readlane(ls, Ls[s] + 1);
+      ns[s] = sen[s] - sst[s] < kk ? sen[s] - sst[s] : kk;
+    }
+    const int n0 = sen[0] - sst[0], n1 = sen[1] - sst[1], n2 = sen[2] - sst[2];
+    if (n0 + n1 + n2 <= kWave) {
+      // the three seed layers side by side: lane -> (seed layer, member)
+      int s = -1, st = 0, en = 0;
+      if (lane < n0) { s = 0; st = sst[0]; en = sen[0]; }
+      else if (lane < n0 + n1) { s = 1; st = sst[1]; en = sen[1]; }
+      else if (lane < n0 + n1 + n2) { s = 2; st = sst[2]; en = sen[2]; }
+      const int e = st + lane - (s == 1 ? n0 : (s == 2 ? n0 + n1 : 0));
+      unsigned long long key = 0;
+      if (s >= 0) key = ((unsigned long long)__float_as_uint(M.adx[e]) << 32) | (unsigned)M.mem[e].h;
+      const int nmax = max(n0, max(n1, n2));
+      int rank = 0;
+      for (int t = 0; t < nmax; ++t) {
+        const int e2 = st + t;
+        if (s >= 0 && e2 < en) {
           const unsigned long long k2 =
               ((unsigned long long)__float_as_uint(M.adx[e2]) << 32) | (unsigned)M.mem[e2].h;
           rank += k2 < key;
         }
-        if (rank < kk) M.seed[s][rank] = e;
+      }
+      if (s >= 0 && rank < kk) M.seed[s][rank] = e;
+    } else {
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        const int st = sst[s], en = sen[s];
+        for (int e = st + lane; e < en; e += kWave) {
+          const unsigned long long key =
+              ((unsigned long long)__float_as_uint(M.adx[e]) << 32) | (unsigned)M.mem[e].h;
+          int rank = 0;
+          for (int e2 = st; e2 < en; ++e2) {
+            const unsigned long long k2 =
+                ((unsigned long long)__float_as_uint(M.adx[e2]) << 32) | (unsigned)M.mem[e2].h;
+            rank += k2 < key;
+          }
+          if (rank < kk) M.seed[s][rank] = e;
+        }
       }
     }
     // the grouped raw records are dead from here on; the union holds the
     // per-lane inlier rows
-    int32_t* hitL = M.u.hit[lane];
-    for (int L = 0; L < HT_MAX_LAYERS; ++L) hitL[L] = -1;
-    __syncthreads();
+    uint16_t* hitL = M.u.hit[lane];
+    for (int L = 0; L < HT_MAX_LAYERS; ++L) hitL[L] = kNoHit;
+    wave_sync();
     if (A.origin_seed) ns[0] = 1;
     const int nc = ns[0] * ns[1] * ns[2];
     // one combination per lane
@@ -725,9 +879,6 @@ __global__ __launch_bounds__(kWave) void refine_kernel(AssocArgs A) {
       if (!A.origin_seed) { xa = A.hx[ha]; ya = A.hy[ha]; }
       ok = circle3(xa, ya, A.hx[hb], A.hy[hb], A.hx[hc], A.hy[hc], &cA, &cB, &cC, &cD);
       if (ok) {
-        const double kapc = -(kCLight * A.bfield) *
-                            (A.qpt_lo + ((double)j + 0.5) * (A.qpt_hi - A.qpt_lo) / (double)A.n_qpt);
-        const double d0c = A.d0_lo + ((double)k + 0.5) * (A.d0_hi - A.d0_lo) / (double)A.n_d0;
         double ktol = (0.5 + (double)cfg.box_margin) * A.kap_bin;
         if (ktol < 1e-6) ktol = 1e-6;
         const double dtol = (0.5 + (double)cfg.box_margin) * A.d0_bin + road;
@@ -755,6 +906,9 @@ __global__ __launch_bounds__(kWave) void refine_kernel(AssocArgs A) {
       const float mag = fabsf(Af) * qmax + (fabsf(Bf) + fabsf(Cf)) * rmax + fabsf(Df);
       thr = pre + mag * 1e-6f;
     }
+    // road tests the method defines for this candidate: every member
+    // against every admissible seed circle
+    tests += (unsigned long long)__popcll(__ballot(ok)) * (unsigned long long)n;
     int n_in = ok ? 0 : -1;
     bool active = ok;
     // visiting order: layers that are not seed layers, then the seed layers
@@ -784,7 +938,7 @@ __global__ __launch_bounds__(kWave) void refine_kernel(AssocArgs A) {
         if (bh < 0 || dist < bd || (dist == bd && hh < bh)) { bh = hh; bd = dist; }
       }
       if (active) {
-        hitL[L] = bh;
+        hitL[L] = bh < 0 ? kNoHit : (uint16_t)bh;
         if (bh >= 0) ++n_in;
       }
     }
@@ -792,14 +946,14 @@ __global__ __launch_bounds__(kWave) void refine_kernel(AssocArgs A) {
     const int best_n = wave_max_i32(n_in);
     if (best_n < cfg.min_layers) {
       if (lane == 0) { A.cstat[p] = -1; A.cnl[p] = nS; }
-      __syncthreads();
+      wave_sync();
       continue;
     }
     double ss = 0.0;
     if (n_in == best_n) {
       for (unsigned lm = lmask; lm; lm &= lm - 1u) {
         const int hh = hitL[__builtin_ctz(lm)];
-        if (hh < 0) continue;
+        if (hh == kNoHit) continue;
         const double d = fabs(circle_dist(cA, cB, cC, cD, A.hx[hh], A.hy[hh], A.hq[hh]));
         ss += d * d;
       }
@@ -816,10 +970,14 @@ __global__ __launch_bounds__(kWave) void refine_kernel(AssocArgs A) {
       g[0] = ss; g[1] = cA; g[2] = cB; g[3] = cC; g[4] = cD;
       atomicAdd(&A.sc[S_NCAND], 1);
     }
-    __syncthreads();
-    if (lane < HT_MAX_LAYERS) A.chit[(size_t)p * HT_MAX_LAYERS + lane] = M.u.hit[win][lane];
-    __syncthreads();
+    wave_sync();
+    if (lane < HT_MAX_LAYERS) {
+      const int hh = M.u.hit[win][lane];
+      A.chit[(size_t)p * HT_MAX_LAYERS + lane] = hh == kNoHit ? -1 : hh;
+    }
+    wave_sync();
   }
+  if (lane == 0 && tests) atomicAdd(reinterpret_cast<unsigned long long*>(A.sc + S_TESTS), tests);
 }
 
 // ---- ownership -----------------------------------------------------------------
@@ -947,10 +1105,8 @@ __global__ __launch_bounds__(256) void fit_kernel(AssocArgs A) {
     const double gA = g[1], gB = g[2], gC = g[3], gD = g[4];
     const int lin = tr.lin;
     const int i = lin % A.n_phi, col = lin / A.n_phi, j = col % A.n_qpt, k = col / A.n_qpt;
-    const double cb = kCLight * A.bfield;
-    const double kap_c =
-        -cb * (A.qpt_lo + ((double)j + 0.5) * (A.qpt_hi - A.qpt_lo) / (double)A.n_qpt);
-    const double d0_c = A.d0_lo + ((double)k + 0.5) * (A.d0_hi - A.d0_lo) / (double)A.n_d0;
+    const double kap_c = A.kapc[j];
+    const double d0_c = A.d0c[k];
     const double sq0 = sqrt(gB * gB + gC * gC);
     double p0 = atan2(gB, -gC);
     double p1 = fk ? 2.0 * gA : kap_c;
@@ -1027,7 +1183,7 @@ __global__ __launch_bounds__(256) void fit_kernel(AssocArgs A) {
     if (lane == 0) {
       tr.status = status;
       tr.phi0 = (float)wrap_pi(p0);
-      tr.qpt = (float)(-p1 / cb);
+      tr.qpt = (float)(-p1 / A.cb);
       tr.d0 = (float)p2;
       tr.chi2 = (float)chi2;
     }
@@ -1237,7 +1393,8 @@ __global__ void counts_kernel(AssocArgs A) {
   c[4] = A.sc[S_NOVER];
   const unsigned long long pairs = *reinterpret_cast<const unsigned long long*>(A.sc + S_PAIRS);
   c[5] = pairs > 0x7fffffffull ? 0x7fffffff : (int32_t)pairs;
-  c[6] = 0;
+  const unsigned long long tests = *reinterpret_cast<const unsigned long long*>(A.sc + S_TESTS);
+  c[6] = tests > 0x7fffffffull ? 0x7fffffff : (int32_t)tests;
   c[7] = 0;
 }
 
@@ -1251,6 +1408,12 @@ int blocks_for(int64_t n, int per) {
   if (b < 1) b = 1;
   if (b > kGridCap) b = kGridCap;
   return (int)b;
+}
+
+template <int CAP>
+void launch_refine(const AssocArgs& A, int peak_cap, hipStream_t s) {
+  constexpr int W = RefineShape<CAP>::kWaves;
+  refine_kernel<CAP><<<blocks_for(peak_cap, W), W * kWave, 0, s>>>(A);
 }
 
 }  // namespace
@@ -1267,6 +1430,8 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   A.phi_lo = P.phi_lo;
   A.invw = P.invw;
   A.kap = P.d_kap;
+  A.kapc = P.d_kapc;
+  A.d0c = P.d_d0c;
   A.qt = P.d_q;
   A.tt = P.d_t;
   A.origin_seed = (g.n_d0 == 1 && g.d0_lo == 0.0f && g.d0_hi == 0.0f);
@@ -1275,11 +1440,7 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   A.d0_bin = ((double)g.d0_hi - (double)g.d0_lo) / (double)g.n_d0;
   A.hk = (float)(0.5 * A.kap_bin);
   A.hd0 = (float)(0.5 * A.d0_bin);
-  A.d0_lo = (double)g.d0_lo;
-  A.d0_hi = (double)g.d0_hi;
-  A.qpt_lo = (double)g.qpt_lo;
-  A.qpt_hi = (double)g.qpt_hi;
-  A.bfield = (double)g.bfield;
+  A.cb = cb;
   A.r = r;
   A.phi = phi;
   A.layer = layer;
@@ -1287,7 +1448,6 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   A.hx = P.d_hx;
   A.hy = P.d_hy;
   A.hq = P.d_hq;
-  A.hitA = P.d_hitA;
   A.hitB = P.d_hitB;
   A.peaks = peaks;
   A.n_peaks = n_peaks;
@@ -1296,7 +1456,7 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   A.pbits = P.d_pbits;
   A.col_first = P.d_col_first;
   A.mcount = P.d_mcount;
-  A.pool = reinterpret_cast<uint16_t*>(P.d_mem);
+  A.pool = P.d_mem;
   A.cstat = P.d_cstat;
   A.cnl = P.d_cnl;
   A.cgeo = P.d_cgeo;
@@ -1315,23 +1475,27 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
 
   const int words = P.n_tiles * 8 + 2;
   const int64_t init_n = words > n_hits ? words : n_hits;
+  P.prof_mark(HT_STAGE_ASSOC, 0, s);
   init_kernel<<<blocks_for(init_n, 256), 256, 0, s>>>(A, words);
   HT_CHECK(hipGetLastError());
   mark_kernel<<<blocks_for(peak_cap, 256), 256, 0, s>>>(A);
   HT_CHECK(hipGetLastError());
   dim3 sweep((g.n_qpt + kWave - 1) / kWave, g.n_d0);
+  P.prof_mark(HT_STAGE_MEMBERS, 0, s);
   member_kernel<<<sweep, kSweepThreads, 0, s>>>(A);
   HT_CHECK(hipGetLastError());
-  const int rblocks = blocks_for(peak_cap, 1) > 16384 ? 16384 : blocks_for(peak_cap, 1);
+  P.prof_mark(HT_STAGE_MEMBERS, 1, s);
+  P.prof_mark(HT_STAGE_REFINE, 0, s);
   if (cfg.member_cap <= 128)
-    refine_kernel<128><<<rblocks, kWave, 0, s>>>(A);
+    launch_refine<128>(A, peak_cap, s);
   else if (cfg.member_cap <= 256)
-    refine_kernel<256><<<rblocks, kWave, 0, s>>>(A);
+    launch_refine<256>(A, peak_cap, s);
   else if (cfg.member_cap <= 512)
-    refine_kernel<512><<<rblocks, kWave, 0, s>>>(A);
+    launch_refine<512>(A, peak_cap, s);
   else
-    refine_kernel<kMaxMembers><<<rblocks, kWave, 0, s>>>(A);
+    launch_refine<kMaxMembers>(A, peak_cap, s);
   HT_CHECK(hipGetLastError());
+  P.prof_mark(HT_STAGE_REFINE, 1, s);
   own_kernel<<<blocks_for(peak_cap, 256), 256, 0, s>>>(A);
   HT_CHECK(hipGetLastError());
   const int tiles = (peak_cap + 255) / 256 > 0 ? (peak_cap + 255) / 256 : 1;
@@ -1368,6 +1532,7 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   }
   counts_kernel<<<1, 1, 0, s>>>(A);
   HT_CHECK(hipGetLastError());
+  P.prof_mark(HT_STAGE_ASSOC, 1, s);
   return HT_OK;
 }
 

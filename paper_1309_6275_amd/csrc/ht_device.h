@@ -1,0 +1,63 @@
+// Device arithmetic shared by the kernels of the gfx950 Hough trigger
+// library: hit validity, the correctly rounded square root and the canonical
+// float32 arcsine of the vote.  Every floating-point expression here is
+// evaluated one IEEE operation at a time: the library is compiled with
+// -ffp-contract=off and the pragma below, so no multiply-add is fused.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#pragma clang fp contract(off)
+
+namespace ht {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kCLight = 0.299792458e-2;  // cm^-1 per (T GeV^-1)
+constexpr int kWave = 64;
+
+// Hit validity: r in (0, 1e4) cm, |phi| <= 4 rad, no NaN.
+__device__ __forceinline__ bool hit_ok(float r, float phi) {
+  return r > 0.0f && r < 1.0e4f && fabsf(phi) <= 4.0f;
+}
+
+// Correctly rounded square root for x = 0 or 2^-24 <= x <= 1 (the arguments
+// 1 - |u| of the arcsine and 1 - u*u of the member window never lie below
+// 2^-24 unless they are 0).  The
+// hardware v_sqrt_f32 is within one ulp; the neighbours s -/+ 1 ulp are
+// tested by the exact residuals x - s_dn*s and x - s_up*s (one fused
+// rounding each), which decide round-to-nearest because no float x lies
+// strictly between s_dn*s and the squared midpoint.  At x = 0 both tests
+// fail and 0 is returned.  (Inputs here are never denormal, so the general
+// expansion's rescaling and class checks are not needed.)
+__device__ __forceinline__ float sqrt_unit(float x) {
+  const float s = __builtin_amdgcn_sqrtf(x);
+  const float s_dn = __int_as_float(__float_as_int(s) - 1);
+  const float s_up = __int_as_float(__float_as_int(s) + 1);
+  const float r_dn = __builtin_fmaf(-s_dn, s, x);
+  const float r_up = __builtin_fmaf(-s_up, s, x);
+  float t = r_dn <= 0.0f ? s_dn : s;
+  t = r_up > 0.0f ? s_up : t;
+  return t;
+}
+
+// Canonical arcsine: Abramowitz & Stegun 4.4.46,
+//   asin a = pi/2 - sqrt(1 - a) (a0 + a1 a + ... + a7 a^7),  0 <= a <= 1,
+// Horner with separate multiply and add, correctly rounded square root,
+// sign restored with copysign.
+__device__ __forceinline__ float asin_f(float u) {
+  const float a = fabsf(u);
+  float p = -0.0012624911f;
+  p = p * a; p = p + 0.0066700901f;
+  p = p * a; p = p + -0.0170881256f;
+  p = p * a; p = p + 0.0308918810f;
+  p = p * a; p = p + -0.0501743046f;
+  p = p * a; p = p + 0.0889789874f;
+  p = p * a; p = p + -0.2145988016f;
+  p = p * a; p = p + 1.5707963050f;
+  const float s = sqrt_unit(1.0f - a);
+  const float r = 1.57079632679489661923f - s * p;
+  return copysignf(r, u);
+}
+
+}  // namespace ht

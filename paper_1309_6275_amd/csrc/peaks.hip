@@ -2,16 +2,19 @@
 // Algorithm"), written in cell order.
 //
 // Three launches, each a sweep over the cell range:
-//   1. flag: one thread per cell evaluates the 26-neighbour rule, a wave's
-//      flags become two bitmap words through one ballot, and each
-//      256-cell tile writes its peak count;
+//   1. flag: the 26-neighbour rule; a wave's flags become ballot words and
+//      each tile writes its peak count;
 //   2. scan: one workgroup turns tile counts into tile offsets and the
 //      total count;
-//   3. emit: one workgroup per tile reads its 8 bitmap words and writes its
-//      peaks at offset + rank, the rank coming from ballot/popcount prefix
-//      sums, so the list is sorted by cell index with no sort.
-// Neighbour reads of pass 1 hit L2 (the accumulator rows of a tile are read
-// by neighbouring tiles at the same time).
+//   3. emit: one workgroup per tile reads its ballot words and writes its
+//      peaks at offset + rank, the rank coming from popcount prefix sums, so
+//      the list is sorted by cell index with no sort.
+// When n_phi is a multiple of 4 (and the accumulator 16-byte aligned) a lane
+// takes 4 consecutive cells of one row: each of the 9 neighbour rows is one
+// 16-byte load plus the two cells beside it, 6.75 loads per cell instead of
+// 27, and a tile is 1024 cells.  Otherwise a lane takes one cell and a tile
+// is 256 cells.  Neighbour reads hit L2 (the rows of a tile are read by
+// neighbouring tiles at about the same time).
 #include "ht_internal.h"
 
 namespace ht {
@@ -106,6 +109,137 @@ __global__ __launch_bounds__(kTile) void emit_kernel(const int32_t* __restrict__
   }
 }
 
+// ---- four cells per lane ------------------------------------------------------
+constexpr int kTile4 = 1024;  // 4 waves x 64 lanes x 4 cells
+constexpr int kXcds = 8;      // MI355X: workgroup b runs on XCD b mod 8
+
+// Tile of workgroup b: each XCD takes one contiguous range of tiles, so the
+// neighbour rows that consecutive tiles share stay in that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int n_tiles) {
+  const int per = n_tiles / kXcds, rem = n_tiles % kXcds;
+  const int x = b % kXcds, i = b / kXcds;
+  return x * per + min(x, rem) + i;
+}
+
+// cells i0-1 .. i0+4 of a row (phi0 periodic); i0 is a multiple of 4
+__device__ __forceinline__ void load_row6(const int32_t* __restrict__ row, int i0, int n_phi,
+                                          int32_t w[6]) {
+  const int4 m = *reinterpret_cast<const int4*>(row + i0);
+  w[0] = row[i0 == 0 ? n_phi - 1 : i0 - 1];
+  w[1] = m.x;
+  w[2] = m.y;
+  w[3] = m.z;
+  w[4] = m.w;
+  w[5] = row[i0 + 4 == n_phi ? 0 : i0 + 4];
+}
+
+// Ballot words: wave w of tile b writes 4 words at (b * 4 + w) * 4; bit l of
+// word t flags cell b * 1024 + w * 256 + 4 l + t.
+__global__ __launch_bounds__(256) void flag4_kernel(const int32_t* __restrict__ acc, int n_phi,
+                                                    int n_qpt, int n_d0, int64_t n_cells,
+                                                    int32_t thr, uint64_t* __restrict__ bits,
+                                                    int32_t* __restrict__ tile_cnt) {
+  __shared__ int32_t wcnt[4];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x >> 6;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t lin0 = (int64_t)tile * kTile4 + (int64_t)threadIdx.x * 4;
+  bool f[4] = {false, false, false, false};
+  if (lin0 < n_cells) {  // n_cells is a multiple of 4: all four cells exist
+    const int i0 = (int)(lin0 % n_phi);
+    const int64_t col = lin0 / n_phi;
+    const int j = (int)(col % n_qpt);
+    const int k = (int)(col / n_qpt);
+    const int4 c4 = *reinterpret_cast<const int4*>(acc + lin0);
+    const int32_t v[4] = {c4.x, c4.y, c4.z, c4.w};
+    bool any = false;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      f[t] = v[t] >= thr;
+      any = any || f[t];
+    }
+    if (any) {
+#pragma unroll
+      for (int dk = -1; dk <= 1; ++dk) {
+        const int kk = k + dk;
+        if (kk < 0 || kk >= n_d0) continue;
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj) {
+          const int jj = j + dj;
+          if (jj < 0 || jj >= n_qpt) continue;
+          int32_t w[6];
+          load_row6(acc + ((size_t)kk * n_qpt + jj) * n_phi, i0, n_phi, w);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int32_t a = w[t], b = w[t + 1], c = w[t + 2];  // cells i-1, i, i+1
+            if (dk < 0 || (dk == 0 && dj < 0))
+              f[t] = f[t] && v[t] > a && v[t] > b && v[t] > c;
+            else if (dk == 0 && dj == 0)
+              f[t] = f[t] && v[t] > a && v[t] >= c;
+            else
+              f[t] = f[t] && v[t] >= a && v[t] >= b && v[t] >= c;
+          }
+        }
+      }
+    }
+  }
+  uint64_t m[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) m[t] = __ballot(f[t]);
+  if (lane == 0) {
+    uint64_t* wb = bits + ((size_t)tile * 4 + wave) * 4;
+    int c = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      wb[t] = m[t];
+      c += __popcll(m[t]);
+    }
+    wcnt[wave] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) tile_cnt[tile] = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+}
+
+__global__ __launch_bounds__(256) void emit4_kernel(const int32_t* __restrict__ acc,
+                                                    const uint64_t* __restrict__ bits,
+                                                    const int32_t* __restrict__ tile_off,
+                                                    int64_t n_cells, ht_peak* __restrict__ out,
+                                                    int32_t capacity) {
+  __shared__ int32_t wpre[4];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x >> 6;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const uint64_t* wb = bits + ((size_t)tile * 4 + wave) * 4;
+  uint64_t m[4];
+  int c = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    m[t] = wb[t];
+    c += __popcll(m[t]);
+  }
+  if (lane == 0) wpre[wave] = c;
+  __syncthreads();
+  int64_t idx = tile_off[tile];
+  for (int w = 0; w < wave; ++w) idx += wpre[w];
+  const uint64_t below = lane ? ((1ull << lane) - 1ull) : 0ull;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) idx += __popcll(m[t] & below);
+  const int64_t lin0 = (int64_t)tile * kTile4 + (int64_t)threadIdx.x * 4;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if ((m[t] >> lane) & 1ull) {
+      const int64_t lin = lin0 + t;
+      if (idx < capacity && lin < n_cells) {
+        ht_peak p;
+        p.lin = (int32_t)lin;
+        p.votes = acc[lin];
+        out[idx] = p;
+      }
+      ++idx;
+    }
+  }
+}
+
 }  // namespace
 
 int peaks_init(int) { return HT_OK; }
@@ -113,16 +247,27 @@ int peaks_init(int) { return HT_OK; }
 int launch_peaks(const Plan& p, const int32_t* acc, int32_t min_votes, ht_peak* out,
                  int32_t capacity, int32_t* n_found, hipStream_t s) {
   const ht_grid& g = p.grid;
-  const int tiles = p.n_tiles;
-  flag_kernel<<<tiles, kTile, 0, s>>>(acc, g.n_phi, g.n_qpt, g.n_d0, p.n_cells, min_votes,
-                                      p.d_bits, p.d_tile_cnt);
+  const bool four = (g.n_phi & 3) == 0 && ((uintptr_t)acc & 15) == 0;
+  const int tiles = four ? (int)((p.n_cells + kTile4 - 1) / kTile4) : p.n_tiles;
+  p.prof_mark(HT_STAGE_PEAKS, 0, s);
+  if (four)
+    flag4_kernel<<<tiles, 256, 0, s>>>(acc, g.n_phi, g.n_qpt, g.n_d0, p.n_cells, min_votes,
+                                       reinterpret_cast<uint64_t*>(p.d_bits), p.d_tile_cnt);
+  else
+    flag_kernel<<<tiles, kTile, 0, s>>>(acc, g.n_phi, g.n_qpt, g.n_d0, p.n_cells, min_votes,
+                                        p.d_bits, p.d_tile_cnt);
   HT_CHECK(hipGetLastError());
   const int rc = launch_scan(p.d_tile_cnt, p.d_tile_off, tiles, n_found, s);
   if (rc != HT_OK) return rc;
   if (capacity > 0) {
-    emit_kernel<<<tiles, kTile, 0, s>>>(acc, p.d_bits, p.d_tile_off, p.n_cells, out, capacity);
+    if (four)
+      emit4_kernel<<<tiles, 256, 0, s>>>(acc, reinterpret_cast<const uint64_t*>(p.d_bits),
+                                         p.d_tile_off, p.n_cells, out, capacity);
+    else
+      emit_kernel<<<tiles, kTile, 0, s>>>(acc, p.d_bits, p.d_tile_off, p.n_cells, out, capacity);
     HT_CHECK(hipGetLastError());
   }
+  p.prof_mark(HT_STAGE_PEAKS, 1, s);
   return HT_OK;
 }
 

@@ -1,14 +1,17 @@
-// Exclusive prefix sum of int32 counts (tile counts -> tile offsets), one
-// workgroup of 16 waves: each wave owns a contiguous chunk read 64 elements
-// at a time (coalesced); pass 1 sums the chunks, pass 2 scans each chunk
-// from its wave's offset with shuffle prefix sums.  Offsets and the total
-// are clamped to INT32_MAX.
+// Exclusive prefix sum of int32 counts (tile counts -> tile offsets) in one
+// workgroup of 1024 threads.  Thread t owns the contiguous run
+// [t * per, (t + 1) * per) of the n counts: it sums its run, the workgroup
+// scans the 1024 run sums (one wave scan and 16 wave totals), and the thread
+// walks its run again writing offsets.  Each thread's loads stay in its own
+// cache lines, and the only cross-lane steps are one scan per wave, not one
+// per 64 counts.  Offsets and the total are clamped to INT32_MAX.
 #include "ht_internal.h"
 
 namespace ht {
 namespace {
 
-constexpr int kScanWaves = 16;
+constexpr int kScanThreads = 1024;
+constexpr int kScanWaves = kScanThreads / kWave;
 
 __device__ __forceinline__ long long wave_incl_scan(long long v, int lane) {
   for (int d = 1; d < kWave; d <<= 1) {
@@ -18,41 +21,39 @@ __device__ __forceinline__ long long wave_incl_scan(long long v, int lane) {
   return v;
 }
 
-__global__ __launch_bounds__(kScanWaves* kWave) void scan_kernel(const int32_t* __restrict__ cnt,
-                                                                 int32_t* __restrict__ off, int n,
-                                                                 int32_t* __restrict__ total) {
+__device__ __forceinline__ int32_t clamp_i32(long long v) {
+  return v > 0x7fffffffLL ? 0x7fffffff : (int32_t)v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_kernel(const int32_t* __restrict__ cnt,
+                                                            int32_t* __restrict__ off, int n,
+                                                            int32_t* __restrict__ total) {
   __shared__ long long wsum[kScanWaves];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x >> 6;
-  const int chunk = ((n + kScanWaves - 1) / kScanWaves + kWave - 1) / kWave * kWave;
-  const int b = wave * chunk;
-  const int e = min(n, b + chunk);
+  const int t = threadIdx.x;
+  const int lane = t & (kWave - 1);
+  const int wave = t >> 6;
+  const int per = (n + kScanThreads - 1) / kScanThreads;
+  const int b = (int)min((long long)n, (long long)t * per);
+  const int e = min(n, b + per);
   long long s = 0;
-  for (int x = b + lane; x < e; x += kWave) s += cnt[x];
-  for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d);
-  if (lane == 0) wsum[wave] = s;
+  for (int x = b; x < e; ++x) s += cnt[x];
+  const long long incl = wave_incl_scan(s, lane);
+  if (lane == kWave - 1) wsum[wave] = incl;
   __syncthreads();
-  long long run = 0;
-  for (int w = 0; w < wave; ++w) run += wsum[w];
-  for (int base = b; base < e; base += kWave) {
-    const int x = base + lane;
-    const long long v = x < e ? cnt[x] : 0;
-    const long long incl = wave_incl_scan(v, lane);
-    const long long ex = run + incl - v;
-    if (x < e) off[x] = ex > 0x7fffffffLL ? 0x7fffffff : (int32_t)ex;
-    run += __shfl(incl, kWave - 1);
+  long long base = 0;
+  for (int w = 0; w < wave; ++w) base += wsum[w];
+  long long run = base + incl - s;
+  for (int x = b; x < e; ++x) {
+    off[x] = clamp_i32(run);
+    run += cnt[x];
   }
-  if (threadIdx.x == 0 && total) {
-    long long t = 0;
-    for (int w = 0; w < kScanWaves; ++w) t += wsum[w];
-    *total = t > 0x7fffffffLL ? 0x7fffffff : (int32_t)t;
-  }
+  if (t == kScanThreads - 1 && total) *total = clamp_i32(base + incl);
 }
 
 }  // namespace
 
 int launch_scan(const int32_t* cnt, int32_t* off, int n, int32_t* total, hipStream_t s) {
-  scan_kernel<<<1, kScanWaves * kWave, 0, s>>>(cnt, off, n, total);
+  scan_kernel<<<1, kScanThreads, 0, s>>>(cnt, off, n, total);
   HT_CHECK(hipGetLastError());
   return HT_OK;
 }

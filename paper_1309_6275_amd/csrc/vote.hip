@@ -161,9 +161,11 @@ int launch_vote(const Plan& p, const float* r, const float* phi, int32_t n_hits,
   const bool wide = vote_wide(g.n_phi);
   auto kern = pow2 ? (wide ? vote_kernel<true, true> : vote_kernel<true, false>)
                    : (wide ? vote_kernel<false, true> : vote_kernel<false, false>);
+  p.prof_mark(HT_STAGE_VOTE, 0, s);
   kern<<<grid, kVoteThreads, lds_bytes, s>>>(r, phi, n_hits, p.d_kap, p.d_q, p.d_t, g.n_phi,
                                              g.n_qpt, p.phi_lo, p.invw, stride, acc, n_votes);
   HT_CHECK(hipGetLastError());
+  p.prof_mark(HT_STAGE_VOTE, 1, s);
   return HT_OK;
 }
 

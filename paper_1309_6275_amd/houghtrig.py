@@ -86,7 +86,11 @@ def lib():
         L.hough_peaks.argtypes = [vp, vp, i32, vp, i32, vp, vp]
         L.assoc_cluster.argtypes = [vp, vp, vp, vp, i32, vp, vp, i32, vp, vp, vp]
         L.ht_asin_f32.argtypes = [vp, vp, i64, vp]
-        for f in ("ht_plan_create", "hough_vote", "hough_peaks", "assoc_cluster", "ht_asin_f32"):
+        L.ht_profile_begin.argtypes = [vp, i32]
+        L.ht_profile_read.argtypes = [vp, vp, vp]
+        L.ht_profile_end.argtypes = [vp]
+        for f in ("ht_plan_create", "hough_vote", "hough_peaks", "assoc_cluster", "ht_asin_f32",
+                  "ht_profile_begin", "ht_profile_read", "ht_profile_end"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -264,5 +268,33 @@ def asin_f32(u, out, stream=None):
                              int(u.numel()), _stream(stream)), "ht_asin_f32")
 
 
+STAGES = ("vote", "peaks", "assoc", "members", "refine")  # HT_STAGE_* order
+
+
+def profile_begin(plan: "Plan", depth: int = 1024):
+    """Start timing the stages of later calls on ``plan`` with HIP events."""
+    _check(lib().ht_profile_begin(plan.handle, int(depth)), "ht_profile_begin")
+
+
+def profile_read(plan: "Plan", acc: dict | None = None) -> dict:
+    """Add the stage times recorded since the last read to ``acc`` (a dict
+    of stage -> [milliseconds, launches]) and return it."""
+    ms = np.zeros(len(STAGES), np.float64)
+    n = np.zeros(len(STAGES), np.int64)
+    _check(lib().ht_profile_read(plan.handle, ms.ctypes.data_as(C.c_void_p),
+                                 n.ctypes.data_as(C.c_void_p)), "ht_profile_read")
+    acc = {} if acc is None else acc
+    for name, t, c in zip(STAGES, ms, n):
+        a = acc.setdefault(name, [0.0, 0])
+        a[0] += float(t)
+        a[1] += int(c)
+    return acc
+
+
+def profile_end(plan: "Plan"):
+    _check(lib().ht_profile_end(plan.handle), "ht_profile_end")
+
+
 EXPORTS = ("ht_plan_create", "ht_plan_destroy", "ht_strerror", "hough_vote", "hough_peaks",
-           "assoc_cluster", "ht_asin_f32")
+           "assoc_cluster", "ht_asin_f32", "ht_profile_begin", "ht_profile_read",
+           "ht_profile_end")

@@ -5,6 +5,8 @@ Integer results (counts, ownership, track hits, vertex accumulator, objects,
 members) and float results computed by copying or by fixed-order float64
 arithmetic (r_first, seed sums, isotropy) must be bit-exact; the refit uses
 the device asin/atan2 and must agree within 1e-5 relative."""
+from types import SimpleNamespace
+
 import numpy as np
 import pytest
 
@@ -74,7 +76,7 @@ def run_oracle(oracle, grid, ev, acc, pk_gpu, cfg, track_cap=4096, object_cap=51
 
 
 def compare(got, want, label=""):
-    assert np.array_equal(got["counts"][:6], want["counts"][:6]), (label, got["counts"],
+    assert np.array_equal(got["counts"][:7], want["counts"][:7]), (label, got["counts"],
                                                                    want["counts"])
     assert np.array_equal(got["hit_owner"], want["hit_owner"]), label
     gt, wt = got["tracks"], want["tracks"]
@@ -118,6 +120,20 @@ def test_assoc_parity_dense_event_truncated_peaks(torch, ht, oracle):
                            peak_cap=3000)
     want = run_oracle(oracle, W["grid"], ev, acc, pk, W["cluster"])
     compare(got, want, "cfg3/3000")
+
+
+def test_assoc_parity_many_peaks_per_workgroup(torch, ht, oracle):
+    """Over 4096 peaks among one workgroup's 64 columns: the member sweep
+    keeps the candidates' slot counters in global memory instead of LDS."""
+    grid = dict(CF.GRID_2D, n_phi=1024, n_qpt=64)
+    r, phi, layer = G.random_hits(3000, seed=41, r_lo=3.0, r_hi=105.0, bad_fraction=0.02)
+    ev = SimpleNamespace(r=r, phi=phi, layer=layer, n_hits=int(r.size))
+    cfg = dict(CF.CLUSTER_2D, min_layers=4, member_cap=1024)
+    got, acc, pk = run_gpu(torch, ht, grid, ev, 1, cfg)
+    print(f"peaks {pk.shape[0]}", flush=True)
+    assert pk.shape[0] > 4096
+    want = run_oracle(oracle, grid, ev, acc, pk, cfg)
+    compare(got, want, "many peaks")
 
 
 @pytest.mark.parametrize("kind", ["jet", "bh"])
