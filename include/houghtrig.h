@@ -228,6 +228,11 @@ int ht_profile_end(ht_plan* plan);
  * over n device floats (for checking the formula on the device). */
 int ht_asin_f32(const float* u, float* out, int64_t n, void* stream);
 
+/* ht_sqrt_f64 -- the correctly rounded float64 square root the refinement's
+ * seed circles use, elementwise over n device doubles (for checking it on
+ * the device against an IEEE square root). */
+int ht_sqrt_f64(const double* x, double* out, int64_t n, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -227,7 +227,14 @@ int assoc_cluster(const ht_plan* p, const float* r, const float* phi, const uint
 
 int ht_asin_f32(const float* u, float* out, int64_t n, void* stream) {
   if (n < 0 || (n > 0 && (!u || !out))) return HT_EINVAL;
+  if (n > ((int64_t)1 << 38)) return HT_EUNSUPPORTED;  // grid limit
   return ht::launch_asin(u, out, n, (hipStream_t)stream);
+}
+
+int ht_sqrt_f64(const double* x, double* out, int64_t n, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !out))) return HT_EINVAL;
+  if (n > ((int64_t)1 << 38)) return HT_EUNSUPPORTED;  // grid limit
+  return ht::launch_sqrt(x, out, n, (hipStream_t)stream);
 }
 
 int ht_profile_begin(ht_plan* p, int32_t depth) {

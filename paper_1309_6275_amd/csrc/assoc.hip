@@ -142,7 +142,7 @@ __device__ bool circle3(double x1, double y1, double x2, double y2, double x3, d
   double c = q2 * X3 - X2 * q3;
   double nrm2 = b * b + c * c;
   if (!(nrm2 > 0.0)) return false;
-  double nrm = sqrt(nrm2);
+  double nrm = sqrt_d(nrm2);
   double q1 = x1 * x1 + y1 * y1;
   double AA = a;
   double BB = b - 2.0 * a * x1;
@@ -865,14 +865,12 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
     for (int L = 0; L < HT_MAX_LAYERS; ++L) hitL[L] = kNoHit;
     wave_sync();
     if (A.origin_seed) ns[0] = 1;
-    const int nc = ns[0] * ns[1] * ns[2];
-    // one combination per lane
+    // one combination per lane: lane = 16 a + 4 b + c (seed_k <= 4), which
+    // orders the lanes like the combinations (a, b, c)
+    const int a = lane >> 4, b = (lane >> 2) & 3, c = lane & 3;
     double cA = 0.0, cB = 0.0, cC = 0.0, cD = 0.0;
     bool ok = false;
-    if (lane < nc) {
-      const int a = lane / (ns[1] * ns[2]);
-      const int b = (lane / ns[2]) % ns[1];
-      const int c = lane % ns[2];
+    if (a < ns[0] && b < ns[1] && c < ns[2]) {
       const int ha = M.mem[M.seed[0][a]].h, hb = M.mem[M.seed[1][b]].h;
       const int hc = M.mem[M.seed[2][c]].h;
       double xa = 0.0, ya = 0.0;
@@ -889,7 +887,8 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
       }
     }
     // |dist| >= |f| / (1 + |A||f|): a member with |f| > road / (1 - road |A|)
-    // cannot be within the road.  The float32 test allows a margin of 1e-6
+    // cannot be within the road, and road / (1 - x) <= road (1 + 2x) for
+    // x <= 1/2, a bound without a division.  The float32 test allows a margin of 1e-6
     // of a bound on the magnitudes of the terms and partial sums over all
     // members (|x|, |y| <= rmax, q <= qmax), far above what the rounding of
     // the coefficients, of the coordinates and of three fused multiply-adds
@@ -898,7 +897,7 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
     float Af = 0.0f, Bf = 0.0f, Cf = 0.0f, Df = 0.0f, thr = -1.0f;
     if (ok) {
       const double ra = road * fabs(cA);
-      const float pre = ra < 0.5 ? (float)(road / (1.0 - ra) * 1.000001) : __builtin_inff();
+      const float pre = ra <= 0.5 ? (float)(road * (1.0 + 2.0 * ra) * 1.000001) : __builtin_inff();
       Af = (float)cA;
       Bf = (float)cB;
       Cf = (float)cC;

@@ -41,6 +41,31 @@ __device__ __forceinline__ float sqrt_unit(float x) {
   return t;
 }
 
+// Correctly rounded float64 square root for 2^-120 <= x <= 2^120 (other
+// arguments take the hardware path), without the float64 reciprocal square
+// root instruction, whose use in long dependent chains proved slow here:
+// float32 seed of 1/sqrt(x) (relative error < 2^-21), two Newton steps in
+// float64, s = x y, one residual correction, then the exact residual test of
+// s and its neighbours that sqrt_unit uses in float32 (Tuckerman's test: no
+// double x lies strictly between s_dn * s and the squared midpoint, because
+// s_dn * s is a multiple of the square of s's ulp and x a multiple of it).
+__device__ __forceinline__ double sqrt_d(double x) {
+  if (!(x >= 0x1p-120 && x <= 0x1p120)) return __builtin_sqrt(x);
+  double y = (double)__builtin_amdgcn_rsqf((float)x);
+  const double hx = 0.5 * x;
+  y = y * __builtin_fma(-hx * y, y, 1.5);
+  y = y * __builtin_fma(-hx * y, y, 1.5);
+  double s = x * y;
+  s = __builtin_fma(__builtin_fma(-s, s, x), 0.5 * y, s);
+  const double s_dn = __longlong_as_double(__double_as_longlong(s) - 1);
+  const double s_up = __longlong_as_double(__double_as_longlong(s) + 1);
+  const double r_dn = __builtin_fma(-s_dn, s, x);
+  const double r_up = __builtin_fma(-s_up, s, x);
+  double t = r_dn <= 0.0 ? s_dn : s;
+  t = r_up > 0.0 ? s_up : t;
+  return t;
+}
+
 // Canonical arcsine: Abramowitz & Stegun 4.4.46,
 //   asin a = pi/2 - sqrt(1 - a) (a0 + a1 a + ... + a7 a^7),  0 <= a <= 1,
 // Horner with separate multiply and add, correctly rounded square root,

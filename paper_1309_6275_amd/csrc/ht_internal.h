@@ -80,6 +80,7 @@ int launch_assoc(const Plan& p, const float* r, const float* phi, const uint8_t*
                  int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks, int32_t peak_cap,
                  const ht_cluster_cfg& cfg, const ht_cluster_out& out, hipStream_t s);
 int launch_asin(const float* u, float* out, int64_t n, hipStream_t s);
+int launch_sqrt(const double* x, double* out, int64_t n, hipStream_t s);
 int launch_scan(const int32_t* cnt, int32_t* off, int n, int32_t* total, hipStream_t s);
 int vote_init(int n_phi);
 int peaks_init(int n_phi);

@@ -126,6 +126,11 @@ __global__ void asin_kernel(const float* __restrict__ u, float* __restrict__ out
   if (i < n) out[i] = asin_f(u[i]);
 }
 
+__global__ void sqrt_kernel(const double* __restrict__ x, double* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = sqrt_d(x[i]);
+}
+
 __global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
 
 constexpr int kLdsBytes = 160 * 1024;
@@ -166,6 +171,15 @@ int launch_vote(const Plan& p, const float* r, const float* phi, int32_t n_hits,
                                              g.n_qpt, p.phi_lo, p.invw, stride, acc, n_votes);
   HT_CHECK(hipGetLastError());
   p.prof_mark(HT_STAGE_VOTE, 1, s);
+  return HT_OK;
+}
+
+int launch_sqrt(const double* x, double* out, int64_t n, hipStream_t s) {
+  if (n == 0) return HT_OK;
+  const int threads = 256;
+  const int64_t blocks = (n + threads - 1) / threads;
+  sqrt_kernel<<<(unsigned)blocks, threads, 0, s>>>(x, out, n);
+  HT_CHECK(hipGetLastError());
   return HT_OK;
 }
 

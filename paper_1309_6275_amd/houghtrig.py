@@ -86,11 +86,12 @@ def lib():
         L.hough_peaks.argtypes = [vp, vp, i32, vp, i32, vp, vp]
         L.assoc_cluster.argtypes = [vp, vp, vp, vp, i32, vp, vp, i32, vp, vp, vp]
         L.ht_asin_f32.argtypes = [vp, vp, i64, vp]
+        L.ht_sqrt_f64.argtypes = [vp, vp, i64, vp]
         L.ht_profile_begin.argtypes = [vp, i32]
         L.ht_profile_read.argtypes = [vp, vp, vp]
         L.ht_profile_end.argtypes = [vp]
         for f in ("ht_plan_create", "hough_vote", "hough_peaks", "assoc_cluster", "ht_asin_f32",
-                  "ht_profile_begin", "ht_profile_read", "ht_profile_end"):
+                  "ht_sqrt_f64", "ht_profile_begin", "ht_profile_read", "ht_profile_end"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -268,6 +269,12 @@ def asin_f32(u, out, stream=None):
                              int(u.numel()), _stream(stream)), "ht_asin_f32")
 
 
+def sqrt_f64(x, out, stream=None):
+    torch = _torch()
+    _check(lib().ht_sqrt_f64(_ptr(x, torch.float64, "x"), _ptr(out, torch.float64, "out"),
+                             int(x.numel()), _stream(stream)), "ht_sqrt_f64")
+
+
 STAGES = ("vote", "peaks", "assoc", "members", "refine")  # HT_STAGE_* order
 
 
@@ -296,5 +303,5 @@ def profile_end(plan: "Plan"):
 
 
 EXPORTS = ("ht_plan_create", "ht_plan_destroy", "ht_strerror", "hough_vote", "hough_peaks",
-           "assoc_cluster", "ht_asin_f32", "ht_profile_begin", "ht_profile_read",
+           "assoc_cluster", "ht_asin_f32", "ht_sqrt_f64", "ht_profile_begin", "ht_profile_read",
            "ht_profile_end")

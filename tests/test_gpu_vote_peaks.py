@@ -78,6 +78,43 @@ def test_asin_exhaustive_bitwise(torch, ht, oracle):
             assert bad.size == 0, (u[bad[:5]], got[bad[:5]], want[bad[:5]])
 
 
+def sqrt_cases(rng):
+    """Doubles for the float64 square root: random over the whole exponent
+    range, neighbours of exact squares and of squared midpoints (the cases
+    where the rounding decision is hardest), powers of two and specials."""
+    parts = [np.ldexp(rng.uniform(1.0, 2.0, 1 << 22), rng.integers(-1070, 1020, 1 << 22)),
+             np.ldexp(rng.uniform(1.0, 2.0, 1 << 22), rng.integers(-130, 130, 1 << 22))]
+    s = np.ldexp(rng.uniform(1.0, 2.0, 1 << 18), rng.integers(-60, 60, 1 << 18))
+    sq = (s * s).view(np.int64)
+    for d in range(-3, 4):
+        parts.append((sq + d).view(np.float64))
+    u = np.nextafter(s, np.inf) - s
+    mid = s + u / 2  # rounds to s or its neighbour; the square is then near a midpoint square
+    parts.append(mid * mid)
+    p2 = np.ldexp(1.0, np.arange(-1074, 1024)).view(np.int64)
+    for d in (-1, 0, 1):
+        parts.append((p2 + d).view(np.float64))
+    parts.append(np.array([0.0, -0.0, np.inf, 5e-324, 2.2250738585072014e-308, np.nan, -1.0]))
+    x = np.concatenate(parts)
+    return x
+
+
+def test_sqrt_f64_bitwise(torch, ht):
+    """The refinement's float64 square root equals the IEEE square root
+    (numpy, correctly rounded) bit for bit."""
+    x = sqrt_cases(np.random.default_rng(2024))
+    xd = torch.from_numpy(x).cuda()
+    od = torch.empty_like(xd)
+    ht.sqrt_f64(xd, od)
+    got = od.cpu().numpy()
+    with np.errstate(invalid="ignore"):
+        want = np.sqrt(x)
+    nan = np.isnan(want)
+    assert np.array_equal(np.isnan(got), nan)
+    bad = np.flatnonzero(got[~nan].view(np.int64) != want[~nan].view(np.int64))
+    assert bad.size == 0, (x[~nan][bad[:5]], got[~nan][bad[:5]], want[~nan][bad[:5]])
+
+
 @pytest.mark.parametrize("cfg,seeds", [(1, range(6)), (2, range(3)), (3, range(1))])
 def test_vote_parity_workloads(torch, ht, oracle, cfg, seeds):
     W = CF.WORKLOADS[cfg]
