@@ -36,6 +36,7 @@
 #ifndef HOUGHTRIG_H
 #define HOUGHTRIG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -47,7 +48,8 @@ enum {
   HT_EINVAL = -1,        /* bad argument (null pointer, size out of range) */
   HT_ENOMEM = -2,        /* device allocation failed (plan creation only) */
   HT_EDEVICE = -3,       /* a HIP runtime call failed */
-  HT_EUNSUPPORTED = -4   /* valid request beyond this build's kernel limits */
+  HT_EUNSUPPORTED = -4,  /* valid request beyond this build's kernel limits */
+  HT_EBUSY = -5          /* serving loop: every slot busy and the wait queue full */
 };
 
 #define HT_MAX_LAYERS 16
@@ -223,6 +225,132 @@ enum { HT_STAGE_VOTE = 0, HT_STAGE_PEAKS = 1, HT_STAGE_ASSOC = 2, HT_STAGE_MEMBE
 int ht_profile_begin(ht_plan* plan, int32_t depth);
 int ht_profile_read(ht_plan* plan, double* ms, int64_t* launches);
 int ht_profile_end(ht_plan* plan);
+
+/* ---- Learned peak filter ---------------------------------------------------
+ * A 3D CNN scores each threshold peak from the 5 x 5 x 5 votes around it;
+ * peaks scoring below a threshold are dropped before assoc_cluster (the
+ * paper's call for efficiency and purity improvements of the peak finding,
+ * section "Conclusion").  Network: conv3d 1->16 (3x3x3, valid), ReLU,
+ * conv3d 16->16 (3x3x3, valid), ReLU, linear 16->64, ReLU, linear 64->1
+ * (a logit).  Parameters: HT_CNN_PARAMS float32 in the order
+ *   W1[16][27] b1[16] W2[16][16][27] b2[16] W3[64][16] b3[64] W4[64] b4
+ * (tap t = (dk * 3 + dj) * 3 + di).  Arithmetic: bfloat16 inputs, weights
+ * and activations (round to nearest even), float32 accumulation, bias after
+ * the sum.  Windows: HT_CNN_WINDOW bfloat16 per peak, cell (dk, dj, di) in
+ * -2..2 at index (dk+2)*25 + (dj+2)*5 + (di+2), votes * 1/16, phi0 periodic,
+ * cells outside the q/pT and d0 range 0, entries 125..127 zero. */
+#define HT_CNN_PARAMS 8529
+#define HT_CNN_WINDOW 128
+
+/* Device bytes of the workspace the CNN calls below need for max_windows
+ * windows (training != 0: a training step; else inference). */
+size_t ht_cnn_workspace_bytes(int32_t max_windows, int32_t training);
+/* Windows of the first min(*n_peaks, cap) peaks (device count) of a peak
+ * list of this plan's grid into win [cap][HT_CNN_WINDOW] (bfloat16 bits).
+ * cap <= the plan's max_peaks. */
+int ht_cnn_windows(const ht_plan* plan, const int32_t* acc, const ht_peak* peaks,
+                   const int32_t* n_peaks, int32_t cap, uint16_t* win, void* stream);
+/* Logits of n windows: n = min(*n_dev, n_max) when n_dev is not NULL (a
+ * device count), else n_max.  params: device float32 [HT_CNN_PARAMS]. */
+int ht_cnn_forward(const float* params, const uint16_t* win, const int32_t* n_dev, int32_t n_max,
+                   float* logits, void* workspace, size_t workspace_bytes, void* stream);
+/* One SGD step on n labelled windows (labels 0/1 as float): loss = mean over
+ * the windows of w (softplus(z) - y z), w = pos_weight for y = 1, else 1;
+ * mom <- momentum mom + grad; params <- params - lr mom.  *loss (device)
+ * receives the loss before the step.  Gradients are summed with float32
+ * atomics, so the last bits vary from run to run. */
+int ht_cnn_train_step(float* params, float* mom, const uint16_t* win, const float* labels,
+                      int32_t n, float lr, float momentum, float pos_weight, float* loss,
+                      void* workspace, size_t workspace_bytes, void* stream);
+/* Ordered compaction: the peaks among the first min(*n_peaks, cap) whose
+ * logit is >= threshold, in their order, into out [out_cap]; *n_out (device)
+ * receives their full count.  cap <= the plan's max_peaks. */
+int ht_cnn_keep(const ht_plan* plan, const float* logits, const ht_peak* peaks,
+                const int32_t* n_peaks, int32_t cap, float threshold, ht_peak* out,
+                int32_t out_cap, int32_t* n_out, void* stream);
+
+/* ---- Trigger serving loop --------------------------------------------------
+ * Events of any size arrive one by one (the paper's trigger setting: each
+ * event must be processed within the latency the trigger allows, section
+ * "Physics Motivation"; copying the data to the GPU is part of the cost,
+ * section "Preliminary Results").  The server owns a fixed set of slots;
+ * each slot has its own stream, a plan per grid kind and a resident
+ * accumulator, peak list and outputs, and runs one event at a time: copy of
+ * the hits to the device, hough_vote, hough_peaks, assoc_cluster, copy of
+ * the results to pinned host memory.  With use_graphs the device part of a
+ * slot is one HIP graph per kind, captured at creation and replayed for
+ * every event (the hit count travels in device memory).  The number of slots
+ * is the largest that fits hbm_budget (at most max_slots); events that find
+ * every slot busy wait in a FIFO of queue_cap; beyond it ht_server_submit
+ * returns HT_EBUSY (the event is shed).  Results are exactly those of the
+ * three calls made one by one for the same event.  Single-threaded: one
+ * thread calls submit and poll.  Host pointers throughout. */
+#define HT_SERVER_MAX_KINDS 4
+
+typedef struct {
+  ht_grid grid;            /* accumulator grid of this kind of event */
+  ht_cluster_cfg cluster;  /* refinement and vertex settings */
+  int32_t min_votes;       /* peak threshold */
+  int32_t peak_cap;        /* peak-list capacity per event */
+} ht_server_kind;
+
+typedef struct {
+  int32_t n_kinds;                              /* 1 .. HT_SERVER_MAX_KINDS */
+  ht_server_kind kinds[HT_SERVER_MAX_KINDS];
+  int32_t max_hits;        /* hits per event, <= 65535 */
+  int32_t track_cap;       /* tracks copied back per event */
+  int32_t object_cap;      /* vertex objects copied back per event */
+  int32_t member_cap;      /* object members copied back per event */
+  int64_t hbm_budget;      /* device bytes the slots may use */
+  int32_t max_slots;       /* concurrent events at most, >= 1 */
+  int32_t queue_cap;       /* events waiting for a slot at most, >= 0 */
+  int32_t use_graphs;      /* 1: replay a captured HIP graph per slot and kind */
+} ht_server_cfg;
+
+/* Where the results of one event go (host memory, any pointer may be NULL;
+ * at most the given capacities are written). */
+typedef struct {
+  ht_track* tracks;
+  int32_t track_cap;
+  int32_t* hit_owner;      /* [n_hits of the event] */
+  ht_object* objects;
+  int32_t object_cap;
+  int32_t* members;
+  int32_t member_cap;
+} ht_server_out;
+
+typedef struct {
+  uint64_t tag;            /* as given to ht_server_submit */
+  int32_t kind, n_hits;
+  int32_t status;          /* HT_OK, or the error of a failed launch */
+  int32_t n_peaks;         /* full peak count */
+  int32_t counts[8];       /* as assoc_cluster's counts */
+  double t_submit, t_start, t_done; /* host steady clock [s]: submitted, on a slot, seen done */
+  double device_ms;        /* device time of the event on its slot (HIP events) */
+} ht_server_result;
+
+typedef struct ht_server ht_server;
+
+/* Creates the slots (allocates device and pinned host memory, captures the
+ * graphs).  HT_ENOMEM when not even one slot fits hbm_budget. */
+int ht_server_create(const ht_server_cfg* cfg, ht_server** out);
+/* Waits for the events on the device, then frees everything. */
+int ht_server_destroy(ht_server* server);
+/* Slot count and device bytes per slot. */
+int ht_server_info(const ht_server* server, int32_t* n_slots, int64_t* slot_bytes);
+/* Submits one event: r, phi, layer are host arrays of n_hits (copied before
+ * the call returns); out says where its results go (the pointers must stay
+ * valid until the event is returned by ht_server_poll).  Returns HT_EBUSY
+ * when every slot is busy and the queue is full. */
+int ht_server_submit(ht_server* server, int32_t kind, const float* r, const float* phi,
+                     const uint8_t* layer, int32_t n_hits, const ht_server_out* out,
+                     uint64_t tag);
+/* Collects up to max finished events into results (in completion order),
+ * copies their outputs to the places given at submit, starts waiting events
+ * on the freed slots.  wait != 0 blocks until at least one event is done or
+ * none is pending. */
+int ht_server_poll(ht_server* server, ht_server_result* results, int32_t max, int32_t wait,
+                   int32_t* n_results);
 
 /* ht_asin_f32 -- the canonical float32 arcsine of hough_vote, elementwise
  * over n device floats (for checking the formula on the device). */

@@ -44,3 +44,11 @@ WORKLOADS = {
     3: dict(name="high-pileup event, 3D Hough 512x256x64, ~55k hits", grid=GRID_3D,
             min_votes=7, cluster=CLUSTER_3D_DENSE, seed0=3_000_000),
 }
+
+# The paper's toy detector (evenly spaced layers to 110 cm, 0.4 mm
+# resolution, 3.0 cm beam pipe): road and fit resolution 0.4 mm, vertex grid
+# from the beam pipe radius (the paper's IP filter), peaks at 7 votes as in
+# its studies.
+CLUSTER_PAPER = dict(CLUSTER_3D, sigma_rphi=0.04, rho_lo=3.0, rho_hi=67.0)
+PAPER_WORKLOAD = dict(name="paper toy detector, 3D Hough 512x256x64", grid=GRID_3D,
+                      min_votes=7, cluster=CLUSTER_PAPER, seed0=5_100_000)

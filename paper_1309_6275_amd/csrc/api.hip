@@ -62,6 +62,23 @@ void free_plan(Plan* p) {
 
 }  // namespace
 
+namespace ht {
+int check_cluster(const Plan& p, const ht_cluster_cfg& c, int32_t n_hits, int32_t peak_cap,
+                  int32_t track_cap) {
+  if (c.win_bins < 0 || c.min_layers < 3 || c.min_layers > HT_MAX_LAYERS || c.seed_k < 1 ||
+      c.member_cap < 1 || !(c.road_sigmas > 0.0f) || !(c.box_margin >= 0.0f) ||
+      c.fit_iters < 0 || c.n_rho < 1 || c.n_theta < 4 || !(c.rho_hi > c.rho_lo) ||
+      !(c.rho_lo > 0.0f) || !(c.sigma_rphi > 0.0f) || !isfinite(c.rho_hi) ||
+      !isfinite(c.bh_max_isotropy) || !isfinite(c.road_sigmas) || !isfinite(c.box_margin))
+    return HT_EINVAL;
+  if (c.seed_k > 4 || n_hits > p.lim.max_hits || peak_cap > p.lim.max_peaks ||
+      c.member_cap > p.lim.max_member_cap || track_cap > p.lim.max_tracks ||
+      (int64_t)c.n_rho * c.n_theta > p.lim.max_vertex_cells || c.n_rho > p.lim.max_n_rho)
+    return HT_EUNSUPPORTED;
+  return HT_OK;
+}
+}  // namespace ht
+
 extern "C" {
 
 const char* ht_strerror(int status) {
@@ -71,6 +88,7 @@ const char* ht_strerror(int status) {
     case HT_ENOMEM: return "device allocation failed";
     case HT_EDEVICE: return "HIP runtime error";
     case HT_EUNSUPPORTED: return "unsupported size for this build";
+    case HT_EBUSY: return "every slot busy and the queue full";
     default: return "unknown status";
   }
 }
@@ -210,18 +228,9 @@ int assoc_cluster(const ht_plan* p, const float* r, const float* phi, const uint
   if ((out->track_cap > 0 && !out->tracks) || (out->object_cap > 0 && !out->objects) ||
       (out->member_cap > 0 && !out->members))
     return HT_EINVAL;
-  const ht_cluster_cfg& c = *cfg;
-  if (c.win_bins < 0 || c.min_layers < 3 || c.min_layers > HT_MAX_LAYERS || c.seed_k < 1 ||
-      c.member_cap < 1 || !(c.road_sigmas > 0.0f) || !(c.box_margin >= 0.0f) ||
-      c.fit_iters < 0 || c.n_rho < 1 || c.n_theta < 4 || !(c.rho_hi > c.rho_lo) ||
-      !(c.rho_lo > 0.0f) || !(c.sigma_rphi > 0.0f) || !isfinite(c.rho_hi) ||
-      !isfinite(c.bh_max_isotropy) || !isfinite(c.road_sigmas) || !isfinite(c.box_margin))
-    return HT_EINVAL;
-  if (c.seed_k > 4 || n_hits > p->lim.max_hits || peak_cap > p->lim.max_peaks ||
-      c.member_cap > p->lim.max_member_cap || out->track_cap > p->lim.max_tracks ||
-      (int64_t)c.n_rho * c.n_theta > p->lim.max_vertex_cells || c.n_rho > p->lim.max_n_rho)
-    return HT_EUNSUPPORTED;
-  return ht::launch_assoc(*p, r, phi, layer, n_hits, peaks, n_peaks, peak_cap, c, *out,
+  const int rc = ht::check_cluster(*p, *cfg, n_hits, peak_cap, out->track_cap);
+  if (rc != HT_OK) return rc;
+  return ht::launch_assoc(*p, r, phi, layer, n_hits, peaks, n_peaks, peak_cap, *cfg, *out,
                           (hipStream_t)stream);
 }
 
@@ -235,6 +244,48 @@ int ht_sqrt_f64(const double* x, double* out, int64_t n, void* stream) {
   if (n < 0 || (n > 0 && (!x || !out))) return HT_EINVAL;
   if (n > ((int64_t)1 << 38)) return HT_EUNSUPPORTED;  // grid limit
   return ht::launch_sqrt(x, out, n, (hipStream_t)stream);
+}
+
+size_t ht_cnn_workspace_bytes(int32_t max_windows, int32_t training) {
+  return ht::cnn_workspace_bytes(max_windows, training);
+}
+
+int ht_cnn_windows(const ht_plan* p, const int32_t* acc, const ht_peak* peaks,
+                   const int32_t* n_peaks, int32_t cap, uint16_t* win, void* stream) {
+  if (!p || !acc || !n_peaks || cap < 0 || (cap > 0 && (!peaks || !win))) return HT_EINVAL;
+  if (cap > p->lim.max_peaks) return HT_EUNSUPPORTED;
+  if (cap == 0) return HT_OK;
+  return ht::launch_cnn_windows(*p, acc, peaks, n_peaks, cap, win, (hipStream_t)stream);
+}
+
+int ht_cnn_forward(const float* params, const uint16_t* win, const int32_t* n_dev, int32_t n_max,
+                   float* logits, void* ws, size_t ws_bytes, void* stream) {
+  if (!params || n_max < 0 || (n_max > 0 && (!win || !logits)) || !ws) return HT_EINVAL;
+  if (ws_bytes < ht::cnn_workspace_bytes(n_max, 0)) return HT_EINVAL;
+  if (n_max > (1 << 26)) return HT_EUNSUPPORTED;
+  if (n_max == 0) return HT_OK;
+  return ht::launch_cnn_forward(params, win, n_dev, n_max, logits, ws, (hipStream_t)stream);
+}
+
+int ht_cnn_train_step(float* params, float* mom, const uint16_t* win, const float* labels,
+                      int32_t n, float lr, float momentum, float pos_weight, float* loss,
+                      void* ws, size_t ws_bytes, void* stream) {
+  if (!params || !mom || !loss || !ws || n < 1 || !win || !labels) return HT_EINVAL;
+  if (!(lr >= 0.0f) || !(momentum >= 0.0f) || !(pos_weight > 0.0f)) return HT_EINVAL;
+  if (ws_bytes < ht::cnn_workspace_bytes(n, 1)) return HT_EINVAL;
+  if (n > (1 << 24)) return HT_EUNSUPPORTED;
+  return ht::launch_cnn_train(params, mom, win, labels, n, lr, momentum, pos_weight, loss, ws,
+                              (hipStream_t)stream);
+}
+
+int ht_cnn_keep(const ht_plan* p, const float* logits, const ht_peak* peaks,
+                const int32_t* n_peaks, int32_t cap, float threshold, ht_peak* out,
+                int32_t out_cap, int32_t* n_out, void* stream) {
+  if (!p || !n_peaks || !n_out || cap < 0 || out_cap < 0) return HT_EINVAL;
+  if ((cap > 0 && (!logits || !peaks)) || (out_cap > 0 && !out)) return HT_EINVAL;
+  if (cap > p->lim.max_peaks) return HT_EUNSUPPORTED;
+  return ht::launch_cnn_keep(*p, logits, peaks, n_peaks, cap, threshold, out, out_cap, n_out,
+                             (hipStream_t)stream);
 }
 
 int ht_profile_begin(ht_plan* p, int32_t depth) {

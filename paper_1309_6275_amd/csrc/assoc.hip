@@ -232,7 +232,8 @@ struct AssocArgs {
   const float* r;
   const float* phi;
   const uint8_t* layer;
-  int n_hits;
+  int n_hits;                 // hits, or the bound of the device count below
+  const int32_t* n_hits_dev;  // device hit count (optional)
   double* hx;
   double* hy;
   double* hq;
@@ -266,6 +267,9 @@ struct AssocArgs {
 };
 
 __device__ __forceinline__ int n_cands(const AssocArgs& A) { return A.sc[S_NP]; }
+__device__ __forceinline__ int hits_of(const AssocArgs& A) {
+  return A.n_hits_dev ? min(max(*A.n_hits_dev, 0), A.n_hits) : A.n_hits;
+}
 
 // ---- prep ------------------------------------------------------------------
 __global__ void init_kernel(AssocArgs A, int words) {
@@ -278,7 +282,8 @@ __global__ void init_kernel(AssocArgs A, int words) {
     A.sc[S_NP] = np;
   }
   for (int64_t w = tid; w < words; w += stride) A.pbits[w] = 0u;
-  for (int64_t h = tid; h < A.n_hits; h += stride) {
+  const int n_hits = hits_of(A);
+  for (int64_t h = tid; h < n_hits; h += stride) {
     const float r = A.r[h], ph = A.phi[h];
     const bool ok = hit_ok(r, ph);
     double s, c;
@@ -398,11 +403,12 @@ __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S
     }
     head += nproc;
   };
-  for (int base = wave * kWave; base < A.n_hits; base += kSweepThreads) {
+  const int n_hits = hits_of(A);
+  for (int base = wave * kWave; base < n_hits; base += kSweepThreads) {
     const int h = base + lane;
     float hr = 1.0f, hp = 0.0f;
     bool hv = false;
-    if (h < A.n_hits) {
+    if (h < n_hits) {
       hr = A.r[h];
       hp = A.phi[h];
       hv = hit_ok(hr, hp) && A.layer[h] < HT_MAX_LAYERS;
@@ -1419,7 +1425,8 @@ void launch_refine(const AssocArgs& A, int peak_cap, hipStream_t s) {
 
 int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t* layer,
                  int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks, int32_t peak_cap,
-                 const ht_cluster_cfg& cfg, const ht_cluster_out& out, hipStream_t s) {
+                 const ht_cluster_cfg& cfg, const ht_cluster_out& out, hipStream_t s,
+                 const int32_t* n_hits_dev) {
   const ht_grid& g = P.grid;
   AssocArgs A;
   A.n_phi = g.n_phi;
@@ -1444,6 +1451,7 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   A.phi = phi;
   A.layer = layer;
   A.n_hits = n_hits;
+  A.n_hits_dev = n_hits_dev;
   A.hx = P.d_hx;
   A.hy = P.d_hy;
   A.hq = P.d_hq;

@@ -72,16 +72,32 @@ struct ht_plan : ht::Plan {};
 
 // Launch helpers implemented in the kernel files.
 namespace ht {
+// n_hits_dev (optional): device hit count of the event, at most n_hits,
+// which then only bounds it (graph replays of events of any size)
 int launch_vote(const Plan& p, const float* r, const float* phi, int32_t n_hits, int32_t* acc,
-                unsigned long long* n_votes, hipStream_t s);
+                unsigned long long* n_votes, hipStream_t s, const int32_t* n_hits_dev = nullptr);
 int launch_peaks(const Plan& p, const int32_t* acc, int32_t min_votes, ht_peak* out,
                  int32_t capacity, int32_t* n_found, hipStream_t s);
 int launch_assoc(const Plan& p, const float* r, const float* phi, const uint8_t* layer,
                  int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks, int32_t peak_cap,
-                 const ht_cluster_cfg& cfg, const ht_cluster_out& out, hipStream_t s);
+                 const ht_cluster_cfg& cfg, const ht_cluster_out& out, hipStream_t s,
+                 const int32_t* n_hits_dev = nullptr);
 int launch_asin(const float* u, float* out, int64_t n, hipStream_t s);
 int launch_sqrt(const double* x, double* out, int64_t n, hipStream_t s);
 int launch_scan(const int32_t* cnt, int32_t* off, int n, int32_t* total, hipStream_t s);
+// assoc_cluster's configuration checks (HT_OK, HT_EINVAL or HT_EUNSUPPORTED)
+int check_cluster(const Plan& p, const ht_cluster_cfg& c, int32_t n_hits, int32_t peak_cap,
+                  int32_t track_cap);
+size_t cnn_workspace_bytes(int32_t max_windows, int training);
+int launch_cnn_windows(const Plan& p, const int32_t* acc, const ht_peak* peaks, const int32_t* n_peaks,
+                       int32_t cap, uint16_t* win, hipStream_t s);
+int launch_cnn_forward(const float* params, const uint16_t* win, const int32_t* n_dev, int32_t n_max,
+                       float* logits, void* ws, hipStream_t s);
+int launch_cnn_train(float* params, float* mom, const uint16_t* win, const float* labels, int32_t n,
+                     float lr, float momentum, float pos_weight, float* loss, void* ws, hipStream_t s);
+int launch_cnn_keep(const Plan& p, const float* logits, const ht_peak* peaks, const int32_t* n_peaks,
+                    int32_t cap, float thr, ht_peak* out, int32_t out_cap, int32_t* n_out,
+                    hipStream_t s);
 int vote_init(int n_phi);
 int peaks_init(int n_phi);
 }  // namespace ht

@@ -29,11 +29,14 @@ __device__ __forceinline__ float bcast(float v, int lane) {
 
 template <bool POW2, bool WIDE>
 __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
-    const float* __restrict__ r, const float* __restrict__ phi, int n_hits,
-    const float* __restrict__ kap, const float* __restrict__ qt, const float* __restrict__ tt,
+    const float* __restrict__ r, const float* __restrict__ phi, int n_hits_max,
+    const int32_t* __restrict__ n_hits_dev, const float* __restrict__ kap, const float* __restrict__ qt, const float* __restrict__ tt,
     int n_phi, int n_qpt, float phi_lo, float invw, int stride, int32_t* __restrict__ acc,
     unsigned long long* __restrict__ n_votes) {
   extern __shared__ uint32_t lds[];
+  // hits of this event: the device count when given (clamped to the bound the
+  // buffers were checked for), else the host count
+  const int n_hits = n_hits_dev ? min(max(*n_hits_dev, 0), n_hits_max) : n_hits_max;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x >> 6;
   const int j0 = blockIdx.x * kWave;
@@ -153,7 +156,7 @@ int vote_init(int n_phi) {
 }
 
 int launch_vote(const Plan& p, const float* r, const float* phi, int32_t n_hits, int32_t* acc,
-                unsigned long long* n_votes, hipStream_t s) {
+                unsigned long long* n_votes, hipStream_t s, const int32_t* n_hits_dev) {
   const ht_grid& g = p.grid;
   const int stride = vote_stride(g.n_phi);
   const size_t lds_bytes = (size_t)kWave * stride * 4;
@@ -167,7 +170,7 @@ int launch_vote(const Plan& p, const float* r, const float* phi, int32_t n_hits,
   auto kern = pow2 ? (wide ? vote_kernel<true, true> : vote_kernel<true, false>)
                    : (wide ? vote_kernel<false, true> : vote_kernel<false, false>);
   p.prof_mark(HT_STAGE_VOTE, 0, s);
-  kern<<<grid, kVoteThreads, lds_bytes, s>>>(r, phi, n_hits, p.d_kap, p.d_q, p.d_t, g.n_phi,
+  kern<<<grid, kVoteThreads, lds_bytes, s>>>(r, phi, n_hits, n_hits_dev, p.d_kap, p.d_q, p.d_t, g.n_phi,
                                              g.n_qpt, p.phi_lo, p.invw, stride, acc, n_votes);
   HT_CHECK(hipGetLastError());
   p.prof_mark(HT_STAGE_VOTE, 1, s);

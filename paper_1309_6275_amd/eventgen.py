@@ -156,11 +156,12 @@ def crossings(vx, vy, psi, kappa, radii=RADII):
 
 
 class _Builder:
-    def __init__(self, rng, bfield=B_TESLA, radii=RADII, smear=SMEAR_CM):
+    def __init__(self, rng, bfield=B_TESLA, radii=RADII, smear=SMEAR_CM, smear_xy=0.0):
         self.rng = rng
         self.bfield = bfield
         self.radii = radii
         self.smear = smear
+        self.smear_xy = smear_xy  # Gaussian smear of x and y each (then r moves too)
         self.hits = []          # (r, phi, layer, track, forward)
         self.trk = []           # (phi0, qpt, d0, vertex, nhits, nfwd)
         self.vtx = []           # (rho, theta, kind, ntrk)
@@ -172,6 +173,10 @@ class _Builder:
         nh = nf = 0
         for li, x, y, fwd in crossings(vx, vy, psi, kap, self.radii):
             rl = self.radii[li]
+            if self.smear_xy > 0:
+                x = x + self.rng.normal(0.0, self.smear_xy)
+                y = y + self.rng.normal(0.0, self.smear_xy)
+                rl = float(np.hypot(x, y))
             ph = np.arctan2(y, x)
             if self.smear > 0:
                 ph += self.rng.normal(0.0, self.smear / rl)
@@ -190,7 +195,10 @@ class _Builder:
         li = self.rng.integers(0, len(self.radii), size=n)
         ph = self.rng.uniform(-np.pi, np.pi, size=n)
         for a, b in zip(li, ph):
-            self.hits.append((self.radii[int(a)], float(b), int(a), -1, False))
+            rl = self.radii[int(a)]
+            if self.smear_xy > 0:
+                rl = float(rl + self.rng.normal(0.0, self.smear_xy))
+            self.hits.append((rl, float(b), int(a), -1, False))
 
     def add_vertex(self, rho, theta, kind, ntrk):
         self.vtx.append((rho, theta, kind, ntrk))
@@ -359,3 +367,45 @@ def random_hits(n, seed, r_lo=1.0, r_hi=110.0, bad_fraction=0.0):
             else:
                 r[i] = 0.0
     return r, phi, layer
+
+
+def make_serving_event(kind: int, seed: int, h_lo: int = 2000, h_hi: int = 60000) -> Event:
+    """Event of a mixed trigger stream: kind 0 is a prompt-only event of the
+    2D workload's composition (20% noise hits), kind 1 an event of the 3D
+    workload's composition (two displaced neutrals, 14% noise hits); the
+    prompt and noise counts are scaled so the hit count is close to a target
+    drawn from U[h_lo, h_hi]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    target = int(rng.uniform(h_lo, h_hi))
+    if kind == 0:
+        n_noise = int(0.2 * target)
+        return make_event(1, seed, n_prompt=max(1, round((target - n_noise) / 10.0)),
+                          n_noise=n_noise)
+    n_noise = int(0.14 * target)
+    return make_event(2, seed, n_prompt=max(1, round((target - n_noise - 160) / 9.7)),
+                      n_noise=n_noise)
+
+
+# The paper's toy detector (section "Hough Transform Algorithm", sample input
+# data): transverse plane, 3.0 cm beam pipe, ten evenly spaced layers out to
+# 110 cm (here at 11, 22, ..., 110 cm), 0.4 mm resolution in x and in y.
+PAPER_RADII = tuple(11.0 * (i + 1) for i in range(10))
+PAPER_SMEAR_XY = 0.04
+
+
+def make_paper_event(seed: int, n_prompt: int = 0, n_jets: int = 1, jet_ntrk: int = 10,
+                     rho_lo: float = 4.0, rho_hi: float = 10.0) -> Event:
+    """Event of the paper's efficiency studies on its toy detector: n_prompt
+    tracks from the interaction point and n_jets displaced jets of jet_ntrk
+    tracks each, dispersion half-angles U[15, 60] degrees; jet vertices at
+    radius U[rho_lo, rho_hi], inside the first layer so that their tracks
+    have ten hits, as in the studies."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    b = _Builder(rng, radii=PAPER_RADII, smear=0.0, smear_xy=PAPER_SMEAR_XY)
+    for _ in range(n_prompt):
+        b.add_perigee_track(rng.uniform(-np.pi, np.pi), _qpt_uniform(rng), 0.0)
+    for _ in range(n_jets):
+        _displaced_jet(b, rng, jet_ntrk, rho_lo=rho_lo, rho_hi=rho_hi)
+    return b.build(meta=dict(paper=True, seed=seed, n_prompt=n_prompt, n_jets=n_jets,
+                             jet_ntrk=jet_ntrk))
+

@@ -66,6 +66,35 @@ class ClusterOut(C.Structure):
                 ("vacc", C.c_void_p), ("counts", C.c_void_p)]
 
 
+SERVER_MAX_KINDS = 4
+HT_EBUSY = -5
+
+
+class ServerKind(C.Structure):
+    _fields_ = [("grid", Grid), ("cluster", ClusterCfg), ("min_votes", C.c_int32),
+                ("peak_cap", C.c_int32)]
+
+
+class ServerCfg(C.Structure):
+    _fields_ = [("n_kinds", C.c_int32), ("kinds", ServerKind * SERVER_MAX_KINDS),
+                ("max_hits", C.c_int32), ("track_cap", C.c_int32), ("object_cap", C.c_int32),
+                ("member_cap", C.c_int32), ("hbm_budget", C.c_int64), ("max_slots", C.c_int32),
+                ("queue_cap", C.c_int32), ("use_graphs", C.c_int32)]
+
+
+class ServerOut(C.Structure):
+    _fields_ = [("tracks", C.c_void_p), ("track_cap", C.c_int32), ("hit_owner", C.c_void_p),
+                ("objects", C.c_void_p), ("object_cap", C.c_int32), ("members", C.c_void_p),
+                ("member_cap", C.c_int32)]
+
+
+class ServerResult(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("kind", C.c_int32), ("n_hits", C.c_int32),
+                ("status", C.c_int32), ("n_peaks", C.c_int32), ("counts", C.c_int32 * 8),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+                ("device_ms", C.c_double)]
+
+
 _lib = None
 
 
@@ -87,11 +116,26 @@ def lib():
         L.assoc_cluster.argtypes = [vp, vp, vp, vp, i32, vp, vp, i32, vp, vp, vp]
         L.ht_asin_f32.argtypes = [vp, vp, i64, vp]
         L.ht_sqrt_f64.argtypes = [vp, vp, i64, vp]
+        L.ht_cnn_workspace_bytes.argtypes = [i32, i32]
+        L.ht_cnn_workspace_bytes.restype = C.c_size_t
+        L.ht_cnn_windows.argtypes = [vp, vp, vp, vp, i32, vp, vp]
+        L.ht_cnn_forward.argtypes = [vp, vp, vp, i32, vp, vp, C.c_size_t, vp]
+        L.ht_cnn_train_step.argtypes = [vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, vp,
+                                        vp, C.c_size_t, vp]
+        L.ht_cnn_keep.argtypes = [vp, vp, vp, vp, i32, C.c_float, vp, i32, vp, vp]
+        L.ht_server_create.argtypes = [vp, vp]
+        L.ht_server_destroy.argtypes = [vp]
+        L.ht_server_info.argtypes = [vp, vp, vp]
+        L.ht_server_submit.argtypes = [vp, i32, vp, vp, vp, i32, vp, C.c_uint64]
+        L.ht_server_poll.argtypes = [vp, vp, i32, i32, vp]
         L.ht_profile_begin.argtypes = [vp, i32]
         L.ht_profile_read.argtypes = [vp, vp, vp]
         L.ht_profile_end.argtypes = [vp]
         for f in ("ht_plan_create", "hough_vote", "hough_peaks", "assoc_cluster", "ht_asin_f32",
-                  "ht_sqrt_f64", "ht_profile_begin", "ht_profile_read", "ht_profile_end"):
+                  "ht_sqrt_f64", "ht_profile_begin", "ht_profile_read", "ht_profile_end",
+                  "ht_server_create", "ht_server_destroy", "ht_server_info", "ht_server_submit",
+                  "ht_server_poll", "ht_cnn_windows", "ht_cnn_forward", "ht_cnn_train_step",
+                  "ht_cnn_keep"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -275,6 +319,62 @@ def sqrt_f64(x, out, stream=None):
                              int(x.numel()), _stream(stream)), "ht_sqrt_f64")
 
 
+CNN_PARAMS = 8529
+CNN_WINDOW = 128
+
+
+def cnn_workspace(n_windows, training=False):
+    """A device workspace (uint8 tensor) for the CNN calls on n_windows."""
+    torch = _torch()
+    nb = int(lib().ht_cnn_workspace_bytes(int(n_windows), int(bool(training))))
+    return torch.empty(nb, dtype=torch.uint8, device="cuda")
+
+
+def cnn_windows(plan: "Plan", acc, peaks, n_peaks, win, stream=None):
+    """Windows (bfloat16 [cap, 128]) of the first min(n_peaks, cap) peaks."""
+    torch = _torch()
+    cap = int(peaks.shape[0])
+    if tuple(win.shape) != (cap, CNN_WINDOW):
+        raise ValueError("win must be [cap, 128]")
+    _check(lib().ht_cnn_windows(plan.handle, _ptr(acc, torch.int32, "acc"),
+                                _ptr(peaks, torch.int32, "peaks"),
+                                _ptr(n_peaks, torch.int32, "n_peaks"), cap,
+                                _ptr(win, torch.bfloat16, "win"), _stream(stream)), "ht_cnn_windows")
+
+
+def cnn_forward(params, win, logits, workspace, n_dev=None, stream=None):
+    torch = _torch()
+    n_max = int(win.shape[0])
+    _check(lib().ht_cnn_forward(_ptr(params, torch.float32, "params"),
+                                _ptr(win, torch.bfloat16, "win"),
+                                _ptr(n_dev, torch.int32, "n_dev") if n_dev is not None else None,
+                                n_max, _ptr(logits, torch.float32, "logits"),
+                                _ptr(workspace, torch.uint8, "workspace"), int(workspace.numel()),
+                                _stream(stream)), "ht_cnn_forward")
+
+
+def cnn_train_step(params, mom, win, labels, lr, momentum, pos_weight, loss, workspace,
+                   stream=None):
+    torch = _torch()
+    _check(lib().ht_cnn_train_step(_ptr(params, torch.float32, "params"),
+                                   _ptr(mom, torch.float32, "mom"),
+                                   _ptr(win, torch.bfloat16, "win"),
+                                   _ptr(labels, torch.float32, "labels"), int(win.shape[0]),
+                                   float(lr), float(momentum), float(pos_weight),
+                                   _ptr(loss, torch.float32, "loss"),
+                                   _ptr(workspace, torch.uint8, "workspace"),
+                                   int(workspace.numel()), _stream(stream)), "ht_cnn_train_step")
+
+
+def cnn_keep(plan: "Plan", logits, peaks, n_peaks, threshold, out, n_out, stream=None):
+    torch = _torch()
+    _check(lib().ht_cnn_keep(plan.handle, _ptr(logits, torch.float32, "logits"),
+                             _ptr(peaks, torch.int32, "peaks"), _ptr(n_peaks, torch.int32, "n_peaks"),
+                             int(peaks.shape[0]), float(threshold), _ptr(out, torch.int32, "out"),
+                             int(out.shape[0]), _ptr(n_out, torch.int32, "n_out"),
+                             _stream(stream)), "ht_cnn_keep")
+
+
 STAGES = ("vote", "peaks", "assoc", "members", "refine")  # HT_STAGE_* order
 
 
@@ -302,6 +402,111 @@ def profile_end(plan: "Plan"):
     _check(lib().ht_profile_end(plan.handle), "ht_profile_end")
 
 
+class Server:
+    """The trigger serving loop (ht_server_*): events of several grid kinds,
+    submitted one by one from host arrays, processed on device-resident
+    slots; results come back through poll().  kinds: list of dicts with
+    grid, cluster, min_votes, peak_cap."""
+
+    def __init__(self, kinds, max_hits=65535, track_cap=4096, object_cap=256, member_cap=4096,
+                 hbm_budget=64 << 30, max_slots=4, queue_cap=256, use_graphs=True):
+        if not 1 <= len(kinds) <= SERVER_MAX_KINDS:
+            raise ValueError("1..4 kinds")
+        _torch()  # a GPU must be there
+        cfg = ServerCfg()
+        cfg.n_kinds = len(kinds)
+        for i, k in enumerate(kinds):
+            cfg.kinds[i].grid = grid_struct(k["grid"])
+            cfg.kinds[i].cluster = cluster_struct(k["cluster"])
+            cfg.kinds[i].min_votes = int(k["min_votes"])
+            cfg.kinds[i].peak_cap = int(k["peak_cap"])
+        cfg.max_hits, cfg.track_cap = int(max_hits), int(track_cap)
+        cfg.object_cap, cfg.member_cap = int(object_cap), int(member_cap)
+        cfg.hbm_budget, cfg.max_slots = int(hbm_budget), int(max_slots)
+        cfg.queue_cap, cfg.use_graphs = int(queue_cap), int(bool(use_graphs))
+        self.cfg = cfg
+        h = C.c_void_p()
+        _check(lib().ht_server_create(C.byref(cfg), C.byref(h)), "ht_server_create")
+        self._h = h
+        self._keep = {}
+        n, b = C.c_int32(), C.c_int64()
+        _check(lib().ht_server_info(h, C.byref(n), C.byref(b)), "ht_server_info")
+        self.n_slots, self.slot_bytes = int(n.value), int(b.value)
+
+    def submit(self, kind, r, phi, layer, tag, want_outputs=True):
+        """Submit one event (numpy float32 r, phi; uint8 layer).  Returns False
+        when the event is shed (every slot busy, queue full)."""
+        r = np.ascontiguousarray(r, np.float32)
+        phi = np.ascontiguousarray(phi, np.float32)
+        layer = np.ascontiguousarray(layer, np.uint8)
+        out = ServerOut()
+        bufs = None
+        if want_outputs:
+            c = self.cfg
+            bufs = dict(tracks=np.zeros(c.track_cap, TRACK_DTYPE),
+                        hit_owner=np.full(max(r.size, 1), -1, np.int32),
+                        objects=np.zeros(c.object_cap, OBJECT_DTYPE),
+                        members=np.zeros(c.member_cap, np.int32))
+            out.tracks = bufs["tracks"].ctypes.data
+            out.track_cap = c.track_cap
+            out.hit_owner = bufs["hit_owner"].ctypes.data
+            out.objects = bufs["objects"].ctypes.data
+            out.object_cap = c.object_cap
+            out.members = bufs["members"].ctypes.data
+            out.member_cap = c.member_cap
+        rc = lib().ht_server_submit(self._h, int(kind), r.ctypes.data, phi.ctypes.data,
+                                    layer.ctypes.data, int(r.size), C.byref(out), int(tag))
+        if rc == HT_EBUSY:
+            return False
+        _check(rc, "ht_server_submit")
+        self._keep[int(tag)] = (bufs, r.size)
+        return True
+
+    def poll(self, wait=False, max_results=256):
+        res = (ServerResult * max_results)()
+        n = C.c_int32()
+        _check(lib().ht_server_poll(self._h, res, int(max_results), int(bool(wait)), C.byref(n)),
+               "ht_server_poll")
+        out = []
+        for i in range(n.value):
+            x = res[i]
+            bufs, nh = self._keep.pop(int(x.tag), (None, 0))
+            d = dict(tag=int(x.tag), kind=int(x.kind), n_hits=int(x.n_hits), status=int(x.status),
+                     n_peaks=int(x.n_peaks), counts=np.array(x.counts[:], np.int32),
+                     t_submit=x.t_submit, t_start=x.t_start, t_done=x.t_done,
+                     device_ms=x.device_ms)
+            if bufs is not None:
+                c = d["counts"]
+                d["tracks"] = bufs["tracks"][:min(c[1], self.cfg.track_cap)].copy()
+                d["hit_owner"] = bufs["hit_owner"][:nh].copy()
+                d["objects"] = bufs["objects"][:min(c[2], self.cfg.object_cap)].copy()
+                d["members"] = bufs["members"][:min(c[3], self.cfg.member_cap)].copy()
+            out.append(d)
+        return out
+
+    def drain(self):
+        done = []
+        while self._keep:
+            got = self.poll(wait=True)
+            if not got:
+                break
+            done += got
+        return done
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ht_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 EXPORTS = ("ht_plan_create", "ht_plan_destroy", "ht_strerror", "hough_vote", "hough_peaks",
            "assoc_cluster", "ht_asin_f32", "ht_sqrt_f64", "ht_profile_begin", "ht_profile_read",
-           "ht_profile_end")
+           "ht_profile_end", "ht_server_create", "ht_server_destroy", "ht_server_info",
+           "ht_server_submit", "ht_server_poll", "ht_cnn_workspace_bytes", "ht_cnn_windows",
+           "ht_cnn_forward", "ht_cnn_train_step", "ht_cnn_keep")

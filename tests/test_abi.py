@@ -50,6 +50,11 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(H.ClusterCfg) == 15 * 4
     assert H.TRACK_DTYPE.itemsize == 13 * 4 + 16 * 4
     assert H.OBJECT_DTYPE.itemsize == 8 * 4
+    # serving loop structs (static_asserts on the C side hold the same sizes)
+    assert ctypes.sizeof(H.ServerKind) == 100
+    assert ctypes.sizeof(H.ServerCfg) == 448
+    assert ctypes.sizeof(H.ServerOut) == 56
+    assert ctypes.sizeof(H.ServerResult) == 88
 
 
 def test_strerror_without_gpu(libpath):

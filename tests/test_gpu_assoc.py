@@ -136,6 +136,20 @@ def test_assoc_parity_many_peaks_per_workgroup(torch, ht, oracle):
     compare(got, want, "many peaks")
 
 
+@pytest.mark.parametrize("kw", [dict(n_prompt=0, n_jets=1, jet_ntrk=10),
+                                dict(n_prompt=0, n_jets=4, jet_ntrk=10),
+                                dict(n_prompt=600, n_jets=2, jet_ntrk=10)])
+def test_assoc_parity_paper_geometry(torch, ht, oracle, kw):
+    """The paper's toy detector (layers every 11 cm to 110 cm, 0.4 mm in x
+    and y, vertex grid from the 3.0 cm pipe)."""
+    W = CF.PAPER_WORKLOAD
+    ev = G.make_paper_event(W["seed0"] + 7 + kw["n_prompt"] + kw["n_jets"], **kw)
+    print(f"paper {kw} hits {ev.n_hits}", flush=True)
+    got, acc, pk = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], W["cluster"])
+    want = run_oracle(oracle, W["grid"], ev, acc, pk, W["cluster"])
+    compare(got, want, f"paper {kw}")
+
+
 @pytest.mark.parametrize("kind", ["jet", "bh"])
 def test_assoc_parity_vertex_events(torch, ht, oracle, kind):
     W = CF.WORKLOADS[2]

@@ -1,0 +1,134 @@
+"""Learned peak filter on the device against the oracle (oracle/cnn.py):
+windows bit-exact, logits and one training step within the tolerance the
+bfloat16 contract leaves (activations rounded from float32 on the device and
+from float64 in the oracle can differ by one bfloat16 step near a rounding
+boundary), and the ordered compaction exactly."""
+import numpy as np
+import pytest
+
+from oracle import cnn
+from paper_1309_6275_amd import configs as CF
+from paper_1309_6275_amd import eventgen as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+@pytest.fixture(scope="module")
+def ht(torch):
+    from paper_1309_6275_amd import houghtrig
+    houghtrig.lib()
+    return houghtrig
+
+
+@pytest.fixture(scope="module")
+def event_peaks(torch, ht):
+    W = CF.WORKLOADS[2]
+    plan = ht.Plan(W["grid"], max_peaks=1 << 19, max_member_cap=128, max_tracks=4096)
+    ev = G.make_event(2, W["seed0"] + 3)
+    r = torch.from_numpy(ev.r).cuda()
+    phi = torch.from_numpy(ev.phi).cuda()
+    acc = torch.empty(plan.acc_shape, dtype=torch.int32, device="cuda")
+    ht.hough_vote(plan, r, phi, acc)
+    peaks = torch.zeros((1 << 19, 2), dtype=torch.int32, device="cuda")
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ht.hough_peaks(plan, acc, W["min_votes"], peaks, nf)
+    torch.cuda.synchronize()
+    return plan, acc, peaks, nf
+
+
+def gpu_windows(torch, ht, plan, acc, peaks, cap):
+    pk = peaks[:cap].contiguous()
+    n = torch.tensor([cap], dtype=torch.int32, device="cuda")
+    win = torch.empty((cap, ht.CNN_WINDOW), dtype=torch.bfloat16, device="cuda")
+    ht.cnn_windows(plan, acc, pk, n, win)
+    return win
+
+
+def test_windows_bitexact(torch, ht, event_peaks):
+    plan, acc, peaks, nf = event_peaks
+    # the first peaks (d0 plane 0: clipped neighbours) and the last (top plane)
+    n = int(nf.item())
+    sel = torch.cat([peaks[:3000], peaks[n - 3000:n]]).contiguous()
+    win = gpu_windows(torch, ht, plan, acc, sel, sel.shape[0])
+    got = win.float().cpu().numpy()
+    want = cnn.windows(acc.cpu().numpy(), sel[:, 0].cpu().numpy())
+    assert np.array_equal(got[:, :125], want.reshape(-1, 125))
+    assert np.all(got[:, 125:] == 0)
+
+
+def test_forward_matches_oracle(torch, ht, event_peaks):
+    plan, acc, peaks, nf = event_peaks
+    cap = 4099  # several wave tiles and a ragged tail
+    win = gpu_windows(torch, ht, plan, acc, peaks, cap)
+    rng = np.random.default_rng(11)
+    for seed in (1, 2):
+        params = cnn.init_params(seed)
+        params[cnn.N_PARAMS - 1] = 0.25
+        p = torch.from_numpy(params).cuda()
+        logits = torch.full((cap,), np.nan, dtype=torch.float32, device="cuda")
+        ws = ht.cnn_workspace(cap)
+        ht.cnn_forward(p, win, logits, ws)
+        got = logits.cpu().numpy()
+        want, _ = cnn.forward(params, win.float().cpu().numpy()[:, :125].reshape(-1, 5, 5, 5))
+        err = np.abs(got - want)
+        assert np.all(np.isfinite(got))
+        assert np.all(err <= 2e-2 + 2e-2 * np.abs(want)), err.max()
+        assert np.median(err) <= 1e-4 + 1e-4 * np.median(np.abs(want)), np.median(err)
+    # device count: only the first n logits are written
+    n_dev = torch.tensor([100], dtype=torch.int32, device="cuda")
+    logits = torch.full((cap,), 7.0, dtype=torch.float32, device="cuda")
+    ht.cnn_forward(p, win, logits, ht.cnn_workspace(cap), n_dev=n_dev)
+    out = logits.cpu().numpy()
+    assert np.all(out[100:] == 7.0) and not np.any(out[:100] == 7.0)
+
+
+def test_train_step_matches_oracle(torch, ht, event_peaks):
+    plan, acc, peaks, nf = event_peaks
+    n = 517
+    win = gpu_windows(torch, ht, plan, acc, peaks[20000:], n)
+    rng = np.random.default_rng(12)
+    labels = (rng.uniform(size=n) < 0.2).astype(np.float32)
+    params = cnn.init_params(4)
+    mom = rng.normal(0, 1e-3, cnn.N_PARAMS).astype(np.float32)
+    lr, mu, pw = 0.05, 0.9, 3.0
+    x = win.float().cpu().numpy()[:, :125].reshape(-1, 5, 5, 5)
+    loss_w, g_w, _ = cnn.loss_and_grad(params, x, labels, pw)
+    p_w, m_w = cnn.sgd_step(params, mom, g_w, lr, mu)
+    p = torch.from_numpy(params).cuda()
+    m = torch.from_numpy(mom).cuda()
+    lab = torch.from_numpy(labels).cuda()
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ht.cnn_train_step(p, m, win, lab, lr, mu, pw, loss, ht.cnn_workspace(n, training=True))
+    torch.cuda.synchronize()
+    assert abs(loss.item() - loss_w) <= 1e-3 * abs(loss_w)
+    g_got = m.cpu().numpy().astype(np.float64) - mu * mom
+    scale = np.abs(g_w).max()
+    assert np.abs(g_got - g_w).max() <= 2e-2 * scale, (np.abs(g_got - g_w).max(), scale)
+    assert np.median(np.abs(g_got - g_w)) <= 1e-4 * scale
+    assert np.abs(p.cpu().numpy() - p_w).max() <= lr * 2e-2 * scale + 1e-7
+
+
+def test_keep_compaction(torch, ht, event_peaks):
+    plan, acc, peaks, nf = event_peaks
+    rng = np.random.default_rng(13)
+    for cap, thr in ((70001, 0.3), (256, -1.0), (1, 0.0), (0, 0.0)):
+        lg = rng.normal(0, 1, max(cap, 1)).astype(np.float32)
+        logits = torch.from_numpy(lg).cuda()
+        pk = peaks[:max(cap, 1)].contiguous()
+        n_in = torch.tensor([min(cap, 60000)], dtype=torch.int32, device="cuda")
+        out = torch.full((max(cap, 1), 2), -1, dtype=torch.int32, device="cuda")
+        n_out = torch.zeros(1, dtype=torch.int32, device="cuda")
+        ht.cnn_keep(plan, logits[:cap] if cap else logits[:0], pk[:cap] if cap else pk[:0], n_in,
+                    thr, out, n_out)
+        m = min(cap, 60000)
+        keep = np.flatnonzero(lg[:m] >= thr)
+        assert int(n_out.item()) == keep.size
+        assert np.array_equal(out[:keep.size].cpu().numpy(), pk[:max(cap, 1)].cpu().numpy()[keep])

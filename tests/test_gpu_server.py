@@ -1,0 +1,151 @@
+"""The trigger serving loop (ht_server_*): results equal the oracle's for
+events of two grid kinds submitted in a mix; an event gives bit-identical
+results alone and inside a mix; graph replay equals direct launches across
+events of different sizes; admission by HBM budget and queue bound."""
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+from paper_1309_6275_amd import configs as CF
+from paper_1309_6275_amd import eventgen as G
+
+from test_gpu_assoc import compare
+
+pytestmark = pytest.mark.gpu
+
+KINDS = [dict(grid=CF.WORKLOADS[1]["grid"], cluster=CF.WORKLOADS[1]["cluster"],
+              min_votes=CF.WORKLOADS[1]["min_votes"], peak_cap=1 << 16),
+         dict(grid=CF.WORKLOADS[2]["grid"], cluster=CF.WORKLOADS[2]["cluster"],
+              min_votes=CF.WORKLOADS[2]["min_votes"], peak_cap=1 << 19)]
+SERVER_ARGS = dict(max_hits=8192, track_cap=2048, object_cap=128, member_cap=4096,
+                   hbm_budget=24 << 30, max_slots=3, queue_cap=64)
+
+
+@pytest.fixture(scope="module")
+def ht():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1309_6275_amd import houghtrig
+    houghtrig.lib()
+    return houghtrig
+
+
+def oracle_result(oracle, kind, ev):
+    K = KINDS[kind]
+    acc, _ = oracle.hough_vote(K["grid"], ev.r, ev.phi)
+    pk, _ = oracle.hough_peaks(K["grid"], acc, K["min_votes"])
+    pk = pk[:K["peak_cap"]]
+    return oracle.assoc_cluster(K["grid"], ev.r, ev.phi, ev.layer, pk, K["cluster"],
+                                track_cap=SERVER_ARGS["track_cap"],
+                                object_cap=SERVER_ARGS["object_cap"],
+                                member_cap=SERVER_ARGS["member_cap"])
+
+
+def as_got(res):
+    return dict(counts=res["counts"], hit_owner=res["hit_owner"], tracks=res["tracks"],
+                objects=res["objects"], members=res["members"], vacc=np.zeros(1, np.int32))
+
+
+def mixed_events():
+    evs = []
+    for s in range(3):
+        evs.append((0, G.make_event(1, CF.WORKLOADS[1]["seed0"] + 40 + s)))
+    for s in range(2):
+        evs.append((1, G.make_event(2, CF.WORKLOADS[2]["seed0"] + 40 + s)))
+    order = [0, 3, 1, 4, 2]
+    return [evs[i] for i in order]
+
+
+def run_all(srv, events, tag0=0):
+    for i, (kind, ev) in enumerate(events):
+        assert srv.submit(kind, ev.r, ev.phi, ev.layer, tag0 + i)
+    got = {}
+    for d in srv.drain():
+        got[d["tag"]] = d
+    assert len(got) == len(events)
+    return got
+
+
+def test_server_matches_oracle(ht, oracle):
+    srv = ht.Server(KINDS, **SERVER_ARGS)
+    print(f"slots {srv.n_slots} bytes/slot {srv.slot_bytes}", flush=True)
+    events = mixed_events()
+    got = run_all(srv, events)
+    for i, (kind, ev) in enumerate(events):
+        d = got[i]
+        assert d["status"] == 0
+        want = oracle_result(oracle, kind, ev)
+        want = dict(want, vacc=np.zeros(1, np.int32))
+        compare(as_got(d), want, f"server event {i} kind {kind}")
+    srv.close()
+
+
+def test_server_alone_vs_mix_bitexact(ht):
+    """An event's results do not depend on what else is in flight."""
+    kind, ev = 1, G.make_event(2, CF.WORKLOADS[2]["seed0"] + 77)
+    srv = ht.Server(KINDS, **SERVER_ARGS)
+    alone = run_all(srv, [(kind, ev)])[0]
+    rng = np.random.default_rng(5)
+    mix = []
+    for i in range(12):
+        k = int(rng.integers(0, 2))
+        n = int(rng.integers(0, 8000))
+        r, phi, layer = G.random_hits(n, seed=1000 + i, r_lo=3.0, r_hi=105.0)
+        mix.append((k, SimpleNamespace(r=r, phi=phi, layer=layer, n_hits=n)))
+    mix.insert(5, (kind, ev))
+    got = run_all(srv, mix, tag0=100)
+    inmix = got[105]
+    for key in ("counts", "hit_owner", "tracks", "objects", "members"):
+        assert inmix[key].tobytes() == alone[key].tobytes(), key
+    assert inmix["n_peaks"] == alone["n_peaks"]
+    srv.close()
+
+
+def test_server_graph_replay_equals_direct(ht):
+    """Graph replays with the hit count in device memory give the results of
+    direct launches, for events of different sizes in a row (and the empty
+    event)."""
+    rng = np.random.default_rng(9)
+    events = []
+    for i, n in enumerate([3000, 17, 0, 8192, 500, 4096, 1]):
+        r, phi, layer = G.random_hits(n, seed=2000 + i, r_lo=3.0, r_hi=105.0,
+                                      bad_fraction=0.03 if n > 100 else 0.0)
+        events.append((i % 2, SimpleNamespace(r=r, phi=phi, layer=layer, n_hits=n)))
+    events.append((1, G.make_event(2, CF.WORKLOADS[2]["seed0"] + 78)))
+    events.append((0, G.make_event(1, CF.WORKLOADS[1]["seed0"] + 78)))
+    res = []
+    for graphs in (True, False):
+        srv = ht.Server(KINDS, use_graphs=graphs, **SERVER_ARGS)
+        res.append(run_all(srv, events + events, tag0=0))
+        srv.close()
+    for t in range(2 * len(events)):
+        a, b = res[0][t], res[1][t]
+        for key in ("counts", "hit_owner", "tracks", "objects", "members"):
+            assert a[key].tobytes() == b[key].tobytes(), (t, key)
+        assert a["n_peaks"] == b["n_peaks"]
+        # the second pass replays the same events on reused slots: same results
+        if t >= len(events):
+            c = res[0][t - len(events)]
+            assert a["counts"].tobytes() == c["counts"].tobytes(), t
+
+
+def test_server_admission_and_shedding(ht):
+    args = dict(SERVER_ARGS, max_slots=8, queue_cap=0)
+    one = ht.Server(KINDS, **dict(args, max_slots=1))
+    per_slot = one.slot_bytes
+    one.close()
+    srv = ht.Server(KINDS, **dict(args, hbm_budget=int(per_slot * 2.5)))
+    assert srv.n_slots == 2
+    ev = G.make_event(1, CF.WORKLOADS[1]["seed0"] + 5)
+    assert srv.submit(0, ev.r, ev.phi, ev.layer, 1)
+    assert srv.submit(0, ev.r, ev.phi, ev.layer, 2)
+    assert not srv.submit(0, ev.r, ev.phi, ev.layer, 3)  # both slots busy until polled, no queue
+    done = srv.drain()
+    assert sorted(d["tag"] for d in done) == [1, 2]
+    assert done[0]["counts"].tobytes() == done[1]["counts"].tobytes()
+    srv.close()
+    with pytest.raises(ht.HoughError) as e:
+        ht.Server(KINDS, **dict(args, hbm_budget=per_slot // 4))
+    assert e.value.code == ht.HT_ENOMEM
