@@ -94,6 +94,9 @@ typedef struct {
   int32_t vtx_min_votes;   /* vertex peak threshold */
   int32_t bh_min_tracks;   /* black-hole-like: at least this many member tracks */
   float bh_max_isotropy;   /* ... and |mean member direction| at most this */
+  float vtx_min_d0;        /* tracks with seed |d0| below this [cm] cast no vertex votes (0: all vote) */
+  int32_t fit_kind;        /* refit: 0 Gauss-Newton least squares, 1 extended Kalman filter */
+  int32_t reserved;        /* must be 0 */
 } ht_cluster_cfg;
 
 typedef struct {
@@ -188,12 +191,17 @@ int hough_peaks(const ht_plan* plan, const int32_t* acc, int32_t min_votes, ht_p
  *   ownership  each inlier hit goes to the candidate with the most inlier
  *              layers, then the smallest seed sum (float32), then the lowest
  *              cell; tracks own at least min_layers of their hits;
- *   refit      float64 Gauss-Newton of (phi0, kappa, d0) from the seed;
+ *   refit      float64 Gauss-Newton of (phi0, kappa, d0) from the seed, or
+ *              (fit_kind 1) an extended Kalman filter over the hits in
+ *              increasing radius: weak prior diag(0.1^2, 0.01^2, 10^2) at
+ *              the seed, no process noise, fit_iters passes;
  *   vertices   each track votes for the (rho, theta) cells its seed circle
  *              crosses between |d0| and its first hit radius, rho >= rho_lo;
  *              vertex peaks by the local-maximum rule; members are tracks
  *              within one cell; black-hole-like when >= bh_min_tracks members
- *              and |mean perigee direction| <= bh_max_isotropy.
+ *              and |mean perigee direction| <= bh_max_isotropy; tracks whose seed
+ *              circle passes within vtx_min_d0 of the beam line are
+ *              features at the interaction point and cast no vertex votes.
  *   r, phi, layer  [n_hits] hits (layer index increasing with radius)
  *   peaks, n_peaks peak list and device count from hough_peaks (sorted by
  *                  lin, no cell twice); entries beyond min(*n_peaks,

@@ -773,6 +773,104 @@ static void fit_track(const or_grid* g, const float* r, const float* phi, const 
   t->chi2 = (float)chi2;
 }
 
+/* Refit by a Kalman filter (the paper refines candidates with a Kalman
+ * filter on the CPU, section "Jet and Black Hole Detection"; here it runs on
+ * the device as an alternative to the Gauss-Newton fit).  Reading: state
+ * p = (phi0, kappa, d0) at the perigee, the free ones only (as in the
+ * Gauss-Newton fit), starting from the seed circle.  Each pass filters the
+ * deviation dp from a reference state (the seed, then the previous pass's
+ * result), with the measurement model phi0 + asin(u(r; kappa, d0))
+ * linearised at the reference, as track fits do about a reference
+ * trajectory: prior dp = 0 with covariance diag(0.1^2, 0.01^2, 10^2) (rad,
+ * cm^-1, cm), weak against the hits; the owned hits in increasing radius,
+ * each an azimuth measurement of variance (sigma / r)^2 with innovation
+ * res - H dp; no process noise (the toy detector has no material); the pass
+ * ends with p += dp.  iters passes.  Status 1 when a hit has |u| >= 1, 2 when
+ * an innovation variance is not positive; chi2 as for the Gauss-Newton fit. */
+static void kf_track(const or_grid* g, const float* r, const float* phi, const int32_t* hits,
+                     int32_t lin, const cand_t* cd, int iters, float sigma, or_track* t) {
+  const int np = g->n_phi, nq = g->n_qpt;
+  int i = lin % np, col = lin / np, j = col % nq, k = col / nq;
+  double p[3];
+  double sq0 = sqrt(cd->B * cd->B + cd->C * cd->C);
+  p[0] = atan2(cd->B, -cd->C);
+  p[1] = g->n_qpt > 1 ? 2.0 * cd->A : kappa_centre(g, j);
+  p[2] = g->n_d0 > 1 ? 2.0 * cd->D / (1.0 + sq0) : d0_centre(g, k);
+  int freep[3] = {1, g->n_qpt > 1, g->n_d0 > 1};
+  const double prior[3] = {0.01, 1e-4, 100.0};
+  const double s2 = (double)sigma * (double)sigma;
+  int idx[3], nfree = 0;
+  for (int a = 0; a < 3; ++a)
+    if (freep[a]) idx[nfree++] = a;
+  int status = 0;
+  for (int it = 0; it < iters && status == 0; ++it) {
+    double P[3][3] = {{0}};
+    double dp[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < nfree; ++a) P[a][a] = prior[idx[a]];
+    for (int L = 0; L < OR_MAX_LAYERS; ++L) {
+      int h = hits[L];
+      if (h < 0) continue;
+      double rr = (double)r[h], ph = (double)phi[h];
+      double kap = p[1], d0 = p[2];
+      double den = 1.0 + kap * d0;
+      double u = (kap * (rr * rr + d0 * d0) + 2.0 * d0) / (2.0 * rr * den);
+      if (!(fabs(u) < 1.0)) { status = 1; break; }
+      double sq = sqrt(1.0 - u * u);
+      double res = wrap_pi(ph - (p[0] + asin(u)));
+      double jac[3];
+      jac[0] = 1.0;
+      jac[1] = (rr * rr - d0 * d0) / (2.0 * rr * den * den) / sq;
+      jac[2] = (den * den + 1.0 - kap * kap * rr * rr) / (2.0 * rr * den * den) / sq;
+      double H[3], PH[3];
+      for (int a = 0; a < nfree; ++a) H[a] = jac[idx[a]];
+      for (int a = 0; a < nfree; ++a) {
+        double s = 0.0;
+        for (int b = 0; b < nfree; ++b) s += P[a][b] * H[b];
+        PH[a] = s;
+      }
+      double S = s2 / (rr * rr);
+      for (int a = 0; a < nfree; ++a) S += H[a] * PH[a];
+      if (!(S > 0.0)) { status = 2; break; }
+      double K[3];
+      double innov = res;
+      for (int a = 0; a < nfree; ++a) innov -= H[a] * dp[a];
+      for (int a = 0; a < nfree; ++a) K[a] = PH[a] / S;
+      for (int a = 0; a < nfree; ++a) dp[a] += K[a] * innov;
+      for (int a = 0; a < nfree; ++a)
+        for (int b = 0; b < nfree; ++b) P[a][b] -= K[a] * PH[b];
+    }
+    if (status) break;
+    for (int a = 0; a < nfree; ++a) p[idx[a]] += dp[a];
+  }
+  double chi2 = 0.0;
+  if (status == 0) {
+    for (int L = 0; L < OR_MAX_LAYERS; ++L) {
+      int h = hits[L];
+      if (h < 0) continue;
+      double rr = (double)r[h], ph = (double)phi[h];
+      double kap = p[1], d0 = p[2];
+      double den = 1.0 + kap * d0;
+      double u = (kap * (rr * rr + d0 * d0) + 2.0 * d0) / (2.0 * rr * den);
+      if (!(fabs(u) < 1.0)) { status = 1; break; }
+      double res = wrap_pi(ph - (p[0] + asin(u)));
+      double z = rr * res / (double)sigma;
+      chi2 += z * z;
+    }
+  }
+  double cb = C_LIGHT * (double)g->bfield;
+  if (status != 0) {
+    p[0] = phi0_centre(g, i);
+    p[1] = kappa_centre(g, j);
+    p[2] = d0_centre(g, k);
+    chi2 = -1.0;
+  }
+  t->status = status;
+  t->phi0 = (float)wrap_pi(p[0]);
+  t->qpt = (float)(-p[1] / cb);
+  t->d0 = (float)p[2];
+  t->chi2 = (float)chi2;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Second transform (section "Jet and Black Hole Detection"): tracks that
  * share a displaced vertex lie on one sinusoid of the track-parameter space;
@@ -837,7 +935,8 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
   if (cfg->win_bins < 0 || cfg->min_layers < 3 || cfg->min_layers > OR_MAX_LAYERS ||
       cfg->seed_k < 1 || cfg->seed_k > 64 || cfg->member_cap < 1 || !(cfg->road_sigmas > 0.0f) ||
       !(cfg->box_margin >= 0.0f) || cfg->fit_iters < 0 || cfg->n_rho < 1 || cfg->n_theta < 4 ||
-      !(cfg->rho_hi > cfg->rho_lo) || !(cfg->rho_lo > 0.0f) || !(cfg->sigma_rphi > 0.0f))
+      !(cfg->rho_hi > cfg->rho_lo) || !(cfg->rho_lo > 0.0f) || !(cfg->sigma_rphi > 0.0f) ||
+      !(cfg->vtx_min_d0 >= 0.0f) || cfg->fit_kind < 0 || cfg->fit_kind > 1)
     return -1;
   tables tb;
   if (make_tables(g, &tb)) { free_tables(&tb); return -2; }
@@ -935,9 +1034,14 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
 
   /* 4. refit */
 #pragma omp parallel for schedule(dynamic, 8)
-  for (int32_t t = 0; t < n_stored; ++t)
-    fit_track(g, r, phi, tracks[t].hits, tracks[t].lin, &cd[trk_peak[t]], cfg->fit_iters,
-              cfg->sigma_rphi, &tracks[t]);
+  for (int32_t t = 0; t < n_stored; ++t) {
+    if (cfg->fit_kind == 1)
+      kf_track(g, r, phi, tracks[t].hits, tracks[t].lin, &cd[trk_peak[t]], cfg->fit_iters,
+               cfg->sigma_rphi, &tracks[t]);
+    else
+      fit_track(g, r, phi, tracks[t].hits, tracks[t].lin, &cd[trk_peak[t]], cfg->fit_iters,
+                cfg->sigma_rphi, &tracks[t]);
+  }
 
   /* 5. vertex transform over the stored tracks */
   const int nm = cfg->n_rho, nt = cfg->n_theta;
@@ -951,6 +1055,9 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
     double sn = sqrt(c->B * c->B + c->C * c->C);
     double pca = fabs(2.0 * c->D / (1.0 + sn));
     double rf = (double)tracks[t].r_first;
+    /* a track passing within vtx_min_d0 of the beam line is a feature at
+     * the interaction point (the paper's filter near the IP): no votes */
+    int votes = !(pca < (double)cfg->vtx_min_d0);
     for (int m = 0; m < nm; ++m) {
       tv0[(size_t)t * nm + m] = 0;
       tvn[(size_t)t * nm + m] = 0;
@@ -958,7 +1065,7 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
       double e1 = (double)cfg->rho_lo + (double)(m + 1) * rw;
       double ra = e0 > pca ? e0 : pca;
       double rb = e1 < rf ? e1 : rf;
-      if (!(ra < rb)) continue;
+      if (!votes || !(ra < rb)) continue;
       int ta = theta_bin(crossing_theta(c, sn, ra), nt);
       int tb = theta_bin(crossing_theta(c, sn, rb), nt);
       int d = ((tb - ta) % nt + nt) % nt; /* steps from ta to tb going up */

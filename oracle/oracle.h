@@ -50,6 +50,9 @@ typedef struct {
   int32_t vtx_min_votes;   /* vertex peak threshold */
   int32_t bh_min_tracks;   /* black-hole-like: at least this many member tracks */
   float bh_max_isotropy;   /* ... and |mean member direction| at most this */
+  float vtx_min_d0;        /* tracks with seed |d0| below this cast no vertex votes */
+  int32_t fit_kind;        /* refit: 0 Gauss-Newton least squares, 1 extended Kalman filter */
+  int32_t reserved;        /* 0 */
 } or_cluster_cfg;
 
 typedef struct {

@@ -31,7 +31,7 @@ GRID_3D = dict(n_phi=512, n_qpt=256, n_d0=64, qpt_lo=-1.0, qpt_hi=1.0, d0_lo=-20
 CLUSTER_2D = dict(win_bins=1, min_layers=8, seed_k=4, member_cap=256, road_sigmas=5.0,
                   box_margin=16.0, sigma_rphi=20e-4, fit_iters=3, n_rho=64, n_theta=256,
                   rho_lo=4.0, rho_hi=68.0, vtx_min_votes=5, bh_min_tracks=20,
-                  bh_max_isotropy=0.75)
+                  bh_max_isotropy=0.75, vtx_min_d0=0.0, fit_kind=0)
 CLUSTER_3D = dict(CLUSTER_2D, min_layers=7, member_cap=128)
 # ~55k hits: about 700 hits fall in a cell's member window
 CLUSTER_3D_DENSE = dict(CLUSTER_3D, member_cap=1024)
@@ -49,6 +49,6 @@ WORKLOADS = {
 # resolution, 3.0 cm beam pipe): road and fit resolution 0.4 mm, vertex grid
 # from the beam pipe radius (the paper's IP filter), peaks at 7 votes as in
 # its studies.
-CLUSTER_PAPER = dict(CLUSTER_3D, sigma_rphi=0.04, rho_lo=3.0, rho_hi=67.0)
+CLUSTER_PAPER = dict(CLUSTER_3D, sigma_rphi=0.04, rho_lo=3.0, rho_hi=67.0, vtx_min_d0=0.2)
 PAPER_WORKLOAD = dict(name="paper toy detector, 3D Hough 512x256x64", grid=GRID_3D,
                       min_votes=7, cluster=CLUSTER_PAPER, seed0=5_100_000)

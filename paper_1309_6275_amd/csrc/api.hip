@@ -69,7 +69,9 @@ int check_cluster(const Plan& p, const ht_cluster_cfg& c, int32_t n_hits, int32_
       c.member_cap < 1 || !(c.road_sigmas > 0.0f) || !(c.box_margin >= 0.0f) ||
       c.fit_iters < 0 || c.n_rho < 1 || c.n_theta < 4 || !(c.rho_hi > c.rho_lo) ||
       !(c.rho_lo > 0.0f) || !(c.sigma_rphi > 0.0f) || !isfinite(c.rho_hi) ||
-      !isfinite(c.bh_max_isotropy) || !isfinite(c.road_sigmas) || !isfinite(c.box_margin))
+      !isfinite(c.bh_max_isotropy) || !isfinite(c.road_sigmas) || !isfinite(c.box_margin) ||
+      !(c.vtx_min_d0 >= 0.0f) || !isfinite(c.vtx_min_d0) || c.fit_kind < 0 || c.fit_kind > 1 ||
+      c.reserved != 0)
     return HT_EINVAL;
   if (c.seed_k > 4 || n_hits > p.lim.max_hits || peak_cap > p.lim.max_peaks ||
       c.member_cap > p.lim.max_member_cap || track_cap > p.lim.max_tracks ||

@@ -1195,6 +1195,101 @@ __global__ __launch_bounds__(256) void fit_kernel(AssocArgs A) {
   }
 }
 
+// Refit by a Kalman filter (the paper's Kalman filter that refines
+// candidates, section "Jet and Black Hole Detection", run on the device as
+// its outlook suggests).  State (phi0, kappa, d0) at the perigee from the
+// seed circle.  Each pass filters the deviation dp from a reference state
+// (the seed, then the previous pass's result) with the azimuth model
+// phi0 + asin(u) linearised at the reference, as track fits do about a
+// reference trajectory: prior dp = 0 with covariance diag(0.1^2, 0.01^2,
+// 10^2); the owned hits in layer order, each of variance (sigma / r)^2 with
+// innovation res - H dp; no process noise; the pass ends with p += dp.
+// A fixed parameter (one-column grid axis) keeps a zero row and column in
+// the covariance, so its gain is zero and it never moves.  Status 1 when a
+// hit has |u| >= 1, 2 when an innovation variance is not positive.  The
+// filter is sequential in the hits, so one thread owns one track.
+__global__ __launch_bounds__(64) void kf_kernel(AssocArgs A) {
+  const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t >= ntrk) return;
+  const bool fk = A.n_qpt > 1, fd = A.n_d0 > 1;
+  ht_track& tr = A.out.tracks[t];
+  const int p = A.trk_peak[t];
+  const double* g = A.cgeo + (size_t)p * 5;
+  const double gA = g[1], gB = g[2], gC = g[3], gD = g[4];
+  const int lin = tr.lin;
+  const int i = lin % A.n_phi, col = lin / A.n_phi, j = col % A.n_qpt, k = col / A.n_qpt;
+  const double kap_c = A.kapc[j];
+  const double d0_c = A.d0c[k];
+  const double sq0 = sqrt(gB * gB + gC * gC);
+  double x[3];
+  x[0] = atan2(gB, -gC);
+  x[1] = fk ? 2.0 * gA : kap_c;
+  x[2] = fd ? 2.0 * gD / (1.0 + sq0) : d0_c;
+  const double prior[3] = {0.01, fk ? 1e-4 : 0.0, fd ? 100.0 : 0.0};
+  const double s2 = (double)A.cfg.sigma_rphi * (double)A.cfg.sigma_rphi;
+  int hit[HT_MAX_LAYERS];
+  for (int L = 0; L < HT_MAX_LAYERS; ++L) hit[L] = tr.hits[L];
+  int status = 0;
+  for (int it = 0; it < A.cfg.fit_iters && status == 0; ++it) {
+    double P[3][3];
+    double dp[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) P[a][b] = a == b ? prior[a] : 0.0;
+    for (int L = 0; L < HT_MAX_LAYERS; ++L) {
+      const int h = hit[L];
+      if (h < 0) continue;
+      const double rr = (double)A.r[h], ph = (double)A.phi[h];
+      const double kap = x[1], d0 = x[2];
+      const double den = 1.0 + kap * d0;
+      const double u = (kap * (rr * rr + d0 * d0) + 2.0 * d0) / (2.0 * rr * den);
+      if (!(fabs(u) < 1.0)) { status = 1; break; }
+      const double sq = sqrt(1.0 - u * u);
+      const double res = wrap_pi(ph - (x[0] + asin(u)));
+      double H[3];
+      H[0] = 1.0;
+      H[1] = fk ? (rr * rr - d0 * d0) / (2.0 * rr * den * den) / sq : 0.0;
+      H[2] = fd ? (den * den + 1.0 - kap * kap * rr * rr) / (2.0 * rr * den * den) / sq : 0.0;
+      double PH[3];
+      for (int a = 0; a < 3; ++a) PH[a] = P[a][0] * H[0] + P[a][1] * H[1] + P[a][2] * H[2];
+      const double S = s2 / (rr * rr) + H[0] * PH[0] + H[1] * PH[1] + H[2] * PH[2];
+      if (!(S > 0.0)) { status = 2; break; }
+      const double innov = res - H[0] * dp[0] - H[1] * dp[1] - H[2] * dp[2];
+      double K[3];
+      for (int a = 0; a < 3; ++a) K[a] = PH[a] / S;
+      for (int a = 0; a < 3; ++a) dp[a] += K[a] * innov;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) P[a][b] -= K[a] * PH[b];
+    }
+    if (status != 0) break;
+    for (int a = 0; a < 3; ++a) x[a] += dp[a];
+  }
+  double chi2 = 0.0;
+  if (status == 0) {
+    for (int L = 0; L < HT_MAX_LAYERS; ++L) {
+      const int h = hit[L];
+      if (h < 0) continue;
+      const double rr = (double)A.r[h], ph = (double)A.phi[h];
+      const double den = 1.0 + x[1] * x[2];
+      const double u = (x[1] * (rr * rr + x[2] * x[2]) + 2.0 * x[2]) / (2.0 * rr * den);
+      if (!(fabs(u) < 1.0)) { status = 1; break; }
+      const double z = rr * wrap_pi(ph - (x[0] + asin(u))) / (double)A.cfg.sigma_rphi;
+      chi2 += z * z;
+    }
+  }
+  if (status != 0) {
+    x[0] = -kPi + ((double)i + 0.5) * (2.0 * kPi / (double)A.n_phi);
+    x[1] = kap_c;
+    x[2] = d0_c;
+    chi2 = -1.0;
+  }
+  tr.status = status;
+  tr.phi0 = (float)wrap_pi(x[0]);
+  tr.qpt = (float)(-x[1] / A.cb);
+  tr.d0 = (float)x[2];
+  tr.chi2 = (float)chi2;
+}
+
 // ---- second transform --------------------------------------------------------------
 __device__ __forceinline__ double crossing_theta(double cA, double cB, double cC, double cD,
                                                  double sn, double rho) {
@@ -1224,13 +1319,15 @@ __global__ void vvote_kernel(AssocArgs A) {
     const double sn = sqrt(cB * cB + cC * cC);
     const double pca = fabs(2.0 * cD / (1.0 + sn));
     const double rf = (double)A.out.tracks[t].r_first;
+    // a track passing within vtx_min_d0 of the beam line is an IP feature
+    const bool votes = !(pca < (double)A.cfg.vtx_min_d0);
     for (int m = 0; m < nm; ++m) {
       int start = 0, len = 0;
       const double e0 = (double)A.cfg.rho_lo + (double)m * rw;
       const double e1 = (double)A.cfg.rho_lo + (double)(m + 1) * rw;
       const double ra = e0 > pca ? e0 : pca;
       const double rb = e1 < rf ? e1 : rf;
-      if (ra < rb) {
+      if (votes && ra < rb) {
         const int ta = theta_bin(crossing_theta(cA, cB, cC, cD, sn, ra), nt);
         const int tb = theta_bin(crossing_theta(cA, cB, cC, cD, sn, rb), nt);
         int d = (tb - ta) % nt;
@@ -1514,7 +1611,10 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   HT_CHECK(hipGetLastError());
   const int tcap = out.track_cap > 0 ? out.track_cap : 1;
   if (out.track_cap > 0) {
-    fit_kernel<<<blocks_for(tcap, 4), 256, 0, s>>>(A);
+    if (cfg.fit_kind == 1)
+      kf_kernel<<<blocks_for(tcap, 64), 64, 0, s>>>(A);
+    else
+      fit_kernel<<<blocks_for(tcap, 4), 256, 0, s>>>(A);
     HT_CHECK(hipGetLastError());
     vvote_kernel<<<blocks_for(tcap, 64), 64, 0, s>>>(A);
     HT_CHECK(hipGetLastError());

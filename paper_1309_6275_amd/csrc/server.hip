@@ -27,8 +27,8 @@
 #include "ht_internal.h"
 
 // layouts the Python binding mirrors
-static_assert(sizeof(ht_server_kind) == 100, "ht_server_kind layout");
-static_assert(sizeof(ht_server_cfg) == 448, "ht_server_cfg layout");
+static_assert(sizeof(ht_server_kind) == 112, "ht_server_kind layout");
+static_assert(sizeof(ht_server_cfg) == 496, "ht_server_cfg layout");
 static_assert(sizeof(ht_server_out) == 56, "ht_server_out layout");
 static_assert(sizeof(ht_server_result) == 88, "ht_server_result layout");
 

@@ -56,7 +56,8 @@ class ClusterCfg(C.Structure):
                 ("fit_iters", C.c_int32), ("n_rho", C.c_int32), ("n_theta", C.c_int32),
                 ("rho_lo", C.c_float), ("rho_hi", C.c_float),
                 ("vtx_min_votes", C.c_int32), ("bh_min_tracks", C.c_int32),
-                ("bh_max_isotropy", C.c_float)]
+                ("bh_max_isotropy", C.c_float), ("vtx_min_d0", C.c_float),
+                ("fit_kind", C.c_int32), ("reserved", C.c_int32)]
 
 
 class ClusterOut(C.Structure):
@@ -188,7 +189,8 @@ def cluster_struct(c: dict) -> ClusterCfg:
                       float(c["sigma_rphi"]), int(c["fit_iters"]), int(c["n_rho"]),
                       int(c["n_theta"]), float(c["rho_lo"]), float(c["rho_hi"]),
                       int(c["vtx_min_votes"]), int(c["bh_min_tracks"]),
-                      float(c["bh_max_isotropy"]))
+                      float(c["bh_max_isotropy"]),
+                      float(c.get("vtx_min_d0", 0.0)), int(c.get("fit_kind", 0)), 0)
 
 
 class Plan:

@@ -1,0 +1,225 @@
+"""Train and evaluate the learned peak filter on the device (ht_cnn_*).
+
+Labels (the truth matching of the track metrics): a threshold peak is
+positive when the track that assoc_cluster builds from it survives and
+matches a generated track (at least 75% and at least min_layers of its hits
+from that track); every other peak is negative.  Windows of all peaks come
+from the device; the training set keeps every positive and a stated number
+of random negatives per event.  Training: SGD with momentum on the device,
+positives weighted by the negative/positive ratio.  The threshold keeps a
+stated fraction of the validation positives.  Evaluation on other events:
+track efficiency, fake rate, peaks kept and the time of assoc_cluster with
+and without the filter (the filter's own time included).
+
+Seeds: training events 5 000 000 + e, validation 5 500 000 + e, test
+5 900 000 + e, all of the 3D displaced-jet composition.
+
+    python -m paper_1309_6275_amd.peakfilter [--train-events 60] [--epochs 6]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import configs as CF
+from . import eventgen as G
+from . import metrics as M
+
+
+class Pipeline:
+    def __init__(self, torch, H, W, peak_cap=1 << 19):
+        self.torch, self.H, self.W = torch, H, W
+        g, cl = W["grid"], W["cluster"]
+        self.plan = H.Plan(g, max_hits=65535, max_peaks=peak_cap,
+                           max_member_cap=cl["member_cap"], max_tracks=1 << 13)
+        self.acc = torch.empty(self.plan.acc_shape, dtype=torch.int32, device="cuda")
+        self.peaks = torch.empty((peak_cap, 2), dtype=torch.int32, device="cuda")
+        self.kept = torch.empty((peak_cap, 2), dtype=torch.int32, device="cuda")
+        self.nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self.nk = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self.win = torch.empty((peak_cap, H.CNN_WINDOW), dtype=torch.bfloat16, device="cuda")
+        self.logits = torch.empty(peak_cap, dtype=torch.float32, device="cuda")
+        self.ws = H.cnn_workspace(peak_cap)
+        self.bufs = H.ClusterBuffers(65535, 1 << 13, 256, 1 << 14, cl["n_rho"], cl["n_theta"])
+        self.cap = peak_cap
+
+    def upload(self, ev):
+        t = self.torch
+        return dict(r=t.from_numpy(ev.r).cuda(), phi=t.from_numpy(ev.phi).cuda(),
+                    layer=t.from_numpy(ev.layer).cuda())
+
+    def peaks_of(self, d):
+        H = self.H
+        H.hough_vote(self.plan, d["r"], d["phi"], self.acc)
+        H.hough_peaks(self.plan, self.acc, self.W["min_votes"], self.peaks, self.nf)
+
+    def assoc(self, d, peaks, n):
+        self.H.assoc_cluster(self.plan, d["r"], d["phi"], d["layer"], peaks, n, self.W["cluster"],
+                             self.bufs, with_vacc=False)
+
+    def filter(self, params, thr):
+        H = self.H
+        H.cnn_windows(self.plan, self.acc, self.peaks, self.nf, self.win)
+        H.cnn_forward(params, self.win, self.logits, self.ws, n_dev=self.nf)
+        H.cnn_keep(self.plan, self.logits, self.peaks, self.nf, thr, self.kept, self.nk)
+
+
+def label_event(pl, ev, cl):
+    """Windows (host bf16 bits as int16) and labels of all peaks of one event."""
+    t = pl.torch
+    d = pl.upload(ev)
+    pl.peaks_of(d)
+    pl.assoc(d, pl.peaks, pl.nf)
+    t.cuda.synchronize()
+    n = min(int(pl.nf.item()), pl.cap)
+    out = pl.bufs.to_host(ev.n_hits)
+    tm = M.match_tracks(out["tracks"]["hits"], ev.hit_track, cl["min_layers"])
+    y = np.zeros(n, np.float32)
+    good = out["tracks"]["peak"][tm >= 0]
+    y[good[good < n]] = 1.0
+    pl.H.cnn_windows(pl.plan, pl.acc, pl.peaks, pl.nf, pl.win)
+    t.cuda.synchronize()
+    return pl.win[:n].view(t.int16).cpu().numpy(), y
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train-events", type=int, default=60)
+    ap.add_argument("--val-events", type=int, default=10)
+    ap.add_argument("--test-events", type=int, default=10)
+    ap.add_argument("--neg-per-event", type=int, default=3000)
+    ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=0.05)
+    ap.add_argument("--keep", type=float, default=0.995,
+                    help="fraction of validation positives the threshold keeps")
+    args = ap.parse_args(argv)
+    import torch
+    from . import houghtrig as H
+    W = CF.WORKLOADS[2]
+    cl = W["cluster"]
+    pl = Pipeline(torch, H, W)
+    rng = np.random.default_rng(5_000_000)
+
+    # training set
+    t0 = time.perf_counter()
+    xs, ys = [], []
+    for e in range(args.train_events):
+        win, y = label_event(pl, G.make_event(2, 5_000_000 + e), cl)
+        pos = np.flatnonzero(y > 0.5)
+        neg = np.flatnonzero(y < 0.5)
+        neg = rng.choice(neg, min(args.neg_per_event, neg.size), replace=False)
+        sel = np.concatenate([pos, neg])
+        xs.append(win[sel])
+        ys.append(y[sel])
+    X = np.concatenate(xs)
+    Y = np.concatenate(ys)
+    n_pos = int(Y.sum())
+    t_data = time.perf_counter() - t0
+    pos_weight = (Y.size - n_pos) / max(n_pos, 1)
+
+    # training on the device
+    params = torch.from_numpy(init_params(7)).cuda()
+    mom = torch.zeros_like(params)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    Xd = torch.from_numpy(X).cuda().view(torch.bfloat16)
+    Yd = torch.from_numpy(Y).cuda()
+    ws = H.cnn_workspace(args.batch, training=True)
+    losses = []
+    t0 = time.perf_counter()
+    steps = 0
+    for ep in range(args.epochs):
+        perm = torch.from_numpy(rng.permutation(Y.size)).cuda()
+        ep_loss = []
+        for b in range(0, Y.size - args.batch + 1, args.batch):
+            idx = perm[b:b + args.batch]
+            H.cnn_train_step(params, mom, Xd[idx].contiguous(), Yd[idx].contiguous(), args.lr, 0.9,
+                             pos_weight, loss, ws)
+            ep_loss.append(loss.clone())
+            steps += 1
+        torch.cuda.synchronize()
+        losses.append(float(torch.cat(ep_loss).mean().item()))
+    t_train = time.perf_counter() - t0
+
+    # threshold on validation events: keep the requested fraction of positives
+    pos_logits = []
+    for e in range(args.val_events):
+        ev = G.make_event(2, 5_500_000 + e)
+        win, y = label_event(pl, ev, cl)
+        n = y.size
+        ws_i = pl.ws
+        H.cnn_forward(params, pl.win[:n].contiguous(), pl.logits[:n], ws_i)
+        torch.cuda.synchronize()
+        pos_logits.append(pl.logits[:n].cpu().numpy()[y > 0.5])
+    pos_logits = np.concatenate(pos_logits)
+    thr = float(np.quantile(pos_logits, 1.0 - args.keep)) if pos_logits.size else 0.0
+
+    # evaluation: the same events with all peaks and with the kept peaks
+    rows = []
+    ev_s, ev_e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for e in range(args.test_events):
+        ev = G.make_event(2, 5_900_000 + e)
+        d = pl.upload(ev)
+        res = {}
+        for mode in ("all", "filtered"):
+            pl.peaks_of(d)
+            torch.cuda.synchronize()
+            ev_s.record()
+            if mode == "all":
+                pl.assoc(d, pl.peaks, pl.nf)
+            else:
+                pl.filter(params, thr)
+                pl.assoc(d, pl.kept, pl.nk)
+            ev_e.record()
+            torch.cuda.synchronize()
+            out = pl.bufs.to_host(ev.n_hits)
+            tm = M.track_metrics(ev, W["grid"], cl["min_layers"], out["tracks"]["hits"])
+            res[mode] = dict(ms=ev_s.elapsed_time(ev_e), eff=tm["efficiency"],
+                             fake=tm["fake_rate"], n_found=tm["n_found"], n_acc=tm["n_truth_acc"],
+                             n_fake=tm["n_fake"], n_tracks=tm["n_tracks"])
+        res["peaks"] = int(pl.nf.item())
+        res["kept"] = int(pl.nk.item())
+        rows.append(res)
+
+    def agg(mode, key):
+        return float(np.mean([r[mode][key] for r in rows]))
+
+    def ratio(mode, a, b):
+        return sum(r[mode][a] for r in rows) / max(1, sum(r[mode][b] for r in rows))
+
+    line = {
+        "train_windows": int(Y.size), "train_positives": n_pos, "pos_weight": pos_weight,
+        "data_seconds": t_data, "train_steps": steps, "train_seconds": t_train,
+        "epoch_loss": losses, "threshold": thr, "keep_target": args.keep,
+        "peaks_per_event": float(np.mean([r["peaks"] for r in rows])),
+        "kept_fraction": sum(r["kept"] for r in rows) / max(1, sum(r["peaks"] for r in rows)),
+        "assoc_ms_all": agg("all", "ms"), "filter_plus_assoc_ms": agg("filtered", "ms"),
+        "efficiency_all": ratio("all", "n_found", "n_acc"),
+        "efficiency_filtered": ratio("filtered", "n_found", "n_acc"),
+        "fake_rate_all": ratio("all", "n_fake", "n_tracks"),
+        "fake_rate_filtered": ratio("filtered", "n_fake", "n_tracks"),
+    }
+    print(json.dumps(line), flush=True)
+    return line, params
+
+
+def init_params(seed):
+    """He-style normal weights (fan-in scaled), zero biases, in the flat
+    layout of the device parameters."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape, fan_in in (((16, 27), 27), ((16,), 0), ((16, 16, 27), 432), ((16,), 0),
+                          ((64, 16), 16), ((64,), 0), ((64,), 64), ((1,), 0)):
+        if fan_in:
+            parts.append(rng.normal(0.0, np.sqrt(2.0 / fan_in), shape).reshape(-1))
+        else:
+            parts.append(np.zeros(int(np.prod(shape))))
+    return np.concatenate(parts).astype(np.float32)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -38,12 +38,12 @@ SCANS = {
 }
 
 
-def run_event(H, torch, plan, W, ev, bufs, acc, peaks, nf):
+def run_event(H, torch, plan, W, cl, ev, bufs, acc, peaks, nf):
     d = dict(r=torch.from_numpy(ev.r).cuda(), phi=torch.from_numpy(ev.phi).cuda(),
              layer=torch.from_numpy(ev.layer).cuda())
     H.hough_vote(plan, d["r"], d["phi"], acc)
     H.hough_peaks(plan, acc, W["min_votes"], peaks, nf)
-    H.assoc_cluster(plan, d["r"], d["phi"], d["layer"], peaks, nf, W["cluster"], bufs,
+    H.assoc_cluster(plan, d["r"], d["phi"], d["layer"], peaks, nf, cl, bufs,
                     with_vacc=False)
     return bufs.to_host(ev.n_hits)
 
@@ -57,7 +57,9 @@ def main(argv=None):
     from . import houghtrig as H
     W = CF.PAPER_WORKLOAD
     g, cl = W["grid"], W["cluster"]
-    plan = H.Plan(g, max_hits=65535, max_peaks=1 << 21, max_member_cap=cl["member_cap"],
+    # 3000 tracks put several hundred hits in a cell's member window
+    dense = dict(cl, member_cap=1024)
+    plan = H.Plan(g, max_hits=65535, max_peaks=1 << 21, max_member_cap=dense["member_cap"],
                   max_tracks=1 << 13)
     acc = torch.empty(plan.acc_shape, dtype=torch.int32, device="cuda")
     peaks = torch.empty((1 << 21, 2), dtype=torch.int32, device="cuda")
@@ -74,7 +76,8 @@ def main(argv=None):
             t0 = time.perf_counter()
             for e in range(n_ev):
                 ev = G.make_paper_event(W["seed0"] + 100_000 * fig + 1000 * x + e, **kw(x))
-                res = run_event(H, torch, plan, W, ev, bufs, acc, peaks, nf)
+                res = run_event(H, torch, plan, W, dense if fig == 10 else cl, ev, bufs, acc,
+                                peaks, nf)
                 tm = M.match_tracks(res["tracks"]["hits"], ev.hit_track, cl["min_layers"])
                 vm = M.vertex_metrics(ev, res["objects"], res["members"], tm, rho_bin, theta_bin,
                                       min_tracks=2)

@@ -47,12 +47,12 @@ def test_binding_names_match_header():
 def test_struct_sizes_match_header_layout():
     from paper_1309_6275_amd import houghtrig as H
     assert ctypes.sizeof(H.Grid) == 32
-    assert ctypes.sizeof(H.ClusterCfg) == 15 * 4
+    assert ctypes.sizeof(H.ClusterCfg) == 18 * 4
     assert H.TRACK_DTYPE.itemsize == 13 * 4 + 16 * 4
     assert H.OBJECT_DTYPE.itemsize == 8 * 4
     # serving loop structs (static_asserts on the C side hold the same sizes)
-    assert ctypes.sizeof(H.ServerKind) == 100
-    assert ctypes.sizeof(H.ServerCfg) == 448
+    assert ctypes.sizeof(H.ServerKind) == 112
+    assert ctypes.sizeof(H.ServerCfg) == 496
     assert ctypes.sizeof(H.ServerOut) == 56
     assert ctypes.sizeof(H.ServerResult) == 88
 

@@ -150,6 +150,25 @@ def test_assoc_parity_paper_geometry(torch, ht, oracle, kw):
     compare(got, want, f"paper {kw}")
 
 
+@pytest.mark.parametrize("case", ["cfg1", "cfg2", "paper"])
+def test_assoc_parity_kalman_refit(torch, ht, oracle, case):
+    """fit_kind 1: the Kalman-filter refit instead of Gauss-Newton (2D grid
+    with d0 fixed, 3D grid, the paper's geometry)."""
+    if case == "paper":
+        W = CF.PAPER_WORKLOAD
+        ev = G.make_paper_event(W["seed0"] + 21, n_prompt=300, n_jets=3)
+    else:
+        cid = int(case[-1])
+        W = CF.WORKLOADS[cid]
+        ev = G.make_event(cid, W["seed0"] + 21)
+    cfg = dict(W["cluster"], fit_kind=1, fit_iters=3)
+    print(f"kalman {case} hits {ev.n_hits}", flush=True)
+    got, acc, pk = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], cfg)
+    want = run_oracle(oracle, W["grid"], ev, acc, pk, cfg)
+    compare(got, want, f"kalman {case}")
+    assert (want["tracks"]["status"] == 0).mean() > 0.9
+
+
 @pytest.mark.parametrize("kind", ["jet", "bh"])
 def test_assoc_parity_vertex_events(torch, ht, oracle, kind):
     W = CF.WORKLOADS[2]
@@ -215,7 +234,8 @@ def test_assoc_rejects_bad_config(torch, ht):
     bufs = ht.ClusterBuffers(ev.n_hits, 16, 4, 16, 64, 256)
     for bad, code in ((dict(min_layers=2), ht.HT_EINVAL), (dict(seed_k=5), ht.HT_EUNSUPPORTED),
                       (dict(member_cap=4096), ht.HT_EUNSUPPORTED),
-                      (dict(rho_lo=-1.0), ht.HT_EINVAL)):
+                      (dict(rho_lo=-1.0), ht.HT_EINVAL), (dict(fit_kind=2), ht.HT_EINVAL),
+                      (dict(vtx_min_d0=-0.1), ht.HT_EINVAL)):
         with pytest.raises(ht.HoughError) as e:
             ht.assoc_cluster(plan, r, r, layer, peaks, nf, dict(W["cluster"], **bad), bufs)
         assert e.value.code == code, bad

@@ -352,6 +352,39 @@ def test_vertex_transform_finds_known_vertex(oracle):
     assert res["vacc"].sum() > 0
 
 
+def test_vertex_min_d0_filters_prompt_tracks(oracle):
+    """On the paper's detector (vertex grid from the 3 cm pipe, first layer at
+    11 cm) prompt tracks would vote between 3 and 11 cm; with vtx_min_d0
+    above their seed |d0| they cast no vertex votes, while a displaced
+    vertex's tracks vote as before."""
+    W = CF.PAPER_WORKLOAD
+    g = W["grid"]
+    on_cfg = W["cluster"]
+    off_cfg = dict(on_cfg, vtx_min_d0=0.0)
+    rng = np.random.default_rng(17)
+    prompt = [(rng.uniform(-np.pi, np.pi), rng.choice([-1, 1]) * rng.uniform(0.3, 0.9), 0.0)
+              for _ in range(12)]
+    ev = G.make_tracks_event(prompt, smear=0.0, radii=G.PAPER_RADII)
+    acc, _ = oracle.hough_vote(g, ev.r, ev.phi)
+    pk, _ = oracle.hough_peaks(g, acc, W["min_votes"])
+    off = oracle.assoc_cluster(g, ev.r, ev.phi, ev.layer, pk, off_cfg)
+    on = oracle.assoc_cluster(g, ev.r, ev.phi, ev.layer, pk, on_cfg)
+    assert off["counts"][1] == 12 and on["counts"][1] == 12
+    assert off["vacc"].sum() > 0 and on["vacc"].sum() == 0
+    assert on["counts"][2] == 0
+    # displaced vertex inside the first layer, tracks with |d0| >= 0.5 cm
+    rho, theta = 7.5, 0.63
+    psis = theta + rng.choice([-1, 1], 10) * rng.uniform(0.1, 0.6, 10)
+    qpts = rng.choice([-1, 1], 10) * rng.uniform(0.2, 0.9, 10)
+    ev = G.make_vertex_event(rho, theta, psis, qpts, smear=0.0, radii=G.PAPER_RADII)
+    acc, _ = oracle.hough_vote(g, ev.r, ev.phi)
+    pk, _ = oracle.hough_peaks(g, acc, W["min_votes"])
+    a = oracle.assoc_cluster(g, ev.r, ev.phi, ev.layer, pk, off_cfg)
+    b = oracle.assoc_cluster(g, ev.r, ev.phi, ev.layer, pk, on_cfg)
+    assert a["counts"][1] == 10 and b["counts"][1] == 10
+    assert a["vacc"].sum() > 0 and np.array_equal(a["vacc"], b["vacc"])
+
+
 def test_black_hole_like_vertex(oracle):
     """A high-multiplicity isotropic decay a few cm out is classified as
     black-hole-like; a narrow jet is not."""
