@@ -57,6 +57,10 @@ def parse():
                          "2D/3D event stream, p50/p99 latency, shedding, closed-loop throughput")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="seconds of arrivals per Poisson rate in --serve")
+    ap.add_argument("--two-pass", action="store_true",
+                    help="benchmark iterative hit removal instead: prompt pass on the 2D grid, "
+                         "removal of its hits, displaced pass on the 3D grid, against the "
+                         "single pass on the same events")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (read + write) 5 times, the "
                          "reference for scaling HBM byte counters")
@@ -233,6 +237,109 @@ def serve_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def two_pass_bench(args):
+    """Events/s and physics of iterative hit removal on the displaced-jet
+    workload, beside the single pass over the same events."""
+    import torch
+    from paper_1309_6275_amd import configs as CF
+    from paper_1309_6275_amd import eventgen as G
+    from paper_1309_6275_amd import houghtrig as H
+    from paper_1309_6275_amd import iterative
+    from paper_1309_6275_amd import metrics as M
+
+    W = CF.WORKLOADS[2]
+    D = CF.TWO_PASS["displaced"]
+    B = args.batch
+    events = [G.make_event(2, W["seed0"] + 100 + e) for e in range(B)]
+    dev = [dict(r=torch.from_numpy(ev.r).cuda(), phi=torch.from_numpy(ev.phi).cuda(),
+                layer=torch.from_numpy(ev.layer).cuda()) for ev in events]
+    tp = iterative.TwoPass(max_hits=65535, track_cap=1 << 13)
+    plan = H.Plan(W["grid"], max_hits=65535, max_peaks=1 << 19,
+                  max_member_cap=W["cluster"]["member_cap"], max_tracks=1 << 13)
+    acc = torch.empty(plan.acc_shape, dtype=torch.int32, device="cuda")
+    peaks = torch.empty((1 << 19, 2), dtype=torch.int32, device="cuda")
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    bufs = H.ClusterBuffers(65535, 1 << 13, 1024, 1 << 15, W["cluster"]["n_rho"],
+                            W["cluster"]["n_theta"])
+    cl = W["cluster"]
+    rho_bin = (cl["rho_hi"] - cl["rho_lo"]) / cl["n_rho"]
+    theta_bin = 2 * np.pi / cl["n_theta"]
+
+    def single(d):
+        H.hough_vote(plan, d["r"], d["phi"], acc)
+        H.hough_peaks(plan, acc, W["min_votes"], peaks, nf)
+        H.assoc_cluster(plan, d["r"], d["phi"], d["layer"], peaks, nf, cl, bufs)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            for d in dev:
+                fn(d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for d in dev:
+                fn(d)
+        torch.cuda.synchronize()
+        return args.steps * B / (time.perf_counter() - t0)
+
+    rate_two = timed(lambda d: tp.run(d["r"], d["phi"], d["layer"]))
+    rate_one = timed(single)
+
+    def physics(run_one):
+        found = truth = fake = ntrk = vfound = vfind = nv = kept = 0
+        for ev, d in zip(events, dev):
+            hits, objects, members, k = run_one(ev, d)
+            kept += k
+            hit_rows = np.concatenate(hits) if len(hits) > 1 else hits[0]
+            tm = M.track_metrics(ev, W["grid"], cl["min_layers"], hit_rows)
+            found += tm["n_found"]
+            truth += tm["n_truth_acc"]
+            fake += tm["n_fake"]
+            ntrk += tm["n_tracks"]
+            match = M.match_tracks(hits[-1], ev.hit_track, cl["min_layers"])
+            vm = M.vertex_metrics(ev, objects, members, match, rho_bin, theta_bin, min_tracks=2)
+            vfound += vm["n_found"]
+            vfind += vm["n_findable"]
+            nv += vm["n_vertices"]
+        return dict(track_efficiency=found / max(truth, 1), fake_rate=fake / max(ntrk, 1),
+                    tracks_per_event=ntrk / B, vertices_found=vfound, vertices_findable=vfind,
+                    vertices=nv, hits_in_displaced_pass=kept / B)
+
+    def run_two(ev, d):
+        tp.run(d["r"], d["phi"], d["layer"])
+        torch.cuda.synchronize()
+        first, keep, second = tp.to_host(ev.n_hits)
+        return ([first["tracks"]["hits"], second["tracks"]["hits"]], second["objects"],
+                second["members"], keep.size)
+
+    def run_single(ev, d):
+        single(d)
+        torch.cuda.synchronize()
+        out = bufs.to_host(ev.n_hits)
+        return [out["tracks"]["hits"]], out["objects"], out["members"], ev.n_hits
+
+    line = {
+        "metric": "events_per_s",
+        "value": rate_two,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "higher_is_better": True,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": W["name"] + ", iterative hit removal",
+                   "passes": CF.TWO_PASS["name"], "events_per_step": B,
+                   "parallelism": "single GPU, events back to back on one stream"},
+        "two_pass": physics(run_two),
+        "single_pass_events_per_s": rate_one,
+        "single_pass": physics(run_single),
+        "note": "one host read of the kept-hit count per event between the passes",
+    }
+    tp.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -251,6 +358,9 @@ def main():
         hip_build.build()
     if args.serve:
         serve_bench(args)
+        return
+    if args.two_pass:
+        two_pass_bench(args)
         return
     from paper_1309_6275_amd import configs as CF
     from paper_1309_6275_amd import eventgen as G

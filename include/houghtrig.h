@@ -192,9 +192,11 @@ int hough_peaks(const ht_plan* plan, const int32_t* acc, int32_t min_votes, ht_p
  *              layers, then the smallest seed sum (float32), then the lowest
  *              cell; tracks own at least min_layers of their hits;
  *   refit      float64 Gauss-Newton of (phi0, kappa, d0) from the seed, or
- *              (fit_kind 1) an extended Kalman filter over the hits in
- *              increasing radius: weak prior diag(0.1^2, 0.01^2, 10^2) at
- *              the seed, no process noise, fit_iters passes;
+ *              (fit_kind 1) a Kalman filter over the hits in increasing
+ *              radius of the deviation from a reference state (the seed,
+ *              then the previous pass), the azimuth model linearised at the
+ *              reference: weak prior diag(0.1^2, 0.01^2, 10^2), no process
+ *              noise, fit_iters passes;
  *   vertices   each track votes for the (rho, theta) cells its seed circle
  *              crosses between |d0| and its first hit radius, rho >= rho_lo;
  *              vertex peaks by the local-maximum rule; members are tracks
@@ -213,6 +215,36 @@ int assoc_cluster(const ht_plan* plan, const float* r, const float* phi, const u
                   int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks,
                   int32_t peak_cap, const ht_cluster_cfg* cfg, const ht_cluster_out* out,
                   void* stream);
+
+/* Iterative hit removal (paper, section "Current Tracker and Tracking
+ * Algorithm": earlier passes find the easier, prompt tracks, whose hits are
+ * then removed so that later passes search for displaced tracks among far
+ * fewer combinations).  Typical use: a prompt pass (hough_vote,
+ * hough_peaks, assoc_cluster on a one-column d0 grid), ht_compact_hits on
+ * its hit_owner, a displaced pass on the kept hits, then
+ * ht_remap_track_hits so that that pass's tracks name hits of the event.
+ *
+ * ht_compact_hits -- keeps the hits with hit_owner < 0, in event order.
+ *   r, phi, layer  [n_hits] device hits of the event
+ *   hit_owner      [n_hits] device owner array of assoc_cluster
+ *   out_r, out_phi, out_layer, out_index
+ *                  [n_hits] device outputs; out_index[i] is the event index
+ *                  of kept hit i
+ *   n_out          device int32 receiving the number of kept hits
+ * n_hits is 0..65535 (HT_EUNSUPPORTED above); outputs must not overlap the
+ * inputs.  Allocates nothing; one kernel on `stream`.
+ *
+ * ht_remap_track_hits -- replaces every hit index h >= 0 of the first
+ * min(counts[1], track_cap) tracks by index[h] (h < n_index; others are
+ * left alone).
+ *   tracks, track_cap  device track array of an assoc_cluster call
+ *   counts             that call's device counts
+ *   index              [n_index] device out_index of ht_compact_hits */
+int ht_compact_hits(const float* r, const float* phi, const uint8_t* layer, int32_t n_hits,
+                    const int32_t* hit_owner, float* out_r, float* out_phi, uint8_t* out_layer,
+                    int32_t* out_index, int32_t* n_out, void* stream);
+int ht_remap_track_hits(ht_track* tracks, int32_t track_cap, const int32_t* counts,
+                        const int32_t* index, int32_t n_index, void* stream);
 
 /* Stage timing, for measurement.  After ht_profile_begin, each later call
  * on the plan records HIP events on its stream around its stages:

@@ -218,3 +218,42 @@ def refine_one(grid: dict, r, phi, layer, lin: int, cfg: dict):
 
 def set_threads(n: int):
     lib().oracle_set_threads(int(n))
+
+
+# --------------------------------------------------------------------------
+# Iterative hit removal (section "Current Tracker and Tracking Algorithm":
+# an earlier pass finds the easier, prompt tracks, their hits are removed,
+# and a later pass searches the rest for displaced tracks).
+
+def compact_hits(r, phi, layer, hit_owner):
+    """The hits that no track owns (hit_owner < 0), in event order, and the
+    event index of each."""
+    keep = np.flatnonzero(np.asarray(hit_owner) < 0).astype(np.int32)
+    return (np.asarray(r)[keep], np.asarray(phi)[keep], np.asarray(layer)[keep], keep)
+
+
+def remap_track_hits(tracks, index):
+    """Tracks of a pass over kept hits, with their hit indices mapped back
+    to the event through index."""
+    out = tracks.copy()
+    h = out["hits"]
+    m = h >= 0
+    h[m] = np.asarray(index)[h[m]]
+    return out
+
+
+def two_pass(grid_prompt: dict, min_votes_prompt: int, cfg_prompt: dict, grid: dict,
+             min_votes: int, cfg: dict, r, phi, layer, peak_cap=None, **caps):
+    """Prompt pass (vote, peaks, association on grid_prompt), removal of its
+    owned hits, displaced pass on the rest; the displaced pass's tracks name
+    event hits.  Returns (prompt result, kept event indices, displaced
+    result)."""
+    acc, _ = hough_vote(grid_prompt, r, phi)
+    pk, _ = hough_peaks(grid_prompt, acc, min_votes_prompt, peak_cap)
+    first = assoc_cluster(grid_prompt, r, phi, layer, pk, cfg_prompt, **caps)
+    r2, phi2, layer2, keep = compact_hits(r, phi, layer, first["hit_owner"])
+    acc2, _ = hough_vote(grid, r2, phi2)
+    pk2, _ = hough_peaks(grid, acc2, min_votes, peak_cap)
+    second = assoc_cluster(grid, r2, phi2, layer2, pk2, cfg, **caps)
+    second["tracks"] = remap_track_hits(second["tracks"], keep)
+    return first, keep, second

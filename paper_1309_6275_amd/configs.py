@@ -52,3 +52,10 @@ WORKLOADS = {
 CLUSTER_PAPER = dict(CLUSTER_3D, sigma_rphi=0.04, rho_lo=3.0, rho_hi=67.0, vtx_min_d0=0.2)
 PAPER_WORKLOAD = dict(name="paper toy detector, 3D Hough 512x256x64", grid=GRID_3D,
                       min_votes=7, cluster=CLUSTER_PAPER, seed0=5_100_000)
+
+# Iterative hit removal (the paper's tracker practice, section "Current
+# Tracker and Tracking Algorithm"): a prompt pass on the 2D grid (beam-line
+# seed), then the displaced-jet pass on the hits it leaves.
+TWO_PASS = dict(name="prompt pass 2D 256x256, then displaced pass 3D 512x256x64",
+                prompt=dict(grid=GRID_2D, min_votes=8, cluster=dict(CLUSTER_2D, member_cap=512)),
+                displaced=dict(grid=GRID_3D, min_votes=7, cluster=CLUSTER_3D))

@@ -236,6 +236,27 @@ int assoc_cluster(const ht_plan* p, const float* r, const float* phi, const uint
                           (hipStream_t)stream);
 }
 
+int ht_compact_hits(const float* r, const float* phi, const uint8_t* layer, int32_t n_hits,
+                    const int32_t* hit_owner, float* out_r, float* out_phi, uint8_t* out_layer,
+                    int32_t* out_index, int32_t* n_out, void* stream) {
+  if (n_hits < 0 || !n_out) return HT_EINVAL;
+  if (n_hits > 0 && (!r || !phi || !layer || !hit_owner || !out_r || !out_phi || !out_layer ||
+                     !out_index))
+    return HT_EINVAL;
+  if (n_hits > 65535) return HT_EUNSUPPORTED;
+  return ht::launch_compact(r, phi, layer, hit_owner, n_hits, out_r, out_phi, out_layer,
+                            out_index, n_out, (hipStream_t)stream);
+}
+
+int ht_remap_track_hits(ht_track* tracks, int32_t track_cap, const int32_t* counts,
+                        const int32_t* index, int32_t n_index, void* stream) {
+  if (track_cap < 0 || n_index < 0 || !counts || (track_cap > 0 && !tracks) ||
+      (n_index > 0 && !index))
+    return HT_EINVAL;
+  if (track_cap == 0) return HT_OK;
+  return ht::launch_remap(tracks, track_cap, counts, index, n_index, (hipStream_t)stream);
+}
+
 int ht_asin_f32(const float* u, float* out, int64_t n, void* stream) {
   if (n < 0 || (n > 0 && (!u || !out))) return HT_EINVAL;
   if (n > ((int64_t)1 << 38)) return HT_EUNSUPPORTED;  // grid limit

@@ -85,6 +85,11 @@ int launch_assoc(const Plan& p, const float* r, const float* phi, const uint8_t*
 int launch_asin(const float* u, float* out, int64_t n, hipStream_t s);
 int launch_sqrt(const double* x, double* out, int64_t n, hipStream_t s);
 int launch_scan(const int32_t* cnt, int32_t* off, int n, int32_t* total, hipStream_t s);
+int launch_compact(const float* r, const float* phi, const uint8_t* layer, const int32_t* owner,
+                   int32_t n, float* out_r, float* out_phi, uint8_t* out_layer,
+                   int32_t* out_index, int32_t* n_out, hipStream_t s);
+int launch_remap(ht_track* tracks, int32_t track_cap, const int32_t* counts,
+                 const int32_t* index, int32_t n_index, hipStream_t s);
 // assoc_cluster's configuration checks (HT_OK, HT_EINVAL or HT_EUNSUPPORTED)
 int check_cluster(const Plan& p, const ht_cluster_cfg& c, int32_t n_hits, int32_t peak_cap,
                   int32_t track_cap);

@@ -332,10 +332,13 @@ def make_tracks_event(tracks, n_noise=0, seed=0, smear=SMEAR_CM, shuffle=True,
 
 
 def make_vertex_event(rho, theta, psis, qpts, n_noise=0, seed=0, smear=SMEAR_CM,
-                      radii=RADII, bfield=B_TESLA) -> Event:
-    """Event with tracks produced at one vertex (test helper)."""
+                      radii=RADII, bfield=B_TESLA, prompt=()) -> Event:
+    """Event with tracks produced at one vertex, after prompt tracks
+    [(phi0, qpt), ...] from the beam line (test helper)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     b = _Builder(rng, bfield=bfield, radii=radii, smear=smear)
+    for phi0, q in prompt:
+        b.add_perigee_track(float(phi0), float(q), 0.0)
     vid = b.add_vertex(rho, theta, 0, len(psis))
     vx, vy = rho * np.cos(theta), rho * np.sin(theta)
     for psi, q in zip(psis, qpts):

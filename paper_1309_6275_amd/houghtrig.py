@@ -116,6 +116,8 @@ def lib():
         L.hough_peaks.argtypes = [vp, vp, i32, vp, i32, vp, vp]
         L.assoc_cluster.argtypes = [vp, vp, vp, vp, i32, vp, vp, i32, vp, vp, vp]
         L.ht_asin_f32.argtypes = [vp, vp, i64, vp]
+        L.ht_compact_hits.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.ht_remap_track_hits.argtypes = [vp, i32, vp, vp, i32, vp]
         L.ht_sqrt_f64.argtypes = [vp, vp, i64, vp]
         L.ht_cnn_workspace_bytes.argtypes = [i32, i32]
         L.ht_cnn_workspace_bytes.restype = C.c_size_t
@@ -289,6 +291,36 @@ class ClusterBuffers:
         return dict(hit_owner=self.hit_owner[:n_hits].cpu().numpy(), tracks=tr, objects=ob,
                     members=self.members[:nm].cpu().numpy(), vacc=self.vacc.cpu().numpy(),
                     counts=counts)
+
+
+def compact_hits(r, phi, layer, hit_owner, out_r, out_phi, out_layer, out_index, n_out,
+                 stream=None):
+    """Keeps the hits with hit_owner < 0 in event order (ht_compact_hits);
+    out_*: [n_hits] device tensors, n_out: int32 [1] device."""
+    torch = _torch()
+    n = int(r.numel())
+    for t in (phi, layer, hit_owner, out_r, out_phi, out_layer, out_index):
+        if t.numel() < n:
+            raise ValueError("shape mismatch")
+    _check(lib().ht_compact_hits(_ptr(r, torch.float32, "r"), _ptr(phi, torch.float32, "phi"),
+                                 _ptr(layer, torch.uint8, "layer"),
+                                 n, _ptr(hit_owner, torch.int32, "hit_owner"),
+                                 _ptr(out_r, torch.float32, "out_r"),
+                                 _ptr(out_phi, torch.float32, "out_phi"),
+                                 _ptr(out_layer, torch.uint8, "out_layer"),
+                                 _ptr(out_index, torch.int32, "out_index"),
+                                 _ptr(n_out, torch.int32, "n_out"), _stream(stream)),
+           "ht_compact_hits")
+
+
+def remap_track_hits(bufs: "ClusterBuffers", index, stream=None):
+    """Maps the hit indices of bufs' tracks through index (ht_remap_track_hits)."""
+    torch = _torch()
+    _check(lib().ht_remap_track_hits(bufs.tracks.data_ptr(), bufs.track_cap,
+                                     _ptr(bufs.counts, torch.int32, "counts"),
+                                     _ptr(index, torch.int32, "index"), int(index.numel()),
+                                     _stream(stream)),
+           "ht_remap_track_hits")
 
 
 def assoc_cluster(plan: Plan, r, phi, layer, peaks, n_peaks, cfg: dict, bufs: ClusterBuffers,
@@ -511,4 +543,5 @@ EXPORTS = ("ht_plan_create", "ht_plan_destroy", "ht_strerror", "hough_vote", "ho
            "assoc_cluster", "ht_asin_f32", "ht_sqrt_f64", "ht_profile_begin", "ht_profile_read",
            "ht_profile_end", "ht_server_create", "ht_server_destroy", "ht_server_info",
            "ht_server_submit", "ht_server_poll", "ht_cnn_workspace_bytes", "ht_cnn_windows",
-           "ht_cnn_forward", "ht_cnn_train_step", "ht_cnn_keep")
+           "ht_cnn_forward", "ht_cnn_train_step", "ht_cnn_keep", "ht_compact_hits",
+           "ht_remap_track_hits")
