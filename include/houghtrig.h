@@ -162,6 +162,27 @@ const char* ht_strerror(int status);
 int hough_vote(const ht_plan* plan, const float* r, const float* phi, int32_t n_hits,
                int32_t* acc, unsigned long long* n_votes, void* stream);
 
+/* hough_vote_cell -- band (cell) variant of hough_vote (the paper's feature
+ * instances are cells of the parameter space, section "Hough Transform
+ * Algorithm"): a valid hit votes once for every phi0 bin its curve reaches
+ * while (kappa, d0) range over the column's cell, instead of the point at
+ * the column centre.  u is increasing in kappa and d0 over the cell (for
+ * r > |d0| and kappa^2 r^2 < (1 + kappa d0)^2 + 1), so the band lies between
+ * the coordinates of two corners, each from the float32 formula of
+ * hough_vote with that corner's tables (float64, rounded once):
+ *   u_lo at (KAP = -c_B qpt_edge[j+1], d0_edge[k]),
+ *   u_hi at (KAP = -c_B qpt_edge[j],   d0_edge[k+1]);
+ * no vote when u_lo > 1 or u_hi < -1, else u clipped to [-1, 1],
+ *   x_a = (phi - asin_f(u_hi) - PHI_LO) * INVW,
+ *   x_b = (phi - asin_f(u_lo) - PHI_LO) * INVW,
+ * and one vote in every bin from floor(min(x_a, x_b)) to floor(max(x_a,
+ * x_b)), periodic (a band of n_phi or more bins votes once in every bin).
+ * Arguments, layout, errors and n_votes (the total of band widths) as for
+ * hough_vote.  The peak finder and assoc_cluster take its accumulator
+ * unchanged. */
+int hough_vote_cell(const ht_plan* plan, const float* r, const float* phi, int32_t n_hits,
+                    int32_t* acc, unsigned long long* n_votes, void* stream);
+
 /* hough_peaks -- local maxima of the accumulator (paper, section "Hough
  * Transform Algorithm"; reused for the second transform).  Cell c is a peak
  * iff acc[c] >= min_votes and for each of its 26 neighbours c+o inside the

@@ -253,6 +253,76 @@ int oracle_hough_vote(const or_grid* g, const float* r, const float* phi, int32_
 }
 
 /* ------------------------------------------------------------------------ */
+/* Band (cell) vote, a variant of the vote above: instead of the point at
+ * the column centre, a hit votes for every phi0 bin that its curve reaches
+ * while (kappa, d0) range over the column's cell (the paper's instances are
+ * cells of the parameter space, section "Hough Transform Algorithm").
+ * Reading used: u is increasing in kappa and in d0 over the cell (true
+ * while r > |d0| and kappa^2 r^2 < (1 + kappa d0)^2 + 1), so u spans
+ * [u_lo, u_hi] with u_lo at (smallest kappa, lower d0 edge) and u_hi at
+ * (largest kappa, upper d0 edge); kappa = -0.299792458e-2 B q/pT, so the
+ * smallest kappa is at the upper q/pT edge.  Both come from the float32
+ * vote formula with the corner's tables (float64, rounded once).  No vote
+ * when u_lo > 1 or u_hi < -1; otherwise u is clipped to [-1, 1], the band's
+ * coordinates are x_a = (phi - asin_f(u_hi) - PHI_LO) INVW and x_b =
+ * (phi - asin_f(u_lo) - PHI_LO) INVW, and every bin from floor(min) to
+ * floor(max) gets one vote (periodic; a band of n_phi or more bins votes
+ * once in every bin). */
+static double qpt_edge(const or_grid* g, int j) {
+  return (double)g->qpt_lo + (double)j * ((double)g->qpt_hi - (double)g->qpt_lo) / (double)g->n_qpt;
+}
+static double d0_edge(const or_grid* g, int k) {
+  return (double)g->d0_lo + (double)k * ((double)g->d0_hi - (double)g->d0_lo) / (double)g->n_d0;
+}
+
+int oracle_hough_vote_cell(const or_grid* g, const float* r, const float* phi, int32_t n_hits,
+                           int32_t* acc, uint64_t* n_votes) {
+  if (!grid_ok(g) || n_hits < 0 || !acc) return -1;
+  const int np = g->n_phi, nq = g->n_qpt, nd = g->n_d0;
+  const int64_t ncol = (int64_t)nq * nd;
+  const double cb = C_LIGHT * (double)g->bfield;
+  const float phi_lo = (float)(-OR_PI);
+  const float invw = (float)((double)np / (2.0 * OR_PI));
+  uint64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
+  for (int64_t col = 0; col < ncol; ++col) {
+    int j = (int)(col % nq), k = (int)(col / nq);
+    /* corners: (smallest kappa, lower d0 edge) and (largest kappa, upper d0 edge) */
+    double klo = -cb * qpt_edge(g, j + 1), khi = -cb * qpt_edge(g, j);
+    double dlo = d0_edge(g, k), dhi = d0_edge(g, k + 1);
+    float kl = (float)klo, kh = (float)khi;
+    float ql = (float)(klo * dlo * dlo + 2.0 * dlo), tl = (float)(0.5 / (1.0 + klo * dlo));
+    float qh = (float)(khi * dhi * dhi + 2.0 * dhi), th = (float)(0.5 / (1.0 + khi * dhi));
+    int32_t* row = acc + col * np;
+    for (int i = 0; i < np; ++i) row[i] = 0;
+    for (int32_t h = 0; h < n_hits; ++h) {
+      if (!hit_valid(r[h], phi[h])) continue;
+      float r2 = r[h] * r[h];
+      float ir = 1.0f / r[h];
+      float ulo = ((kl * r2 + ql) * ir) * tl;
+      float uhi = ((kh * r2 + qh) * ir) * th;
+      if (ulo > 1.0f || uhi < -1.0f || ulo != ulo || uhi != uhi) continue;
+      if (ulo < -1.0f) ulo = -1.0f;
+      if (uhi > 1.0f) uhi = 1.0f;
+      float xa = ((phi[h] - oracle_asin_f(uhi)) - phi_lo) * invw;
+      float xb = ((phi[h] - oracle_asin_f(ulo)) - phi_lo) * invw;
+      float lo = xa < xb ? xa : xb, hi = xa < xb ? xb : xa;
+      int ia = (int)floorf(lo), ib = (int)floorf(hi);
+      int m = ib - ia + 1;
+      if (m >= np) {
+        for (int i = 0; i < np; ++i) row[i] += 1;
+        total += (uint64_t)np;
+      } else {
+        for (int q = 0; q < m; ++q) row[(((ia + q) % np) + np) % np] += 1;
+        total += (uint64_t)m;
+      }
+    }
+  }
+  if (n_votes) *n_votes = total;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Peaks: local maxima of the accumulator (section "Hough Transform
  * Algorithm"; the same finder serves the second transform, section "Jet and
  * Black Hole Detection").  Reading used: cell c is a peak iff acc[c] >= T and,

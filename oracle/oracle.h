@@ -97,6 +97,8 @@ int oracle_phi0_coord(const or_grid* g, const float* r, const float* phi, int32_
 
 int oracle_hough_vote(const or_grid* g, const float* r, const float* phi, int32_t n_hits,
                       int32_t* acc, uint64_t* n_votes);
+int oracle_hough_vote_cell(const or_grid* g, const float* r, const float* phi, int32_t n_hits,
+                           int32_t* acc, uint64_t* n_votes);
 
 int oracle_hough_peaks(const or_grid* g, const int32_t* acc, int32_t min_votes,
                        or_peak* out, int32_t capacity, int32_t* n_found);

@@ -85,6 +85,7 @@ def lib():
         _lib.oracle_atan2_array.restype = None
         _lib.oracle_phi0_coord.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
         _lib.oracle_hough_vote.argtypes = [vp, vp, vp, i32, vp, vp]
+        _lib.oracle_hough_vote_cell.argtypes = [vp, vp, vp, i32, vp, vp]
         _lib.oracle_hough_peaks.argtypes = [vp, vp, i32, vp, i32, vp]
         _lib.oracle_assoc_cluster.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, i32, vp,
                                               i32, vp, i32, vp, vp]
@@ -92,7 +93,7 @@ def lib():
         _lib.oracle_set_threads.restype = None
         _lib.oracle_refine_one.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, vp]
         for f in ("oracle_refine_one", "oracle_tables", "oracle_phi0_coord", "oracle_hough_vote",
-                  "oracle_hough_peaks", "oracle_assoc_cluster"):
+                  "oracle_hough_vote_cell", "oracle_hough_peaks", "oracle_assoc_cluster"):
             getattr(_lib, f).restype = C.c_int
     return _lib
 
@@ -159,6 +160,19 @@ def hough_vote(grid: dict, r, phi):
     g = _grid(grid)
     _check(lib().oracle_hough_vote(C.byref(g), _p(r), _p(phi), r.size, _p(acc), C.byref(nv)),
            "hough_vote")
+    return acc, int(nv.value)
+
+
+def hough_vote_cell(grid: dict, r, phi):
+    """Band vote: every phi0 bin the hit's curve reaches over each column's
+    (q/pT, d0) cell."""
+    r = np.ascontiguousarray(r, np.float32)
+    phi = np.ascontiguousarray(phi, np.float32)
+    acc = np.empty((grid["n_d0"], grid["n_qpt"], grid["n_phi"]), np.int32)
+    nv = C.c_uint64(0)
+    g = _grid(grid)
+    _check(lib().oracle_hough_vote_cell(C.byref(g), _p(r), _p(phi), r.size, _p(acc),
+                                        C.byref(nv)), "hough_vote_cell")
     return acc, int(nv.value)
 
 

@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "ht_internal.h"
 
@@ -37,6 +38,13 @@ double d0_centre(const ht_grid& g, int k) {
   return (double)g.d0_lo +
          ((double)k + 0.5) * ((double)g.d0_hi - (double)g.d0_lo) / (double)g.n_d0;
 }
+// cell edges (band vote): edge j of q/pT and edge k of d0, j, k = 0 .. n
+double qpt_edge(const ht_grid& g, int j) {
+  return (double)g.qpt_lo + (double)j * ((double)g.qpt_hi - (double)g.qpt_lo) / (double)g.n_qpt;
+}
+double d0_edge(const ht_grid& g, int k) {
+  return (double)g.d0_lo + (double)k * ((double)g.d0_hi - (double)g.d0_lo) / (double)g.n_d0;
+}
 
 template <typename T>
 int dalloc(T** p, size_t n) {
@@ -55,7 +63,8 @@ void free_plan(Plan* p) {
                   p->d_hq,        p->d_hitB,      p->d_mcount,    p->d_mem,      p->d_cstat,
                   p->d_cgeo,      p->d_chit,      p->d_cnl,      p->d_owner_key, p->d_ctile_cnt,
                   p->d_ctile_off, p->d_trk_peak,  p->d_arc0,     p->d_arcn,      p->d_vacc,
-                  p->d_obj_cnt,   p->d_obj_off,   p->d_scalars};
+                  p->d_obj_cnt,   p->d_obj_off,   p->d_scalars,  p->d_ckl,       p->d_ckh,
+                  p->d_cql,       p->d_ctl,       p->d_cqh,      p->d_cth};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -173,6 +182,40 @@ int ht_plan_create(const ht_grid* grid, const ht_limits* lim, ht_plan** out) {
   if (rc == HT_OK) rc = dalloc(&p->d_obj_cnt, (size_t)lim->max_vertex_cells);
   if (rc == HT_OK) rc = dalloc(&p->d_obj_off, (size_t)lim->max_vertex_cells);
   if (rc == HT_OK) rc = dalloc(&p->d_scalars, 16);
+  // band-vote corner tables: (smallest kappa, lower d0 edge) and (largest
+  // kappa, upper d0 edge) of every column
+  if (rc == HT_OK) rc = dalloc(&p->d_ckl, (size_t)g.n_qpt);
+  if (rc == HT_OK) rc = dalloc(&p->d_ckh, (size_t)g.n_qpt);
+  if (rc == HT_OK) rc = dalloc(&p->d_cql, ncol);
+  if (rc == HT_OK) rc = dalloc(&p->d_ctl, ncol);
+  if (rc == HT_OK) rc = dalloc(&p->d_cqh, ncol);
+  if (rc == HT_OK) rc = dalloc(&p->d_cth, ncol);
+  if (rc == HT_OK) {
+    std::vector<float> ckl(g.n_qpt), ckh(g.n_qpt), cql(ncol), ctl(ncol), cqh(ncol), cth(ncol);
+    const double cb = ht::kCLight * (double)g.bfield;
+    for (int j = 0; j < g.n_qpt; ++j) {
+      ckl[j] = (float)(-cb * qpt_edge(g, j + 1));
+      ckh[j] = (float)(-cb * qpt_edge(g, j));
+    }
+    for (int k = 0; k < g.n_d0; ++k) {
+      const double dlo = d0_edge(g, k), dhi = d0_edge(g, k + 1);
+      for (int j = 0; j < g.n_qpt; ++j) {
+        const double klo = -cb * qpt_edge(g, j + 1), khi = -cb * qpt_edge(g, j);
+        const size_t c = (size_t)k * g.n_qpt + j;
+        cql[c] = (float)(klo * dlo * dlo + 2.0 * dlo);
+        ctl[c] = (float)(0.5 / (1.0 + klo * dlo));
+        cqh[c] = (float)(khi * dhi * dhi + 2.0 * dhi);
+        cth[c] = (float)(0.5 / (1.0 + khi * dhi));
+      }
+    }
+    if (hipMemcpy(p->d_ckl, ckl.data(), 4 * (size_t)g.n_qpt, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_ckh, ckh.data(), 4 * (size_t)g.n_qpt, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_cql, cql.data(), 4 * ncol, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_ctl, ctl.data(), 4 * ncol, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_cqh, cqh.data(), 4 * ncol, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_cth, cth.data(), 4 * ncol, hipMemcpyHostToDevice) != hipSuccess)
+      rc = HT_EDEVICE;
+  }
   if (rc == HT_OK &&
       (hipMemcpy(p->d_kap, hk, sizeof(float) * g.n_qpt, hipMemcpyHostToDevice) != hipSuccess ||
        hipMemcpy(p->d_q, hq, sizeof(float) * ncol, hipMemcpyHostToDevice) != hipSuccess ||
@@ -181,6 +224,7 @@ int ht_plan_create(const ht_grid* grid, const ht_limits* lim, ht_plan** out) {
        hipMemcpy(p->d_d0c, hdc, sizeof(double) * g.n_d0, hipMemcpyHostToDevice) != hipSuccess))
     rc = HT_EDEVICE;
   if (rc == HT_OK) rc = ht::vote_init(g.n_phi);
+  if (rc == HT_OK) rc = ht::cell_vote_init(g.n_phi);
   if (rc == HT_OK) rc = ht::peaks_init(g.n_phi);
   delete[] hk;
   delete[] hq;
@@ -211,6 +255,13 @@ int hough_vote(const ht_plan* p, const float* r, const float* phi, int32_t n_hit
   if (!p || !acc || n_hits < 0 || (n_hits > 0 && (!r || !phi))) return HT_EINVAL;
   if (n_hits > 65535 || n_hits > p->lim.max_hits) return HT_EUNSUPPORTED;
   return ht::launch_vote(*p, r, phi, n_hits, acc, n_votes, (hipStream_t)stream);
+}
+
+int hough_vote_cell(const ht_plan* p, const float* r, const float* phi, int32_t n_hits,
+                    int32_t* acc, unsigned long long* n_votes, void* stream) {
+  if (!p || !acc || n_hits < 0 || (n_hits > 0 && (!r || !phi))) return HT_EINVAL;
+  if (n_hits > 65535 || n_hits > p->lim.max_hits) return HT_EUNSUPPORTED;
+  return ht::launch_cell_vote(*p, r, phi, n_hits, acc, n_votes, (hipStream_t)stream);
 }
 
 int hough_peaks(const ht_plan* p, const int32_t* acc, int32_t min_votes, ht_peak* out,

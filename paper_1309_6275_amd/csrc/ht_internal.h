@@ -24,6 +24,14 @@ struct Plan {
   double* d_d0c;   // [n_d0] d0 at the plane centres (float64)
   float* d_q;    // [n_d0][n_qpt]
   float* d_t;    // [n_d0][n_qpt]
+  // band-vote corners: kappa at the smallest / largest edge [n_qpt], and Q,
+  // T at (smallest kappa, lower d0 edge) and (largest kappa, upper d0 edge)
+  float* d_ckl;
+  float* d_ckh;
+  float* d_cql;  // [n_d0][n_qpt]
+  float* d_ctl;
+  float* d_cqh;
+  float* d_cth;
   // peak finder scratch
   uint32_t* d_bits;      // peak ballots, one bit per cell (tiles rounded up to 1024 cells)
   int32_t* d_tile_cnt;   // [n_tiles]
@@ -76,6 +84,9 @@ namespace ht {
 // which then only bounds it (graph replays of events of any size)
 int launch_vote(const Plan& p, const float* r, const float* phi, int32_t n_hits, int32_t* acc,
                 unsigned long long* n_votes, hipStream_t s, const int32_t* n_hits_dev = nullptr);
+int launch_cell_vote(const Plan& p, const float* r, const float* phi, int32_t n_hits,
+                     int32_t* acc, unsigned long long* n_votes, hipStream_t s);
+int cell_vote_init(int n_phi);
 int launch_peaks(const Plan& p, const int32_t* acc, int32_t min_votes, ht_peak* out,
                  int32_t capacity, int32_t* n_found, hipStream_t s);
 int launch_assoc(const Plan& p, const float* r, const float* phi, const uint8_t* layer,

@@ -113,6 +113,7 @@ def lib():
         L.ht_plan_destroy.argtypes = [vp]
         L.ht_plan_destroy.restype = None
         L.hough_vote.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+        L.hough_vote_cell.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.hough_peaks.argtypes = [vp, vp, i32, vp, i32, vp, vp]
         L.assoc_cluster.argtypes = [vp, vp, vp, vp, i32, vp, vp, i32, vp, vp, vp]
         L.ht_asin_f32.argtypes = [vp, vp, i64, vp]
@@ -138,7 +139,7 @@ def lib():
                   "ht_sqrt_f64", "ht_profile_begin", "ht_profile_read", "ht_profile_end",
                   "ht_server_create", "ht_server_destroy", "ht_server_info", "ht_server_submit",
                   "ht_server_poll", "ht_cnn_windows", "ht_cnn_forward", "ht_cnn_train_step",
-                  "ht_cnn_keep"):
+                  "ht_cnn_keep", "hough_vote_cell", "ht_compact_hits", "ht_remap_track_hits"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -245,6 +246,20 @@ def hough_vote(plan: Plan, r, phi, acc, n_votes=None, stream=None):
                             _ptr(acc, torch.int32, "acc"),
                             _ptr(n_votes, torch.int64, "n_votes"), _stream(stream)),
            "hough_vote")
+
+
+def hough_vote_cell(plan: Plan, r, phi, acc, n_votes=None, stream=None):
+    """Band variant of hough_vote: each hit votes for every phi0 bin its
+    curve reaches over each column's (q/pT, d0) cell."""
+    torch = _torch()
+    n = int(r.numel())
+    if phi.numel() != n or tuple(acc.shape) != plan.acc_shape:
+        raise ValueError("shape mismatch")
+    _check(lib().hough_vote_cell(plan.handle, _ptr(r, torch.float32, "r"),
+                                 _ptr(phi, torch.float32, "phi"), n,
+                                 _ptr(acc, torch.int32, "acc"),
+                                 _ptr(n_votes, torch.int64, "n_votes"), _stream(stream)),
+           "hough_vote_cell")
 
 
 def hough_peaks(plan: Plan, acc, min_votes: int, out, n_found, stream=None):
@@ -539,7 +554,8 @@ class Server:
             pass
 
 
-EXPORTS = ("ht_plan_create", "ht_plan_destroy", "ht_strerror", "hough_vote", "hough_peaks",
+EXPORTS = ("ht_plan_create", "ht_plan_destroy", "ht_strerror", "hough_vote", "hough_vote_cell",
+           "hough_peaks",
            "assoc_cluster", "ht_asin_f32", "ht_sqrt_f64", "ht_profile_begin", "ht_profile_read",
            "ht_profile_end", "ht_server_create", "ht_server_destroy", "ht_server_info",
            "ht_server_submit", "ht_server_poll", "ht_cnn_workspace_bytes", "ht_cnn_windows",
