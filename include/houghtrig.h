@@ -237,12 +237,28 @@ int assoc_cluster(const ht_plan* plan, const float* r, const float* phi, const u
                   int32_t peak_cap, const ht_cluster_cfg* cfg, const ht_cluster_out* out,
                   void* stream);
 
+/* hough_vote_n, assoc_cluster_n -- hough_vote and assoc_cluster with the
+ * event's hit count read on the device from *n_hits_dev (clamped to
+ * [0, n_hits_max]), for hit counts that are produced on the device (the
+ * kept hits of ht_compact_hits) so that no host synchronisation sits
+ * between two passes.  n_hits_max bounds the buffers and takes the limits
+ * n_hits has in the plain calls; hit_owner entries beyond the device count
+ * are not written.  n_hits_dev must not be NULL (HT_EINVAL). */
+int hough_vote_n(const ht_plan* plan, const float* r, const float* phi, int32_t n_hits_max,
+                 const int32_t* n_hits_dev, int32_t* acc, unsigned long long* n_votes,
+                 void* stream);
+int assoc_cluster_n(const ht_plan* plan, const float* r, const float* phi, const uint8_t* layer,
+                    int32_t n_hits_max, const int32_t* n_hits_dev, const ht_peak* peaks,
+                    const int32_t* n_peaks, int32_t peak_cap, const ht_cluster_cfg* cfg,
+                    const ht_cluster_out* out, void* stream);
+
 /* Iterative hit removal (paper, section "Current Tracker and Tracking
  * Algorithm": earlier passes find the easier, prompt tracks, whose hits are
  * then removed so that later passes search for displaced tracks among far
  * fewer combinations).  Typical use: a prompt pass (hough_vote,
  * hough_peaks, assoc_cluster on a one-column d0 grid), ht_compact_hits on
- * its hit_owner, a displaced pass on the kept hits, then
+ * its hit_owner, a displaced pass on the kept hits (hough_vote_n,
+ * hough_peaks, assoc_cluster_n with n_out as the hit count), then
  * ht_remap_track_hits so that that pass's tracks name hits of the event.
  *
  * ht_compact_hits -- keeps the hits with hit_owner < 0, in event order.

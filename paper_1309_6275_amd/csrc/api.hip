@@ -257,6 +257,15 @@ int hough_vote(const ht_plan* p, const float* r, const float* phi, int32_t n_hit
   return ht::launch_vote(*p, r, phi, n_hits, acc, n_votes, (hipStream_t)stream);
 }
 
+int hough_vote_n(const ht_plan* p, const float* r, const float* phi, int32_t n_hits_max,
+                 const int32_t* n_hits_dev, int32_t* acc, unsigned long long* n_votes,
+                 void* stream) {
+  if (!n_hits_dev) return HT_EINVAL;
+  if (!p || !acc || n_hits_max < 0 || (n_hits_max > 0 && (!r || !phi))) return HT_EINVAL;
+  if (n_hits_max > 65535 || n_hits_max > p->lim.max_hits) return HT_EUNSUPPORTED;
+  return ht::launch_vote(*p, r, phi, n_hits_max, acc, n_votes, (hipStream_t)stream, n_hits_dev);
+}
+
 int hough_vote_cell(const ht_plan* p, const float* r, const float* phi, int32_t n_hits,
                     int32_t* acc, unsigned long long* n_votes, void* stream) {
   if (!p || !acc || n_hits < 0 || (n_hits > 0 && (!r || !phi))) return HT_EINVAL;
@@ -306,6 +315,25 @@ int ht_remap_track_hits(ht_track* tracks, int32_t track_cap, const int32_t* coun
     return HT_EINVAL;
   if (track_cap == 0) return HT_OK;
   return ht::launch_remap(tracks, track_cap, counts, index, n_index, (hipStream_t)stream);
+}
+
+int assoc_cluster_n(const ht_plan* p, const float* r, const float* phi, const uint8_t* layer,
+                    int32_t n_hits_max, const int32_t* n_hits_dev, const ht_peak* peaks,
+                    const int32_t* n_peaks, int32_t peak_cap, const ht_cluster_cfg* cfg,
+                    const ht_cluster_out* out, void* stream) {
+  if (!n_hits_dev) return HT_EINVAL;
+  if (!p || !cfg || !out || !n_peaks || n_hits_max < 0 || peak_cap < 0) return HT_EINVAL;
+  if (n_hits_max > 0 && (!r || !phi || !layer || !out->hit_owner)) return HT_EINVAL;
+  if (peak_cap > 0 && !peaks) return HT_EINVAL;
+  if (!out->counts || out->track_cap < 0 || out->object_cap < 0 || out->member_cap < 0)
+    return HT_EINVAL;
+  if ((out->track_cap > 0 && !out->tracks) || (out->object_cap > 0 && !out->objects) ||
+      (out->member_cap > 0 && !out->members))
+    return HT_EINVAL;
+  const int rc = ht::check_cluster(*p, *cfg, n_hits_max, peak_cap, out->track_cap);
+  if (rc != HT_OK) return rc;
+  return ht::launch_assoc(*p, r, phi, layer, n_hits_max, peaks, n_peaks, peak_cap, *cfg, *out,
+                          (hipStream_t)stream, n_hits_dev);
 }
 
 int ht_asin_f32(const float* u, float* out, int64_t n, void* stream) {

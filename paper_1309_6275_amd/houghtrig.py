@@ -114,6 +114,8 @@ def lib():
         L.ht_plan_destroy.restype = None
         L.hough_vote.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.hough_vote_cell.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+        L.hough_vote_n.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+        L.assoc_cluster_n.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, i32, vp, vp, vp]
         L.hough_peaks.argtypes = [vp, vp, i32, vp, i32, vp, vp]
         L.assoc_cluster.argtypes = [vp, vp, vp, vp, i32, vp, vp, i32, vp, vp, vp]
         L.ht_asin_f32.argtypes = [vp, vp, i64, vp]
@@ -139,7 +141,8 @@ def lib():
                   "ht_sqrt_f64", "ht_profile_begin", "ht_profile_read", "ht_profile_end",
                   "ht_server_create", "ht_server_destroy", "ht_server_info", "ht_server_submit",
                   "ht_server_poll", "ht_cnn_windows", "ht_cnn_forward", "ht_cnn_train_step",
-                  "ht_cnn_keep", "hough_vote_cell", "ht_compact_hits", "ht_remap_track_hits"):
+                  "ht_cnn_keep", "hough_vote_cell", "ht_compact_hits", "ht_remap_track_hits",
+                  "hough_vote_n", "assoc_cluster_n"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -356,6 +359,40 @@ def assoc_cluster(plan: Plan, r, phi, layer, peaks, n_peaks, cfg: dict, bufs: Cl
            "assoc_cluster")
 
 
+def hough_vote_n(plan: Plan, r, phi, n_hits_dev, acc, n_votes=None, stream=None):
+    """hough_vote with the hit count read on the device from n_hits_dev
+    (int32 [1]); r and phi hold at least that many hits."""
+    torch = _torch()
+    n = int(r.numel())
+    if phi.numel() != n or tuple(acc.shape) != plan.acc_shape:
+        raise ValueError("shape mismatch")
+    _check(lib().hough_vote_n(plan.handle, _ptr(r, torch.float32, "r"),
+                              _ptr(phi, torch.float32, "phi"), n,
+                              _ptr(n_hits_dev, torch.int32, "n_hits_dev"),
+                              _ptr(acc, torch.int32, "acc"),
+                              _ptr(n_votes, torch.int64, "n_votes"), _stream(stream)),
+           "hough_vote_n")
+
+
+def assoc_cluster_n(plan: Plan, r, phi, layer, n_hits_dev, peaks, n_peaks, cfg: dict,
+                    bufs: ClusterBuffers, with_vacc=True, stream=None):
+    """assoc_cluster with the hit count read on the device from n_hits_dev."""
+    torch = _torch()
+    n = int(r.numel())
+    if phi.numel() != n or layer.numel() != n:
+        raise ValueError("shape mismatch")
+    c = cluster_struct(cfg)
+    o = bufs.struct(with_vacc)
+    _check(lib().assoc_cluster_n(plan.handle, _ptr(r, torch.float32, "r"),
+                                 _ptr(phi, torch.float32, "phi"),
+                                 _ptr(layer, torch.uint8, "layer"), n,
+                                 _ptr(n_hits_dev, torch.int32, "n_hits_dev"),
+                                 _ptr(peaks, torch.int32, "peaks"),
+                                 _ptr(n_peaks, torch.int32, "n_peaks"), int(peaks.shape[0]),
+                                 C.byref(c), C.byref(o), _stream(stream)),
+           "assoc_cluster_n")
+
+
 def asin_f32(u, out, stream=None):
     torch = _torch()
     _check(lib().ht_asin_f32(_ptr(u, torch.float32, "u"), _ptr(out, torch.float32, "out"),
@@ -560,4 +597,4 @@ EXPORTS = ("ht_plan_create", "ht_plan_destroy", "ht_strerror", "hough_vote", "ho
            "ht_profile_end", "ht_server_create", "ht_server_destroy", "ht_server_info",
            "ht_server_submit", "ht_server_poll", "ht_cnn_workspace_bytes", "ht_cnn_windows",
            "ht_cnn_forward", "ht_cnn_train_step", "ht_cnn_keep", "ht_compact_hits",
-           "ht_remap_track_hits")
+           "ht_remap_track_hits", "hough_vote_n", "assoc_cluster_n")

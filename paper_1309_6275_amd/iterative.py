@@ -6,11 +6,13 @@ the rest for displaced tracks among far fewer combinations).
 Pass 1 runs hough_vote, hough_peaks and assoc_cluster on the prompt grid
 (one d0 column, beam-line seeds); ht_compact_hits keeps the hits it left;
 pass 2 runs the displaced-jet path (3D grid, vertex transform) on those;
-ht_remap_track_hits makes pass-2 tracks name event hits.  The only host
-synchronisation is the read of the kept-hit count between the passes.
+ht_remap_track_hits makes pass-2 tracks name event hits.  The displaced
+pass takes the kept-hit count from device memory (hough_vote_n,
+assoc_cluster_n), so the whole chain is asynchronous on one stream.
 
     tp = TwoPass(max_hits=65535)
-    first, keep, second = tp.run(r, phi, layer)   # device tensors in
+    tp.run(r, phi, layer)                      # device tensors in
+    first, keep, second = tp.to_host(n_hits)   # synchronises
 """
 from __future__ import annotations
 
@@ -44,11 +46,10 @@ class TwoPass:
         self.layer2 = torch.empty(max_hits, dtype=torch.uint8, device=dev)
         self.keep = torch.empty(max_hits, dtype=torch.int32, device=dev)
         self.n_keep = torch.zeros(1, dtype=torch.int32, device=dev)
-        self.n_keep_host = torch.zeros(1, dtype=torch.int32, pin_memory=True)
 
     def run(self, r, phi, layer, with_vacc=True):
-        """Both passes on one event; returns the kept-hit count (the outputs
-        stay in bufs_p, keep and bufs_d)."""
+        """Both passes on one event, asynchronous on the current stream (the
+        outputs stay in bufs_p, keep, n_keep and bufs_d)."""
         P, D = self.spec["prompt"], self.spec["displaced"]
         n = int(r.numel())
         H.hough_vote(self.plan_p, r, phi, self.acc_p)
@@ -57,18 +58,16 @@ class TwoPass:
                         self.bufs_p, with_vacc=False)
         H.compact_hits(r, phi, layer, self.bufs_p.hit_owner[:n], self.r2[:n], self.phi2[:n],
                        self.layer2[:n], self.keep[:n], self.n_keep)
-        self.n_keep_host.copy_(self.n_keep, non_blocking=True)
-        self.torch.cuda.current_stream().synchronize()
-        m = int(self.n_keep_host[0])
-        H.hough_vote(self.plan_d, self.r2[:m], self.phi2[:m], self.acc_d)
+        # the displaced pass reads the kept-hit count on the device
+        H.hough_vote_n(self.plan_d, self.r2[:n], self.phi2[:n], self.n_keep, self.acc_d)
         H.hough_peaks(self.plan_d, self.acc_d, D["min_votes"], self.pk_d, self.nf[1:2])
-        H.assoc_cluster(self.plan_d, self.r2[:m], self.phi2[:m], self.layer2[:m], self.pk_d,
-                        self.nf[1:2], D["cluster"], self.bufs_d, with_vacc=with_vacc)
-        H.remap_track_hits(self.bufs_d, self.keep[:m])
-        return m
+        H.assoc_cluster_n(self.plan_d, self.r2[:n], self.phi2[:n], self.layer2[:n], self.n_keep,
+                          self.pk_d, self.nf[1:2], D["cluster"], self.bufs_d,
+                          with_vacc=with_vacc)
+        H.remap_track_hits(self.bufs_d, self.keep[:n])
 
     def to_host(self, n_hits):
-        m = int(self.n_keep_host[0])
+        m = int(self.n_keep.item())
         return (self.bufs_p.to_host(n_hits), self.keep[:m].cpu().numpy(),
                 self.bufs_d.to_host(m))
 

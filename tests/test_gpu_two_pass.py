@@ -50,8 +50,7 @@ def test_two_pass_parity(torch, tp, oracle, label):
     r = torch.from_numpy(ev.r).cuda()
     phi = torch.from_numpy(ev.phi).cuda()
     layer = torch.from_numpy(ev.layer).cuda()
-    m = tp.run(r, phi, layer)
-    torch.cuda.synchronize()
+    tp.run(r, phi, layer)
     first, keep, second = tp.to_host(ev.n_hits)
     P, D = CF.TWO_PASS["prompt"], CF.TWO_PASS["displaced"]
     w1, wkeep, w2 = oracle.two_pass(P["grid"], P["min_votes"], P["cluster"], D["grid"],
@@ -64,7 +63,7 @@ def test_two_pass_parity(torch, tp, oracle, label):
     w1t = w1["tracks"]
     for f in ("lin", "n_inliers", "n_owned", "seed_ss", "hits", "status"):
         assert np.array_equal(first["tracks"][f], w1t[f]), (label, f)
-    assert m == wkeep.size and np.array_equal(keep, wkeep), label
+    assert keep.size == wkeep.size and np.array_equal(keep, wkeep), label
     compare(second, w2, f"{label} displaced pass")
     assert second["tracks"].size > 0
 
@@ -100,3 +99,41 @@ def test_compact_hits_edge_cases(torch):
         # nothing beyond the kept hits is written
         if k < n:
             assert (outs[3][k:n].cpu().numpy() == -7).all()
+
+
+def test_device_count_calls_match_host_count(torch, oracle):
+    """hough_vote_n and assoc_cluster_n over buffers of n hits with a device
+    count k < n equal hough_vote and assoc_cluster on the first k hits."""
+    from paper_1309_6275_amd import houghtrig as H
+    W = CF.WORKLOADS[2]
+    g, cl = W["grid"], W["cluster"]
+    ev = G.make_event(2, W["seed0"] + 9)
+    k = ev.n_hits - 1000
+    print(f"device count {k} of {ev.n_hits}", flush=True)
+    plan = H.Plan(g, max_peaks=1 << 20, max_tracks=1 << 13)
+    r = torch.from_numpy(ev.r).cuda()
+    phi = torch.from_numpy(ev.phi).cuda()
+    layer = torch.from_numpy(ev.layer).cuda()
+    nk = torch.tensor([k], dtype=torch.int32, device="cuda")
+    outs = []
+    for dev in (True, False):
+        acc = torch.full(plan.acc_shape, -1, dtype=torch.int32, device="cuda")
+        nv = torch.zeros(1, dtype=torch.int64, device="cuda")
+        peaks = torch.full((1 << 20, 2), -1, dtype=torch.int32, device="cuda")
+        nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+        bufs = H.ClusterBuffers(ev.n_hits, 4096, 512, 1 << 15, cl["n_rho"], cl["n_theta"])
+        if dev:
+            H.hough_vote_n(plan, r, phi, nk, acc, nv)
+            H.hough_peaks(plan, acc, W["min_votes"], peaks, nf)
+            H.assoc_cluster_n(plan, r, phi, layer, nk, peaks, nf, cl, bufs)
+        else:
+            H.hough_vote(plan, r[:k], phi[:k], acc, nv)
+            H.hough_peaks(plan, acc, W["min_votes"], peaks, nf)
+            H.assoc_cluster(plan, r[:k], phi[:k], layer[:k], peaks, nf, cl, bufs)
+        torch.cuda.synchronize()
+        outs.append((acc.cpu().numpy(), int(nv.item()), bufs.to_host(k)))
+    (a1, v1, o1), (a2, v2, o2) = outs
+    assert v1 == v2 and np.array_equal(a1, a2)
+    compare(o1, o2, "device count")
+    assert np.array_equal(o1["tracks"]["phi0"], o2["tracks"]["phi0"])
+    plan.close()
