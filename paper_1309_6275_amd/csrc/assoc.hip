@@ -42,9 +42,16 @@ constexpr int kSweepThreads = kSweepWaves * kWave;
 constexpr int kMaxMembers = 1024; // largest member_cap (LDS slots per wave in refine)
 constexpr int kGridCap = 8192;    // grid-stride launches use at most this many blocks
 
-// S_PAIRS and S_TESTS are 64-bit counters over slots 6-7 and 8-9 (8-byte aligned)
-enum { S_NP = 0, S_NCAND = 1, S_NOVER = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5, S_PAIRS = 6,
-       S_TESTS = 8 };
+// S_PAIRS is a 64-bit counter over slots 6-7 (8-byte aligned)
+enum { S_NP = 0, S_NOVER = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5, S_PAIRS = 6 };
+// The seed search's per-wave totals (refined candidates, road tests) go to
+// kSpread counters in separate 128-byte lines, chosen by wave: tens of
+// thousands of waves adding into one address serialise in one L2 channel
+// (about a fifth of the kernel's time when measured); counts_kernel sums
+// the slots.
+constexpr int kSpread = 64;
+constexpr int kSpreadStride = 16;  // 64-bit words: one 128-byte line per slot
+enum { SP_TESTS = 0, SP_NCAND = kSpread };
 
 __device__ __forceinline__ float bcastf(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -262,6 +269,7 @@ struct AssocArgs {
   int32_t* vacc;
   int32_t* obj_cnt;
   int32_t* sc;  // device scalars
+  unsigned long long* spread;  // [2 * kSpread * kSpreadStride] spread counters
   // outputs
   ht_cluster_out out;
 };
@@ -276,6 +284,7 @@ __global__ void init_kernel(AssocArgs A, int words) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   if (tid < 16) A.sc[tid] = 0;
+  for (int64_t w = tid; w < 2 * kSpread * kSpreadStride; w += stride) A.spread[w] = 0ull;
   if (tid == 0) {
     int np = *A.n_peaks;
     np = np < 0 ? 0 : (np > A.peak_cap ? A.peak_cap : np);
@@ -745,7 +754,7 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
   const ht_cluster_cfg& cfg = A.cfg;
   const int cap = cfg.member_cap;
   const double road = (double)cfg.road_sigmas * (double)cfg.sigma_rphi;
-  unsigned long long tests = 0;
+  unsigned long long tests = 0, ncand = 0;
   for (int p = blockIdx.x * W + wave; p < np; p += gridDim.x * W) {
     const int lin = A.peaks[p].lin;
     const int n = A.mcount[p];
@@ -973,8 +982,8 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
       A.cnl[p] = nS;
       double* g = A.cgeo + (size_t)p * 5;
       g[0] = ss; g[1] = cA; g[2] = cB; g[3] = cC; g[4] = cD;
-      atomicAdd(&A.sc[S_NCAND], 1);
     }
+    ++ncand;
     wave_sync();
     if (lane < HT_MAX_LAYERS) {
       const int hh = M.u.hit[win][lane];
@@ -982,7 +991,11 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
     }
     wave_sync();
   }
-  if (lane == 0 && tests) atomicAdd(reinterpret_cast<unsigned long long*>(A.sc + S_TESTS), tests);
+  if (lane == 0) {
+    const int slot = (blockIdx.x * W + wave) & (kSpread - 1);
+    if (tests) atomicAdd(&A.spread[(size_t)(SP_TESTS + slot) * kSpreadStride], tests);
+    if (ncand) atomicAdd(&A.spread[(size_t)(SP_NCAND + slot) * kSpreadStride], ncand);
+  }
 }
 
 // ---- ownership -----------------------------------------------------------------
@@ -1488,14 +1501,18 @@ __global__ __launch_bounds__(256) void vmembers_kernel(AssocArgs A, const int32_
 
 __global__ void counts_kernel(AssocArgs A) {
   int32_t* c = A.out.counts;
-  c[0] = A.sc[S_NCAND];
+  unsigned long long ncand = 0, tests = 0;
+  for (int i = 0; i < kSpread; ++i) {
+    ncand += A.spread[(size_t)(SP_NCAND + i) * kSpreadStride];
+    tests += A.spread[(size_t)(SP_TESTS + i) * kSpreadStride];
+  }
+  c[0] = (int32_t)ncand;
   c[1] = A.sc[S_NTRK];
   c[2] = A.sc[S_NOBJ];
   c[3] = A.sc[S_NMEM];
   c[4] = A.sc[S_NOVER];
   const unsigned long long pairs = *reinterpret_cast<const unsigned long long*>(A.sc + S_PAIRS);
   c[5] = pairs > 0x7fffffffull ? 0x7fffffff : (int32_t)pairs;
-  const unsigned long long tests = *reinterpret_cast<const unsigned long long*>(A.sc + S_TESTS);
   c[6] = tests > 0x7fffffffull ? 0x7fffffff : (int32_t)tests;
   c[7] = 0;
 }
@@ -1574,6 +1591,7 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   A.vacc = out.vacc ? out.vacc : P.d_vacc;
   A.obj_cnt = P.d_obj_cnt;
   A.sc = P.d_scalars;
+  A.spread = P.d_spread;
   A.out = out;
   if (cfg.member_cap > kMaxMembers) return HT_EUNSUPPORTED;
 

@@ -60,6 +60,7 @@ struct Plan {
   int32_t* d_obj_cnt;    // [max_vertex_cells] member count per object
   int32_t* d_obj_off;    // [max_vertex_cells] member offset per object
   int32_t* d_scalars;    // [16] device counters
+  unsigned long long* d_spread;  // [2 * 64 * 16] counters spread over 128-byte lines
   // stage timing (ht_profile_*): HIP events recorded around the stages of
   // later calls; plan calls are ordered, so the counters need no locking
   mutable int32_t prof_depth;          // 0: off
