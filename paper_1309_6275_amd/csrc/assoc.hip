@@ -1321,11 +1321,18 @@ __device__ __forceinline__ int theta_bin(double th, int nt) {
   return t < 0 ? t + nt : t;
 }
 
-__global__ void vvote_kernel(AssocArgs A) {
+// One thread per (track, vertex row): the row's two crossings and its arc
+// of votes.  (A thread per track walked its rows in sequence, a chain of
+// float64 square roots and arctangents per row on only as many threads as
+// tracks.)
+__global__ __launch_bounds__(256) void vvote_kernel(AssocArgs A) {
   const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
   const int nm = A.cfg.n_rho, nt = A.cfg.n_theta;
   const double rw = ((double)A.cfg.rho_hi - (double)A.cfg.rho_lo) / (double)nm;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntrk; t += gridDim.x * blockDim.x) {
+  const int64_t work = (int64_t)ntrk * nm;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < work;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(e / nm), m = (int)(e - (int64_t)t * nm);
     const int p = A.trk_peak[t];
     const double* g = A.cgeo + (size_t)p * 5;
     const double cA = g[1], cB = g[2], cC = g[3], cD = g[4];
@@ -1334,40 +1341,48 @@ __global__ void vvote_kernel(AssocArgs A) {
     const double rf = (double)A.out.tracks[t].r_first;
     // a track passing within vtx_min_d0 of the beam line is an IP feature
     const bool votes = !(pca < (double)A.cfg.vtx_min_d0);
-    for (int m = 0; m < nm; ++m) {
-      int start = 0, len = 0;
-      const double e0 = (double)A.cfg.rho_lo + (double)m * rw;
-      const double e1 = (double)A.cfg.rho_lo + (double)(m + 1) * rw;
-      const double ra = e0 > pca ? e0 : pca;
-      const double rb = e1 < rf ? e1 : rf;
-      if (votes && ra < rb) {
-        const int ta = theta_bin(crossing_theta(cA, cB, cC, cD, sn, ra), nt);
-        const int tb = theta_bin(crossing_theta(cA, cB, cC, cD, sn, rb), nt);
-        int d = (tb - ta) % nt;
-        if (d < 0) d += nt;
-        if (d <= nt / 2) { start = ta; len = d + 1; }
-        else { start = tb; len = nt - d + 1; }
-        for (int q = 0; q < len; ++q) {
-          int c = start + q;
-          if (c >= nt) c -= nt;
-          atomicAdd(&A.vacc[m * nt + c], 1);
-        }
+    int start = 0, len = 0;
+    const double e0 = (double)A.cfg.rho_lo + (double)m * rw;
+    const double e1 = (double)A.cfg.rho_lo + (double)(m + 1) * rw;
+    const double ra = e0 > pca ? e0 : pca;
+    const double rb = e1 < rf ? e1 : rf;
+    if (votes && ra < rb) {
+      const int ta = theta_bin(crossing_theta(cA, cB, cC, cD, sn, ra), nt);
+      const int tb = theta_bin(crossing_theta(cA, cB, cC, cD, sn, rb), nt);
+      int d = (tb - ta) % nt;
+      if (d < 0) d += nt;
+      if (d <= nt / 2) { start = ta; len = d + 1; }
+      else { start = tb; len = nt - d + 1; }
+      for (int q = 0; q < len; ++q) {
+        int c = start + q;
+        if (c >= nt) c -= nt;
+        atomicAdd(&A.vacc[m * nt + c], 1);
       }
-      A.arc0[(size_t)t * nm + m] = start;
-      A.arcn[(size_t)t * nm + m] = len;
     }
+    A.arc0[(size_t)t * nm + m] = start;
+    A.arcn[(size_t)t * nm + m] = len;
   }
 }
 
-// vertex peaks in cell order, by one workgroup
-__global__ __launch_bounds__(1024) void vpeaks_kernel(AssocArgs A) {
+// vertex peaks in cell order, by one workgroup; a vertex accumulator of up
+// to kVLds cells is read into LDS once (coalesced), larger ones are read
+// from global memory.  It also clears the first n_zero object member counts
+// (the input of the member-offset scan).
+constexpr int kVLds = 16384;
+__global__ __launch_bounds__(1024) void vpeaks_kernel(AssocArgs A, int n_zero) {
   __shared__ int32_t wc[16];
   __shared__ int32_t run;
+  __shared__ int32_t sv[kVLds];
   const int nm = A.cfg.n_rho, nt = A.cfg.n_theta;
   const int ncell = nm * nt;
   const int thr = A.cfg.vtx_min_votes;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double rw = ((double)A.cfg.rho_hi - (double)A.cfg.rho_lo) / (double)nm;
+  const bool staged = ncell <= kVLds;
+  for (int c = threadIdx.x; c < n_zero; c += 1024) A.obj_cnt[c] = 0;
+  if (staged)
+    for (int c = threadIdx.x; c < ncell; c += 1024) sv[c] = A.vacc[c];
+  const int32_t* vv = staged ? sv : A.vacc;
   if (threadIdx.x == 0) run = 0;
   __syncthreads();
   for (int base = 0; base < ncell; base += 1024) {
@@ -1375,7 +1390,7 @@ __global__ __launch_bounds__(1024) void vpeaks_kernel(AssocArgs A) {
     bool pk = false;
     if (c < ncell) {
       const int m = c / nt, ti = c - m * nt;
-      const int v = A.vacc[c];
+      const int v = vv[c];
       pk = v >= thr;
       for (int dm = -1; dm <= 1 && pk; ++dm) {
         const int mm = m + dm;
@@ -1384,7 +1399,7 @@ __global__ __launch_bounds__(1024) void vpeaks_kernel(AssocArgs A) {
           if (dm == 0 && dt == 0) continue;
           int tt = ti + dt;
           tt = tt < 0 ? tt + nt : (tt >= nt ? tt - nt : tt);
-          const int w = A.vacc[mm * nt + tt];
+          const int w = vv[mm * nt + tt];
           const bool neg = dm < 0 || (dm == 0 && dt < 0);
           if (neg ? !(v > w) : !(v >= w)) { pk = false; break; }
         }
@@ -1402,7 +1417,7 @@ __global__ __launch_bounds__(1024) void vpeaks_kernel(AssocArgs A) {
         const int m = c / nt, ti = c - m * nt;
         ht_object ob;
         ob.lin = c;
-        ob.votes = A.vacc[c];
+        ob.votes = vv[c];
         ob.n_tracks = 0;
         ob.kind = 0;
         ob.rho = (float)((double)A.cfg.rho_lo + ((double)m + 0.5) * rw);
@@ -1517,10 +1532,6 @@ __global__ void counts_kernel(AssocArgs A) {
   c[7] = 0;
 }
 
-// zero the member-count prefix input when there are no objects
-__global__ void zero_i32_kernel(int32_t* p, int n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
-}
 
 int blocks_for(int64_t n, int per) {
   int64_t b = (n + per - 1) / per;
@@ -1634,14 +1645,12 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
     else
       fit_kernel<<<blocks_for(tcap, 4), 256, 0, s>>>(A);
     HT_CHECK(hipGetLastError());
-    vvote_kernel<<<blocks_for(tcap, 64), 64, 0, s>>>(A);
+    vvote_kernel<<<blocks_for((int64_t)tcap * cfg.n_rho, 256), 256, 0, s>>>(A);
     HT_CHECK(hipGetLastError());
   }
-  vpeaks_kernel<<<1, 1024, 0, s>>>(A);
-  HT_CHECK(hipGetLastError());
   const int ocap = out.object_cap > 0 ? out.object_cap : 1;
   const int ozero = ocap < P.lim.max_vertex_cells ? ocap : P.lim.max_vertex_cells;
-  zero_i32_kernel<<<blocks_for(ozero, 256), 256, 0, s>>>(P.d_obj_cnt, ozero);
+  vpeaks_kernel<<<1, 1024, 0, s>>>(A, ozero);
   HT_CHECK(hipGetLastError());
   if (out.object_cap > 0) {
     vcount_kernel<<<blocks_for(ocap, 4), 256, 0, s>>>(A);
