@@ -143,13 +143,14 @@ __global__ __launch_bounds__(256) void flag4_kernel(const int32_t* __restrict__ 
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x >> 6;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int64_t lin0 = (int64_t)tile * kTile4 + (int64_t)threadIdx.x * 4;
+  // n_cells < 2^31, so cell indices of a tile fit in 32 bits unsigned
+  const uint32_t lin0 = (uint32_t)tile * kTile4 + threadIdx.x * 4u;
   bool f[4] = {false, false, false, false};
-  if (lin0 < n_cells) {  // n_cells is a multiple of 4: all four cells exist
-    const int i0 = (int)(lin0 % n_phi);
-    const int64_t col = lin0 / n_phi;
-    const int j = (int)(col % n_qpt);
-    const int k = (int)(col / n_qpt);
+  if (lin0 < (uint64_t)n_cells) {  // n_cells is a multiple of 4: all four cells exist
+    const uint32_t col = lin0 / (uint32_t)n_phi;
+    const int i0 = (int)(lin0 - col * (uint32_t)n_phi);
+    const int k = (int)(col / (uint32_t)n_qpt);
+    const int j = (int)col - k * n_qpt;
     const int4 c4 = *reinterpret_cast<const int4*>(acc + lin0);
     const int32_t v[4] = {c4.x, c4.y, c4.z, c4.w};
     bool any = false;
@@ -159,6 +160,14 @@ __global__ __launch_bounds__(256) void flag4_kernel(const int32_t* __restrict__ 
       any = any || f[t];
     }
     if (any) {
+      // The rule in maxima: a cell must exceed the largest of its neighbours
+      // in the rows before it (dk < 0, or dk = 0 and dj < 0) and of its left
+      // neighbour, and reach the largest in the rows after it and its right
+      // neighbour.  Per row the 3-cell maxima of the four cells share their
+      // pairwise maxima.
+      int32_t neg[4], pos[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) neg[t] = pos[t] = INT32_MIN;
 #pragma unroll
       for (int dk = -1; dk <= 1; ++dk) {
         const int kk = k + dk;
@@ -169,18 +178,26 @@ __global__ __launch_bounds__(256) void flag4_kernel(const int32_t* __restrict__ 
           if (jj < 0 || jj >= n_qpt) continue;
           int32_t w[6];
           load_row6(acc + ((size_t)kk * n_qpt + jj) * n_phi, i0, n_phi, w);
+          if (dk == 0 && dj == 0) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) f[t] = f[t] && v[t] > w[t] && v[t] >= w[t + 2];
+            continue;
+          }
+          int32_t pm[5];
+#pragma unroll
+          for (int t = 0; t < 5; ++t) pm[t] = max(w[t], w[t + 1]);
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
-            const int32_t a = w[t], b = w[t + 1], c = w[t + 2];  // cells i-1, i, i+1
+            const int32_t m3 = max(pm[t], w[t + 2]);  // cells i-1, i, i+1
             if (dk < 0 || (dk == 0 && dj < 0))
-              f[t] = f[t] && v[t] > a && v[t] > b && v[t] > c;
-            else if (dk == 0 && dj == 0)
-              f[t] = f[t] && v[t] > a && v[t] >= c;
+              neg[t] = max(neg[t], m3);
             else
-              f[t] = f[t] && v[t] >= a && v[t] >= b && v[t] >= c;
+              pos[t] = max(pos[t], m3);
           }
         }
       }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) f[t] = f[t] && v[t] > neg[t] && v[t] >= pos[t];
     }
   }
   uint64_t m[4];
