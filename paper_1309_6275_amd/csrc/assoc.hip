@@ -1364,55 +1364,63 @@ __global__ __launch_bounds__(256) void vvote_kernel(AssocArgs A) {
   }
 }
 
-// vertex peaks in cell order, by one workgroup; a vertex accumulator of up
-// to kVLds cells is read into LDS once (coalesced), larger ones are read
-// from global memory.  It also clears the first n_zero object member counts
-// (the input of the member-offset scan).
+// vertex peaks in cell order, by one workgroup: thread t tests a run of
+// consecutive cells (a vertex accumulator of up to kVLds cells is first read
+// into LDS, coalesced; larger ones are read from global memory), a scan of
+// the per-thread counts places each run's objects, and every thread writes
+// its own in cell order.  It also clears the first n_zero object member
+// counts (the input of the member-offset scan).
 constexpr int kVLds = 16384;
-__global__ __launch_bounds__(1024) void vpeaks_kernel(AssocArgs A, int n_zero) {
-  __shared__ int32_t wc[16];
-  __shared__ int32_t run;
+constexpr int kVThreads = 1024;
+__device__ __forceinline__ bool vertex_peak(const int32_t* vv, int nm, int nt, int c, int thr) {
+  const int m = c / nt, ti = c - m * nt;
+  const int v = vv[c];
+  if (v < thr) return false;
+  for (int dm = -1; dm <= 1; ++dm) {
+    const int mm = m + dm;
+    if (mm < 0 || mm >= nm) continue;
+    for (int dt = -1; dt <= 1; ++dt) {
+      if (dm == 0 && dt == 0) continue;
+      int tt = ti + dt;
+      tt = tt < 0 ? tt + nt : (tt >= nt ? tt - nt : tt);
+      const int w = vv[mm * nt + tt];
+      const bool neg = dm < 0 || (dm == 0 && dt < 0);
+      if (neg ? !(v > w) : !(v >= w)) return false;
+    }
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(kVThreads) void vpeaks_kernel(AssocArgs A, int n_zero) {
+  __shared__ int32_t wsum[kVThreads / kWave];
   __shared__ int32_t sv[kVLds];
   const int nm = A.cfg.n_rho, nt = A.cfg.n_theta;
   const int ncell = nm * nt;
   const int thr = A.cfg.vtx_min_votes;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   const double rw = ((double)A.cfg.rho_hi - (double)A.cfg.rho_lo) / (double)nm;
   const bool staged = ncell <= kVLds;
-  for (int c = threadIdx.x; c < n_zero; c += 1024) A.obj_cnt[c] = 0;
+  for (int c = threadIdx.x; c < n_zero; c += kVThreads) A.obj_cnt[c] = 0;
   if (staged)
-    for (int c = threadIdx.x; c < ncell; c += 1024) sv[c] = A.vacc[c];
-  const int32_t* vv = staged ? sv : A.vacc;
-  if (threadIdx.x == 0) run = 0;
+    for (int c = threadIdx.x; c < ncell; c += kVThreads) sv[c] = A.vacc[c];
   __syncthreads();
-  for (int base = 0; base < ncell; base += 1024) {
-    const int c = base + threadIdx.x;
-    bool pk = false;
-    if (c < ncell) {
-      const int m = c / nt, ti = c - m * nt;
-      const int v = vv[c];
-      pk = v >= thr;
-      for (int dm = -1; dm <= 1 && pk; ++dm) {
-        const int mm = m + dm;
-        if (mm < 0 || mm >= nm) continue;
-        for (int dt = -1; dt <= 1; ++dt) {
-          if (dm == 0 && dt == 0) continue;
-          int tt = ti + dt;
-          tt = tt < 0 ? tt + nt : (tt >= nt ? tt - nt : tt);
-          const int w = vv[mm * nt + tt];
-          const bool neg = dm < 0 || (dm == 0 && dt < 0);
-          if (neg ? !(v > w) : !(v >= w)) { pk = false; break; }
-        }
-      }
-    }
-    const uint64_t msk = __ballot(pk);
-    if (lane == 0) wc[wave] = __popcll(msk);
-    __syncthreads();
-    int before = run;
-    for (int w = 0; w < wave; ++w) before += wc[w];
-    if (pk) {
-      const uint64_t lower = lane ? (msk & ((1ull << lane) - 1ull)) : 0ull;
-      const int o = before + __popcll(lower);
+  const int32_t* vv = staged ? sv : A.vacc;
+  const int run = (ncell + kVThreads - 1) / kVThreads;
+  const int c0 = min(threadIdx.x * run, ncell), c1 = min(c0 + run, ncell);
+  int cnt = 0;
+  for (int c = c0; c < c1; ++c) cnt += vertex_peak(vv, nm, nt, c, thr) ? 1 : 0;
+  int x = cnt;  // inclusive scan over the wave, then over the 16 wave totals
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  if (lane == kWave - 1) wsum[wave] = x;
+  __syncthreads();
+  int o = x - cnt;
+  for (int w = 0; w < wave; ++w) o += wsum[w];
+  if (cnt) {
+    for (int c = c0; c < c1; ++c) {
+      if (!vertex_peak(vv, nm, nt, c, thr)) continue;
       if (o < A.out.object_cap) {
         const int m = c / nt, ti = c - m * nt;
         ht_object ob;
@@ -1426,16 +1434,10 @@ __global__ __launch_bounds__(1024) void vpeaks_kernel(AssocArgs A, int n_zero) {
         ob.member_begin = 0;
         A.out.objects[o] = ob;
       }
+      ++o;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int s = 0;
-      for (int w = 0; w < 16; ++w) s += wc[w];
-      run += s;
-    }
-    __syncthreads();
   }
-  if (threadIdx.x == 0) A.sc[S_NOBJ] = run;
+  if (threadIdx.x == kVThreads - 1) A.sc[S_NOBJ] = o;
 }
 
 __device__ __forceinline__ bool is_member(const AssocArgs& A, int t, int m, int ti) {
@@ -1514,13 +1516,18 @@ __global__ __launch_bounds__(256) void vmembers_kernel(AssocArgs A, const int32_
   }
 }
 
-__global__ void counts_kernel(AssocArgs A) {
+// one wave: lane i reads spread slot i of both counters
+__global__ __launch_bounds__(kWave) void counts_kernel(AssocArgs A) {
+  static_assert(kSpread == kWave, "one spread slot per lane");
   int32_t* c = A.out.counts;
-  unsigned long long ncand = 0, tests = 0;
-  for (int i = 0; i < kSpread; ++i) {
-    ncand += A.spread[(size_t)(SP_NCAND + i) * kSpreadStride];
-    tests += A.spread[(size_t)(SP_TESTS + i) * kSpreadStride];
+  const int lane = threadIdx.x;
+  unsigned long long ncand = A.spread[(size_t)(SP_NCAND + lane) * kSpreadStride];
+  unsigned long long tests = A.spread[(size_t)(SP_TESTS + lane) * kSpreadStride];
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    ncand += __shfl_xor(ncand, off);
+    tests += __shfl_xor(tests, off);
   }
+  if (lane != 0) return;
   c[0] = (int32_t)ncand;
   c[1] = A.sc[S_NTRK];
   c[2] = A.sc[S_NOBJ];
@@ -1664,7 +1671,7 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
     vmembers_kernel<<<blocks_for(ocap, 4), 256, 0, s>>>(A, P.d_obj_off);
     HT_CHECK(hipGetLastError());
   }
-  counts_kernel<<<1, 1, 0, s>>>(A);
+  counts_kernel<<<1, kWave, 0, s>>>(A);
   HT_CHECK(hipGetLastError());
   P.prof_mark(HT_STAGE_ASSOC, 1, s);
   return HT_OK;
