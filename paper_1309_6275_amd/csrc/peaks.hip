@@ -217,6 +217,110 @@ __global__ __launch_bounds__(256) void flag4_kernel(const int32_t* __restrict__ 
   if (threadIdx.x == 0) tile_cnt[tile] = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
 }
 
+// The same flags with the tile's neighbourhood staged in LDS, for grids
+// whose phi axis divides the 1024-cell tile (n_phi = 1024 / R) and whose
+// q/pT axis is a multiple of R, so a tile is R whole rows of one d0 plane.
+// The 3 x (R + 2) rows around it are read once, coalesced, instead of nine
+// overlapping row reads per lane from L2.
+template <int R>
+__global__ __launch_bounds__(256) void flag4s_kernel(const int32_t* __restrict__ acc,
+                                                     int n_qpt, int n_d0, int32_t thr,
+                                                     uint64_t* __restrict__ bits,
+                                                     int32_t* __restrict__ tile_cnt) {
+  constexpr int NP = kTile4 / R;  // n_phi
+  constexpr int ROWS = R + 2;
+  __shared__ int32_t sm[3][ROWS][NP];
+  __shared__ int32_t wcnt[4];
+  __shared__ int32_t rok[3][ROWS];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x >> 6;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int c0 = tile * R;          // first row (q/pT, d0 column) of the tile
+  const int k = c0 / n_qpt;
+  const int j0 = c0 - k * n_qpt;
+  if (threadIdx.x < 3 * ROWS) {
+    const int dk = threadIdx.x / ROWS - 1, jr = threadIdx.x % ROWS - 1;
+    const int kk = k + dk, jj = j0 + jr;
+    rok[dk + 1][jr + 1] = (kk >= 0 && kk < n_d0 && jj >= 0 && jj < n_qpt) ? 1 : 0;
+  }
+  __syncthreads();
+  constexpr int Q = NP / 4;  // int4 per row
+  for (int e = threadIdx.x; e < 3 * ROWS * Q; e += 256) {
+    const int row = e / Q, q4 = e - row * Q;
+    const int dk = row / ROWS, jr = row - dk * ROWS;
+    if (!rok[dk][jr]) continue;
+    const int kk = k + dk - 1, jj = j0 + jr - 1;
+    const int4 v4 = *reinterpret_cast<const int4*>(acc + ((size_t)kk * n_qpt + jj) * NP + q4 * 4);
+    *reinterpret_cast<int4*>(&sm[dk][jr][q4 * 4]) = v4;
+  }
+  __syncthreads();
+  const int r = (threadIdx.x * 4) / NP;       // row of the tile
+  const int i0 = (threadIdx.x * 4) % NP;
+  const int im = i0 == 0 ? NP - 1 : i0 - 1;   // phi0 periodic
+  const int ip = i0 + 4 == NP ? 0 : i0 + 4;
+  int32_t v[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) v[t] = sm[1][r + 1][i0 + t];
+  bool f[4];
+  bool any = false;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f[t] = v[t] >= thr;
+    any = any || f[t];
+  }
+  if (any) {
+    int32_t neg[4], pos[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) neg[t] = pos[t] = INT32_MIN;
+#pragma unroll
+    for (int dk = 0; dk < 3; ++dk) {
+#pragma unroll
+      for (int dj = 0; dj < 3; ++dj) {
+        if (!rok[dk][r + dj]) continue;
+        const int32_t* row = sm[dk][r + dj];
+        int32_t w[6];
+        w[0] = row[im];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) w[t + 1] = row[i0 + t];
+        w[5] = row[ip];
+        if (dk == 1 && dj == 1) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) f[t] = f[t] && v[t] > w[t] && v[t] >= w[t + 2];
+          continue;
+        }
+        int32_t pm[5];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) pm[t] = max(w[t], w[t + 1]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int32_t m3 = max(pm[t], w[t + 2]);
+          if (dk < 1 || (dk == 1 && dj < 1))
+            neg[t] = max(neg[t], m3);
+          else
+            pos[t] = max(pos[t], m3);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) f[t] = f[t] && v[t] > neg[t] && v[t] >= pos[t];
+  }
+  uint64_t m[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) m[t] = __ballot(f[t]);
+  if (lane == 0) {
+    uint64_t* wb = bits + ((size_t)tile * 4 + wave) * 4;
+    int c = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      wb[t] = m[t];
+      c += __popcll(m[t]);
+    }
+    wcnt[wave] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) tile_cnt[tile] = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+}
+
 __global__ __launch_bounds__(256) void emit4_kernel(const int32_t* __restrict__ acc,
                                                     const uint64_t* __restrict__ bits,
                                                     const int32_t* __restrict__ tile_off,
@@ -267,9 +371,17 @@ int launch_peaks(const Plan& p, const int32_t* acc, int32_t min_votes, ht_peak* 
   const bool four = (g.n_phi & 3) == 0 && ((uintptr_t)acc & 15) == 0;
   const int tiles = four ? (int)((p.n_cells + kTile4 - 1) / kTile4) : p.n_tiles;
   p.prof_mark(HT_STAGE_PEAKS, 0, s);
-  if (four)
+  const int R = four && kTile4 % g.n_phi == 0 ? kTile4 / g.n_phi : 0;
+  uint64_t* bits4 = reinterpret_cast<uint64_t*>(p.d_bits);
+  if (R == 1 && g.n_qpt % 1 == 0)
+    flag4s_kernel<1><<<tiles, 256, 0, s>>>(acc, g.n_qpt, g.n_d0, min_votes, bits4, p.d_tile_cnt);
+  else if (R == 2 && g.n_qpt % 2 == 0)
+    flag4s_kernel<2><<<tiles, 256, 0, s>>>(acc, g.n_qpt, g.n_d0, min_votes, bits4, p.d_tile_cnt);
+  else if (R == 4 && g.n_qpt % 4 == 0)
+    flag4s_kernel<4><<<tiles, 256, 0, s>>>(acc, g.n_qpt, g.n_d0, min_votes, bits4, p.d_tile_cnt);
+  else if (four)
     flag4_kernel<<<tiles, 256, 0, s>>>(acc, g.n_phi, g.n_qpt, g.n_d0, p.n_cells, min_votes,
-                                       reinterpret_cast<uint64_t*>(p.d_bits), p.d_tile_cnt);
+                                       bits4, p.d_tile_cnt);
   else
     flag_kernel<<<tiles, kTile, 0, s>>>(acc, g.n_phi, g.n_qpt, g.n_d0, p.n_cells, min_votes,
                                         p.d_bits, p.d_tile_cnt);
