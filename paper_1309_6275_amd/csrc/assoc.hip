@@ -925,13 +925,35 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
     tests += (unsigned long long)__popcll(__ballot(ok)) * (unsigned long long)n;
     int n_in = ok ? 0 : -1;
     bool active = ok;
-    // visiting order: layers that are not seed layers, then the seed layers
+    // visiting order: the layers that are not seed layers by increasing
+    // member count (then index), so that lanes meet a layer without an
+    // inlier early and drop out after few members; then the seed layers.
+    // The per-lane outcome does not depend on the order.
     const unsigned smask = (1u << Ls[0]) | (1u << Ls[1]) | (1u << Ls[2]);
-    unsigned seq = (lmask & ~smask) | (smask << HT_MAX_LAYERS);
+    const unsigned nsm = lmask & ~smask;
+    const int n_ns = __popc(nsm);
+    int orderv = 0;  // lane i: the i-th layer to visit
+    {
+      const int nxt = __shfl_down(ls, 1, kWave);  // start of the next layer
+      const bool mine = lane < HT_MAX_LAYERS && ((nsm >> lane) & 1u);
+      const int key = mine ? (((nxt - ls) << 4) | lane) : 0x7fffffff;
+      int rank = 0;
+      for (int t = 0; t < HT_MAX_LAYERS; ++t) rank += __shfl(key, t, kWave) < key ? 1 : 0;
+      for (int t = 0; t < HT_MAX_LAYERS; ++t) {
+        const int rt = __shfl(rank, t, kWave);
+        if (((nsm >> t) & 1u) && rt == lane) orderv = t;
+      }
+    }
+    unsigned sseq = smask;
     int remaining = nS;
-    while (seq) {
-      const int L = __builtin_ctz(seq) & (HT_MAX_LAYERS - 1);
-      seq &= seq - 1u;
+    for (int it = 0; it < nS; ++it) {
+      int L;
+      if (it < n_ns) {
+        L = __builtin_amdgcn_readlane(orderv, it);
+      } else {
+        L = __builtin_ctz(sseq);
+        sseq &= sseq - 1u;
+      }
       --remaining;
       if (active && n_in + remaining + 1 < cfg.min_layers) {
         active = false;
