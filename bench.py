@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--workload", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=2,
+    ap.add_argument("--cpu-sample", type=int, default=16,
                     help="events of the CPU oracle baseline (0 skips it)")
     ap.add_argument("--serve", action="store_true",
                     help="benchmark the trigger serving loop instead: Poisson arrivals of a mixed "
