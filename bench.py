@@ -50,6 +50,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--streams", type=int, default=1,
+                    help="HIP streams, each with its own plan and scratch; events are "
+                         "assigned round-robin and run concurrently.  The per-launch kernel "
+                         "times of the roofline are meaningful with one stream only")
+    ap.add_argument("--concurrent", type=int, default=2,
+                    help="after the timed region, also time the same steps on this many "
+                         "concurrent streams (0 skips it); reported as concurrent_streams")
     ap.add_argument("--cpu-sample", type=int, default=16,
                     help="events of the CPU oracle baseline (0 skips it)")
     ap.add_argument("--serve", action="store_true",
@@ -373,15 +380,18 @@ def main():
     B = args.batch
     events = [G.make_event(args.workload, W["seed0"] + 100 + e) for e in range(B)]
     peak_cap = 1 << 19 if args.workload < 3 else 1 << 21
-    plan = H.Plan(g, max_hits=65535, max_peaks=peak_cap, max_member_cap=cl["member_cap"],
-                  max_tracks=1 << 14)
+    S = max(1, args.streams)
+    plans = [H.Plan(g, max_hits=65535, max_peaks=peak_cap, max_member_cap=cl["member_cap"],
+                    max_tracks=1 << 14) for _ in range(S)]
+    plan = plans[0]
     dev = []
     for ev in events:
         dev.append(dict(r=torch.from_numpy(ev.r).cuda(), phi=torch.from_numpy(ev.phi).cuda(),
                         layer=torch.from_numpy(ev.layer).cuda(), n=ev.n_hits))
-    acc = torch.empty(plan.acc_shape, dtype=torch.int32, device="cuda")
-    peaks = torch.empty((peak_cap, 2), dtype=torch.int32, device="cuda")
-    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx = [dict(acc=torch.empty(plan.acc_shape, dtype=torch.int32, device="cuda"),
+                peaks=torch.empty((peak_cap, 2), dtype=torch.int32, device="cuda"),
+                nf=torch.zeros(1, dtype=torch.int32, device="cuda")) for _ in range(S)]
+    acc = ctx[0]["acc"]
     nv = torch.zeros(1, dtype=torch.int64, device="cuda")
     bufs = [H.ClusterBuffers(ev.n_hits, 1 << 14, 1024, 1 << 16, cl["n_rho"], cl["n_theta"])
             for ev in events]
@@ -396,27 +406,32 @@ def main():
         ok = (ev.r > 0) & (ev.r < 1e4) & (np.abs(ev.phi) <= 4)
         evals.append(int(ok.sum()) * ncol)
 
-    stream = torch.cuda.current_stream()
+    # default-priority streams, one plan (tables and scratch) per stream
+    streams = [torch.cuda.Stream() for _ in range(S)]
+    torch.cuda.synchronize()
     ev_a = [torch.cuda.Event(enable_timing=True) for _ in range(B)]
     ev_c = [torch.cuda.Event(enable_timing=True) for _ in range(B)]
 
     def step(record):
         for e, d in enumerate(dev):
-            if record:
-                ev_a[e].record(stream)
-            H.hough_vote(plan, d["r"], d["phi"], acc)
-            H.hough_peaks(plan, acc, W["min_votes"], peaks, nf)
-            H.assoc_cluster(plan, d["r"], d["phi"], d["layer"], peaks, nf, cl, bufs[e],
-                            with_vacc=False)
-            if record:
-                ev_c[e].record(stream)
+            c, st, pl = ctx[e % S], streams[e % S], plans[e % S]
+            with torch.cuda.stream(st):
+                if record:
+                    ev_a[e].record(st)
+                H.hough_vote(pl, d["r"], d["phi"], c["acc"])
+                H.hough_peaks(pl, c["acc"], W["min_votes"], c["peaks"], c["nf"])
+                H.assoc_cluster(pl, d["r"], d["phi"], d["layer"], c["peaks"], c["nf"], cl,
+                                bufs[e], with_vacc=False)
+                if record:
+                    ev_c[e].record(st)
 
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
-    # stage timers: HIP events the library records around its kernels on the
-    # launch stream, read after each step
-    H.profile_begin(plan, depth=2 * B)
+    # stage timers: HIP events the library records around its kernels on each
+    # plan's launch stream, read after each step
+    for pl in plans:
+        H.profile_begin(pl, depth=2 * B)
     stages = {}
     lat_ms = []
     t0 = time.perf_counter()
@@ -425,10 +440,51 @@ def main():
         torch.cuda.synchronize()  # per-step sync so the events of this step can be read
         for e in range(B):
             lat_ms.append(ev_a[e].elapsed_time(ev_c[e]))
-        H.profile_read(plan, stages)
+        for pl in plans:
+            H.profile_read(pl, stages)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    H.profile_end(plan)
+    for pl in plans:
+        H.profile_end(pl)
+
+    # the same steps on concurrent streams, each with its own plan: throughput
+    # when kernels of several events overlap (not the headline value, whose
+    # per-launch kernel times the roofline needs)
+    conc = None
+    if args.concurrent > 1 and S == 1:
+        C = args.concurrent
+        cplans = [plan] + [H.Plan(g, max_hits=65535, max_peaks=peak_cap,
+                                  max_member_cap=cl["member_cap"], max_tracks=1 << 14)
+                           for _ in range(C - 1)]
+        cctx = [ctx[0]] + [dict(acc=torch.empty(plan.acc_shape, dtype=torch.int32, device="cuda"),
+                                peaks=torch.empty((peak_cap, 2), dtype=torch.int32, device="cuda"),
+                                nf=torch.zeros(1, dtype=torch.int32, device="cuda"))
+                           for _ in range(C - 1)]
+        cstreams = [torch.cuda.Stream() for _ in range(C)]
+
+        def cstep():
+            for e, d in enumerate(dev):
+                c, st, pl = cctx[e % C], cstreams[e % C], cplans[e % C]
+                with torch.cuda.stream(st):
+                    H.hough_vote(pl, d["r"], d["phi"], c["acc"])
+                    H.hough_peaks(pl, c["acc"], W["min_votes"], c["peaks"], c["nf"])
+                    H.assoc_cluster(pl, d["r"], d["phi"], d["layer"], c["peaks"], c["nf"], cl,
+                                    bufs[e], with_vacc=False)
+
+        for _ in range(args.warmup):
+            cstep()
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        for _ in range(args.steps):
+            cstep()
+        torch.cuda.synchronize()
+        cw = time.perf_counter() - tc
+        conc = {"streams": C, "events_per_s": args.steps * B / cw,
+                "votes_per_s": args.steps * sum(votes) / cw,
+                "note": "same steps after the timed region, events round-robin over streams "
+                        "with one plan each"}
+        for pl in cplans[1:]:
+            pl.close()
 
     n_events = args.steps * B
     total_votes = args.steps * sum(votes)
@@ -487,7 +543,9 @@ def main():
         "config": {"workload": W["name"], "events_per_step": B,
                    "grid": f"{g['n_phi']}x{g['n_qpt']}x{g['n_d0']}",
                    "mean_hits": float(np.mean([ev.n_hits for ev in events])),
-                   "parallelism": "single GPU, events back to back on one stream"},
+                   "parallelism": ("single GPU, events back to back on one stream" if S == 1
+                                   else f"single GPU, {S} streams with one plan each, events "
+                                        "round-robin and concurrent")},
         "events_per_s": n_events / wall,
         "p50_ms": float(np.percentile(lat_ms, 50)),
         "p99_ms": float(np.percentile(lat_ms, 99)),
@@ -499,6 +557,7 @@ def main():
         "roofline": roofline(dominant),
         "roofline_vote": roofline("vote"),
         "cpu_baseline": cpu,
+        "concurrent_streams": conc,
     }
     print(json.dumps(line), flush=True)
 
