@@ -6,26 +6,31 @@
 // Launch sequence (all on the caller's stream, no host synchronisation; the
 // device peak count bounds every per-candidate loop):
 //   prep      per hit: float64 Cartesian coordinates (canonical sincos),
-//             ownership keys cleared;
+//             ownership keys cleared; counters and the vertex accumulator
+//             zeroed;
 //   mark      peak bitmap and the first peak index of every column;
 //   members   a sweep shaped like the vote (workgroup = 64 columns of one
 //             d0, lane = column, hits broadcast through SGPRs) that
 //             re-evaluates each hit's phi0 coordinate and appends it to
 //             every peak of the column whose member window holds it;
 //   refine    one wave per candidate: member layers, seed layers, the
-//             seed_k nearest members of each seed layer by wave argmin, then
-//             one seed combination per lane (<= 64) scored against all
-//             members in LDS; the best lane wins by (inliers, sum, index);
+//             seed_k nearest members of each seed layer by rank, then one
+//             seed combination per lane (<= 64) scored against the members
+//             in LDS, smallest non-seed layers first; the best lane wins by
+//             (inliers, sum, index);
 //   own       per candidate, 64-bit atomicMax of (inliers, -sum, -index) on
 //             each inlier hit;
 //   survive   ordered compaction of the candidates owning >= min_layers
 //             hits into the track list (tile counts, scan, emit);
-//   fit       one thread per track, float64 Gauss-Newton;
-//   vvote     one thread per track: crossing arcs per vertex row, atomic
-//             votes into the vertex accumulator;
+//   fit       float64 Gauss-Newton, one wave per track (lanes = hits), or
+//             the Kalman filter, one thread per track;
+//   vvote     one thread per (track, vertex row): crossing arc, atomic votes
+//             into the vertex accumulator;
 //   vpeaks    one workgroup: vertex local maxima in cell order;
-//   vmembers  one wave per object: member tracks by ballot, written in
-//             order, isotropy summed in track order.
+//   vcount,   member counts per object, their scan, then one wave per
+//   vmembers  object: member tracks by ballot, written in order, isotropy
+//             summed in track order;
+//   counts    the output counts.
 // Every decision that selects an integer result uses float32 vote
 // arithmetic or float64 arithmetic and square roots in a fixed order, so the
 // results match the CPU reference bit for bit; the refit uses the device

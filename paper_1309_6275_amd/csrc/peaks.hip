@@ -10,11 +10,11 @@
 //      peaks at offset + rank, the rank coming from popcount prefix sums, so
 //      the list is sorted by cell index with no sort.
 // When n_phi is a multiple of 4 (and the accumulator 16-byte aligned) a lane
-// takes 4 consecutive cells of one row: each of the 9 neighbour rows is one
-// 16-byte load plus the two cells beside it, 6.75 loads per cell instead of
-// 27, and a tile is 1024 cells.  Otherwise a lane takes one cell and a tile
-// is 256 cells.  Neighbour reads hit L2 (the rows of a tile are read by
-// neighbouring tiles at about the same time).
+// takes 4 consecutive cells of one row and a tile is 1024 cells.  If n_phi
+// divides the tile (and n_qpt is a multiple of the tile's rows), the tile's
+// 3 x (rows + 2) neighbour rows are staged in LDS once; otherwise each of the
+// 9 neighbour rows is one 16-byte load plus the two cells beside it, from
+// L2.  Other n_phi: a lane takes one cell and a tile is 256 cells.
 #include "ht_internal.h"
 
 namespace ht {
