@@ -224,6 +224,11 @@ def serve_bench(args):
     tput_2d = closed_loop(srv2, two_d, 8 * len(two_d))
     n_slots, slot_bytes = srv2.n_slots, srv2.slot_bytes
     srv2.close()
+    # the serial per-event baseline: one slot, so events never overlap
+    serial = make(slots=1)
+    closed_loop(serial, pool, len(pool))
+    tput_serial = closed_loop(serial, pool, 2 * len(pool))
+    serial.close()
     best = max(ok) if ok else None
     best_r = next((r for r in rates if r["rate"] == best), None)
     line = {
@@ -240,6 +245,7 @@ def serve_bench(args):
         "closed_loop_events_per_s": tput,
         "closed_loop_events_per_s_direct_launches": tput_direct,
         "closed_loop_2d_only_events_per_s": tput_2d,
+        "closed_loop_events_per_s_one_slot": tput_serial,
     }
     print(json.dumps(line), flush=True)
 
