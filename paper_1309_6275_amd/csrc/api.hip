@@ -182,7 +182,7 @@ int ht_plan_create(const ht_grid* grid, const ht_limits* lim, ht_plan** out) {
   if (rc == HT_OK) rc = dalloc(&p->d_obj_cnt, (size_t)lim->max_vertex_cells);
   if (rc == HT_OK) rc = dalloc(&p->d_obj_off, (size_t)lim->max_vertex_cells);
   if (rc == HT_OK) rc = dalloc(&p->d_scalars, 16);
-  if (rc == HT_OK) rc = dalloc(&p->d_spread, 2 * 64 * 16);
+  if (rc == HT_OK) rc = dalloc(&p->d_spread, ht::kSpreadWords);
   // band-vote corner tables: (smallest kappa, lower d0 edge) and (largest
   // kappa, upper d0 edge) of every column
   if (rc == HT_OK) rc = dalloc(&p->d_ckl, (size_t)g.n_qpt);

@@ -47,16 +47,20 @@ constexpr int kSweepThreads = kSweepWaves * kWave;
 constexpr int kMaxMembers = 1024; // largest member_cap (LDS slots per wave in refine)
 constexpr int kGridCap = 8192;    // grid-stride launches use at most this many blocks
 
-// S_PAIRS is a 64-bit counter over slots 6-7 (8-byte aligned)
-enum { S_NP = 0, S_NOVER = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5, S_PAIRS = 6 };
-// The seed search's per-wave totals (refined candidates, road tests) go to
-// kSpread counters in separate 128-byte lines, chosen by wave: tens of
-// thousands of waves adding into one address serialise in one L2 channel
-// (about a fifth of the kernel's time when measured); counts_kernel sums
-// the slots.
+enum { S_NP = 0, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5 };
+// The seed search's totals (road tests, refined candidates, candidates over
+// member_cap, (candidate, member) pairs within it) are summed per workgroup
+// and added to kSpread counters in separate 128-byte lines, chosen by
+// workgroup: tens of thousands of waves adding into one address serialise in
+// one L2 channel (about a fifth of the kernel's time when measured, and most
+// of it on events where every candidate overflows); counts_kernel sums the
+// slots.
 constexpr int kSpread = 64;
 constexpr int kSpreadStride = 16;  // 64-bit words: one 128-byte line per slot
-enum { SP_TESTS = 0, SP_NCAND = kSpread };
+// group g of the counters starts at slot g * kSpread: 0 road tests,
+// 1 refined candidates, 2 candidates over member_cap, 3 pairs within it
+enum { SP_TESTS = 0, SP_NCAND = kSpread, SP_NOVER = 2 * kSpread, SP_PAIRS = 3 * kSpread };
+static_assert(4 * kSpread * kSpreadStride == kSpreadWords, "spread counter layout");
 
 __device__ __forceinline__ float bcastf(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -274,7 +278,7 @@ struct AssocArgs {
   int32_t* vacc;
   int32_t* obj_cnt;
   int32_t* sc;  // device scalars
-  unsigned long long* spread;  // [2 * kSpread * kSpreadStride] spread counters
+  unsigned long long* spread;  // [kSpreadWords] spread counters
   // outputs
   ht_cluster_out out;
 };
@@ -289,7 +293,7 @@ __global__ void init_kernel(AssocArgs A, int words) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   if (tid < 16) A.sc[tid] = 0;
-  for (int64_t w = tid; w < 2 * kSpread * kSpreadStride; w += stride) A.spread[w] = 0ull;
+  for (int64_t w = tid; w < kSpreadWords; w += stride) A.spread[w] = 0ull;
   if (tid == 0) {
     int np = *A.n_peaks;
     np = np < 0 ? 0 : (np > A.peak_cap ? A.peak_cap : np);
@@ -346,7 +350,10 @@ constexpr int kMaxWgPeaks = 4096; // LDS counters; more peaks fall back to globa
 constexpr int kQueue = 2 * kWave; // per-wave queue of (hit, column) pairs with a peak in reach
 
 struct SweepShared {
-  uint32_t cbits[kWave][kMaxPhiWords + 1];
+  uint32_t cbits[kWave][kMaxPhiWords + 1];  // every peak of the column (candidate indices)
+  // the peaks still taking members: a candidate's bit is cleared once it
+  // holds more than member_cap (it is dropped whatever else it would get)
+  uint32_t lbits[kWave][kMaxPhiWords + 1];
   int32_t cpre[kWave][kMaxPhiWords + 1];
   int32_t ccnt[kWave];
   int32_t cfirst[kWave];      // first peak of each column, relative to p_lo
@@ -363,14 +370,22 @@ struct SweepShared {
 };
 
 // One pass over the workgroup's (hit, column) pairs; for every member
-// (candidate q = p - p_lo, hit h, |x - cell centre| adx) call fn(q, h, adx).  A lane (column) first
+// (candidate q = p - p_lo, hit h, |x - cell centre| adx) call fn(q, h, adx),
+// which returns true when the candidate has just gone over member_cap; its
+// live bit is then cleared and later hits skip it.  A lane (column) first
 // bounds the window from above with cheap arithmetic and reads the peak bits
 // it covers; the rare pairs with a peak bit in range are queued and resolved
 // (exact window, candidate index, fn) a wave at a time, so the exact test
 // does not run with most lanes idle.
+// The live bits are cleared by other lanes during the sweep; a stale bit
+// only means one more member test of a candidate that is dropped anyway.
+__device__ __forceinline__ uint32_t live_bits(SweepShared& S, int cl, int w) {
+  return __hip_atomic_load(&S.lbits[cl][w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 template <typename F>
 __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S, int k, int j0,
-                                              F fn) {
+                                              int h0, int h1, F fn) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x >> 6;
   const int n_phi = A.n_phi;
@@ -412,17 +427,16 @@ __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S
         const uint32_t below = S.cbits[cl][wi] & ((1u << (ic & 31)) - 1u);
         const int q = S.cfirst[cl] + S.cpre[cl][wi] + __popc(below);
         if (q < 0 || q >= np_wg) continue;  // only for peak lists not sorted by cell
-        fn(q, hh, adx);
+        if (fn(q, hh, adx)) atomicAnd(&S.lbits[cl][wi], ~(1u << (ic & 31)));
       }
     }
     head += nproc;
   };
-  const int n_hits = hits_of(A);
-  for (int base = wave * kWave; base < n_hits; base += kSweepThreads) {
+  for (int base = h0 + wave * kWave; base < h1; base += kSweepThreads) {
     const int h = base + lane;
     float hr = 1.0f, hp = 0.0f;
     bool hv = false;
-    if (h < n_hits) {
+    if (h < h1) {
       hr = A.r[h];
       hp = A.phi[h];
       hv = hit_ok(hr, hp) && A.layer[h] < HT_MAX_LAYERS;
@@ -462,7 +476,8 @@ __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S
           iw0 = ilo < 0 ? ilo + n_phi : (ilo >= n_phi ? ilo - n_phi : ilo);
           const int w0 = iw0 >> 5;
           const int w1 = w0 + 1 == nwords ? 0 : w0 + 1;
-          const uint64_t two = (uint64_t)S.cbits[lane][w0] | ((uint64_t)S.cbits[lane][w1] << 32);
+          const uint64_t two = (uint64_t)live_bits(S, lane, w0) |
+                               ((uint64_t)live_bits(S, lane, w1) << 32);
           bits = (uint32_t)((two >> (iw0 & 31)) & ((1ull << len) - 1ull));
         } else {
           slow = true;
@@ -495,7 +510,7 @@ __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S
           int span = 32 - bit;
           span = min(span, ihi - i + 1);
           span = min(span, n_phi - iw);
-          uint32_t wbits = S.cbits[lane][wi] >> bit;
+          uint32_t wbits = live_bits(S, lane, wi) >> bit;
           if (span < 32) wbits &= (1u << span) - 1u;
           while (wbits) {
             const int b = __builtin_ctz(wbits);
@@ -507,7 +522,7 @@ __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S
             const uint32_t below = S.cbits[lane][wi] & ((1u << (bit + b)) - 1u);
             const int q = cfirst + S.cpre[lane][wi] + __popc(below);
             if (q < 0 || q >= np_wg) continue;  // only for peak lists not sorted by cell
-            fn(q, hh, adx);
+            if (fn(q, hh, adx)) atomicAnd(&S.lbits[lane][wi], ~(1u << (ic & 31)));
           }
           i += span;
         }
@@ -517,19 +532,17 @@ __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S
   while (tail > head) drain(min(kWave, tail - head));
 }
 
-// adds the (candidate, member) pairs of the wave's candidates within
-// member_cap (each <= member_cap) to the 64-bit device total
-__device__ __forceinline__ void wg_add_pairs(const AssocArgs& A, int pairs) {
-  unsigned long long v = (unsigned long long)pairs;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  if ((threadIdx.x & (kWave - 1)) == 0 && v)
-    atomicAdd(reinterpret_cast<unsigned long long*>(A.sc + S_PAIRS), v);
-}
-
 __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
   __shared__ SweepShared S;
   const int j0 = blockIdx.x * kWave;
   const int k = blockIdx.y;
+  // this workgroup's slice of the hits (gridDim.z slices, see hit_slices)
+  const int n_all = hits_of(A);
+  const int n_slices = gridDim.z;
+  const int chunk = ((n_all + n_slices - 1) / n_slices + kWave - 1) / kWave * kWave;
+  const int h0 = (int)blockIdx.z * chunk;
+  const int h1 = min(n_all, h0 + chunk);
+  if (h0 >= h1) return;
   const int n_phi = A.n_phi;
   const int nwords = (n_phi + 31) >> 5;
   const int cap = A.cfg.member_cap;
@@ -549,6 +562,7 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
       if (nb < 32) v &= (1u << nb) - 1u;
     }
     S.cbits[cl][w] = v;
+    S.lbits[cl][w] = v;
   }
   __syncthreads();
   if (threadIdx.x < kWave) {
@@ -584,35 +598,25 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
   }
   __syncthreads();
   uint2* pool = A.pool + (size_t)p_lo * cap;
-  if (np_wg <= kMaxWgPeaks) {
+  if (gridDim.z == 1 && np_wg <= kMaxWgPeaks) {
     for (int q = threadIdx.x; q < np_wg; q += kSweepThreads) S.cnt[q] = 0;
     __syncthreads();
-    sweep_members(A, S, k, j0, [&](int q, int hh, float adx) {
+    sweep_members(A, S, k, j0, h0, h1, [&](int q, int hh, float adx) {
       const int slot = atomicAdd(&S.cnt[q], 1);
       if (slot < cap) pool[(size_t)q * cap + slot] = make_uint2((unsigned)hh, __float_as_uint(adx));
+      return slot == cap;
     });
     __syncthreads();
-    int pairs = 0;
-    for (int q = threadIdx.x; q < np_wg; q += kSweepThreads) {
-      const int c = S.cnt[q];
-      A.mcount[p_lo + q] = c;
-      pairs += c <= cap ? c : 0;
-    }
-    wg_add_pairs(A, pairs);
+    for (int q = threadIdx.x; q < np_wg; q += kSweepThreads) A.mcount[p_lo + q] = S.cnt[q];
   } else {
-    // counters in global memory (zeroed by mark_kernel)
+    // counters in global memory (zeroed by mark_kernel), shared by the hit
+    // slices; each slice drops a candidate at its first member past the cap
     int32_t* cnt = A.mcount + p_lo;
-    sweep_members(A, S, k, j0, [&](int q, int hh, float adx) {
+    sweep_members(A, S, k, j0, h0, h1, [&](int q, int hh, float adx) {
       const int slot = atomicAdd(&cnt[q], 1);
       if (slot < cap) pool[(size_t)q * cap + slot] = make_uint2((unsigned)hh, __float_as_uint(adx));
+      return slot >= cap;
     });
-    __syncthreads();
-    int pairs = 0;
-    for (int q = threadIdx.x; q < np_wg; q += kSweepThreads) {
-      const int c = atomicAdd(&cnt[q], 0);  // read back at the device scope
-      pairs += c <= cap ? c : 0;
-    }
-    wg_add_pairs(A, pairs);
   }
 }
 
@@ -759,6 +763,14 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
   const ht_cluster_cfg& cfg = A.cfg;
   const int cap = cfg.member_cap;
   const double road = (double)cfg.road_sigmas * (double)cfg.sigma_rphi;
+  // the wave's rarely changed totals (candidates over member_cap, member
+  // pairs) stay in its LDS slot, kept by lane 0, rather than in registers
+  // live across the whole search
+  __shared__ unsigned long long tot[W][4];
+  if (lane == 0) {
+    tot[wave][2] = 0;
+    tot[wave][3] = 0;
+  }
   unsigned long long tests = 0, ncand = 0;
   for (int p = blockIdx.x * W + wave; p < np; p += gridDim.x * W) {
     const int lin = A.peaks[p].lin;
@@ -768,9 +780,10 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
       continue;
     }
     if (n > cap) {
-      if (lane == 0) { A.cstat[p] = -2; A.cnl[p] = 0; atomicAdd(&A.sc[S_NOVER], 1); }
+      if (lane == 0) { A.cstat[p] = -2; A.cnl[p] = 0; tot[wave][2] += 1; }
       continue;
     }
+    if (lane == 0) tot[wave][3] += (unsigned long long)n;
     const int col = lin / A.n_phi;
     const int j = col % A.n_qpt;
     const int k = col / A.n_qpt;
@@ -1018,10 +1031,18 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
     }
     wave_sync();
   }
+  // the workgroup's totals, one atomic per counter from lanes 0-3 of wave 0
   if (lane == 0) {
-    const int slot = (blockIdx.x * W + wave) & (kSpread - 1);
-    if (tests) atomicAdd(&A.spread[(size_t)(SP_TESTS + slot) * kSpreadStride], tests);
-    if (ncand) atomicAdd(&A.spread[(size_t)(SP_NCAND + slot) * kSpreadStride], ncand);
+    tot[wave][0] = tests;
+    tot[wave][1] = ncand;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    unsigned long long v = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) v += tot[w][threadIdx.x];
+    const int slot = blockIdx.x & (kSpread - 1);
+    if (v) atomicAdd(&A.spread[(size_t)(threadIdx.x * kSpread + slot) * kSpreadStride], v);
   }
 }
 
@@ -1550,17 +1571,20 @@ __global__ __launch_bounds__(kWave) void counts_kernel(AssocArgs A) {
   const int lane = threadIdx.x;
   unsigned long long ncand = A.spread[(size_t)(SP_NCAND + lane) * kSpreadStride];
   unsigned long long tests = A.spread[(size_t)(SP_TESTS + lane) * kSpreadStride];
+  unsigned long long nover = A.spread[(size_t)(SP_NOVER + lane) * kSpreadStride];
+  unsigned long long pairs = A.spread[(size_t)(SP_PAIRS + lane) * kSpreadStride];
   for (int off = kWave / 2; off > 0; off >>= 1) {
     ncand += __shfl_xor(ncand, off);
     tests += __shfl_xor(tests, off);
+    nover += __shfl_xor(nover, off);
+    pairs += __shfl_xor(pairs, off);
   }
   if (lane != 0) return;
   c[0] = (int32_t)ncand;
   c[1] = A.sc[S_NTRK];
   c[2] = A.sc[S_NOBJ];
   c[3] = A.sc[S_NMEM];
-  c[4] = A.sc[S_NOVER];
-  const unsigned long long pairs = *reinterpret_cast<const unsigned long long*>(A.sc + S_PAIRS);
+  c[4] = (int32_t)nover;
   c[5] = pairs > 0x7fffffffull ? 0x7fffffff : (int32_t)pairs;
   c[6] = tests > 0x7fffffffull ? 0x7fffffff : (int32_t)tests;
   c[7] = 0;
@@ -1647,7 +1671,8 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   HT_CHECK(hipGetLastError());
   mark_kernel<<<blocks_for(peak_cap, 256), 256, 0, s>>>(A);
   HT_CHECK(hipGetLastError());
-  dim3 sweep((g.n_qpt + kWave - 1) / kWave, g.n_d0);
+  const int col_tiles = (g.n_qpt + kWave - 1) / kWave;
+  dim3 sweep(col_tiles, g.n_d0, hit_slices(col_tiles * g.n_d0, n_hits));
   P.prof_mark(HT_STAGE_MEMBERS, 0, s);
   member_kernel<<<sweep, kSweepThreads, 0, s>>>(A);
   HT_CHECK(hipGetLastError());

@@ -11,7 +11,9 @@
 // Same gfx950 mapping as the point vote: a workgroup owns 64 q/pT columns of
 // one d0 plane in LDS (lane = column), waves split the hits and broadcast
 // them through SGPRs.  A hit adds one LDS atomic per bin of its band, about
-// four per column on the displaced-jet grid.
+// four per column on the displaced-jet grid.  Grids with few tiles also split
+// the hits into slices that add their tiles into a cleared accumulator, as
+// the point vote does.
 #include "ht_internal.h"
 
 namespace ht {
@@ -41,12 +43,17 @@ __device__ __forceinline__ void add_vote(uint32_t* col, int i) {
 
 template <bool WIDE>
 __global__ __launch_bounds__(kCellThreads) void cell_vote_kernel(
-    const float* __restrict__ r, const float* __restrict__ phi, int n_hits,
+    const float* __restrict__ r, const float* __restrict__ phi, int n_all,
     const float* __restrict__ kl, const float* __restrict__ kh, const float* __restrict__ ql,
     const float* __restrict__ tl, const float* __restrict__ qh, const float* __restrict__ th,
     int n_phi, int n_qpt, float phi_lo, float invw, int stride, int32_t* __restrict__ acc,
     unsigned long long* __restrict__ n_votes) {
   extern __shared__ uint32_t lds[];
+  const int n_slices = gridDim.z;
+  const int chunk = ((n_all + n_slices - 1) / n_slices + kWave - 1) / kWave * kWave;
+  const int h0 = (int)blockIdx.z * chunk;
+  const int n_hits = min(n_all, h0 + chunk);
+  if (n_slices > 1 && h0 >= n_hits) return;  // an empty slice adds nothing
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x >> 6;
   const int j0 = blockIdx.x * kWave;
@@ -69,7 +76,7 @@ __global__ __launch_bounds__(kCellThreads) void cell_vote_kernel(
 
   uint32_t* col = lds + lane * stride;
   unsigned long long votes = 0;
-  for (int base = wave * kWave; base < n_hits; base += kCellThreads) {
+  for (int base = h0 + wave * kWave; base < n_hits; base += kCellThreads) {
     const int h = base + lane;
     float hr = 1.0f, hp = 0.0f;
     bool hv = false;
@@ -123,12 +130,17 @@ __global__ __launch_bounds__(kCellThreads) void cell_vote_kernel(
   for (int e = threadIdx.x; e < total; e += kCellThreads) {
     const int cj = e / n_phi;
     const int i = e - cj * n_phi;
+    int32_t v;
     if (WIDE) {
-      out[e] = (int32_t)lds[cj * stride + i];
+      v = (int32_t)lds[cj * stride + i];
     } else {
       const uint32_t w = lds[cj * stride + (i >> 1)];
-      out[e] = (int32_t)((i & 1) ? (w >> 16) : (w & 0xFFFFu));
+      v = (int32_t)((i & 1) ? (w >> 16) : (w & 0xFFFFu));
     }
+    if (n_slices == 1)
+      out[e] = v;
+    else if (v)
+      atomicAdd(&out[e], v);
   }
 
   if (n_votes) {
@@ -139,6 +151,12 @@ __global__ __launch_bounds__(kCellThreads) void cell_vote_kernel(
 }
 
 __global__ void zero_u64(unsigned long long* p) { *p = 0ull; }
+
+__global__ void zero_i32(int32_t* __restrict__ p, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = 0;
+}
 
 }  // namespace
 
@@ -159,7 +177,15 @@ int launch_cell_vote(const Plan& p, const float* r, const float* phi, int32_t n_
     zero_u64<<<1, 1, 0, s>>>(n_votes);
     HT_CHECK(hipGetLastError());
   }
-  dim3 grid((g.n_qpt + kWave - 1) / kWave, g.n_d0);
+  const int tiles = (g.n_qpt + kWave - 1) / kWave * g.n_d0;
+  const int slices = hit_slices(tiles, n_hits);
+  dim3 grid((g.n_qpt + kWave - 1) / kWave, g.n_d0, slices);
+  if (slices > 1) {
+    const int64_t cells = p.n_cells;
+    const int64_t blocks = (cells + 1023) / 1024 < 1024 ? (cells + 1023) / 1024 : 1024;
+    zero_i32<<<(unsigned)blocks, 256, 0, s>>>(acc, cells);
+    HT_CHECK(hipGetLastError());
+  }
   auto kern = cell_wide(g.n_phi) ? cell_vote_kernel<true> : cell_vote_kernel<false>;
   p.prof_mark(HT_STAGE_VOTE, 0, s);
   kern<<<grid, kCellThreads, lds_bytes, s>>>(r, phi, n_hits, p.d_ckl, p.d_ckh, p.d_cql, p.d_ctl,

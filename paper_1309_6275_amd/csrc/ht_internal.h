@@ -11,6 +11,21 @@
 
 namespace ht {
 
+// four groups of 64 counters, one 128-byte line each (the seed search's totals)
+constexpr int kSpreadWords = 4 * 64 * 16;
+
+// Hit slices for launches of one workgroup per 64-column tile: grids with
+// fewer than 128 tiles also split the hits, so that about 256 workgroups run,
+// with slices of at least 1024 hits of the bound the buffers were checked
+// for (the kernels divide the hit count they read at run time).
+inline int hit_slices(int tiles, int n_hits_bound) {
+  if (tiles >= 128 || n_hits_bound < 2048) return 1;
+  int n = (256 + tiles - 1) / tiles;
+  const int by_hits = n_hits_bound / 1024;
+  n = n < by_hits ? n : by_hits;
+  return n > 1 ? n : 1;
+}
+
 // Per-plan state.  Tables are float32 bin-centre constants computed in
 // float64 on the host and rounded once.
 struct Plan {
@@ -60,7 +75,7 @@ struct Plan {
   int32_t* d_obj_cnt;    // [max_vertex_cells] member count per object
   int32_t* d_obj_off;    // [max_vertex_cells] member offset per object
   int32_t* d_scalars;    // [16] device counters
-  unsigned long long* d_spread;  // [2 * 64 * 16] counters spread over 128-byte lines
+  unsigned long long* d_spread;  // [kSpreadWords] counters spread over 128-byte lines
   // stage timing (ht_profile_*): HIP events recorded around the stages of
   // later calls; plan calls are ordered, so the counters need no locking
   mutable int32_t prof_depth;          // 0: off

@@ -139,7 +139,7 @@ int64_t plan_bytes(const ht_server_cfg& c, const ht_server_kind& k) {
   b += nh * (3 * 8 + 16 + 8);
   b += np * (4 + 4 + 4 + 40 + 64) + (np / 256 + 16) * 8;
   b += np * (int64_t)k.cluster.member_cap * 8;
-  b += (int64_t)c.track_cap * (4 + 8 * k.cluster.n_rho) + vcells * 12 + 64 + 2 * 64 * 16 * 8;
+  b += (int64_t)c.track_cap * (4 + 8 * k.cluster.n_rho) + vcells * 12 + 64 + (int64_t)ht::kSpreadWords * 8;
   return b;
 }
 

@@ -15,6 +15,13 @@
 // operands plus one LDS atomic.  The tile is written to HBM once, by
 // contiguous stores, so no clearing pass is needed.  No MFMA: the vote is a
 // scatter, not a contraction.
+//
+// Grids with few tiles (the 2D grid has four) would leave most CUs idle, so
+// there the hits are also split into slices (gridDim.z): each workgroup votes
+// one slice of the hits into its LDS tile and adds the non-zero counters into
+// the accumulator, cleared beforehand, with integer atomics (exact in any
+// order).  The slices divide the hit count read at run time, so an event of
+// any size spreads over the whole chip.
 #include "ht_internal.h"
 
 namespace ht {
@@ -36,7 +43,12 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
   extern __shared__ uint32_t lds[];
   // hits of this event: the device count when given (clamped to the bound the
   // buffers were checked for), else the host count
-  const int n_hits = n_hits_dev ? min(max(*n_hits_dev, 0), n_hits_max) : n_hits_max;
+  const int n_all = n_hits_dev ? min(max(*n_hits_dev, 0), n_hits_max) : n_hits_max;
+  const int n_slices = gridDim.z;
+  const int chunk = ((n_all + n_slices - 1) / n_slices + kWave - 1) / kWave * kWave;
+  const int h0 = (int)blockIdx.z * chunk;
+  const int n_hits = min(n_all, h0 + chunk);
+  if (n_slices > 1 && h0 >= n_hits) return;  // an empty slice adds nothing
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x >> 6;
   const int j0 = blockIdx.x * kWave;
@@ -55,7 +67,7 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
 
   uint32_t* col = lds + lane * stride;
   uint32_t votes = 0;
-  for (int base = wave * kWave; base < n_hits; base += kVoteThreads) {
+  for (int base = h0 + wave * kWave; base < n_hits; base += kVoteThreads) {
     const int h = base + lane;
     float hr = 1.0f, hp = 0.0f;
     bool hv = false;
@@ -109,12 +121,17 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
   for (int e = threadIdx.x; e < total; e += kVoteThreads) {
     const int cj = e / n_phi;
     const int i = e - cj * n_phi;
+    int32_t v;
     if (WIDE) {
-      out[e] = (int32_t)lds[cj * stride + i];
+      v = (int32_t)lds[cj * stride + i];
     } else {
       const uint32_t w = lds[cj * stride + (i >> 1)];
-      out[e] = (int32_t)((i & 1) ? (w >> 16) : (w & 0xFFFFu));
+      v = (int32_t)((i & 1) ? (w >> 16) : (w & 0xFFFFu));
     }
+    if (n_slices == 1)
+      out[e] = v;
+    else if (v)
+      atomicAdd(&out[e], v);
   }
 
   if (n_votes) {
@@ -135,6 +152,12 @@ __global__ void sqrt_kernel(const double* __restrict__ x, double* __restrict__ o
 }
 
 __global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
+
+__global__ void zero_i32_kernel(int32_t* __restrict__ p, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = 0;
+}
 
 constexpr int kLdsBytes = 160 * 1024;
 bool vote_wide(int n_phi) { return (size_t)kWave * (size_t)(n_phi | 1) * 4 <= (size_t)kLdsBytes; }
@@ -164,7 +187,17 @@ int launch_vote(const Plan& p, const float* r, const float* phi, int32_t n_hits,
     zero_u64_kernel<<<1, 1, 0, s>>>(n_votes);
     HT_CHECK(hipGetLastError());
   }
-  dim3 grid((g.n_qpt + kWave - 1) / kWave, g.n_d0);
+  const int tiles = (g.n_qpt + kWave - 1) / kWave * g.n_d0;
+  const int slices = hit_slices(tiles, n_hits);
+  dim3 grid((g.n_qpt + kWave - 1) / kWave, g.n_d0, slices);
+  if (slices > 1) {
+    // the slices add into the accumulator: clear it first (a kernel, so the
+    // sequence can be captured in a graph)
+    const int64_t cells = p.n_cells;
+    const int64_t blocks = (cells + 1023) / 1024 < 1024 ? (cells + 1023) / 1024 : 1024;
+    zero_i32_kernel<<<(unsigned)blocks, 256, 0, s>>>(acc, cells);
+    HT_CHECK(hipGetLastError());
+  }
   const bool pow2 = (g.n_phi & (g.n_phi - 1)) == 0;
   const bool wide = vote_wide(g.n_phi);
   auto kern = pow2 ? (wide ? vote_kernel<true, true> : vote_kernel<true, false>)
