@@ -231,11 +231,24 @@ int hough_peaks(const ht_plan* plan, const int32_t* acc, int32_t min_votes, ht_p
  *                  peak_cap) are ignored; entries with lin outside the grid
  *                  are no candidates; any other list gives unspecified
  *                  results (memory accesses stay in bounds)
+ *   acc            NULL, or the accumulator hough_vote (or hough_vote_n)
+ *                  wrote for these hits with this plan (device, read only).
+ *                  Results are the same either way; with it, a candidate
+ *                  whose member count provably exceeds member_cap is dropped
+ *                  before the member search: every valid hit with a layer
+ *                  below HT_MAX_LAYERS that votes within win_bins bins of
+ *                  the cell in its column is a member, so the votes of those
+ *                  2 win_bins + 1 cells, less the valid hits of higher
+ *                  layers, bound the count from below.  Used on grids with
+ *                  a d0 axis (half d0 width >= 1e-20 cm) and
+ *                  n_phi >= 4 (win_bins + 1); ignored otherwise.  Any other
+ *                  accumulator (the band vote's included) gives unspecified
+ *                  results.
  *   out            outputs (device pointers) */
 int assoc_cluster(const ht_plan* plan, const float* r, const float* phi, const uint8_t* layer,
                   int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks,
-                  int32_t peak_cap, const ht_cluster_cfg* cfg, const ht_cluster_out* out,
-                  void* stream);
+                  int32_t peak_cap, const int32_t* acc, const ht_cluster_cfg* cfg,
+                  const ht_cluster_out* out, void* stream);
 
 /* hough_vote_n, assoc_cluster_n -- hough_vote and assoc_cluster with the
  * event's hit count read on the device from *n_hits_dev (clamped to
@@ -249,8 +262,8 @@ int hough_vote_n(const ht_plan* plan, const float* r, const float* phi, int32_t 
                  void* stream);
 int assoc_cluster_n(const ht_plan* plan, const float* r, const float* phi, const uint8_t* layer,
                     int32_t n_hits_max, const int32_t* n_hits_dev, const ht_peak* peaks,
-                    const int32_t* n_peaks, int32_t peak_cap, const ht_cluster_cfg* cfg,
-                    const ht_cluster_out* out, void* stream);
+                    const int32_t* n_peaks, int32_t peak_cap, const int32_t* acc,
+                    const ht_cluster_cfg* cfg, const ht_cluster_out* out, void* stream);
 
 /* Iterative hit removal (paper, section "Current Tracker and Tracking
  * Algorithm": earlier passes find the easier, prompt tracks, whose hits are

@@ -282,7 +282,8 @@ int hough_peaks(const ht_plan* p, const int32_t* acc, int32_t min_votes, ht_peak
 
 int assoc_cluster(const ht_plan* p, const float* r, const float* phi, const uint8_t* layer,
                   int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks, int32_t peak_cap,
-                  const ht_cluster_cfg* cfg, const ht_cluster_out* out, void* stream) {
+                  const int32_t* acc, const ht_cluster_cfg* cfg, const ht_cluster_out* out,
+                  void* stream) {
   if (!p || !cfg || !out || !n_peaks || n_hits < 0 || peak_cap < 0) return HT_EINVAL;
   if (n_hits > 0 && (!r || !phi || !layer || !out->hit_owner)) return HT_EINVAL;
   if (peak_cap > 0 && !peaks) return HT_EINVAL;
@@ -293,7 +294,7 @@ int assoc_cluster(const ht_plan* p, const float* r, const float* phi, const uint
     return HT_EINVAL;
   const int rc = ht::check_cluster(*p, *cfg, n_hits, peak_cap, out->track_cap);
   if (rc != HT_OK) return rc;
-  return ht::launch_assoc(*p, r, phi, layer, n_hits, peaks, n_peaks, peak_cap, *cfg, *out,
+  return ht::launch_assoc(*p, r, phi, layer, n_hits, peaks, n_peaks, peak_cap, acc, *cfg, *out,
                           (hipStream_t)stream);
 }
 
@@ -320,8 +321,8 @@ int ht_remap_track_hits(ht_track* tracks, int32_t track_cap, const int32_t* coun
 
 int assoc_cluster_n(const ht_plan* p, const float* r, const float* phi, const uint8_t* layer,
                     int32_t n_hits_max, const int32_t* n_hits_dev, const ht_peak* peaks,
-                    const int32_t* n_peaks, int32_t peak_cap, const ht_cluster_cfg* cfg,
-                    const ht_cluster_out* out, void* stream) {
+                    const int32_t* n_peaks, int32_t peak_cap, const int32_t* acc,
+                    const ht_cluster_cfg* cfg, const ht_cluster_out* out, void* stream) {
   if (!n_hits_dev) return HT_EINVAL;
   if (!p || !cfg || !out || !n_peaks || n_hits_max < 0 || peak_cap < 0) return HT_EINVAL;
   if (n_hits_max > 0 && (!r || !phi || !layer || !out->hit_owner)) return HT_EINVAL;
@@ -333,8 +334,8 @@ int assoc_cluster_n(const ht_plan* p, const float* r, const float* phi, const ui
     return HT_EINVAL;
   const int rc = ht::check_cluster(*p, *cfg, n_hits_max, peak_cap, out->track_cap);
   if (rc != HT_OK) return rc;
-  return ht::launch_assoc(*p, r, phi, layer, n_hits_max, peaks, n_peaks, peak_cap, *cfg, *out,
-                          (hipStream_t)stream, n_hits_dev);
+  return ht::launch_assoc(*p, r, phi, layer, n_hits_max, peaks, n_peaks, peak_cap, acc, *cfg,
+                          *out, (hipStream_t)stream, n_hits_dev);
 }
 
 int ht_asin_f32(const float* u, float* out, int64_t n, void* stream) {

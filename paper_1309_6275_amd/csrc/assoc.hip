@@ -47,7 +47,8 @@ constexpr int kSweepThreads = kSweepWaves * kWave;
 constexpr int kMaxMembers = 1024; // largest member_cap (LDS slots per wave in refine)
 constexpr int kGridCap = 8192;    // grid-stride launches use at most this many blocks
 
-enum { S_NP = 0, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5 };
+// S_NBAD: valid hits whose layer is HT_MAX_LAYERS or more (they vote but are no members)
+enum { S_NP = 0, S_NBAD = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5 };
 // The seed search's totals (road tests, refined candidates, candidates over
 // member_cap, (candidate, member) pairs within it) are summed per workgroup
 // and added to kSpread counters in separate 128-byte lines, chosen by
@@ -254,6 +255,8 @@ struct AssocArgs {
   double* hy;
   double* hq;
   float4* hitB;  // x, y, x^2+y^2 (float32), layer
+  // the point-vote accumulator of these hits, or null (no member-count bound)
+  const int32_t* acc;
   // peaks
   const ht_peak* peaks;
   const int32_t* n_peaks;
@@ -322,6 +325,11 @@ __global__ void init_kernel(AssocArgs A, int words) {
 }
 
 __global__ void mark_kernel(AssocArgs A) {
+  if (A.acc) {
+    const int n_hits = hits_of(A);
+    for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < n_hits; h += gridDim.x * blockDim.x)
+      if (A.layer[h] >= HT_MAX_LAYERS && hit_ok(A.r[h], A.phi[h])) atomicAdd(&A.sc[S_NBAD], 1);
+  }
   const int np = n_cands(A);
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
     A.mcount[p] = 0;
@@ -532,6 +540,54 @@ __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S
   while (tail > head) drain(min(kWave, tail - head));
 }
 
+// Candidates that provably hold more than member_cap members are dropped
+// before the sweep (their member count is set past the cap and their live
+// bit cleared).  Every valid hit with a layer below HT_MAX_LAYERS that votes
+// in one of the 2 win_bins + 1 cells around the candidate in its column is a
+// member: its |x - cell centre| is at most win_bins + 0.5 (float rounding is
+// monotone and the interval ends are exact), and the member window is never
+// narrower (0.5 + win_bins plus a term that is positive on grids with a d0
+// axis).  So those cells' votes, less the valid hits of higher layers, bound
+// the member count from below.
+__device__ void drop_overfull(const AssocArgs& A, SweepShared& S, int k, int j0, int32_t* cnt_lds,
+                              int32_t* cnt_glob) {
+  const int n_phi = A.n_phi;
+  const int nwords = (n_phi + 31) >> 5;
+  const int b = A.cfg.win_bins;
+  const int cap = A.cfg.member_cap;
+  const long long lim = (long long)cap + A.sc[S_NBAD];
+  const int np_wg = S.np_wg;
+  for (int e = threadIdx.x; e < kWave * nwords; e += kSweepThreads) {
+    const int cl = e / nwords, w = e - cl * nwords;
+    const int j = j0 + cl;
+    const uint32_t bits = S.cbits[cl][w];
+    if (j >= A.n_qpt || !bits) continue;
+    const int32_t* row = A.acc + ((size_t)k * A.n_qpt + j) * n_phi;
+    const int q0 = S.cfirst[cl] + S.cpre[cl][w];
+    uint32_t rest = bits;
+    int rank = 0;
+    while (rest) {
+      const int bit = __builtin_ctz(rest);
+      rest &= rest - 1u;
+      const int ic = w * 32 + bit;
+      long long sum = 0;
+      for (int d = -b; d <= b; ++d) {
+        int ii = ic + d;  // |d| < n_phi / 4: one period of correction
+        ii = ii < 0 ? ii + n_phi : (ii >= n_phi ? ii - n_phi : ii);
+        sum += row[ii];
+      }
+      const int q = q0 + rank;
+      ++rank;
+      if (sum <= lim || q < 0 || q >= np_wg) continue;
+      atomicAnd(&S.lbits[cl][w], ~(1u << bit));
+      if (cnt_lds)
+        cnt_lds[q] = cap + 1;
+      else
+        atomicMax(&cnt_glob[q], cap + 1);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
   __shared__ SweepShared S;
   const int j0 = blockIdx.x * kWave;
@@ -598,9 +654,16 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
   }
   __syncthreads();
   uint2* pool = A.pool + (size_t)p_lo * cap;
-  if (gridDim.z == 1 && np_wg <= kMaxWgPeaks) {
+  const bool lds_cnt = gridDim.z == 1 && np_wg <= kMaxWgPeaks;
+  if (lds_cnt) {
     for (int q = threadIdx.x; q < np_wg; q += kSweepThreads) S.cnt[q] = 0;
     __syncthreads();
+  }
+  if (A.acc) {
+    drop_overfull(A, S, k, j0, lds_cnt ? S.cnt : nullptr, A.mcount + p_lo);
+    __syncthreads();
+  }
+  if (lds_cnt) {
     sweep_members(A, S, k, j0, h0, h1, [&](int q, int hh, float adx) {
       const int slot = atomicAdd(&S.cnt[q], 1);
       if (slot < cap) pool[(size_t)q * cap + slot] = make_uint2((unsigned)hh, __float_as_uint(adx));
@@ -1608,8 +1671,8 @@ void launch_refine(const AssocArgs& A, int peak_cap, hipStream_t s) {
 
 int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t* layer,
                  int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks, int32_t peak_cap,
-                 const ht_cluster_cfg& cfg, const ht_cluster_out& out, hipStream_t s,
-                 const int32_t* n_hits_dev) {
+                 const int32_t* acc, const ht_cluster_cfg& cfg, const ht_cluster_out& out,
+                 hipStream_t s, const int32_t* n_hits_dev) {
   const ht_grid& g = P.grid;
   AssocArgs A;
   A.n_phi = g.n_phi;
@@ -1639,6 +1702,10 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   A.hy = P.d_hy;
   A.hq = P.d_hq;
   A.hitB = P.d_hitB;
+  // the member-count bound needs a window of at least 0.5 + win_bins bins
+  // (a d0 axis keeps its extra term positive) and distinct neighbour cells
+  A.acc = (acc && A.hd0 >= 1e-20f && (int64_t)g.n_phi >= 4 * ((int64_t)cfg.win_bins + 1)) ? acc
+                                                                                        : nullptr;
   A.peaks = peaks;
   A.n_peaks = n_peaks;
   A.peak_cap = peak_cap;

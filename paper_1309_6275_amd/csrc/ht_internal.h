@@ -107,8 +107,8 @@ int launch_peaks(const Plan& p, const int32_t* acc, int32_t min_votes, ht_peak* 
                  int32_t capacity, int32_t* n_found, hipStream_t s);
 int launch_assoc(const Plan& p, const float* r, const float* phi, const uint8_t* layer,
                  int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks, int32_t peak_cap,
-                 const ht_cluster_cfg& cfg, const ht_cluster_out& out, hipStream_t s,
-                 const int32_t* n_hits_dev = nullptr);
+                 const int32_t* acc, const ht_cluster_cfg& cfg, const ht_cluster_out& out,
+                 hipStream_t s, const int32_t* n_hits_dev = nullptr);
 int launch_asin(const float* u, float* out, int64_t n, hipStream_t s);
 int launch_sqrt(const double* x, double* out, int64_t n, hipStream_t s);
 int launch_scan(const int32_t* cnt, int32_t* off, int n, int32_t* total, hipStream_t s);

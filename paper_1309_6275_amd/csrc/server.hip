@@ -186,7 +186,7 @@ int device_part(const ht_server_cfg& c, Slot& s, int k) {
   o.vacc = nullptr;
   o.counts = s.d_counts;
   rc = ht::launch_assoc(P, s.d_r, s.d_phi, s.d_layer, c.max_hits, s.d_peaks, s.d_npeaks,
-                        K.peak_cap, K.cluster, o, s.stream, s.d_nhits);
+                        K.peak_cap, s.d_acc, K.cluster, o, s.stream, s.d_nhits);
   if (rc != HT_OK) return rc;
   const hipMemcpyKind d2h = hipMemcpyDeviceToHost;
   HT_CHECK(hipMemcpyAsync(s.h_out->counts, s.d_counts, 8 * sizeof(int32_t), d2h, s.stream));

@@ -118,20 +118,20 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
   const int ncol = min(kWave, n_qpt - j0);
   int32_t* out = acc + ((size_t)k * n_qpt + j0) * n_phi;
   const int total = ncol * n_phi;
-  for (int e = threadIdx.x; e < total; e += kVoteThreads) {
+  auto tile = [&](int e) {
     const int cj = e / n_phi;
     const int i = e - cj * n_phi;
-    int32_t v;
-    if (WIDE) {
-      v = (int32_t)lds[cj * stride + i];
-    } else {
-      const uint32_t w = lds[cj * stride + (i >> 1)];
-      v = (int32_t)((i & 1) ? (w >> 16) : (w & 0xFFFFu));
+    if (WIDE) return (int32_t)lds[cj * stride + i];
+    const uint32_t w = lds[cj * stride + (i >> 1)];
+    return (int32_t)((i & 1) ? (w >> 16) : (w & 0xFFFFu));
+  };
+  if (n_slices == 1) {
+    for (int e = threadIdx.x; e < total; e += kVoteThreads) out[e] = tile(e);
+  } else {
+    for (int e = threadIdx.x; e < total; e += kVoteThreads) {
+      const int32_t v = tile(e);
+      if (v) atomicAdd(&out[e], v);
     }
-    if (n_slices == 1)
-      out[e] = v;
-    else if (v)
-      atomicAdd(&out[e], v);
   }
 
   if (n_votes) {

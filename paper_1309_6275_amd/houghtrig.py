@@ -115,9 +115,9 @@ def lib():
         L.hough_vote.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.hough_vote_cell.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.hough_vote_n.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
-        L.assoc_cluster_n.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, i32, vp, vp, vp]
+        L.assoc_cluster_n.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, i32, vp, vp, vp, vp]
         L.hough_peaks.argtypes = [vp, vp, i32, vp, i32, vp, vp]
-        L.assoc_cluster.argtypes = [vp, vp, vp, vp, i32, vp, vp, i32, vp, vp, vp]
+        L.assoc_cluster.argtypes = [vp, vp, vp, vp, i32, vp, vp, i32, vp, vp, vp, vp]
         L.ht_asin_f32.argtypes = [vp, vp, i64, vp]
         L.ht_compact_hits.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.ht_remap_track_hits.argtypes = [vp, i32, vp, vp, i32, vp]
@@ -341,9 +341,19 @@ def remap_track_hits(bufs: "ClusterBuffers", index, stream=None):
            "ht_remap_track_hits")
 
 
+def _acc_ptr(plan: Plan, acc):
+    if acc is None:
+        return None
+    if tuple(acc.shape) != plan.acc_shape:
+        raise ValueError("shape mismatch")
+    return _ptr(acc, _torch().int32, "acc")
+
+
 def assoc_cluster(plan: Plan, r, phi, layer, peaks, n_peaks, cfg: dict, bufs: ClusterBuffers,
-                  with_vacc=True, stream=None):
-    """peaks: int32 [cap, 2] from hough_peaks; n_peaks: int32 [1] device."""
+                  with_vacc=True, stream=None, acc=None):
+    """peaks: int32 [cap, 2] from hough_peaks; n_peaks: int32 [1] device;
+    acc: optionally the hough_vote accumulator of these hits (candidates it
+    proves to exceed member_cap skip the member search; same results)."""
     torch = _torch()
     n = int(r.numel())
     if phi.numel() != n or layer.numel() != n:
@@ -355,7 +365,7 @@ def assoc_cluster(plan: Plan, r, phi, layer, peaks, n_peaks, cfg: dict, bufs: Cl
                                _ptr(layer, torch.uint8, "layer"), n,
                                _ptr(peaks, torch.int32, "peaks"),
                                _ptr(n_peaks, torch.int32, "n_peaks"), int(peaks.shape[0]),
-                               C.byref(c), C.byref(o), _stream(stream)),
+                               _acc_ptr(plan, acc), C.byref(c), C.byref(o), _stream(stream)),
            "assoc_cluster")
 
 
@@ -375,7 +385,7 @@ def hough_vote_n(plan: Plan, r, phi, n_hits_dev, acc, n_votes=None, stream=None)
 
 
 def assoc_cluster_n(plan: Plan, r, phi, layer, n_hits_dev, peaks, n_peaks, cfg: dict,
-                    bufs: ClusterBuffers, with_vacc=True, stream=None):
+                    bufs: ClusterBuffers, with_vacc=True, stream=None, acc=None):
     """assoc_cluster with the hit count read on the device from n_hits_dev."""
     torch = _torch()
     n = int(r.numel())
@@ -389,7 +399,7 @@ def assoc_cluster_n(plan: Plan, r, phi, layer, n_hits_dev, peaks, n_peaks, cfg: 
                                  _ptr(n_hits_dev, torch.int32, "n_hits_dev"),
                                  _ptr(peaks, torch.int32, "peaks"),
                                  _ptr(n_peaks, torch.int32, "n_peaks"), int(peaks.shape[0]),
-                                 C.byref(c), C.byref(o), _stream(stream)),
+                                 _acc_ptr(plan, acc), C.byref(c), C.byref(o), _stream(stream)),
            "assoc_cluster_n")
 
 

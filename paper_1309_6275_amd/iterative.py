@@ -63,7 +63,7 @@ class TwoPass:
         H.hough_peaks(self.plan_d, self.acc_d, D["min_votes"], self.pk_d, self.nf[1:2])
         H.assoc_cluster_n(self.plan_d, self.r2[:n], self.phi2[:n], self.layer2[:n], self.n_keep,
                           self.pk_d, self.nf[1:2], D["cluster"], self.bufs_d,
-                          with_vacc=with_vacc)
+                          with_vacc=with_vacc, acc=self.acc_d)
         H.remap_track_hits(self.bufs_d, self.keep[:n])
 
     def to_host(self, n_hits):

@@ -47,7 +47,9 @@ def plan_for(ht, grid, member_cap=1024):
 
 
 def run_gpu(torch, ht, grid, ev, min_votes, cfg, peak_cap=None, track_cap=4096,
-            object_cap=512, member_cap=1 << 15, with_vacc=True):
+            object_cap=512, member_cap=1 << 15, with_vacc=True, use_acc=True):
+    """Vote, peaks and assoc_cluster on the device; assoc_cluster gets the
+    accumulator (member-count bound) unless use_acc is False."""
     plan = plan_for(ht, grid)
     r = torch.from_numpy(ev.r).cuda()
     phi = torch.from_numpy(ev.phi).cuda()
@@ -60,7 +62,8 @@ def run_gpu(torch, ht, grid, ev, min_votes, cfg, peak_cap=None, track_cap=4096,
     ht.hough_peaks(plan, acc, min_votes, peaks[:cap], nf)
     bufs = ht.ClusterBuffers(max(ev.n_hits, 1), track_cap, object_cap, member_cap,
                              cfg["n_rho"], cfg["n_theta"])
-    ht.assoc_cluster(plan, r, phi, layer, peaks[:cap], nf, cfg, bufs, with_vacc=with_vacc)
+    ht.assoc_cluster(plan, r, phi, layer, peaks[:cap], nf, cfg, bufs, with_vacc=with_vacc,
+                     acc=acc if use_acc else None)
     torch.cuda.synchronize()
     got = bufs.to_host(ev.n_hits)
     return got, acc.cpu().numpy(), peaks[:min(int(nf.item()), cap)].cpu().numpy()

@@ -170,3 +170,120 @@ def test_sliced_cell_vote_parity(torch, ht, oracle, gi, n_hits):
     want, nv_w = oracle.hough_vote_cell(g, r, phi)
     assert int(nv.item()) == nv_w
     _same(acc.cpu().numpy(), want)
+
+
+def _same_outputs(a, b, label):
+    """Every output of two device runs is identical (the accumulator only
+    lets assoc_cluster skip work)."""
+    for key in ("counts", "hit_owner", "vacc", "members"):
+        assert np.array_equal(a[key], b[key]), (label, key)
+    for key in ("tracks", "objects"):
+        assert a[key].shape == b[key].shape, (label, key)
+        for f in a[key].dtype.names:
+            assert np.array_equal(a[key][f], b[key][f]), (label, key, f)
+
+
+def _three_cell_votes(acc, lin, n_phi):
+    flat = acc.reshape(-1, n_phi)
+    cols, i = lin // n_phi, lin % n_phi
+    return flat[cols, (i - 1) % n_phi] + flat[cols, i] + flat[cols, (i + 1) % n_phi]
+
+
+def test_member_bound_dense_event_truncated_peaks(torch, ht, oracle):
+    """The 55k-hit workload with member_cap 128 and its first 3000 peaks:
+    the accumulator bound drops most candidates before the member search;
+    the outputs equal the oracle's and those of the run without the bound."""
+    W = CF.WORKLOADS[3]
+    ev = G.make_event(3, W["seed0"] + 1)
+    cfg = dict(W["cluster"], member_cap=128)
+    print(f"bound cfg3 hits {ev.n_hits}", flush=True)
+    got, acc, pk = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], cfg, peak_cap=3000)
+    plain, _, _ = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], cfg, peak_cap=3000,
+                          use_acc=False)
+    _same_outputs(got, plain, "bound vs none")
+    want = run_oracle(oracle, W["grid"], ev, acc, pk, cfg)
+    compare(got, want, "bound cfg3/3000")
+    fired = int((_three_cell_votes(acc, pk[:, 0], W["grid"]["n_phi"]) > 128).sum())
+    assert fired > pk.shape[0] // 2
+    assert want["counts"][4] >= fired
+
+
+def test_member_bound_few_hits_beyond_the_layer_range(torch, ht, oracle):
+    """A 20k-hit event in which 10 hits carry layer 20 (they vote but are no
+    members): the bound, less those 10, still drops candidates."""
+    W = CF.WORKLOADS[2]
+    ev = G.make_serving_event(1, 8400, h_lo=20000, h_hi=20001)
+    layer = ev.layer.copy()
+    layer[::2000] = 20
+    ev2 = SimpleNamespace(r=ev.r, phi=ev.phi, layer=layer, n_hits=ev.n_hits)
+    cfg = dict(W["cluster"], member_cap=48)
+    print(f"bound few bad layers hits {ev.n_hits}", flush=True)
+    got, acc, pk = run_gpu(torch, ht, W["grid"], ev2, W["min_votes"], cfg, peak_cap=2000)
+    plain, _, _ = run_gpu(torch, ht, W["grid"], ev2, W["min_votes"], cfg, peak_cap=2000,
+                          use_acc=False)
+    _same_outputs(got, plain, "few bad layers")
+    want = run_oracle(oracle, W["grid"], ev2, acc, pk, cfg)
+    compare(got, want, "few bad layers")
+    n_bad = int((layer >= 16).sum())
+    assert (_three_cell_votes(acc, pk[:, 0], W["grid"]["n_phi"]) - n_bad > 48).sum() > 0
+
+
+def test_member_bound_pile_of_hits_beyond_the_layer_range(torch, ht, oracle):
+    """300 identical hits with layer 20 over 2000 random hits: every column
+    gets a cell of 300 votes that holds few members.  Without subtracting
+    the high-layer hits the bound would drop those candidates."""
+    W = CF.WORKLOADS[2]
+    r, phi, layer = G.random_hits(2000, seed=88, r_lo=3.0, r_hi=105.0, bad_fraction=0.0)
+    r = np.concatenate([r, np.full(300, 50.0, np.float32)])
+    phi = np.concatenate([phi, np.full(300, 0.25, np.float32)])
+    layer = np.concatenate([layer, np.full(300, 20, np.uint8)])
+    ev = SimpleNamespace(r=r, phi=phi, layer=layer, n_hits=int(r.size))
+    cfg = dict(W["cluster"], member_cap=256)
+    print(f"bound pile hits {ev.n_hits}", flush=True)
+    got, acc, pk = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], cfg)
+    plain, _, _ = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], cfg, use_acc=False)
+    _same_outputs(got, plain, "pile")
+    want = run_oracle(oracle, W["grid"], ev, acc, pk, cfg)
+    compare(got, want, "pile")
+    naive = int((_three_cell_votes(acc, pk[:, 0], W["grid"]["n_phi"]) > 256).sum())
+    assert naive > 1000 and want["counts"][4] < naive
+
+
+@pytest.mark.parametrize("cap", [8, 40])
+def test_member_bound_small_caps(torch, ht, oracle, cap):
+    """The displaced-jet workload with small member caps, with and without
+    the accumulator."""
+    W = CF.WORKLOADS[2]
+    ev = G.make_event(2, W["seed0"] + 22)
+    cfg = dict(W["cluster"], member_cap=cap)
+    print(f"bound member_cap {cap}", flush=True)
+    got, acc, pk = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], cfg)
+    plain, _, _ = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], cfg, use_acc=False)
+    _same_outputs(got, plain, f"cap {cap}")
+    want = run_oracle(oracle, W["grid"], ev, acc, pk, cfg)
+    compare(got, want, f"bound cap {cap}")
+
+
+def test_member_bound_off_on_the_prompt_grid(torch, ht):
+    """On the one-plane prompt grid the window's extra term can vanish, so
+    the accumulator is ignored; results are those without it."""
+    W = CF.WORKLOADS[1]
+    ev = G.make_serving_event(0, 8500, h_lo=30000, h_hi=30001)
+    got, _, _ = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], W["cluster"])
+    plain, _, _ = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], W["cluster"],
+                          use_acc=False)
+    _same_outputs(got, plain, "prompt grid")
+
+
+def test_assoc_rejects_accumulator_of_wrong_shape(torch, ht):
+    W = CF.WORKLOADS[2]
+    plan = plan_for(ht, W["grid"])
+    cl = W["cluster"]
+    r = torch.ones(8, dtype=torch.float32, device="cuda")
+    layer = torch.zeros(8, dtype=torch.uint8, device="cuda")
+    peaks = torch.zeros((4, 2), dtype=torch.int32, device="cuda")
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    bufs = ht.ClusterBuffers(8, 16, 4, 16, cl["n_rho"], cl["n_theta"])
+    bad = torch.zeros((2, 2), dtype=torch.int32, device="cuda")
+    with pytest.raises(ValueError):
+        ht.assoc_cluster(plan, r, r, layer, peaks, nf, cl, bufs, acc=bad)
