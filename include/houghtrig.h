@@ -372,7 +372,13 @@ int ht_cnn_keep(const ht_plan* plan, const float* logits, const ht_peak* peaks,
  * every event (the hit count travels in device memory).  The number of slots
  * is the largest that fits hbm_budget (at most max_slots); events that find
  * every slot busy wait in a FIFO of queue_cap; beyond it ht_server_submit
- * returns HT_EBUSY (the event is shed).  Results are exactly those of the
+ * returns HT_EBUSY (the event is shed).  With a work budget, the events in
+ * flight share the device by their work (hits times the q/pT x d0 columns
+ * of their kind): a waiting event starts, in FIFO order, when a slot is
+ * free and the work in flight plus its own stays within work_budget, or
+ * when nothing else runs (an event too large for the budget runs alone).
+ * Large events then run one after another, each at the speed of the whole
+ * device, while small ones overlap.  Results are exactly those of the
  * three calls made one by one for the same event.  Single-threaded: one
  * thread calls submit and poll.  Host pointers throughout. */
 #define HT_SERVER_MAX_KINDS 4
@@ -395,6 +401,7 @@ typedef struct {
   int32_t max_slots;       /* concurrent events at most, >= 1 */
   int32_t queue_cap;       /* events waiting for a slot at most, >= 0 */
   int32_t use_graphs;      /* 1: replay a captured HIP graph per slot and kind */
+  int64_t work_budget;     /* hit-columns in flight at most, 0: no limit */
 } ht_server_cfg;
 
 /* Where the results of one event go (host memory, any pointer may be NULL;

@@ -15,8 +15,10 @@
 // Host side: submit copies the hits into the slot's pinned input (or, when
 // every slot is busy, into a FIFO entry), poll finds finished slots by
 // querying their markers, copies the results out and starts the next queued
-// event on the freed slot.  Admission: the slot count is the largest that
-// fits the HBM budget; the FIFO is bounded, and beyond it events are shed.
+// events on free slots.  Admission: the slot count is the largest that fits
+// the HBM budget; an optional work budget bounds the hit-columns in flight
+// (strict FIFO, an event runs alone when nothing else does); the FIFO is
+// bounded, and beyond it events are shed.
 #include <string.h>
 #include <time.h>
 
@@ -28,7 +30,7 @@
 
 // layouts the Python binding mirrors
 static_assert(sizeof(ht_server_kind) == 112, "ht_server_kind layout");
-static_assert(sizeof(ht_server_cfg) == 496, "ht_server_cfg layout");
+static_assert(sizeof(ht_server_cfg) == 504, "ht_server_cfg layout");
 static_assert(sizeof(ht_server_out) == 56, "ht_server_out layout");
 static_assert(sizeof(ht_server_result) == 88, "ht_server_result layout");
 
@@ -87,6 +89,7 @@ struct Slot {
   int32_t* h_members = nullptr;
   // state
   bool busy = false;
+  int64_t work = 0;  // hit-columns of the running event
   Job job;
   double t_start = 0.0;
   int status = HT_OK;
@@ -99,6 +102,7 @@ struct ht_server {
   std::vector<Slot> slots;
   std::deque<Job> queue;
   int64_t slot_bytes = 0;
+  int64_t in_flight = 0;  // hit-columns of the running events
 };
 
 namespace {
@@ -338,10 +342,35 @@ void finish(const ht_server_cfg& c, Slot& s, ht_server_result* res) {
   s.busy = false;
 }
 
+// an event's work: hits times the columns of its kind's grid
+int64_t job_work(const ht_server_cfg& c, const Job& j) {
+  const ht_grid& g = c.kinds[j.kind].grid;
+  return (int64_t)j.n_hits * g.n_qpt * g.n_d0;
+}
+
+// whether an event of work w may start now (a slot being free aside)
+bool fits(const ht_server* srv, int64_t w) {
+  const int64_t b = srv->cfg.work_budget;
+  return b <= 0 || srv->in_flight == 0 || srv->in_flight + w <= b;
+}
+
+Slot* free_slot_of(ht_server* srv) {
+  for (Slot& s : srv->slots)
+    if (!s.busy) return &s;
+  return nullptr;
+}
+
+void run(ht_server* srv, Slot& s, Job&& j) {
+  s.work = job_work(srv->cfg, j);
+  srv->in_flight += s.work;
+  start(srv->cfg, s, std::move(j));
+}
+
 bool cfg_ok(const ht_server_cfg& c) {
   if (c.n_kinds < 1 || c.n_kinds > HT_SERVER_MAX_KINDS) return false;
   if (c.max_hits < 1 || c.max_hits > 65535 || c.track_cap < 0 || c.object_cap < 0 ||
-      c.member_cap < 0 || c.max_slots < 1 || c.queue_cap < 0 || c.hbm_budget <= 0)
+      c.member_cap < 0 || c.max_slots < 1 || c.queue_cap < 0 || c.hbm_budget <= 0 ||
+      c.work_budget < 0)
     return false;
   for (int k = 0; k < c.n_kinds; ++k)
     if (c.kinds[k].peak_cap < 1) return false;
@@ -414,10 +443,10 @@ int ht_server_submit(ht_server* srv, int32_t kind, const float* r, const float* 
   j.tag = tag;
   if (out) j.out = *out;
   j.t_submit = now_s();
-  for (Slot& s : srv->slots) {
-    if (!s.busy && srv->queue.empty()) {
-      stage_inputs(s, r, phi, layer, n_hits);
-      start(srv->cfg, s, std::move(j));
+  if (srv->queue.empty() && fits(srv, job_work(srv->cfg, j))) {
+    if (Slot* s = free_slot_of(srv)) {
+      stage_inputs(*s, r, phi, layer, n_hits);
+      run(srv, *s, std::move(j));
       return HT_OK;
     }
   }
@@ -443,15 +472,21 @@ int ht_server_poll(ht_server* srv, ht_server_result* results, int32_t max, int32
       if (q == hipErrorNotReady) continue;
       if (q != hipSuccess) s.status = HT_EDEVICE;
       finish(srv->cfg, s, &results[(*n_results)++]);
-      if (!srv->queue.empty()) {
-        Job j = std::move(srv->queue.front());
-        srv->queue.pop_front();
-        stage_inputs(s, j.r.data(), j.phi.data(), j.layer.data(), j.n_hits);
-        j.r.clear();
-        j.phi.clear();
-        j.layer.clear();
-        start(srv->cfg, s, std::move(j));
-      }
+      srv->in_flight -= s.work;
+      s.work = 0;
+    }
+    // start waiting events in FIFO order while a slot and the budget allow
+    while (!srv->queue.empty() && fits(srv, job_work(srv->cfg, srv->queue.front()))) {
+      Slot* s = free_slot_of(srv);
+      if (!s) break;
+      Job j = std::move(srv->queue.front());
+      srv->queue.pop_front();
+      stage_inputs(*s, j.r.data(), j.phi.data(), j.layer.data(), j.n_hits);
+      j.r.clear();
+      j.phi.clear();
+      j.layer.clear();
+      run(srv, *s, std::move(j));
+      pending = true;
     }
     if (!wait || *n_results > 0 || !pending || *n_results >= max) break;
   }

@@ -80,7 +80,7 @@ class ServerCfg(C.Structure):
     _fields_ = [("n_kinds", C.c_int32), ("kinds", ServerKind * SERVER_MAX_KINDS),
                 ("max_hits", C.c_int32), ("track_cap", C.c_int32), ("object_cap", C.c_int32),
                 ("member_cap", C.c_int32), ("hbm_budget", C.c_int64), ("max_slots", C.c_int32),
-                ("queue_cap", C.c_int32), ("use_graphs", C.c_int32)]
+                ("queue_cap", C.c_int32), ("use_graphs", C.c_int32), ("work_budget", C.c_int64)]
 
 
 class ServerOut(C.Structure):
@@ -505,7 +505,8 @@ class Server:
     grid, cluster, min_votes, peak_cap."""
 
     def __init__(self, kinds, max_hits=65535, track_cap=4096, object_cap=256, member_cap=4096,
-                 hbm_budget=64 << 30, max_slots=4, queue_cap=256, use_graphs=True):
+                 hbm_budget=64 << 30, max_slots=4, queue_cap=256, use_graphs=True,
+                 work_budget=0):
         if not 1 <= len(kinds) <= SERVER_MAX_KINDS:
             raise ValueError("1..4 kinds")
         _torch()  # a GPU must be there
@@ -520,6 +521,7 @@ class Server:
         cfg.object_cap, cfg.member_cap = int(object_cap), int(member_cap)
         cfg.hbm_budget, cfg.max_slots = int(hbm_budget), int(max_slots)
         cfg.queue_cap, cfg.use_graphs = int(queue_cap), int(bool(use_graphs))
+        cfg.work_budget = int(work_budget)
         self.cfg = cfg
         h = C.c_void_p()
         _check(lib().ht_server_create(C.byref(cfg), C.byref(h)), "ht_server_create")

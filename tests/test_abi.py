@@ -52,7 +52,7 @@ def test_struct_sizes_match_header_layout():
     assert H.OBJECT_DTYPE.itemsize == 8 * 4
     # serving loop structs (static_asserts on the C side hold the same sizes)
     assert ctypes.sizeof(H.ServerKind) == 112
-    assert ctypes.sizeof(H.ServerCfg) == 496
+    assert ctypes.sizeof(H.ServerCfg) == 504
     assert ctypes.sizeof(H.ServerOut) == 56
     assert ctypes.sizeof(H.ServerResult) == 88
 

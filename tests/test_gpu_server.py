@@ -149,3 +149,38 @@ def test_server_admission_and_shedding(ht):
     with pytest.raises(ht.HoughError) as e:
         ht.Server(KINDS, **dict(args, hbm_budget=per_slot // 4))
     assert e.value.code == ht.HT_ENOMEM
+
+
+def test_server_work_budget(ht, oracle):
+    """With a work budget of one 3D event of 8192 hits (hits x q/pT x d0
+    columns), 3D events of 5000-8192 hits run one after another: an event
+    starts only once the one before has been seen done.  Small 2D events
+    still overlap.  Results equal the plain server's and the oracle's."""
+    g3 = KINDS[1]["grid"]
+    budget = 8192 * g3["n_qpt"] * g3["n_d0"]
+    heavy = []
+    for i, n in enumerate([8192, 5000, 7000, 6000]):
+        r, phi, layer = G.random_hits(n, seed=3000 + i, r_lo=3.0, r_hi=105.0)
+        heavy.append((1, SimpleNamespace(r=r, phi=phi, layer=layer, n_hits=n)))
+    light = [(0, G.make_event(1, CF.WORKLOADS[1]["seed0"] + 60 + i)) for i in range(6)]
+    budgeted = ht.Server(KINDS, work_budget=budget, **SERVER_ARGS)
+    plain = ht.Server(KINDS, **SERVER_ARGS)
+    got_h = run_all(budgeted, heavy)
+    ref_h = run_all(plain, heavy)
+    spans = sorted((d["t_start"], d["t_done"]) for d in got_h.values())
+    for (s0, e0), (s1, e1) in zip(spans, spans[1:]):
+        assert s1 >= e0  # no two heavy events in flight together
+    got_l = run_all(budgeted, light, tag0=100)
+    spans = sorted((d["t_start"], d["t_done"]) for d in got_l.values())
+    assert any(s1 < e0 for (s0, e0), (s1, e1) in zip(spans, spans[1:]))  # light ones overlap
+    for t, d in got_h.items():
+        for key in ("counts", "hit_owner", "tracks", "objects", "members"):
+            assert d[key].tobytes() == ref_h[t][key].tobytes(), (t, key)
+    kind, ev = light[2]
+    want = dict(oracle_result(oracle, kind, ev), vacc=np.zeros(1, np.int32))
+    compare(as_got(got_l[102]), want, "budgeted light event")
+    budgeted.close()
+    plain.close()
+    with pytest.raises(ht.HoughError) as e:
+        ht.Server(KINDS, work_budget=-1, **SERVER_ARGS)
+    assert e.value.code == ht.HT_EINVAL
