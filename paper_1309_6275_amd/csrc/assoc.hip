@@ -375,6 +375,12 @@ struct SweepShared {
   uint32_t qbits[kSweepWaves][kQueue];
   uint32_t qmeta[kSweepWaves][kQueue];
   int32_t np_wg, p_lo;
+  // per (distinct hit radius, column): arcsine (NaN when |u| > 1), u, and
+  // the upper bound of the member window
+  RadiusSet R;
+  float s_tab[kMaxRadii][kWave];
+  float u_tab[kMaxRadii][kWave];
+  float whi_tab[kMaxRadii][kWave];
 };
 
 // One pass over the workgroup's (hit, column) pairs; for every member
@@ -408,6 +414,20 @@ __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S
   }
   const int cfirst = S.cfirst[lane];
   const float wbase = 0.5f + (float)A.cfg.win_bins;
+  // the per-radius tables (whole workgroup); thread t fills entry (t / 64, lane)
+  radius_set_build(S.R, A.r, A.phi, h0, h1);
+  for (int t = threadIdx.x; t < S.R.n * kWave; t += kSweepThreads) {
+    const float rv = S.R.r[t >> 6];
+    const float ir = 1.0f / rv;
+    float x = 0.0f, u = 0.0f;
+    const bool ok = col_ok && phi0_coord(rv * rv, ir, 0.0f, ck, cq, ct, A.phi_lo, A.invw, &x, &u);
+    const float e5 = member_e5(rv, ir, A.hd0, A.hk, A.invw);
+    const float gg = 1.0f - u * u;
+    S.s_tab[t >> 6][lane] = ok ? asin_f(u) : __builtin_nanf("");
+    S.u_tab[t >> 6][lane] = u;
+    S.whi_tab[t >> 6][lane] = wbase + e5 * 1.5f * __builtin_amdgcn_rsqf(gg) * 1.001f;
+  }
+  __syncthreads();
   const int np_wg = S.np_wg;
   const int nwords = (n_phi + 31) >> 5;
   const bool fast_bits = (n_phi & 31) == 0;
@@ -452,12 +472,12 @@ __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S
     const float hr2 = hr * hr;
     const float hir = 1.0f / hr;
     const float he5 = member_e5(hr, hir, A.hd0, A.hk, A.invw);
+    const int hri = hv ? radius_index(S.R, hr) : -1;
     uint64_t todo = __ballot(hv);
     while (todo) {
       const int src = __builtin_ctzll(todo);
       todo &= todo - 1;
-      const float r2 = bcastf(hr2, src);
-      const float ir = bcastf(hir, src);
+      const int ri = __builtin_amdgcn_readlane(hri, src);
       const float ph = bcastf(hp, src);
       const float e5 = bcastf(he5, src);
       const int hh = base + src;
@@ -465,11 +485,29 @@ __device__ __forceinline__ void sweep_members(const AssocArgs& A, SweepShared& S
       uint32_t bits = 0u;
       int iw0 = 0, ilo = 0, ihi = -1;
       bool slow = false;
-      if (has && phi0_coord(r2, ir, ph, ck, cq, ct, A.phi_lo, A.invw, &x, &u)) {
-        // upper bound of the window with the hardware reciprocal square root
-        // (1 ulp) and a 0.1% margin
-        const float gg = 1.0f - u * u;
-        const float w_hi = wbase + e5 * 1.5f * __builtin_amdgcn_rsqf(gg) * 1.001f;
+      bool valid = false;
+      float w_hi = 0.0f;
+      if (has) {
+        if (ri >= 0) {
+          // the same operations as phi0_coord, the radius part from the table
+          const float s = S.s_tab[ri][lane];
+          valid = s == s;
+          if (valid) {
+            u = S.u_tab[ri][lane];
+            x = ((ph - s) - A.phi_lo) * A.invw;
+            w_hi = S.whi_tab[ri][lane];
+          }
+        } else {
+          const float r2 = bcastf(hr2, src);
+          const float ir = bcastf(hir, src);
+          valid = phi0_coord(r2, ir, ph, ck, cq, ct, A.phi_lo, A.invw, &x, &u);
+          // upper bound of the window with the hardware reciprocal square
+          // root (1 ulp) and a 0.1% margin
+          const float gg = 1.0f - u * u;
+          w_hi = wbase + e5 * 1.5f * __builtin_amdgcn_rsqf(gg) * 1.001f;
+        }
+      }
+      if (valid) {
         ilo = 0;
         ihi = n_phi - 1;
         if (w_hi < 0.5f * (float)n_phi) {

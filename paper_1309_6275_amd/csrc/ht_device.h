@@ -85,4 +85,80 @@ __device__ __forceinline__ float asin_f(float u) {
   return copysignf(r, u);
 }
 
+// ---- distinct hit radii -------------------------------------------------------
+// The hits of a barrel layer share one radius, so u = ((kappa r^2 + Q) / r) T,
+// its arcsine and everything else that depends only on (r, column) can be
+// computed once per distinct radius and column instead of once per hit.  A
+// workgroup collects the distinct radii of its valid hits in an LDS hash set
+// (kRadSlots slots, linear probing, insertion by compare-and-swap); the first
+// kMaxRadii of them in slot order get an index.  Hits whose radius has no
+// index take the per-hit path.  The values computed per radius come from the
+// same operations on the same operands as the per-hit ones, so both paths
+// give identical bits.
+constexpr int kRadSlots = 64;  // one slot per lane of a wave
+constexpr int kMaxRadii = 16;
+constexpr uint32_t kRadEmpty = 0xffffffffu;  // a NaN pattern, never a valid radius
+
+struct RadiusSet {
+  uint32_t key[kRadSlots];  // float bits of a radius, or kRadEmpty
+  int32_t idx[kRadSlots];   // its index, or -1
+  float r[kMaxRadii];
+  int32_t n;
+};
+
+__device__ __forceinline__ uint32_t rad_hash(uint32_t k) { return (k * 2654435761u) >> 26; }
+
+// Whole workgroup, over the hits [h0, h1); starts and ends with a barrier.
+__device__ inline void radius_set_build(RadiusSet& R, const float* __restrict__ r,
+                                        const float* __restrict__ phi, int h0, int h1) {
+  static_assert(kRadSlots == kWave, "one hash slot per lane");
+  __syncthreads();
+  for (int t = threadIdx.x; t < kRadSlots; t += blockDim.x) R.key[t] = kRadEmpty;
+  __syncthreads();
+  uint32_t last = kRadEmpty;
+  for (int h = h0 + (int)threadIdx.x; h < h1; h += blockDim.x) {
+    const float rv = r[h];
+    if (!hit_ok(rv, phi[h])) continue;
+    const uint32_t k = __float_as_uint(rv);
+    if (k == last) continue;
+    last = k;
+    uint32_t slot = rad_hash(k);
+    for (int p = 0; p < kRadSlots; ++p) {
+      const uint32_t v =
+          __hip_atomic_load(&R.key[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (v == k) break;
+      if (v == kRadEmpty) {
+        const uint32_t old = atomicCAS(&R.key[slot], kRadEmpty, k);
+        if (old == kRadEmpty || old == k) break;
+      }
+      slot = (slot + 1) & (kRadSlots - 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    const bool full = R.key[lane] != kRadEmpty;
+    const uint64_t m = __ballot(full);
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    const int id = (full && rank < kMaxRadii) ? rank : -1;
+    R.idx[lane] = id;
+    if (id >= 0) R.r[id] = __uint_as_float(R.key[lane]);
+    if (lane == 0) R.n = __popcll(m) < kMaxRadii ? __popcll(m) : kMaxRadii;
+  }
+  __syncthreads();
+}
+
+// index of radius rv in the set, or -1
+__device__ __forceinline__ int radius_index(const RadiusSet& R, float rv) {
+  const uint32_t k = __float_as_uint(rv);
+  uint32_t slot = rad_hash(k);
+  for (int p = 0; p < kRadSlots; ++p) {
+    const uint32_t v = R.key[slot];
+    if (v == k) return R.idx[slot];
+    if (v == kRadEmpty) return -1;
+    slot = (slot + 1) & (kRadSlots - 1);
+  }
+  return -1;
+}
+
 }  // namespace ht

@@ -12,7 +12,11 @@
 // the workgroup split the hits: each wave loads 64 hits with one coalesced
 // load, keeps them in VGPRs and broadcasts them one at a time through SGPRs
 // (v_readlane), so the per-evaluation work is pure VALU with scalar hit
-// operands plus one LDS atomic.  The tile is written to HBM once, by
+// operands plus one LDS atomic.  The arcsine and the |u| <= 1 test depend on
+// the hit only through its radius: the workgroup first collects the distinct
+// radii of its hits (the layers of a barrel tracker) and computes them once
+// per radius and column into an LDS table, so a hit on a known radius costs
+// one table read, three operations, the wrap and the atomic.  The tile is written to HBM once, by
 // contiguous stores, so no clearing pass is needed.  No MFMA: the vote is a
 // scatter, not a contraction.
 //
@@ -41,6 +45,8 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
     int n_phi, int n_qpt, float phi_lo, float invw, int stride, int32_t* __restrict__ acc,
     unsigned long long* __restrict__ n_votes) {
   extern __shared__ uint32_t lds[];
+  __shared__ RadiusSet R;
+  __shared__ float s_tab[kMaxRadii][kWave];  // arcsine per (radius, column), NaN: no vote
   // hits of this event: the device count when given (clamped to the bound the
   // buffers were checked for), else the host count
   const int n_all = n_hits_dev ? min(max(*n_hits_dev, 0), n_hits_max) : n_hits_max;
@@ -63,6 +69,19 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
     cq = qt[(size_t)k * n_qpt + j];
     ct = tt[(size_t)k * n_qpt + j];
   }
+  radius_set_build(R, r, phi, h0, n_hits);
+  // thread t fills entry (t / 64, lane): its own column
+  for (int t = threadIdx.x; t < R.n * kWave; t += kVoteThreads) {
+    const float rv = R.r[t >> 6];
+    const float r2 = rv * rv;
+    const float ir = 1.0f / rv;
+    const float a = ck * r2;
+    const float b = a + cq;
+    const float c = b * ir;
+    const float u = c * ct;
+    const bool ok = col_ok && (fabsf(u) <= 1.0f);
+    s_tab[t >> 6][lane] = ok ? asin_f(u) : __builtin_nanf("");
+  }
   __syncthreads();
 
   uint32_t* col = lds + lane * stride;
@@ -78,19 +97,28 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
     }
     const float hr2 = hr * hr;
     const float hir = 1.0f / hr;
+    const int hri = hv ? radius_index(R, hr) : -1;
     uint64_t todo = __ballot(hv);
     while (todo) {
       const int src = __builtin_ctzll(todo);
       todo &= todo - 1;
-      const float r2 = bcast(hr2, src);
-      const float ir = bcast(hir, src);
+      const int ri = __builtin_amdgcn_readlane(hri, src);
       const float ph = bcast(hp, src);
-      const float a = ck * r2;
-      const float b = a + cq;
-      const float c = b * ir;
-      const float u = c * ct;
-      const bool ok = col_ok && (fabsf(u) <= 1.0f);
-      const float s = asin_f(u);
+      bool ok;
+      float s;
+      if (ri >= 0) {
+        s = s_tab[ri][lane];
+        ok = s == s;
+      } else {
+        const float r2 = bcast(hr2, src);
+        const float ir = bcast(hir, src);
+        const float a = ck * r2;
+        const float b = a + cq;
+        const float c = b * ir;
+        const float u = c * ct;
+        ok = col_ok && (fabsf(u) <= 1.0f);
+        s = asin_f(u);
+      }
       const float phi0 = ph - s;
       const float d = phi0 - phi_lo;
       const float x = d * invw;
@@ -159,7 +187,8 @@ __global__ void zero_i32_kernel(int32_t* __restrict__ p, int64_t n) {
     p[e] = 0;
 }
 
-constexpr int kLdsBytes = 160 * 1024;
+// LDS of a CU less the kernel's static arrays (radius set and table)
+constexpr int kLdsBytes = 160 * 1024 - (int)sizeof(RadiusSet) - kMaxRadii * kWave * 4;
 bool vote_wide(int n_phi) { return (size_t)kWave * (size_t)(n_phi | 1) * 4 <= (size_t)kLdsBytes; }
 int vote_stride(int n_phi) {
   const int words = vote_wide(n_phi) ? n_phi : (n_phi + 1) / 2;
