@@ -83,6 +83,11 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
     s_tab[t >> 6][lane] = ok ? asin_f(u) : __builtin_nanf("");
   }
   __syncthreads();
+  // the lane's column of the table in registers, indexed by the
+  // wave-uniform radius index (no LDS round trip per hit)
+  float sreg[kMaxRadii];
+#pragma unroll
+  for (int a = 0; a < kMaxRadii; ++a) sreg[a] = a < R.n ? s_tab[a][lane] : __builtin_nanf("");
 
   uint32_t* col = lds + lane * stride;
   uint32_t votes = 0;
@@ -107,7 +112,7 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
       bool ok;
       float s;
       if (ri >= 0) {
-        s = s_tab[ri][lane];
+        s = sreg[ri];
         ok = s == s;
       } else {
         const float r2 = bcast(hr2, src);

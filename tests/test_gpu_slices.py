@@ -287,3 +287,29 @@ def test_assoc_rejects_accumulator_of_wrong_shape(torch, ht):
     bad = torch.zeros((2, 2), dtype=torch.int32, device="cuda")
     with pytest.raises(ValueError):
         ht.assoc_cluster(plan, r, r, layer, peaks, nf, cl, bufs, acc=bad)
+
+
+@pytest.mark.parametrize("n_radii", [1, 10, 16, 17, 40, 70])
+def test_radius_table_mixed_paths(torch, ht, oracle, n_radii):
+    """Hits on n_radii distinct radii (the vote and member sweep compute the
+    arcsine once per radius for at most 16 of them, per hit for the rest,
+    and keep at most 64 in their hash set): accumulator, vote total and
+    assoc_cluster outputs equal the oracle's."""
+    W = CF.WORKLOADS[2]
+    rng = np.random.default_rng(700 + n_radii)
+    radii = np.sort(rng.uniform(3.0, 105.0, n_radii)).astype(np.float32)
+    n = 3000
+    which = rng.integers(0, n_radii, n)
+    r = radii[which]
+    phi = rng.uniform(-np.pi, np.pi, n).astype(np.float32)
+    layer = np.minimum(np.searchsorted(radii, r), 15).astype(np.uint8)
+    ev = SimpleNamespace(r=r, phi=phi, layer=layer, n_hits=n)
+    print(f"radii {n_radii}", flush=True)
+    acc_d, nv = gpu_vote(torch, ht, W["grid"], r, phi)
+    want, nv_w = oracle.hough_vote(W["grid"], r, phi)
+    assert nv == nv_w
+    _same(acc_d.cpu().numpy(), want)
+    cfg = dict(W["cluster"], min_layers=4, member_cap=256)
+    got, acc, pk = run_gpu(torch, ht, W["grid"], ev, 4, cfg, peak_cap=4000)
+    want = run_oracle(oracle, W["grid"], ev, acc, pk, cfg)
+    compare(got, want, f"radii {n_radii}")
