@@ -216,7 +216,7 @@ def serve_bench(args):
         """Poisson rates in increasing order until the p99 passes 50 ms; the
         highest rate with nothing shed and a p99 under 10 ms."""
         out = []
-        for rate in (50, 100, 150, 200, 250, 300, 400, 600):
+        for rate in (50, 100, 150, 200, 250, 300, 350, 400, 600):
             r = replay(srv, rate, args.serve_seconds, pool, min_events=400)
             out.append(r)
             print(json.dumps(r), file=sys.stderr, flush=True)
