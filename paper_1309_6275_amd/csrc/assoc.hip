@@ -753,7 +753,10 @@ struct WaveMem {
   Mem4 mem[CAP];   // grouped by layer
   float adx[CAP];  // |x - cell centre| of the grouped members
   union {
-    RawMembers<CAP> raw;
+    // members in pool order before grouping, staged in LDS for CAP <= 128;
+    // larger caps stage them in registers (LDS, not registers, limits their
+    // occupancy)
+    RawMembers<(CAP <= 128 ? CAP : 1)> raw;
     uint16_t hit[kWave][HT_MAX_LAYERS + 2];  // each lane's inlier per layer, kNoHit if none
   } u;
   int32_t lstart[HT_MAX_LAYERS + 1];
@@ -890,24 +893,53 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
     const int k = col / A.n_qpt;
     const double kapc = A.kapc[j], d0c = A.d0c[k];  // issued early, used by the box check
     const size_t moff = (size_t)p * cap;
-    // load members in pool order
+    constexpr bool kRawLds = CAP <= 128;
+    constexpr int RM = kRawLds ? 1 : CAP / kWave;
+    Mem4 rec[RM];
+    float radx[RM];
+    int rL[RM], rslot[RM];
     unsigned lmask = 0;
     float qmax = 0.0f;
-    for (int m = lane; m < n; m += kWave) {
-      const uint2 pe = A.pool[moff + m];
-      const int h = (int)pe.x;
-      const float4 hb = A.hitB[h];
-      const int L = (int)hb.w;
-      Mem4 rec;
-      rec.x = hb.x;
-      rec.y = hb.y;
-      rec.q = hb.z;
-      rec.h = h;
-      M.u.raw.mem[m] = rec;
-      M.u.raw.adx[m] = __uint_as_float(pe.y);
-      M.u.raw.L[m] = (int8_t)L;
-      lmask |= 1u << L;
-      qmax = fmaxf(qmax, hb.z);
+    if constexpr (kRawLds) {
+      // load members in pool order
+      for (int m = lane; m < n; m += kWave) {
+        const uint2 pe = A.pool[moff + m];
+        const int h = (int)pe.x;
+        const float4 hb = A.hitB[h];
+        const int L = (int)hb.w;
+        Mem4 r4;
+        r4.x = hb.x;
+        r4.y = hb.y;
+        r4.q = hb.z;
+        r4.h = h;
+        M.u.raw.mem[m] = r4;
+        M.u.raw.adx[m] = __uint_as_float(pe.y);
+        M.u.raw.L[m] = (int8_t)L;
+        lmask |= 1u << L;
+        qmax = fmaxf(qmax, hb.z);
+      }
+    } else {
+      // load members in pool order into registers: member lane + 64 t is
+      // entry t of the lane (n <= cap <= CAP)
+#pragma unroll
+      for (int t = 0; t < RM; ++t) {
+        const int m = lane + t * kWave;
+        rL[t] = -1;
+        if (m < n) {
+          const uint2 pe = A.pool[moff + m];
+          const int h = (int)pe.x;
+          const float4 hb = A.hitB[h];
+          const int L = (int)hb.w;
+          rec[t].x = hb.x;
+          rec[t].y = hb.y;
+          rec[t].q = hb.z;
+          rec[t].h = h;
+          radx[t] = __uint_as_float(pe.y);
+          rL[t] = L;
+          lmask |= 1u << L;
+          qmax = fmaxf(qmax, hb.z);
+        }
+      }
     }
     lmask = wave_or(lmask);
     qmax = wave_max_nonneg(qmax);
@@ -922,8 +954,14 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
     // layer does not matter, every selection breaks ties on the hit index)
     if (lane <= HT_MAX_LAYERS) M.lcnt[lane] = 0;
     wave_sync();
-    for (int m = lane; m < n; m += kWave)
-      M.u.raw.slot[m] = (int16_t)atomicAdd(&M.lcnt[M.u.raw.L[m]], 1);
+    if constexpr (kRawLds) {
+      for (int m = lane; m < n; m += kWave)
+        M.u.raw.slot[m] = (int16_t)atomicAdd(&M.lcnt[M.u.raw.L[m]], 1);
+    } else {
+#pragma unroll
+      for (int t = 0; t < RM; ++t)
+        if (rL[t] >= 0) rslot[t] = atomicAdd(&M.lcnt[rL[t]], 1);
+    }
     wave_sync();
     // layer starts: exclusive scan of the 16 layer counts in the first row
     // of lanes; lane 16 holds the total
@@ -936,10 +974,20 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
       if (lane <= HT_MAX_LAYERS) M.lstart[lane] = ls;
     }
     wave_sync();
-    for (int m = lane; m < n; m += kWave) {
-      const int e = M.lstart[M.u.raw.L[m]] + M.u.raw.slot[m];
-      M.mem[e] = M.u.raw.mem[m];
-      M.adx[e] = M.u.raw.adx[m];
+    if constexpr (kRawLds) {
+      for (int m = lane; m < n; m += kWave) {
+        const int e = M.lstart[M.u.raw.L[m]] + M.u.raw.slot[m];
+        M.mem[e] = M.u.raw.mem[m];
+        M.adx[e] = M.u.raw.adx[m];
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < RM; ++t) {
+        if (rL[t] < 0) continue;
+        const int e = M.lstart[rL[t]] + rslot[t];
+        M.mem[e] = rec[t];
+        M.adx[e] = radx[t];
+      }
     }
     wave_sync();
     // seed layers: innermost, middle and outermost of the outer min(nS, min_layers)
