@@ -8,16 +8,21 @@
 //   prep      per hit: float64 Cartesian coordinates (canonical sincos),
 //             ownership keys cleared; counters and the vertex accumulator
 //             zeroed;
-//   mark      peak bitmap and the first peak index of every column;
+//   mark      peak bitmap and the first peak index of every column (and,
+//             with an accumulator, the count of hits beyond the layer
+//             range);
 //   members   a sweep shaped like the vote (workgroup = 64 columns of one
-//             d0, lane = column, hits broadcast through SGPRs) that
-//             re-evaluates each hit's phi0 coordinate and appends it to
-//             every peak of the column whose member window holds it;
+//             d0, lane = column, hits broadcast through SGPRs; grids with
+//             few tiles also split the hits) that re-evaluates each hit's
+//             phi0 coordinate, from per-radius tables where the hit's radius
+//             is shared, and appends it to every peak of the column whose
+//             member window holds it; candidates past member_cap, or proved
+//             past it by the accumulator, leave the sweep;
 //   refine    one wave per candidate: member layers, seed layers, the
 //             seed_k nearest members of each seed layer by rank, then one
 //             seed combination per lane (<= 64) scored against the members
 //             in LDS, smallest non-seed layers first; the best lane wins by
-//             (inliers, sum, index);
+//             (inliers, sum, index); totals go to spread counters;
 //   own       per candidate, 64-bit atomicMax of (inliers, -sum, -index) on
 //             each inlier hit;
 //   survive   ordered compaction of the candidates owning >= min_layers
@@ -30,7 +35,7 @@
 //   vcount,   member counts per object, their scan, then one wave per
 //   vmembers  object: member tracks by ballot, written in order, isotropy
 //             summed in track order;
-//   counts    the output counts.
+//   counts    the output counts (the spread counters summed).
 // Every decision that selects an integer result uses float32 vote
 // arithmetic or float64 arithmetic and square roots in a fixed order, so the
 // results match the CPU reference bit for bit; the refit uses the device
