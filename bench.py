@@ -381,7 +381,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(events are independent: scale by running one process per GPU)", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -68,3 +68,15 @@ def test_no_cpu_fallback_in_binding():
     """The binding never imports the oracle."""
     src = open(os.path.join(ROOT, "paper_1309_6275_amd", "houghtrig.py")).read()
     assert "oracle" not in src.replace("never imports", "")
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU and exits with status 2 for --gpus above 1,
+    before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 2
+    assert "one GPU" in res.stderr and res.stdout == ""
