@@ -48,7 +48,7 @@ enum {
   HT_EINVAL = -1,        /* bad argument (null pointer, size out of range) */
   HT_ENOMEM = -2,        /* device allocation failed (plan creation only) */
   HT_EDEVICE = -3,       /* a HIP runtime call failed */
-  HT_EUNSUPPORTED = -4,  /* valid request beyond this build's kernel limits */
+  HT_EUNSUPPORTED = -4,  /* valid request beyond the library's kernel limits */
   HT_EBUSY = -5          /* serving loop: every slot busy and the wait queue full */
 };
 

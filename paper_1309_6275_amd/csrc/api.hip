@@ -98,7 +98,7 @@ const char* ht_strerror(int status) {
     case HT_EINVAL: return "invalid argument";
     case HT_ENOMEM: return "device allocation failed";
     case HT_EDEVICE: return "HIP runtime error";
-    case HT_EUNSUPPORTED: return "unsupported size for this build";
+    case HT_EUNSUPPORTED: return "unsupported size (beyond the library's limits)";
     case HT_EBUSY: return "every slot busy and the queue full";
     default: return "unknown status";
   }
