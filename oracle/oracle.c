@@ -738,6 +738,41 @@ static int key_greater(int n_a, float ss_a, int lin_a, int n_b, float ss_b, int 
   return lin_a < lin_b;
 }
 
+/* Candidates p with n_in[p] >= 0 take part, in index order; hits[p][L] is
+ * the inlier hit of layer L (-1 none).  owner[h] receives the candidate that
+ * owns hit h (-1 none), n_owned[p] the inlier hits p owns. */
+static void ownership(int32_t n_cand, const int32_t* n_in, const float* ss, const int32_t* lin,
+                      const int32_t* hits, int32_t n_hits, int32_t* owner, int32_t* n_owned) {
+  for (int32_t h = 0; h < n_hits; ++h) owner[h] = -1;
+  for (int32_t p = 0; p < n_cand; ++p) {
+    if (n_in[p] < 0) continue;
+    for (int L = 0; L < OR_MAX_LAYERS; ++L) {
+      int32_t h = hits[(size_t)p * OR_MAX_LAYERS + L];
+      if (h < 0 || h >= n_hits) continue;
+      int32_t o = owner[h];
+      if (o < 0 || key_greater(n_in[p], ss[p], lin[p], n_in[o], ss[o], lin[o])) owner[h] = p;
+    }
+  }
+  for (int32_t p = 0; p < n_cand; ++p) {
+    int own = 0;
+    if (n_in[p] >= 0)
+      for (int L = 0; L < OR_MAX_LAYERS; ++L) {
+        int32_t h = hits[(size_t)p * OR_MAX_LAYERS + L];
+        if (h >= 0 && h < n_hits && owner[h] == p) ++own;
+      }
+    n_owned[p] = own;
+  }
+}
+
+int oracle_ownership(int32_t n_cand, const int32_t* n_in, const float* ss, const int32_t* lin,
+                     const int32_t* hits, int32_t n_hits, int32_t* owner, int32_t* n_owned) {
+  if (n_cand < 0 || n_hits < 0 || (n_cand > 0 && (!n_in || !ss || !lin || !hits || !n_owned)) ||
+      (n_hits > 0 && !owner))
+    return -1;
+  ownership(n_cand, n_in, ss, lin, hits, n_hits, owner, n_owned);
+  return 0;
+}
+
 /* Refit (stands in for the Kalman filter of section "Jet and Black Hole
  * Detection"): weighted least squares in float64 by Gauss-Newton from the
  * seed circle, model phi_pred(r) = phi0 + asin(u(r; kappa, d0)), residual
@@ -993,6 +1028,20 @@ static int is_peak2(const int32_t* v, int nm, int nt, int m, int t, int32_t thr)
   return 1;
 }
 
+int oracle_vertex_peaks(const int32_t* v, int32_t nm, int32_t nt, int32_t thr, int32_t* out,
+                        int32_t capacity, int32_t* n_found) {
+  if (!v || nm < 1 || nt < 4 || capacity < 0 || (capacity > 0 && !out) || !n_found) return -1;
+  int32_t n = 0;
+  for (int m = 0; m < nm; ++m)
+    for (int t = 0; t < nt; ++t)
+      if (is_peak2(v, nm, nt, m, t, thr)) {
+        if (n < capacity) out[n] = m * nt + t;
+        ++n;
+      }
+  *n_found = n;
+  return 0;
+}
+
 int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
                          const uint8_t* layer, int32_t n_hits, const or_peak* peaks,
                          int32_t n_peaks, const or_cluster_cfg* cfg, int32_t* hit_owner,
@@ -1045,25 +1094,25 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
 
   /* 2. ownership among candidates */
   int32_t* owner = (int32_t*)malloc(sizeof(int32_t) * nh1);
-  for (int32_t h = 0; h < n_hits; ++h) owner[h] = -1;
   int32_t n_cand = 0, n_over = 0;
   int64_t n_pairs = 0, n_tests = 0;
+  size_t np1 = (size_t)(n_peaks > 0 ? n_peaks : 1);
+  int32_t* c_nin = (int32_t*)calloc(np1, sizeof(int32_t));
+  float* c_ss = (float*)calloc(np1, sizeof(float));
+  int32_t* c_lin = (int32_t*)calloc(np1, sizeof(int32_t));
+  int32_t* c_hits = (int32_t*)calloc(np1 * OR_MAX_LAYERS, sizeof(int32_t));
+  int32_t* c_own = (int32_t*)calloc(np1, sizeof(int32_t));
   for (int32_t p = 0; p < n_peaks; ++p) {
     n_pairs += cd[p].n_members;
     n_tests += cd[p].n_tests;
     if (cd[p].status == 2) ++n_over;
-    if (cd[p].status != 0) continue;
-    ++n_cand;
-    float ssp = (float)cd[p].ss;
-    for (int L = 0; L < OR_MAX_LAYERS; ++L) {
-      int32_t h = cd[p].hit[L];
-      if (h < 0) continue;
-      int32_t o = owner[h];
-      if (o < 0 || key_greater(cd[p].n_inliers, ssp, peaks[p].lin, cd[o].n_inliers,
-                               (float)cd[o].ss, peaks[o].lin))
-        owner[h] = p;
-    }
+    if (cd[p].status == 0) ++n_cand;
+    c_nin[p] = cd[p].status == 0 ? cd[p].n_inliers : -1;
+    c_ss[p] = (float)cd[p].ss;
+    c_lin[p] = peaks[p].lin;
+    for (int L = 0; L < OR_MAX_LAYERS; ++L) c_hits[(size_t)p * OR_MAX_LAYERS + L] = cd[p].hit[L];
   }
+  ownership(n_peaks, c_nin, c_ss, c_lin, c_hits, n_hits, owner, c_own);
 
   /* 3. survivors in peak order */
   int32_t n_trk = 0;
@@ -1072,9 +1121,7 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
   for (int32_t p = 0; p < n_peaks; ++p) {
     trk_of_peak[p] = -1;
     if (cd[p].status != 0) continue;
-    int own = 0;
-    for (int L = 0; L < OR_MAX_LAYERS; ++L)
-      if (cd[p].hit[L] >= 0 && owner[cd[p].hit[L]] == p) ++own;
+    int own = c_own[p];
     if (own < cfg->min_layers) continue;
     if (n_trk < track_cap) {
       or_track* t = &tracks[n_trk];
@@ -1204,6 +1251,11 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
 
   free(cd);
   free(owner);
+  free(c_nin);
+  free(c_ss);
+  free(c_lin);
+  free(c_hits);
+  free(c_own);
   free(trk_of_peak);
   free(trk_peak);
   free(vacc);

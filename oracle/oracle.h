@@ -122,6 +122,21 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
                          int32_t object_cap, int32_t* members, int32_t member_cap,
                          int32_t* vacc, int32_t* counts);
 
+/* The duplicate cleaning step of oracle_assoc_cluster on its own (for the
+ * pins): candidates p with n_in[p] >= 0 take part; hits is [n_cand][16], the
+ * inlier hit of each layer (-1 none).  Each hit goes to the candidate with
+ * the most inlier layers, then the smallest ss (float32), then the smallest
+ * lin; owner[n_hits] receives that candidate (-1 none), n_owned[n_cand] the
+ * inlier hits each candidate owns. */
+int oracle_ownership(int32_t n_cand, const int32_t* n_in, const float* ss, const int32_t* lin,
+                     const int32_t* hits, int32_t n_hits, int32_t* owner, int32_t* n_owned);
+
+/* The vertex-peak rule of oracle_assoc_cluster on a given vertex accumulator
+ * v[nm][nt] (theta periodic, rho clipped): cells in cell order into
+ * out[capacity], full count in *n_found. */
+int oracle_vertex_peaks(const int32_t* v, int32_t nm, int32_t nt, int32_t thr, int32_t* out,
+                        int32_t capacity, int32_t* n_found);
+
 /* OpenMP thread count for the calls above (determinism tests). */
 void oracle_set_threads(int n);
 

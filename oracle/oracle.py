@@ -72,30 +72,48 @@ def lib():
         if not os.path.exists(LIB_PATH):
             from . import build as _build
             _build.build()
-        _lib = C.CDLL(LIB_PATH)
-        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
-        _lib.oracle_asin_f.argtypes = [C.c_float]
-        _lib.oracle_asin_f.restype = C.c_float
-        _lib.oracle_asin_f_array.argtypes = [vp, vp, i64]
-        _lib.oracle_asin_f_array.restype = None
-        _lib.oracle_tables.argtypes = [vp, vp, vp, vp, vp]
-        _lib.oracle_sincos_array.argtypes = [vp, vp, vp, i64]
-        _lib.oracle_sincos_array.restype = None
-        _lib.oracle_atan2_array.argtypes = [vp, vp, vp, i64]
-        _lib.oracle_atan2_array.restype = None
-        _lib.oracle_phi0_coord.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
-        _lib.oracle_hough_vote.argtypes = [vp, vp, vp, i32, vp, vp]
-        _lib.oracle_hough_vote_cell.argtypes = [vp, vp, vp, i32, vp, vp]
-        _lib.oracle_hough_peaks.argtypes = [vp, vp, i32, vp, i32, vp]
-        _lib.oracle_assoc_cluster.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, i32, vp,
-                                              i32, vp, i32, vp, vp]
-        _lib.oracle_set_threads.argtypes = [C.c_int]
-        _lib.oracle_set_threads.restype = None
-        _lib.oracle_refine_one.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, vp]
-        for f in ("oracle_refine_one", "oracle_tables", "oracle_phi0_coord", "oracle_hough_vote",
-                  "oracle_hough_vote_cell", "oracle_hough_peaks", "oracle_assoc_cluster"):
-            getattr(_lib, f).restype = C.c_int
+        _lib = _bind(LIB_PATH)
     return _lib
+
+
+def use_library(path):
+    """Binds this wrapper to another build of the oracle (the tests build
+    copies with a planted mistake to show that a pin catches it).  Returns
+    the previous binding, to be passed back to restore it."""
+    global _lib
+    prev = lib()
+    _lib = path if isinstance(path, C.CDLL) else _bind(path)
+    return prev
+
+
+def _bind(path):
+    so = C.CDLL(path)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    so.oracle_asin_f.argtypes = [C.c_float]
+    so.oracle_asin_f.restype = C.c_float
+    so.oracle_asin_f_array.argtypes = [vp, vp, i64]
+    so.oracle_asin_f_array.restype = None
+    so.oracle_tables.argtypes = [vp, vp, vp, vp, vp]
+    so.oracle_sincos_array.argtypes = [vp, vp, vp, i64]
+    so.oracle_sincos_array.restype = None
+    so.oracle_atan2_array.argtypes = [vp, vp, vp, i64]
+    so.oracle_atan2_array.restype = None
+    so.oracle_phi0_coord.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
+    so.oracle_hough_vote.argtypes = [vp, vp, vp, i32, vp, vp]
+    so.oracle_hough_vote_cell.argtypes = [vp, vp, vp, i32, vp, vp]
+    so.oracle_hough_peaks.argtypes = [vp, vp, i32, vp, i32, vp]
+    so.oracle_assoc_cluster.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, i32, vp,
+                                        i32, vp, i32, vp, vp]
+    so.oracle_set_threads.argtypes = [C.c_int]
+    so.oracle_set_threads.restype = None
+    so.oracle_refine_one.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, vp]
+    so.oracle_ownership.argtypes = [i32, vp, vp, vp, vp, i32, vp, vp]
+    so.oracle_vertex_peaks.argtypes = [vp, i32, i32, i32, vp, i32, vp]
+    for f in ("oracle_refine_one", "oracle_tables", "oracle_phi0_coord", "oracle_hough_vote",
+              "oracle_hough_vote_cell", "oracle_hough_peaks", "oracle_assoc_cluster",
+              "oracle_ownership", "oracle_vertex_peaks"):
+        getattr(so, f).restype = C.c_int
+    return so
 
 
 def _check(rc, what):
@@ -228,6 +246,37 @@ def refine_one(grid: dict, r, phi, layer, lin: int, cfg: dict):
                                    C.byref(c), _p(oi), _p(of)), "refine_one")
     return dict(status=int(oi[0]), n_layers=int(oi[1]), n_inliers=int(oi[2]), hits=oi[3:].copy(),
                 ss=float(of[0]), circle=of[1:].copy())
+
+
+def ownership(n_inliers, ss, lin, hits, n_hits: int):
+    """The duplicate-cleaning step alone: per candidate its inlier layer
+    count (-1: not a candidate), seed sum (float32), cell and inlier hit per
+    layer ([n, <=16], -1 none).  Returns (owner per hit, owned hits per
+    candidate)."""
+    n_in = np.ascontiguousarray(n_inliers, np.int32)
+    n = n_in.size
+    ss = np.ascontiguousarray(ss, np.float32)
+    lin = np.ascontiguousarray(lin, np.int32)
+    h = np.full((max(n, 1), MAX_LAYERS), -1, np.int32)
+    hits = np.asarray(hits, np.int32).reshape(n, -1)
+    h[:n, :hits.shape[1]] = hits
+    owner = np.empty(max(n_hits, 1), np.int32)
+    n_owned = np.empty(max(n, 1), np.int32)
+    _check(lib().oracle_ownership(n, _p(n_in), _p(ss), _p(lin), _p(h), int(n_hits), _p(owner),
+                                  _p(n_owned)), "ownership")
+    return owner[:n_hits].copy(), n_owned[:n].copy()
+
+
+def vertex_peaks(vacc, thr: int):
+    """Cells of the vertex accumulator [n_rho, n_theta] that pass the vertex
+    peak rule, in cell order."""
+    v = np.ascontiguousarray(vacc, np.int32)
+    nm, nt = v.shape
+    out = np.empty(v.size, np.int32)
+    nf = C.c_int32(0)
+    _check(lib().oracle_vertex_peaks(_p(v), nm, nt, int(thr), _p(out), v.size, C.byref(nf)),
+           "vertex_peaks")
+    return out[:nf.value].copy()
 
 
 def set_threads(n: int):
