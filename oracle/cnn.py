@@ -2,7 +2,7 @@
 smoke() and bench.py's cpu_baseline leg use it).
 
 The paper asks for efficiency and purity improvements of the peak finding
-(section "Conclusion"); the filter scores each threshold peak from the
+(section "Summary"); the filter scores each threshold peak from the
 5 x 5 x 5 block of votes around it and drops low scores before refinement.
 This module writes the network and its training step out plainly, in
 float64, on the precision contract of the device kernels:

@@ -1,6 +1,6 @@
 // Learned peak filter: a 3D CNN that scores each threshold peak from the
 // 5 x 5 x 5 votes around it (the paper's call for efficiency and purity
-// improvements of the peak finding, section "Conclusion").
+// improvements of the peak finding, section "Summary").
 //
 // Precision contract (identical in the oracle): bfloat16 inputs, weights and
 // activations, float32 accumulation; bias after the sum; ReLU; activations
