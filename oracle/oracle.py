@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# HT_ORACLE_LIB selects another build of the same source (the sanitizer build)
+LIB_PATH = os.environ.get("HT_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 MAX_LAYERS = 16
 
 PEAK_DT = np.dtype([("lin", "<i4"), ("votes", "<i4")])
