@@ -320,7 +320,7 @@ int ht_profile_end(ht_plan* plan);
  * A 3D CNN scores each threshold peak from the 5 x 5 x 5 votes around it;
  * peaks scoring below a threshold are dropped before assoc_cluster (the
  * paper's call for efficiency and purity improvements of the peak finding,
- * section "Conclusion").  Network: conv3d 1->16 (3x3x3, valid), ReLU,
+ * section "Summary").  Network: conv3d 1->16 (3x3x3, valid), ReLU,
  * conv3d 16->16 (3x3x3, valid), ReLU, linear 16->64, ReLU, linear 64->1
  * (a logit).  Parameters: HT_CNN_PARAMS float32 in the order
  *   W1[16][27] b1[16] W2[16][16][27] b2[16] W3[64][16] b3[64] W4[64] b4

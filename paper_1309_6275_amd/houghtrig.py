@@ -178,6 +178,13 @@ def _ptr(t, dtype, what):
     return C.c_void_p(t.data_ptr())
 
 
+def _need(ok, what):
+    """Size checks the C ABI cannot make (it sees pointers only): raise before
+    anything is launched."""
+    if not ok:
+        raise ValueError(what)
+
+
 def _stream(stream=None):
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -244,6 +251,7 @@ def hough_vote(plan: Plan, r, phi, acc, n_votes=None, stream=None):
     n = int(r.numel())
     if phi.numel() != n or tuple(acc.shape) != plan.acc_shape:
         raise ValueError("shape mismatch")
+    _need(n_votes is None or n_votes.numel() >= 1, "n_votes must hold one element")
     _check(lib().hough_vote(plan.handle, _ptr(r, torch.float32, "r"),
                             _ptr(phi, torch.float32, "phi"), n,
                             _ptr(acc, torch.int32, "acc"),
@@ -258,6 +266,7 @@ def hough_vote_cell(plan: Plan, r, phi, acc, n_votes=None, stream=None):
     n = int(r.numel())
     if phi.numel() != n or tuple(acc.shape) != plan.acc_shape:
         raise ValueError("shape mismatch")
+    _need(n_votes is None or n_votes.numel() >= 1, "n_votes must hold one element")
     _check(lib().hough_vote_cell(plan.handle, _ptr(r, torch.float32, "r"),
                                  _ptr(phi, torch.float32, "phi"), n,
                                  _ptr(acc, torch.int32, "acc"),
@@ -270,6 +279,7 @@ def hough_peaks(plan: Plan, acc, min_votes: int, out, n_found, stream=None):
     torch = _torch()
     if tuple(acc.shape) != plan.acc_shape or out.dim() != 2 or out.shape[1] != 2:
         raise ValueError("shape mismatch")
+    _need(n_found.numel() >= 1, "n_found must hold one element")
     _check(lib().hough_peaks(plan.handle, _ptr(acc, torch.int32, "acc"), int(min_votes),
                              _ptr(out, torch.int32, "out"), int(out.shape[0]),
                              _ptr(n_found, torch.int32, "n_found"), _stream(stream)),
@@ -349,6 +359,19 @@ def _acc_ptr(plan: Plan, acc):
     return _ptr(acc, _torch().int32, "acc")
 
 
+def _check_cluster_args(plan: Plan, n, peaks, n_peaks, cfg: dict, bufs: ClusterBuffers,
+                        with_vacc):
+    _need(peaks.dim() == 2 and peaks.shape[1] == 2, "peaks must be int32 [cap, 2]")
+    _need(n_peaks.numel() >= 1, "n_peaks must hold one element")
+    _need(bufs.hit_owner.numel() >= n, "bufs.hit_owner holds fewer entries than there are hits")
+    _need(bufs.counts.numel() >= 8, "bufs.counts must hold 8 entries")
+    _need(bufs.tracks.shape[0] >= bufs.track_cap and bufs.objects.shape[0] >= bufs.object_cap
+          and bufs.members.numel() >= bufs.member_cap, "bufs capacities exceed their tensors")
+    if with_vacc:
+        _need(bufs.vacc.numel() >= int(cfg["n_rho"]) * int(cfg["n_theta"]),
+              "bufs.vacc holds fewer cells than n_rho * n_theta")
+
+
 def assoc_cluster(plan: Plan, r, phi, layer, peaks, n_peaks, cfg: dict, bufs: ClusterBuffers,
                   with_vacc=True, stream=None, acc=None):
     """peaks: int32 [cap, 2] from hough_peaks; n_peaks: int32 [1] device;
@@ -358,6 +381,7 @@ def assoc_cluster(plan: Plan, r, phi, layer, peaks, n_peaks, cfg: dict, bufs: Cl
     n = int(r.numel())
     if phi.numel() != n or layer.numel() != n:
         raise ValueError("shape mismatch")
+    _check_cluster_args(plan, n, peaks, n_peaks, cfg, bufs, with_vacc)
     c = cluster_struct(cfg)
     o = bufs.struct(with_vacc)
     _check(lib().assoc_cluster(plan.handle, _ptr(r, torch.float32, "r"),
@@ -376,6 +400,8 @@ def hough_vote_n(plan: Plan, r, phi, n_hits_dev, acc, n_votes=None, stream=None)
     n = int(r.numel())
     if phi.numel() != n or tuple(acc.shape) != plan.acc_shape:
         raise ValueError("shape mismatch")
+    _need(n_hits_dev.numel() >= 1, "n_hits_dev must hold one element")
+    _need(n_votes is None or n_votes.numel() >= 1, "n_votes must hold one element")
     _check(lib().hough_vote_n(plan.handle, _ptr(r, torch.float32, "r"),
                               _ptr(phi, torch.float32, "phi"), n,
                               _ptr(n_hits_dev, torch.int32, "n_hits_dev"),
@@ -391,6 +417,8 @@ def assoc_cluster_n(plan: Plan, r, phi, layer, n_hits_dev, peaks, n_peaks, cfg: 
     n = int(r.numel())
     if phi.numel() != n or layer.numel() != n:
         raise ValueError("shape mismatch")
+    _need(n_hits_dev.numel() >= 1, "n_hits_dev must hold one element")
+    _check_cluster_args(plan, n, peaks, n_peaks, cfg, bufs, with_vacc)
     c = cluster_struct(cfg)
     o = bufs.struct(with_vacc)
     _check(lib().assoc_cluster_n(plan.handle, _ptr(r, torch.float32, "r"),
@@ -432,6 +460,9 @@ def cnn_windows(plan: "Plan", acc, peaks, n_peaks, win, stream=None):
     cap = int(peaks.shape[0])
     if tuple(win.shape) != (cap, CNN_WINDOW):
         raise ValueError("win must be [cap, 128]")
+    _need(tuple(acc.shape) == plan.acc_shape, "acc must have the plan's shape")
+    _need(peaks.dim() == 2 and peaks.shape[1] == 2, "peaks must be int32 [cap, 2]")
+    _need(n_peaks.numel() >= 1, "n_peaks must hold one element")
     _check(lib().ht_cnn_windows(plan.handle, _ptr(acc, torch.int32, "acc"),
                                 _ptr(peaks, torch.int32, "peaks"),
                                 _ptr(n_peaks, torch.int32, "n_peaks"), cap,
@@ -440,7 +471,11 @@ def cnn_windows(plan: "Plan", acc, peaks, n_peaks, win, stream=None):
 
 def cnn_forward(params, win, logits, workspace, n_dev=None, stream=None):
     torch = _torch()
+    _need(win.dim() == 2 and win.shape[1] == CNN_WINDOW, "win must be [n, 128]")
     n_max = int(win.shape[0])
+    _need(logits.numel() >= n_max, "logits holds fewer entries than there are windows")
+    _need(params.numel() >= CNN_PARAMS, "params must hold HT_CNN_PARAMS floats")
+    _need(n_dev is None or n_dev.numel() >= 1, "n_dev must hold one element")
     _check(lib().ht_cnn_forward(_ptr(params, torch.float32, "params"),
                                 _ptr(win, torch.bfloat16, "win"),
                                 _ptr(n_dev, torch.int32, "n_dev") if n_dev is not None else None,
@@ -452,6 +487,11 @@ def cnn_forward(params, win, logits, workspace, n_dev=None, stream=None):
 def cnn_train_step(params, mom, win, labels, lr, momentum, pos_weight, loss, workspace,
                    stream=None):
     torch = _torch()
+    _need(win.dim() == 2 and win.shape[1] == CNN_WINDOW, "win must be [n, 128]")
+    _need(labels.numel() >= win.shape[0], "labels holds fewer entries than there are windows")
+    _need(params.numel() >= CNN_PARAMS and mom.numel() >= CNN_PARAMS,
+          "params and mom must hold HT_CNN_PARAMS floats")
+    _need(loss.numel() >= 1, "loss must hold one element")
     _check(lib().ht_cnn_train_step(_ptr(params, torch.float32, "params"),
                                    _ptr(mom, torch.float32, "mom"),
                                    _ptr(win, torch.bfloat16, "win"),
@@ -464,6 +504,10 @@ def cnn_train_step(params, mom, win, labels, lr, momentum, pos_weight, loss, wor
 
 def cnn_keep(plan: "Plan", logits, peaks, n_peaks, threshold, out, n_out, stream=None):
     torch = _torch()
+    _need(peaks.dim() == 2 and peaks.shape[1] == 2, "peaks must be int32 [cap, 2]")
+    _need(out.dim() == 2 and out.shape[1] == 2, "out must be int32 [out_cap, 2]")
+    _need(logits.numel() >= peaks.shape[0], "logits holds fewer entries than there are peaks")
+    _need(n_peaks.numel() >= 1 and n_out.numel() >= 1, "n_peaks and n_out must hold one element")
     _check(lib().ht_cnn_keep(plan.handle, _ptr(logits, torch.float32, "logits"),
                              _ptr(peaks, torch.int32, "peaks"), _ptr(n_peaks, torch.int32, "n_peaks"),
                              int(peaks.shape[0]), float(threshold), _ptr(out, torch.int32, "out"),
