@@ -195,6 +195,26 @@ int hough_vote_cell(const ht_plan* plan, const float* r, const float* phi, int32
 int hough_peaks(const ht_plan* plan, const int32_t* acc, int32_t min_votes, ht_peak* out,
                 int32_t capacity, int32_t* n_found, void* stream);
 
+/* hough_peaks_noalloc -- hough_peaks for callers that cannot allocate
+ * device memory or create a plan: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same kernels, same
+ * results (peaks, order, count) as hough_peaks with a plan of `grid`; no
+ * allocation of any kind, no hipMemset.  The scratch (peak ballots and tile
+ * counts) is a fixed device array inside the library, one copy per GPU, held
+ * until the process ends; its device address is looked up once per GPU on
+ * the first call there.  Every call on one GPU shares that copy: calls that
+ * overlap on one GPU (concurrent streams) race and must be ordered by the
+ * caller.  Nothing in it needs clearing between calls (every word read is
+ * written first by the same call).
+ *   grid     host pointer, the accumulator's grid (as for ht_plan_create)
+ *   acc, min_votes, out, capacity, n_found  as for hough_peaks
+ * Returns HT_EINVAL for a bad grid or pointer, HT_EUNSUPPORTED when the grid
+ * has more than 2^24 cells (the array's size: 2 MiB of ballots, 256 KiB of
+ * tile counts and 256 KiB of tile offsets), HT_EDEVICE when the array's
+ * address cannot be found. */
+int hough_peaks_noalloc(const ht_grid* grid, const int32_t* acc, int32_t min_votes, ht_peak* out,
+                        int32_t capacity, int32_t* n_found, void* stream);
+
 /* assoc_cluster -- candidate refinement, duplicate cleaning, refit and the
  * second transform (paper, section "Jet and Black Hole Detection").
  *   members    valid hits whose phi0 coordinate x in the peak's column lies

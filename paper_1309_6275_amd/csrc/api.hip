@@ -280,6 +280,16 @@ int hough_peaks(const ht_plan* p, const int32_t* acc, int32_t min_votes, ht_peak
   return ht::launch_peaks(*p, acc, min_votes, out, capacity, n_found, (hipStream_t)stream);
 }
 
+int hough_peaks_noalloc(const ht_grid* grid, const int32_t* acc, int32_t min_votes, ht_peak* out,
+                        int32_t capacity, int32_t* n_found, void* stream) {
+  if (!grid_ok(grid) || !acc || !n_found || capacity < 0 || (capacity > 0 && !out))
+    return HT_EINVAL;
+  if ((int64_t)grid->n_phi * grid->n_qpt * grid->n_d0 > ht::noalloc_max_cells())
+    return HT_EUNSUPPORTED;
+  return ht::launch_peaks_noalloc(*grid, acc, min_votes, out, capacity, n_found,
+                                  (hipStream_t)stream);
+}
+
 int assoc_cluster(const ht_plan* p, const float* r, const float* phi, const uint8_t* layer,
                   int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks, int32_t peak_cap,
                   const int32_t* acc, const ht_cluster_cfg* cfg, const ht_cluster_out* out,

@@ -105,6 +105,10 @@ int launch_cell_vote(const Plan& p, const float* r, const float* phi, int32_t n_
 int cell_vote_init(int n_phi);
 int launch_peaks(const Plan& p, const int32_t* acc, int32_t min_votes, ht_peak* out,
                  int32_t capacity, int32_t* n_found, hipStream_t s);
+// hough_peaks on the library's fixed device scratch array (no plan)
+int launch_peaks_noalloc(const ht_grid& g, const int32_t* acc, int32_t min_votes, ht_peak* out,
+                         int32_t capacity, int32_t* n_found, hipStream_t s);
+int64_t noalloc_max_cells();
 int launch_assoc(const Plan& p, const float* r, const float* phi, const uint8_t* layer,
                  int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks, int32_t peak_cap,
                  const int32_t* acc, const ht_cluster_cfg& cfg, const ht_cluster_out& out,

@@ -15,6 +15,8 @@
 // 3 x (rows + 2) neighbour rows are staged in LDS once; otherwise each of the
 // 9 neighbour rows is one 16-byte load plus the two cells beside it, from
 // L2.  Other n_phi: a lane takes one cell and a tile is 256 cells.
+#include <mutex>
+
 #include "ht_internal.h"
 
 namespace ht {
@@ -365,39 +367,105 @@ __global__ __launch_bounds__(256) void emit4_kernel(const int32_t* __restrict__ 
 
 int peaks_init(int) { return HT_OK; }
 
-int launch_peaks(const Plan& p, const int32_t* acc, int32_t min_votes, ht_peak* out,
-                 int32_t capacity, int32_t* n_found, hipStream_t s) {
-  const ht_grid& g = p.grid;
+int launch_peaks_core(const ht_grid& g, int64_t n_cells, const int32_t* acc, int32_t min_votes,
+                      ht_peak* out, int32_t capacity, int32_t* n_found, void* bits_v,
+                      int32_t* tile_cnt, int32_t* tile_off, hipStream_t s) {
   const bool four = (g.n_phi & 3) == 0 && ((uintptr_t)acc & 15) == 0;
-  const int tiles = four ? (int)((p.n_cells + kTile4 - 1) / kTile4) : p.n_tiles;
-  p.prof_mark(HT_STAGE_PEAKS, 0, s);
+  const int tiles = (int)(four ? (n_cells + kTile4 - 1) / kTile4 : (n_cells + kTile - 1) / kTile);
   const int R = four && kTile4 % g.n_phi == 0 ? kTile4 / g.n_phi : 0;
-  uint64_t* bits4 = reinterpret_cast<uint64_t*>(p.d_bits);
-  if (R == 1 && g.n_qpt % 1 == 0)
-    flag4s_kernel<1><<<tiles, 256, 0, s>>>(acc, g.n_qpt, g.n_d0, min_votes, bits4, p.d_tile_cnt);
+  uint64_t* bits4 = reinterpret_cast<uint64_t*>(bits_v);
+  uint32_t* bits1 = reinterpret_cast<uint32_t*>(bits_v);
+  if (R == 1)
+    flag4s_kernel<1><<<tiles, 256, 0, s>>>(acc, g.n_qpt, g.n_d0, min_votes, bits4, tile_cnt);
   else if (R == 2 && g.n_qpt % 2 == 0)
-    flag4s_kernel<2><<<tiles, 256, 0, s>>>(acc, g.n_qpt, g.n_d0, min_votes, bits4, p.d_tile_cnt);
+    flag4s_kernel<2><<<tiles, 256, 0, s>>>(acc, g.n_qpt, g.n_d0, min_votes, bits4, tile_cnt);
   else if (R == 4 && g.n_qpt % 4 == 0)
-    flag4s_kernel<4><<<tiles, 256, 0, s>>>(acc, g.n_qpt, g.n_d0, min_votes, bits4, p.d_tile_cnt);
+    flag4s_kernel<4><<<tiles, 256, 0, s>>>(acc, g.n_qpt, g.n_d0, min_votes, bits4, tile_cnt);
   else if (four)
-    flag4_kernel<<<tiles, 256, 0, s>>>(acc, g.n_phi, g.n_qpt, g.n_d0, p.n_cells, min_votes,
-                                       bits4, p.d_tile_cnt);
+    flag4_kernel<<<tiles, 256, 0, s>>>(acc, g.n_phi, g.n_qpt, g.n_d0, n_cells, min_votes, bits4,
+                                       tile_cnt);
   else
-    flag_kernel<<<tiles, kTile, 0, s>>>(acc, g.n_phi, g.n_qpt, g.n_d0, p.n_cells, min_votes,
-                                        p.d_bits, p.d_tile_cnt);
+    flag_kernel<<<tiles, kTile, 0, s>>>(acc, g.n_phi, g.n_qpt, g.n_d0, n_cells, min_votes, bits1,
+                                        tile_cnt);
   HT_CHECK(hipGetLastError());
-  const int rc = launch_scan(p.d_tile_cnt, p.d_tile_off, tiles, n_found, s);
+  const int rc = launch_scan(tile_cnt, tile_off, tiles, n_found, s);
   if (rc != HT_OK) return rc;
   if (capacity > 0) {
     if (four)
-      emit4_kernel<<<tiles, 256, 0, s>>>(acc, reinterpret_cast<const uint64_t*>(p.d_bits),
-                                         p.d_tile_off, p.n_cells, out, capacity);
+      emit4_kernel<<<tiles, 256, 0, s>>>(acc, bits4, tile_off, n_cells, out, capacity);
     else
-      emit_kernel<<<tiles, kTile, 0, s>>>(acc, p.d_bits, p.d_tile_off, p.n_cells, out, capacity);
+      emit_kernel<<<tiles, kTile, 0, s>>>(acc, bits1, tile_off, n_cells, out, capacity);
     HT_CHECK(hipGetLastError());
   }
+  return HT_OK;
+}
+
+int launch_peaks(const Plan& p, const int32_t* acc, int32_t min_votes, ht_peak* out,
+                 int32_t capacity, int32_t* n_found, hipStream_t s) {
+  p.prof_mark(HT_STAGE_PEAKS, 0, s);
+  const int rc = launch_peaks_core(p.grid, p.n_cells, acc, min_votes, out, capacity, n_found,
+                                   p.d_bits, p.d_tile_cnt, p.d_tile_off, s);
+  if (rc != HT_OK) return rc;
   p.prof_mark(HT_STAGE_PEAKS, 1, s);
   return HT_OK;
+}
+
+// Largest accumulator hough_peaks_noalloc takes, and its scratch: the ballot
+// words (one bit per cell, tiles rounded up), the tile counts and the tile
+// offsets (256-cell tiles at most).
+constexpr int64_t kNoAllocMaxCells = (int64_t)1 << 24;
+constexpr size_t kNoAllocBitsBytes = (size_t)(kNoAllocMaxCells / 8) + 256;
+constexpr size_t kNoAllocTileBytes = (size_t)(kNoAllocMaxCells / 256) * 4;
+constexpr size_t kNoAllocScratchBytes = kNoAllocBitsBytes + 2 * kNoAllocTileBytes;
+
+}  // namespace ht
+
+// ---- hough_peaks_noalloc: the same kernels on a fixed device array ------------
+//
+// The scratch lives in this array, one copy per GPU, held until the process
+// ends.  In host code its name is only a host-side stand-in; the device
+// address of the current GPU's copy comes from hipGetSymbolAddress, taken
+// once per device on the first call there and kept.  Every call on a GPU
+// uses that GPU's copy, so calls that overlap on one GPU (two streams) race.
+// Nothing needs clearing between calls: the flag kernel writes every ballot
+// word and tile count that the scan and emit kernels read, and the scan
+// writes every offset.
+static __device__ __align__(256) unsigned char scratch[ht::kNoAllocScratchBytes];
+
+namespace ht {
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+int scratch_address(void** out) {
+  int dev = 0;
+  HT_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return HT_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return HT_EDEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return HT_OK;
+}
+}  // namespace
+
+int64_t noalloc_max_cells() { return kNoAllocMaxCells; }
+
+int launch_peaks_noalloc(const ht_grid& g, const int32_t* acc, int32_t min_votes, ht_peak* out,
+                         int32_t capacity, int32_t* n_found, hipStream_t s) {
+  const int64_t n_cells = (int64_t)g.n_phi * g.n_qpt * g.n_d0;
+  if (n_cells > kNoAllocMaxCells) return HT_EUNSUPPORTED;
+  void* base = nullptr;
+  const int rc = scratch_address(&base);
+  if (rc != HT_OK) return rc;
+  unsigned char* b = static_cast<unsigned char*>(base);
+  int32_t* cnt = reinterpret_cast<int32_t*>(b + kNoAllocBitsBytes);
+  return launch_peaks_core(g, n_cells, acc, min_votes, out, capacity, n_found, b, cnt,
+                           cnt + kNoAllocTileBytes / 4, s);
 }
 
 }  // namespace ht

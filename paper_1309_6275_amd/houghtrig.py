@@ -117,6 +117,7 @@ def lib():
         L.hough_vote_n.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
         L.assoc_cluster_n.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, i32, vp, vp, vp, vp]
         L.hough_peaks.argtypes = [vp, vp, i32, vp, i32, vp, vp]
+        L.hough_peaks_noalloc.argtypes = [vp, vp, i32, vp, i32, vp, vp]
         L.assoc_cluster.argtypes = [vp, vp, vp, vp, i32, vp, vp, i32, vp, vp, vp, vp]
         L.ht_asin_f32.argtypes = [vp, vp, i64, vp]
         L.ht_compact_hits.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
@@ -142,7 +143,7 @@ def lib():
                   "ht_server_create", "ht_server_destroy", "ht_server_info", "ht_server_submit",
                   "ht_server_poll", "ht_cnn_windows", "ht_cnn_forward", "ht_cnn_train_step",
                   "ht_cnn_keep", "hough_vote_cell", "ht_compact_hits", "ht_remap_track_hits",
-                  "hough_vote_n", "assoc_cluster_n"):
+                  "hough_vote_n", "assoc_cluster_n", "hough_peaks_noalloc"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -284,6 +285,20 @@ def hough_peaks(plan: Plan, acc, min_votes: int, out, n_found, stream=None):
                              _ptr(out, torch.int32, "out"), int(out.shape[0]),
                              _ptr(n_found, torch.int32, "n_found"), _stream(stream)),
            "hough_peaks")
+
+
+def hough_peaks_noalloc(grid: dict, acc, min_votes: int, out, n_found, stream=None):
+    """hough_peaks without a plan and without allocating: the library's fixed
+    device scratch array (grids of at most 2^24 cells)."""
+    torch = _torch()
+    g = grid_struct(grid)
+    if tuple(acc.shape) != (g.n_d0, g.n_qpt, g.n_phi) or out.dim() != 2 or out.shape[1] != 2:
+        raise ValueError("shape mismatch")
+    _need(n_found.numel() >= 1, "n_found must hold one element")
+    _check(lib().hough_peaks_noalloc(C.byref(g), _ptr(acc, torch.int32, "acc"), int(min_votes),
+                                     _ptr(out, torch.int32, "out"), int(out.shape[0]),
+                                     _ptr(n_found, torch.int32, "n_found"), _stream(stream)),
+           "hough_peaks_noalloc")
 
 
 class ClusterBuffers:
@@ -653,4 +668,4 @@ EXPORTS = ("ht_plan_create", "ht_plan_destroy", "ht_strerror", "hough_vote", "ho
            "ht_profile_end", "ht_server_create", "ht_server_destroy", "ht_server_info",
            "ht_server_submit", "ht_server_poll", "ht_cnn_workspace_bytes", "ht_cnn_windows",
            "ht_cnn_forward", "ht_cnn_train_step", "ht_cnn_keep", "ht_compact_hits",
-           "ht_remap_track_hits", "hough_vote_n", "assoc_cluster_n")
+           "ht_remap_track_hits", "hough_vote_n", "assoc_cluster_n", "hough_peaks_noalloc")
