@@ -2,15 +2,20 @@
 
 A step is one pass of the whole path -- hough_vote, hough_peaks and
 assoc_cluster (refinement, ownership, refit, vertex transform) -- over a batch
-of synthetic displaced-jet events (512 phi0 x 256 q/pT x 64 d0 accumulator,
-~3.6k hits each), inputs resident in HBM before the timed region.  Prints
-one JSON line: whole-job Hough votes/s (value), events/s, p50/p99 event
-latency, track efficiency and fake rate of the outputs, the roofline of the
-dominant kernel (the seed search of the refinement) and of the vote kernel,
-both from the library's HIP-event stage timers on the launch stream, and the
-CPU oracle timed on a bounded sample on the host cores.
+of synthetic events on the 512 phi0 x 256 q/pT x 64 d0 accumulator, inputs
+resident in HBM before the timed region.  By default the batch is 4
+high-pileup events (~55k hits each, the largest single-GPU workload); the
+displaced-jet workload (~3.6k hits, 16 events per step) is measured after it
+and reported under its own key.  Prints one JSON line: whole-job Hough
+votes/s (value), events/s, p50/p99 event latency, track efficiency and fake
+rate of the outputs, the roofline of the dominant kernel and of the vote
+kernel (the operations each kernel actually executed, against the published
+MI355X vector peak of its precision; the library's HIP-event stage timers on
+the launch stream give the kernel times), and the CPU oracle timed on a
+bounded sample on the host cores.
 
     python bench.py [--steps K] [--warmup W] [--batch B] [--workload 1|2|3]
+                    [--second-workload 0|1|2|3]
 """
 from __future__ import annotations
 
@@ -38,18 +43,32 @@ OPS_PER_VOTE = 22
 # member from a seed circle: f = A q + B x + C y + D (3 multiplies, 3 adds),
 # s = 1 + 4 A f (2, 1), sqrt, 1 + sqrt, 2 f, the division
 OPS_PER_TEST = 13
-# single-issue fp32 VALU rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# MI355X published vector peaks (a fused multiply-add counts two flops):
+# fp32 157.3 TFLOP/s, fp64 78.6 TFLOP/s
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+# single-issue rate of plain (not fused, not packed) vector operations:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, reported beside the published peaks
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+# events per step and CPU-oracle events per workload
+DEFAULT_BATCH = {1: 64, 2: 16, 3: 4}
+DEFAULT_CPU_EVENTS = {1: 64, 2: 16, 3: 2}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=0,
+                    help="events per step (0: 4 for workload 3, 16 for 2, 64 for 1)")
+    ap.add_argument("--workload", type=int, default=3,
+                    help="1: 2D prompt event; 2: displaced-jet event (~3.6k hits); "
+                         "3: high-pileup event (~55k hits), the largest single-GPU workload")
+    ap.add_argument("--second-workload", type=int, default=2,
+                    help="also measure this workload and report it under workload_<n> "
+                         "(0 skips it)")
     ap.add_argument("--streams", type=int, default=1,
                     help="HIP streams, each with its own plan and scratch; events are "
                          "assigned round-robin and run concurrently.  The per-launch kernel "
@@ -57,8 +76,9 @@ def parse():
     ap.add_argument("--concurrent", type=int, default=2,
                     help="after the timed region, also time the same steps on this many "
                          "concurrent streams (0 skips it); reported as concurrent_streams")
-    ap.add_argument("--cpu-sample", type=int, default=16,
-                    help="events of the CPU oracle baseline (0 skips it)")
+    ap.add_argument("--cpu-sample", type=int, default=-1,
+                    help="events of the CPU oracle baseline (0 skips it; -1: 2 events of "
+                         "workload 3, 16 of workload 2)")
     ap.add_argument("--serve", action="store_true",
                     help="benchmark the trigger serving loop instead: Poisson arrivals of a mixed "
                          "2D/3D event stream, p50/p99 latency, shedding, closed-loop throughput")
@@ -117,26 +137,41 @@ def traffic_from_profile(kernel, workload):
     return float(d["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(W, events, votes_per_event):
+def cpu_baseline(W, events, workload):
+    """The oracle (plain C, OpenMP over independent loops) on the host cores.
+    Workloads 1 and 2: the full path on each sample event.  Workload 3 (about
+    40 s of oracle time per event on 8 cores): the vote and peaks of each
+    sample event, and the refinement on every 8th peak of its list (still in
+    cell order), scaled by 8 -- its time is linear in the candidates."""
     from oracle import oracle as O
-    t0 = time.perf_counter()
+    stride = 8 if workload == 3 else 1
+    t_total = 0.0
     total_votes = 0
+    t_wall0 = time.perf_counter()
     for ev in events:
+        t0 = time.perf_counter()
         acc, nv = O.hough_vote(W["grid"], ev.r, ev.phi)
         pk, n = O.hough_peaks(W["grid"], acc, W["min_votes"])
-        O.assoc_cluster(W["grid"], ev.r, ev.phi, ev.layer, pk, W["cluster"])
+        t1 = time.perf_counter()
+        O.assoc_cluster(W["grid"], ev.r, ev.phi, ev.layer, pk[::stride].copy(), W["cluster"])
+        t2 = time.perf_counter()
+        t_total += (t1 - t0) + stride * (t2 - t1)
         total_votes += nv
-    dt = time.perf_counter() - t0
+    wall = time.perf_counter() - t_wall0
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
     threads = int(os.environ.get("OMP_NUM_THREADS", cores))
-    return {"value": total_votes / dt, "unit": "votes/s", "cores": min(cores, threads),
-            "kind": "oracle",
-            "sample": f"{len(events)} events of the same workload, full path (vote, peaks, "
-                      f"refinement, vertex transform), {dt:.1f} s, "
-                      f"{len(events) / dt:.3f} events/s"}
+    sample = (f"{len(events)} events of the same workload, full path (vote, peaks, refinement, "
+              f"vertex transform), {wall:.1f} s, {len(events) / t_total:.3f} events/s")
+    if stride > 1:
+        sample = (f"{len(events)} events of the same workload: vote and peaks of each, and the "
+                  f"refinement and vertex transform on every {stride}th peak, its time scaled "
+                  f"by {stride}; {wall:.1f} s of CPU work, {t_total:.1f} s per "
+                  f"{len(events)} events extrapolated, {len(events) / t_total:.3f} events/s")
+    return {"value": total_votes / t_total, "unit": "votes/s", "cores": min(cores, threads),
+            "kind": "oracle", "sample": sample}
 
 
 # hit-columns in flight at most in the serving loop, as a fraction of the
@@ -284,7 +319,7 @@ def two_pass_bench(args):
 
     W = CF.WORKLOADS[2]
     D = CF.TWO_PASS["displaced"]
-    B = args.batch
+    B = args.batch or 16
     events = [G.make_event(2, W["seed0"] + 100 + e) for e in range(B)]
     dev = [dict(r=torch.from_numpy(ev.r).cuda(), phi=torch.from_numpy(ev.phi).cuda(),
                 layer=torch.from_numpy(ev.layer).cuda()) for ev in events]
@@ -375,6 +410,212 @@ def two_pass_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def measure(args, workload, B, steps, warmup, cpu_events, concurrent):
+    """Times `steps` steps of the whole path over B events of one workload
+    (inputs resident in HBM) and returns the figures of one bench line."""
+    import torch
+    from paper_1309_6275_amd import configs as CF
+    from paper_1309_6275_amd import eventgen as G
+    from paper_1309_6275_amd import houghtrig as H
+    from paper_1309_6275_amd import metrics as M
+
+    W = CF.WORKLOADS[workload]
+    g, cl = W["grid"], W["cluster"]
+    events = [G.make_event(workload, W["seed0"] + 100 + e) for e in range(B)]
+    peak_cap = 1 << 19 if workload < 3 else 1 << 21
+    S = max(1, args.streams)
+    plans = [H.Plan(g, max_hits=65535, max_peaks=peak_cap, max_member_cap=cl["member_cap"],
+                    max_tracks=1 << 14) for _ in range(S)]
+    plan = plans[0]
+    dev = []
+    for ev in events:
+        dev.append(dict(r=torch.from_numpy(ev.r).cuda(), phi=torch.from_numpy(ev.phi).cuda(),
+                        layer=torch.from_numpy(ev.layer).cuda(), n=ev.n_hits))
+    ctx = [dict(acc=torch.empty(plan.acc_shape, dtype=torch.int32, device="cuda"),
+                peaks=torch.empty((peak_cap, 2), dtype=torch.int32, device="cuda"),
+                nf=torch.zeros(1, dtype=torch.int32, device="cuda")) for _ in range(S)]
+    acc = ctx[0]["acc"]
+    nv = torch.zeros(1, dtype=torch.int64, device="cuda")
+    bufs = [H.ClusterBuffers(ev.n_hits, 1 << 14, 1024, 1 << 16, cl["n_rho"], cl["n_theta"])
+            for ev in events]
+
+    # per-event vote counts, evaluations and distinct hit radii (deterministic),
+    # outside timing
+    votes, evals, radii = [], [], []
+    ncol = g["n_qpt"] * g["n_d0"]
+    for d, ev in zip(dev, events):
+        H.hough_vote(plan, d["r"], d["phi"], acc, nv)
+        torch.cuda.synchronize()
+        votes.append(int(nv.item()))
+        ok = (ev.r > 0) & (ev.r < 1e4) & (np.abs(ev.phi) <= 4)
+        evals.append(int(ok.sum()) * ncol)
+        radii.append(int(np.unique(ev.r[ok]).size))
+
+    # default-priority streams, one plan (tables and scratch) per stream
+    streams = [torch.cuda.Stream() for _ in range(S)]
+    torch.cuda.synchronize()
+    ev_a = [torch.cuda.Event(enable_timing=True) for _ in range(B)]
+    ev_c = [torch.cuda.Event(enable_timing=True) for _ in range(B)]
+
+    def step(record):
+        for e, d in enumerate(dev):
+            c, st, pl = ctx[e % S], streams[e % S], plans[e % S]
+            with torch.cuda.stream(st):
+                if record:
+                    ev_a[e].record(st)
+                H.hough_vote(pl, d["r"], d["phi"], c["acc"])
+                H.hough_peaks(pl, c["acc"], W["min_votes"], c["peaks"], c["nf"])
+                H.assoc_cluster(pl, d["r"], d["phi"], d["layer"], c["peaks"], c["nf"], cl,
+                                bufs[e], with_vacc=False)
+                if record:
+                    ev_c[e].record(st)
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    # stage timers: HIP events the library records around its kernels on each
+    # plan's launch stream, read after each step
+    for pl in plans:
+        H.profile_begin(pl, depth=2 * B)
+    stages = {}
+    lat_ms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+        torch.cuda.synchronize()  # per-step sync so the events of this step can be read
+        for e in range(B):
+            lat_ms.append(ev_a[e].elapsed_time(ev_c[e]))
+        for pl in plans:
+            H.profile_read(pl, stages)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for pl in plans:
+        H.profile_end(pl)
+
+    # the same steps on concurrent streams, each with its own plan: throughput
+    # when kernels of several events overlap (not the headline value, whose
+    # per-launch kernel times the roofline needs)
+    conc = None
+    if concurrent > 1 and S == 1:
+        C = concurrent
+        cplans = [plan] + [H.Plan(g, max_hits=65535, max_peaks=peak_cap,
+                                  max_member_cap=cl["member_cap"], max_tracks=1 << 14)
+                           for _ in range(C - 1)]
+        cctx = [ctx[0]] + [dict(acc=torch.empty(plan.acc_shape, dtype=torch.int32, device="cuda"),
+                                peaks=torch.empty((peak_cap, 2), dtype=torch.int32, device="cuda"),
+                                nf=torch.zeros(1, dtype=torch.int32, device="cuda"))
+                           for _ in range(C - 1)]
+        cstreams = [torch.cuda.Stream() for _ in range(C)]
+
+        def cstep():
+            for e, d in enumerate(dev):
+                c, st, pl = cctx[e % C], cstreams[e % C], cplans[e % C]
+                with torch.cuda.stream(st):
+                    H.hough_vote(pl, d["r"], d["phi"], c["acc"])
+                    H.hough_peaks(pl, c["acc"], W["min_votes"], c["peaks"], c["nf"])
+                    H.assoc_cluster(pl, d["r"], d["phi"], d["layer"], c["peaks"], c["nf"], cl,
+                                    bufs[e], with_vacc=False)
+
+        for _ in range(warmup):
+            cstep()
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        for _ in range(steps):
+            cstep()
+        torch.cuda.synchronize()
+        cw = time.perf_counter() - tc
+        conc = {"streams": C, "events_per_s": steps * B / cw,
+                "votes_per_s": steps * sum(votes) / cw,
+                "note": "same steps after the timed region, events round-robin over streams "
+                        "with one plan each"}
+        for pl in cplans[1:]:
+            pl.close()
+
+    n_events = steps * B
+    total_votes = steps * sum(votes)
+    lat_ms = np.array(lat_ms)
+    avg_ms = {k: (v[0] / v[1] if v[1] else float("nan")) for k, v in stages.items()}
+
+    # physics of the outputs (last step) and the seed search's work totals,
+    # outside the timed region
+    effs, fakes, n_trk, defined, executed = [], [], 0, [], []
+    for ev, b in zip(events, bufs):
+        out = b.to_host(ev.n_hits)
+        tm = M.track_metrics(ev, g, cl["min_layers"], out["tracks"]["hits"])
+        effs.append((tm["n_found"], tm["n_truth_acc"]))
+        fakes.append((tm["n_fake"], tm["n_tracks"]))
+        n_trk += tm["n_tracks"]
+        defined.append(int(out["work"][0]))
+        executed.append(int(out["work"][1]))
+    eff = sum(a for a, _ in effs) / max(1, sum(b for _, b in effs))
+    fake = sum(a for a, _ in fakes) / max(1, sum(b for _, b in fakes))
+
+    # Work actually executed per launch.
+    #  vote: the per-radius table path (every hit here lies on one of at most
+    #  16 distinct radii of its workgroup) computes u, the |u| test and the
+    #  arcsine once per (radius, column), 27 fp32 operations, and per vote
+    #  x = ((phi - s) - PHI_LO) * INVW and the floor, 4 operations.
+    #  refine: 13 fp64 operations per float64 circle distance the kernel
+    #  computed (work[1]); the float32 pre-filter is not counted.
+    table_path = all(n <= 16 for n in radii)
+    vote_exec = np.mean([(OPS_PER_EVAL + OPS_PER_VOTE) * n * ncol + 4 * V if table_path
+                         else OPS_PER_EVAL * E + OPS_PER_VOTE * V
+                         for n, E, V in zip(radii, evals, votes)])
+    vote_method = np.mean([OPS_PER_EVAL * E + OPS_PER_VOTE * V for E, V in zip(evals, votes)])
+    refine_exec = OPS_PER_TEST * float(np.mean(executed))
+    refine_method = OPS_PER_TEST * float(np.mean(defined))
+
+    def roofline(kernel, executed_ops, method_ops, peak, dtype):
+        t = avg_ms[kernel] / 1e3
+        achieved = executed_ops / t / 1e12
+        return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": traffic_from_profile(kernel, workload),
+                "kernel": f"{kernel}_kernel", "avg_launch_ms": avg_ms[kernel], "dtype": dtype,
+                "executed_ops_per_launch": executed_ops,
+                "method_ops_per_launch": method_ops,
+                "method_ops_frac": method_ops / t / 1e12 / peak,
+                "single_issue_peak": ALU_PEAK_TOPS,
+                "frac_single_issue": achieved / ALU_PEAK_TOPS}
+
+    rl = {"vote": roofline("vote", vote_exec, vote_method, FP32_PEAK_TFLOPS, "f32"),
+          "refine": roofline("refine", refine_exec, refine_method, FP64_PEAK_TFLOPS, "f64")}
+    # the dominant kernel by measured time among the timed kernels with an
+    # operation count (the member sweep has none of its own)
+    dominant = max(("vote", "refine"), key=lambda k: avg_ms.get(k, 0.0))
+
+    cpu = None
+    if cpu_events > 0:
+        cpu = cpu_baseline(W, events[:cpu_events], workload)
+
+    res = {
+        "workload": W["name"],
+        "events_per_step": B,
+        "mean_hits": float(np.mean([ev.n_hits for ev in events])),
+        "votes_per_s": total_votes / wall,
+        "events_per_s": n_events / wall,
+        "ms_per_step": wall * 1e3 / steps,
+        "p50_ms": float(np.percentile(lat_ms, 50)),
+        "p99_ms": float(np.percentile(lat_ms, 99)),
+        "track_efficiency": eff,
+        "fake_rate": fake,
+        "tracks_per_event": n_trk / B,
+        "vote_kernel_votes_per_s": float(np.mean(votes)) / (avg_ms["vote"] / 1e3),
+        "stage_ms": {k: avg_ms[k] for k in ("vote", "peaks", "members", "refine", "assoc")},
+        "roofline": rl[dominant],
+        "roofline_vote": rl["vote"],
+        "roofline_refine": rl["refine"],
+        "cpu_baseline": cpu,
+        "concurrent_streams": conc,
+        "grid": f"{g['n_phi']}x{g['n_qpt']}x{g['n_d0']}",
+        "parallelism": ("single GPU, events back to back on one stream" if S == 1
+                        else f"single GPU, {S} streams with one plan each, events "
+                             "round-robin and concurrent"),
+    }
+    for pl in plans:
+        pl.close()
+    return res
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -397,196 +638,40 @@ def main():
     if args.two_pass:
         two_pass_bench(args)
         return
-    from paper_1309_6275_amd import configs as CF
-    from paper_1309_6275_amd import eventgen as G
-    from paper_1309_6275_amd import houghtrig as H
-    from paper_1309_6275_amd import metrics as M
-
-    W = CF.WORKLOADS[args.workload]
-    g, cl = W["grid"], W["cluster"]
     torch.cuda.set_device(0)
-    B = args.batch
-    events = [G.make_event(args.workload, W["seed0"] + 100 + e) for e in range(B)]
-    peak_cap = 1 << 19 if args.workload < 3 else 1 << 21
-    S = max(1, args.streams)
-    plans = [H.Plan(g, max_hits=65535, max_peaks=peak_cap, max_member_cap=cl["member_cap"],
-                    max_tracks=1 << 14) for _ in range(S)]
-    plan = plans[0]
-    dev = []
-    for ev in events:
-        dev.append(dict(r=torch.from_numpy(ev.r).cuda(), phi=torch.from_numpy(ev.phi).cuda(),
-                        layer=torch.from_numpy(ev.layer).cuda(), n=ev.n_hits))
-    ctx = [dict(acc=torch.empty(plan.acc_shape, dtype=torch.int32, device="cuda"),
-                peaks=torch.empty((peak_cap, 2), dtype=torch.int32, device="cuda"),
-                nf=torch.zeros(1, dtype=torch.int32, device="cuda")) for _ in range(S)]
-    acc = ctx[0]["acc"]
-    nv = torch.zeros(1, dtype=torch.int64, device="cuda")
-    bufs = [H.ClusterBuffers(ev.n_hits, 1 << 14, 1024, 1 << 16, cl["n_rho"], cl["n_theta"])
-            for ev in events]
-
-    # per-event vote counts and evaluations (deterministic), outside timing
-    votes, evals = [], []
-    ncol = g["n_qpt"] * g["n_d0"]
-    for d, ev in zip(dev, events):
-        H.hough_vote(plan, d["r"], d["phi"], acc, nv)
-        torch.cuda.synchronize()
-        votes.append(int(nv.item()))
-        ok = (ev.r > 0) & (ev.r < 1e4) & (np.abs(ev.phi) <= 4)
-        evals.append(int(ok.sum()) * ncol)
-
-    # default-priority streams, one plan (tables and scratch) per stream
-    streams = [torch.cuda.Stream() for _ in range(S)]
-    torch.cuda.synchronize()
-    ev_a = [torch.cuda.Event(enable_timing=True) for _ in range(B)]
-    ev_c = [torch.cuda.Event(enable_timing=True) for _ in range(B)]
-
-    def step(record):
-        for e, d in enumerate(dev):
-            c, st, pl = ctx[e % S], streams[e % S], plans[e % S]
-            with torch.cuda.stream(st):
-                if record:
-                    ev_a[e].record(st)
-                H.hough_vote(pl, d["r"], d["phi"], c["acc"])
-                H.hough_peaks(pl, c["acc"], W["min_votes"], c["peaks"], c["nf"])
-                H.assoc_cluster(pl, d["r"], d["phi"], d["layer"], c["peaks"], c["nf"], cl,
-                                bufs[e], with_vacc=False)
-                if record:
-                    ev_c[e].record(st)
-
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    # stage timers: HIP events the library records around its kernels on each
-    # plan's launch stream, read after each step
-    for pl in plans:
-        H.profile_begin(pl, depth=2 * B)
-    stages = {}
-    lat_ms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
-        torch.cuda.synchronize()  # per-step sync so the events of this step can be read
-        for e in range(B):
-            lat_ms.append(ev_a[e].elapsed_time(ev_c[e]))
-        for pl in plans:
-            H.profile_read(pl, stages)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    for pl in plans:
-        H.profile_end(pl)
-
-    # the same steps on concurrent streams, each with its own plan: throughput
-    # when kernels of several events overlap (not the headline value, whose
-    # per-launch kernel times the roofline needs)
-    conc = None
-    if args.concurrent > 1 and S == 1:
-        C = args.concurrent
-        cplans = [plan] + [H.Plan(g, max_hits=65535, max_peaks=peak_cap,
-                                  max_member_cap=cl["member_cap"], max_tracks=1 << 14)
-                           for _ in range(C - 1)]
-        cctx = [ctx[0]] + [dict(acc=torch.empty(plan.acc_shape, dtype=torch.int32, device="cuda"),
-                                peaks=torch.empty((peak_cap, 2), dtype=torch.int32, device="cuda"),
-                                nf=torch.zeros(1, dtype=torch.int32, device="cuda"))
-                           for _ in range(C - 1)]
-        cstreams = [torch.cuda.Stream() for _ in range(C)]
-
-        def cstep():
-            for e, d in enumerate(dev):
-                c, st, pl = cctx[e % C], cstreams[e % C], cplans[e % C]
-                with torch.cuda.stream(st):
-                    H.hough_vote(pl, d["r"], d["phi"], c["acc"])
-                    H.hough_peaks(pl, c["acc"], W["min_votes"], c["peaks"], c["nf"])
-                    H.assoc_cluster(pl, d["r"], d["phi"], d["layer"], c["peaks"], c["nf"], cl,
-                                    bufs[e], with_vacc=False)
-
-        for _ in range(args.warmup):
-            cstep()
-        torch.cuda.synchronize()
-        tc = time.perf_counter()
-        for _ in range(args.steps):
-            cstep()
-        torch.cuda.synchronize()
-        cw = time.perf_counter() - tc
-        conc = {"streams": C, "events_per_s": args.steps * B / cw,
-                "votes_per_s": args.steps * sum(votes) / cw,
-                "note": "same steps after the timed region, events round-robin over streams "
-                        "with one plan each"}
-        for pl in cplans[1:]:
-            pl.close()
-
-    n_events = args.steps * B
-    total_votes = args.steps * sum(votes)
-    ms_per_step = wall * 1e3 / args.steps
-    lat_ms = np.array(lat_ms)
-    avg_ms = {k: (v[0] / v[1] if v[1] else float("nan")) for k, v in stages.items()}
-    # algorithmic work per launch: the vote's fp32 operations; the seed
-    # search's float64 road tests as the method defines them (every member
-    # against every admissible seed circle, counts[6] of each event)
-    tests = []
-    for ev, b in zip(events, bufs):
-        tests.append(int(b.to_host(ev.n_hits)["counts"][6]))
-    work = {"vote": np.mean([OPS_PER_EVAL * E + OPS_PER_VOTE * V for E, V in zip(evals, votes)]),
-            "refine": OPS_PER_TEST * float(np.mean(tests))}
-
-    def roofline(kernel):
-        achieved = work[kernel] / (avg_ms[kernel] / 1e3) / 1e12
-        return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
-                "frac": achieved / ALU_PEAK_TOPS,
-                "traffic": traffic_from_profile(kernel, args.workload),
-                "kernel": f"{kernel}_kernel", "avg_launch_ms": avg_ms[kernel]}
-
-    # the dominant kernel by measured time among the timed kernels
-    dominant = max(("vote", "refine", "members"), key=lambda k: avg_ms.get(k, 0.0))
-    if dominant == "members":  # no algorithmic figure of its own: report the next
-        dominant = max(("vote", "refine"), key=lambda k: avg_ms.get(k, 0.0))
-
-    # physics of the outputs (last step), outside the timed region
-    effs, fakes, n_trk = [], [], 0
-    for ev, b in zip(events, bufs):
-        out = b.to_host(ev.n_hits)
-        tm = M.track_metrics(ev, g, cl["min_layers"], out["tracks"]["hits"])
-        effs.append((tm["n_found"], tm["n_truth_acc"]))
-        fakes.append((tm["n_fake"], tm["n_tracks"]))
-        n_trk += tm["n_tracks"]
-    eff = sum(a for a, _ in effs) / max(1, sum(b for _, b in effs))
-    fake = sum(a for a, _ in fakes) / max(1, sum(b for _, b in fakes))
-
-    cpu = None
-    if args.cpu_sample > 0:
-        cpu = cpu_baseline(W, events[:args.cpu_sample], votes[:args.cpu_sample])
-
+    wl = args.workload
+    B = args.batch if args.batch else DEFAULT_BATCH[wl]
+    cpu_events = args.cpu_sample if args.cpu_sample >= 0 else DEFAULT_CPU_EVENTS[wl]
+    r = measure(args, wl, B, args.steps, args.warmup, cpu_events, args.concurrent)
     line = {
         "metric": METRIC,
-        "value": total_votes / wall,
+        "value": r["votes_per_s"],
         "unit": "votes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": W["name"], "events_per_step": B,
-                   "grid": f"{g['n_phi']}x{g['n_qpt']}x{g['n_d0']}",
-                   "mean_hits": float(np.mean([ev.n_hits for ev in events])),
-                   "parallelism": ("single GPU, events back to back on one stream" if S == 1
-                                   else f"single GPU, {S} streams with one plan each, events "
-                                        "round-robin and concurrent")},
-        "events_per_s": n_events / wall,
-        "p50_ms": float(np.percentile(lat_ms, 50)),
-        "p99_ms": float(np.percentile(lat_ms, 99)),
-        "track_efficiency": eff,
-        "fake_rate": fake,
-        "tracks_per_event": n_trk / B,
-        "vote_kernel_votes_per_s": float(np.mean(votes)) / (avg_ms["vote"] / 1e3),
-        "stage_ms": {k: avg_ms[k] for k in ("vote", "peaks", "members", "refine", "assoc")},
-        "roofline": roofline(dominant),
-        "roofline_vote": roofline("vote"),
-        "cpu_baseline": cpu,
-        "concurrent_streams": conc,
+        "config": {"workload": r["workload"], "events_per_step": B, "grid": r["grid"],
+                   "mean_hits": r["mean_hits"], "parallelism": r["parallelism"]},
     }
+    for k in ("events_per_s", "p50_ms", "p99_ms", "track_efficiency", "fake_rate",
+              "tracks_per_event", "vote_kernel_votes_per_s", "stage_ms", "roofline",
+              "roofline_vote", "roofline_refine", "cpu_baseline", "concurrent_streams"):
+        line[k] = r[k]
+    # the displaced-jet workload beside it, where the method reaches its
+    # efficiency; same figures, its own timed region after the first
+    if args.second_workload and args.second_workload != wl:
+        w2 = args.second_workload
+        r2 = measure(args, w2, DEFAULT_BATCH[w2], args.steps, args.warmup, 0, 0)
+        line[f"workload_{w2}"] = {k: r2[k] for k in (
+            "workload", "events_per_step", "mean_hits", "votes_per_s", "events_per_s",
+            "ms_per_step", "p50_ms", "p99_ms", "track_efficiency", "fake_rate",
+            "tracks_per_event", "stage_ms", "roofline", "roofline_vote", "roofline_refine")}
     print(json.dumps(line), flush=True)
 
 

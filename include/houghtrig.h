@@ -133,6 +133,11 @@ typedef struct {
                               over member_cap, (candidate, member) pairs of the others,
                               road tests of the seed search ((admissible seed circle,
                               member) pairs), 0; a count above INT32_MAX reads INT32_MAX */
+  unsigned long long* work;/* [2] device, or NULL: the seed search's work as 64-bit totals:
+                              [0] road tests the method defines (as counts[6], unclamped),
+                              [1] float64 circle distances actually computed (members that
+                              pass the float32 pre-filter on lanes still able to reach
+                              min_layers, plus the tied lanes' distance sums) */
 } ht_cluster_out;
 
 typedef struct ht_plan ht_plan;

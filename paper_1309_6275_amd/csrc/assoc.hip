@@ -64,9 +64,11 @@ enum { S_NP = 0, S_NBAD = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5 };
 constexpr int kSpread = 64;
 constexpr int kSpreadStride = 16;  // 64-bit words: one 128-byte line per slot
 // group g of the counters starts at slot g * kSpread: 0 road tests,
-// 1 refined candidates, 2 candidates over member_cap, 3 pairs within it
-enum { SP_TESTS = 0, SP_NCAND = kSpread, SP_NOVER = 2 * kSpread, SP_PAIRS = 3 * kSpread };
-static_assert(4 * kSpread * kSpreadStride == kSpreadWords, "spread counter layout");
+// 1 refined candidates, 2 candidates over member_cap, 3 pairs within it,
+// 4 float64 circle distances computed
+enum { SP_TESTS = 0, SP_NCAND = kSpread, SP_NOVER = 2 * kSpread, SP_PAIRS = 3 * kSpread,
+       SP_EXEC = 4 * kSpread };
+static_assert(5 * kSpread * kSpreadStride == kSpreadWords, "spread counter layout");
 
 __device__ __forceinline__ float bcastf(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -776,6 +778,10 @@ struct WaveMem {
 template <int CAP>
 struct RefineShape {
   static constexpr int kWaves = CAP <= 128 ? 4 : (CAP <= 256 ? 2 : 1);
+  // workgroups per CU the register budget is set for: six waves per SIMD
+  // for caps up to 128 (the LDS of six workgroups fits), else left to the
+  // compiler (LDS allows no more)
+  static constexpr int kMinBlocks = CAP <= 128 ? 6 : 1;
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -862,8 +868,13 @@ __device__ __forceinline__ int nth_set_bit(unsigned mask, int n) {
 }
 
 template <int CAP>
-__global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kernel(AssocArgs A) {
+__global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave, RefineShape<CAP>::kMinBlocks) void
+refine_kernel(AssocArgs A) {
   constexpr int W = RefineShape<CAP>::kWaves;
+  // members per chunk of the road loop (registers: 4 per member); the
+  // short member lists of caps up to 128 keep one member at a time, which
+  // leaves the registers for a fifth wave per SIMD
+  constexpr int kChunk = CAP <= 128 ? 1 : 8;
   __shared__ WaveMem<CAP> MW[W];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x >> 6;
@@ -875,12 +886,13 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
   // the wave's rarely changed totals (candidates over member_cap, member
   // pairs) stay in its LDS slot, kept by lane 0, rather than in registers
   // live across the whole search
-  __shared__ unsigned long long tot[W][4];
+  __shared__ unsigned long long tot[W][5];
   if (lane == 0) {
     tot[wave][2] = 0;
     tot[wave][3] = 0;
   }
   unsigned long long tests = 0, ncand = 0;
+  uint32_t exec = 0;  // this lane's float64 circle distances
   for (int p = blockIdx.x * W + wave; p < np; p += gridDim.x * W) {
     const int lin = A.peaks[p].lin;
     const int n = A.mcount[p];
@@ -1030,19 +1042,28 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
       }
       if (s >= 0 && rank < kk) M.seed[s][rank] = e;
     } else {
+      // more members than lanes: the ns[s] smallest keys of each seed layer
+      // by repeated wave minima; lane l holds members st + l + 64 t, and the
+      // keys are distinct (a hit is a member once), so each minimum has one
+      // owner, which records it and leaves it out of the next round
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
         const int st = sst[s], en = sen[s];
-        for (int e = st + lane; e < en; e += kWave) {
-          const unsigned long long key =
-              ((unsigned long long)__float_as_uint(M.adx[e]) << 32) | (unsigned)M.mem[e].h;
-          int rank = 0;
-          for (int e2 = st; e2 < en; ++e2) {
-            const unsigned long long k2 =
-                ((unsigned long long)__float_as_uint(M.adx[e2]) << 32) | (unsigned)M.mem[e2].h;
-            rank += k2 < key;
+        unsigned long long taken = 0;
+        for (int r = 0; r < ns[s]; ++r) {
+          unsigned long long mine = ~0ull;
+          int arg = -1;
+          for (int e = st + lane, t = 0; e < en; e += kWave, ++t) {
+            if ((taken >> t) & 1ull) continue;
+            const unsigned long long key =
+                ((unsigned long long)__float_as_uint(M.adx[e]) << 32) | (unsigned)M.mem[e].h;
+            if (key < mine) { mine = key; arg = t; }
           }
-          if (rank < kk) M.seed[s][rank] = e;
+          const unsigned long long best = wave_min_u64(mine);
+          if (arg >= 0 && mine == best) {
+            M.seed[s][r] = st + lane + arg * kWave;
+            taken |= 1ull << arg;
+          }
         }
       }
     }
@@ -1136,14 +1157,46 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
       const int en = __builtin_amdgcn_readlane(ls, L + 1);
       double bd = 0.0;
       int bh = -1;
-      for (int e = st; e < en; ++e) {
-        const Mem4 v = M.mem[e];
-        const float f32 = __builtin_fmaf(Af, v.q, __builtin_fmaf(Bf, v.x, __builtin_fmaf(Cf, v.y, Df)));
-        if (!(active && fabsf(f32) <= thr)) continue;
-        const int hh = v.h;
-        const double dist = fabs(circle_dist(cA, cB, cC, cD, A.hx[hh], A.hy[hh], A.hq[hh]));
-        if (!(dist <= road)) continue;
-        if (bh < 0 || dist < bd || (dist == bd && hh < bh)) { bh = hh; bd = dist; }
+      // members in chunks: the chunk's LDS reads (broadcasts, every lane
+      // reads the same member) are issued together, then the float32
+      // pre-filter of each lane's circle marks the members worth a float64
+      // distance; the selection (smallest distance, then hit index) does not
+      // depend on the visiting order
+      if constexpr (kChunk == 1) {
+        for (int e = st; e < en; ++e) {
+          const Mem4 v = M.mem[e];
+          const float f32 =
+              __builtin_fmaf(Af, v.q, __builtin_fmaf(Bf, v.x, __builtin_fmaf(Cf, v.y, Df)));
+          if (!(active && fabsf(f32) <= thr)) continue;
+          const int hh = v.h;
+          ++exec;
+          const double dist = fabs(circle_dist(cA, cB, cC, cD, A.hx[hh], A.hy[hh], A.hq[hh]));
+          if (!(dist <= road)) continue;
+          if (bh < 0 || dist < bd || (dist == bd && hh < bh)) { bh = hh; bd = dist; }
+        }
+      } else for (int e0 = st; e0 < en; e0 += kChunk) {
+        Mem4 v[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) v[u] = M.mem[min(e0 + u, en - 1)];
+        unsigned pass = 0;
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+          const float f32 =
+              __builtin_fmaf(Af, v[u].q, __builtin_fmaf(Bf, v[u].x, __builtin_fmaf(Cf, v[u].y, Df)));
+          pass |= (fabsf(f32) <= thr ? 1u : 0u) << u;
+        }
+        const int left = en - e0;
+        if (!active) pass = 0;
+        if (left < kChunk) pass &= (1u << left) - 1u;
+        while (pass) {
+          const int u = __builtin_ctz(pass);
+          pass &= pass - 1u;
+          const int hh = M.mem[e0 + u].h;
+          ++exec;
+          const double dist = fabs(circle_dist(cA, cB, cC, cD, A.hx[hh], A.hy[hh], A.hq[hh]));
+          if (!(dist <= road)) continue;
+          if (bh < 0 || dist < bd || (dist == bd && hh < bh)) { bh = hh; bd = dist; }
+        }
       }
       if (active) {
         hitL[L] = bh < 0 ? kNoHit : (uint16_t)bh;
@@ -1162,6 +1215,7 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
       for (unsigned lm = lmask; lm; lm &= lm - 1u) {
         const int hh = hitL[__builtin_ctz(lm)];
         if (hh == kNoHit) continue;
+        ++exec;
         const double d = fabs(circle_dist(cA, cB, cC, cD, A.hx[hh], A.hy[hh], A.hq[hh]));
         ss += d * d;
       }
@@ -1185,13 +1239,16 @@ __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave) void refine_kerne
     }
     wave_sync();
   }
-  // the workgroup's totals, one atomic per counter from lanes 0-3 of wave 0
+  // the workgroup's totals, one atomic per counter from lanes 0-4 of wave 0
+  unsigned long long ex = exec;
+  for (int off = kWave / 2; off > 0; off >>= 1) ex += __shfl_xor(ex, off);
   if (lane == 0) {
     tot[wave][0] = tests;
     tot[wave][1] = ncand;
+    tot[wave][4] = ex;
   }
   __syncthreads();
-  if (threadIdx.x < 4) {
+  if (threadIdx.x < 5) {
     unsigned long long v = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) v += tot[w][threadIdx.x];
@@ -1727,13 +1784,19 @@ __global__ __launch_bounds__(kWave) void counts_kernel(AssocArgs A) {
   unsigned long long tests = A.spread[(size_t)(SP_TESTS + lane) * kSpreadStride];
   unsigned long long nover = A.spread[(size_t)(SP_NOVER + lane) * kSpreadStride];
   unsigned long long pairs = A.spread[(size_t)(SP_PAIRS + lane) * kSpreadStride];
+  unsigned long long exec = A.spread[(size_t)(SP_EXEC + lane) * kSpreadStride];
   for (int off = kWave / 2; off > 0; off >>= 1) {
     ncand += __shfl_xor(ncand, off);
     tests += __shfl_xor(tests, off);
     nover += __shfl_xor(nover, off);
     pairs += __shfl_xor(pairs, off);
+    exec += __shfl_xor(exec, off);
   }
   if (lane != 0) return;
+  if (A.out.work) {
+    A.out.work[0] = tests;
+    A.out.work[1] = exec;
+  }
   c[0] = (int32_t)ncand;
   c[1] = A.sc[S_NTRK];
   c[2] = A.sc[S_NOBJ];

@@ -11,8 +11,8 @@
 
 namespace ht {
 
-// four groups of 64 counters, one 128-byte line each (the seed search's totals)
-constexpr int kSpreadWords = 4 * 64 * 16;
+// five groups of 64 counters, one 128-byte line each (the seed search's totals)
+constexpr int kSpreadWords = 5 * 64 * 16;
 
 // Hit slices for launches of one workgroup per 64-column tile: grids with
 // fewer than 128 tiles also split the hits, so that about 256 workgroups run,

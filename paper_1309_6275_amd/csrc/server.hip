@@ -189,6 +189,7 @@ int device_part(const ht_server_cfg& c, Slot& s, int k) {
   o.member_cap = c.member_cap;
   o.vacc = nullptr;
   o.counts = s.d_counts;
+  o.work = nullptr;
   rc = ht::launch_assoc(P, s.d_r, s.d_phi, s.d_layer, c.max_hits, s.d_peaks, s.d_npeaks,
                         K.peak_cap, s.d_acc, K.cluster, o, s.stream, s.d_nhits);
   if (rc != HT_OK) return rc;

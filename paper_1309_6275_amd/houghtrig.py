@@ -64,7 +64,7 @@ class ClusterOut(C.Structure):
     _fields_ = [("hit_owner", C.c_void_p), ("tracks", C.c_void_p), ("track_cap", C.c_int32),
                 ("objects", C.c_void_p), ("object_cap", C.c_int32),
                 ("members", C.c_void_p), ("member_cap", C.c_int32),
-                ("vacc", C.c_void_p), ("counts", C.c_void_p)]
+                ("vacc", C.c_void_p), ("counts", C.c_void_p), ("work", C.c_void_p)]
 
 
 SERVER_MAX_KINDS = 4
@@ -315,13 +315,15 @@ class ClusterBuffers:
         self.members = torch.zeros(max(member_cap, 1), dtype=torch.int32, device=device)
         self.vacc = torch.zeros((n_rho, n_theta), dtype=torch.int32, device=device)
         self.counts = torch.zeros(8, dtype=torch.int32, device=device)
+        # the seed search's 64-bit work totals: road tests defined, float64 distances computed
+        self.work = torch.zeros(2, dtype=torch.int64, device=device)
         self.track_cap, self.object_cap, self.member_cap = track_cap, object_cap, member_cap
 
     def struct(self, with_vacc=True) -> ClusterOut:
         return ClusterOut(self.hit_owner.data_ptr(), self.tracks.data_ptr(), self.track_cap,
                           self.objects.data_ptr(), self.object_cap, self.members.data_ptr(),
                           self.member_cap, self.vacc.data_ptr() if with_vacc else None,
-                          self.counts.data_ptr())
+                          self.counts.data_ptr(), self.work.data_ptr())
 
     def to_host(self, n_hits):
         """Copy back as numpy (structured track/object arrays), trimmed."""
@@ -333,7 +335,7 @@ class ClusterBuffers:
         ob = self.objects.cpu().numpy().view(OBJECT_DTYPE).reshape(-1)[:no].copy()
         return dict(hit_owner=self.hit_owner[:n_hits].cpu().numpy(), tracks=tr, objects=ob,
                     members=self.members[:nm].cpu().numpy(), vacc=self.vacc.cpu().numpy(),
-                    counts=counts)
+                    counts=counts, work=self.work.cpu().numpy())
 
 
 def compact_hits(r, phi, layer, hit_owner, out_r, out_phi, out_layer, out_index, n_out,

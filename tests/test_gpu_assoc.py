@@ -47,9 +47,11 @@ def plan_for(ht, grid, member_cap=1024):
 
 
 def run_gpu(torch, ht, grid, ev, min_votes, cfg, peak_cap=None, track_cap=4096,
-            object_cap=512, member_cap=1 << 15, with_vacc=True, use_acc=True):
+            object_cap=512, member_cap=1 << 15, with_vacc=True, use_acc=True, peak_stride=1):
     """Vote, peaks and assoc_cluster on the device; assoc_cluster gets the
-    accumulator (member-count bound) unless use_acc is False."""
+    accumulator (member-count bound) unless use_acc is False.  peak_stride > 1
+    hands assoc_cluster every peak_stride-th peak of the full list (still in
+    cell order) instead of the first peak_cap."""
     plan = plan_for(ht, grid)
     r = torch.from_numpy(ev.r).cuda()
     phi = torch.from_numpy(ev.phi).cuda()
@@ -60,6 +62,15 @@ def run_gpu(torch, ht, grid, ev, min_votes, cfg, peak_cap=None, track_cap=4096,
     peaks = torch.full((max(cap, 1), 2), -1, dtype=torch.int32, device="cuda")
     nf = torch.zeros(1, dtype=torch.int32, device="cuda")
     ht.hough_peaks(plan, acc, min_votes, peaks[:cap], nf)
+    if peak_stride > 1:
+        torch.cuda.synchronize()
+        n_all = int(nf.item())
+        assert n_all <= cap
+        sub = peaks[:n_all:peak_stride].contiguous()
+        cap = int(sub.shape[0])
+        peaks = torch.full((max(cap, 1), 2), -1, dtype=torch.int32, device="cuda")
+        peaks[:cap] = sub
+        nf = torch.tensor([cap], dtype=torch.int32, device="cuda")
     bufs = ht.ClusterBuffers(max(ev.n_hits, 1), track_cap, object_cap, member_cap,
                              cfg["n_rho"], cfg["n_theta"])
     ht.assoc_cluster(plan, r, phi, layer, peaks[:cap], nf, cfg, bufs, with_vacc=with_vacc,
@@ -113,16 +124,34 @@ def test_assoc_parity_workloads(torch, ht, oracle, cfgid, seeds):
         compare(got, want, f"cfg{cfgid}/{seed}")
 
 
-def test_assoc_parity_dense_event_truncated_peaks(torch, ht, oracle):
-    """The 55k-hit workload with the candidate list cut to its first 3000
-    peaks (the oracle's per-candidate scan of all hits bounds the size)."""
+def test_assoc_parity_dense_event_strided_peaks(torch, ht, oracle):
+    """The 55k-hit workload with every 64th peak of its list (cell order, so
+    the subset spans every d0 plane)."""
     W = CF.WORKLOADS[3]
     ev = G.make_event(3, W["seed0"])
-    print(f"cfg3 hits {ev.n_hits}", flush=True)
+    print(f"cfg3 hits {ev.n_hits}, every 64th peak", flush=True)
     got, acc, pk = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], W["cluster"],
-                           peak_cap=3000)
+                           peak_stride=64)
+    g = W["grid"]
+    planes = np.unique(pk[:, 0] // (g["n_phi"] * g["n_qpt"]))
+    assert planes.size == g["n_d0"], planes.size
     want = run_oracle(oracle, W["grid"], ev, acc, pk, W["cluster"])
-    compare(got, want, "cfg3/3000")
+    compare(got, want, "cfg3/stride 64")
+
+
+def test_assoc_parity_dense_event_full_list(torch, ht, oracle):
+    """The 55k-hit workload with its whole peak list (about 2.3e5 candidates;
+    the oracle takes about half a minute on 16 cores)."""
+    W = CF.WORKLOADS[3]
+    ev = G.make_event(3, W["seed0"] + 2)
+    print(f"cfg3 hits {ev.n_hits}, full peak list", flush=True)
+    got, acc, pk = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], W["cluster"],
+                           track_cap=1 << 14, object_cap=1024)
+    print(f"peaks {pk.shape[0]}, tracks {int(got['counts'][1])}", flush=True)
+    assert pk.shape[0] > 100000
+    want = run_oracle(oracle, W["grid"], ev, acc, pk, W["cluster"], track_cap=1 << 14,
+                      object_cap=1024)
+    compare(got, want, "cfg3/full")
 
 
 def test_assoc_parity_many_peaks_per_workgroup(torch, ht, oracle):

@@ -132,3 +132,69 @@ def test_keep_compaction(torch, ht, event_peaks):
         keep = np.flatnonzero(lg[:m] >= thr)
         assert int(n_out.item()) == keep.size
         assert np.array_equal(out[:keep.size].cpu().numpy(), pk[:max(cap, 1)].cpu().numpy()[keep])
+
+
+def test_filter_end_to_end_matches_oracle(torch, ht, oracle, event_peaks):
+    """Windows -> ht_cnn_forward -> ht_cnn_keep -> assoc_cluster on the device
+    against oracle windows -> cnn.forward -> the same threshold -> the
+    oracle's assoc_cluster on the kept list.  The threshold is the midpoint
+    of the widest gap between consecutive oracle logits in the middle 60% of
+    them; every keep decision must be the same on both sides (the device
+    forward is deterministic, so this holds or fails for good on these
+    windows), and assoc_cluster on the kept list is held to its usual bar."""
+    from test_gpu_assoc import compare, run_oracle
+    plan, acc, peaks, nf = event_peaks
+    W = CF.WORKLOADS[2]
+    g = W["grid"]
+    # the peaks of the two d0 planes around d0 = 0, where the prompt tracks'
+    # candidates lie (a list in cell order)
+    allp = peaks[:int(nf.item())]
+    k = allp[:, 0] // (g["n_phi"] * g["n_qpt"])
+    pk = allp[(k >= g["n_d0"] // 2 - 1) & (k <= g["n_d0"] // 2)].contiguous()
+    cap = int(pk.shape[0])
+    assert cap > 1000
+    win = gpu_windows(torch, ht, plan, acc, pk, cap)
+    params = cnn.init_params(21)
+    p = torch.from_numpy(params).cuda()
+    logits = torch.empty(cap, dtype=torch.float32, device="cuda")
+    ht.cnn_forward(p, win, logits, ht.cnn_workspace(cap))
+    acc_h = acc.cpu().numpy()
+    x = cnn.windows(acc_h, pk[:, 0].cpu().numpy())
+    z_o, _ = cnn.forward(params, x)
+    z_g = logits.cpu().numpy().astype(np.float64)
+    err = float(np.abs(z_g - z_o).max())
+    assert err <= 2e-2 + 2e-2 * float(np.abs(z_o).max())
+    # the widest gap between consecutive oracle logits with at least 20% of
+    # the windows on each side
+    zs = np.sort(z_o)
+    lo, hi = int(0.2 * cap), int(0.8 * cap)  # noqa: E501
+    gaps = zs[lo + 1:hi] - zs[lo:hi - 1]
+    g = int(np.argmax(gaps))
+    thr = 0.5 * (zs[lo + g] + zs[lo + g + 1])
+    near = int((np.abs(z_o - thr) <= err).sum())
+    print(f"{cap} windows, threshold {thr:.5f}, gap {gaps[g]:.2e}, max logit difference "
+          f"{err:.2e}, oracle logits within it of the threshold: {near}", flush=True)
+    keep_o = np.flatnonzero(z_o >= thr)
+    assert np.array_equal(np.flatnonzero(z_g >= thr), keep_o)
+    n_in = torch.tensor([cap], dtype=torch.int32, device="cuda")
+    kept = torch.full((cap, 2), -1, dtype=torch.int32, device="cuda")
+    n_kept = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ht.cnn_keep(plan, logits, pk, n_in, float(thr), kept, n_kept)
+    torch.cuda.synchronize()
+    nk = int(n_kept.item())
+    assert nk == keep_o.size and 0.2 * cap <= nk <= 0.8 * cap
+    pk_h = pk.cpu().numpy()
+    assert np.array_equal(kept[:nk].cpu().numpy(), pk_h[keep_o])
+    # assoc_cluster on the kept list, device and oracle
+    ev = G.make_event(2, W["seed0"] + 3)
+    r = torch.from_numpy(ev.r).cuda()
+    phi = torch.from_numpy(ev.phi).cuda()
+    layer = torch.from_numpy(ev.layer).cuda()
+    cl = W["cluster"]
+    bufs = ht.ClusterBuffers(ev.n_hits, 4096, 512, 1 << 15, cl["n_rho"], cl["n_theta"])
+    ht.assoc_cluster(plan, r, phi, layer, kept, n_kept, cl, bufs, acc=acc)
+    torch.cuda.synchronize()
+    got = bufs.to_host(ev.n_hits)
+    want = run_oracle(oracle, W["grid"], ev, acc_h, pk_h[keep_o], cl)
+    compare(got, want, "filter end to end")
+    assert int(want["counts"][1]) > 0

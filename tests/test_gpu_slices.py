@@ -189,20 +189,23 @@ def _three_cell_votes(acc, lin, n_phi):
     return flat[cols, (i - 1) % n_phi] + flat[cols, i] + flat[cols, (i + 1) % n_phi]
 
 
-def test_member_bound_dense_event_truncated_peaks(torch, ht, oracle):
-    """The 55k-hit workload with member_cap 128 and its first 3000 peaks:
-    the accumulator bound drops most candidates before the member search;
-    the outputs equal the oracle's and those of the run without the bound."""
+def test_member_bound_dense_event_strided_peaks(torch, ht, oracle):
+    """The 55k-hit workload with member_cap 128 and every 64th peak (all d0
+    planes): the accumulator bound drops most candidates before the member
+    search; the outputs equal the oracle's and those of the run without the
+    bound."""
     W = CF.WORKLOADS[3]
     ev = G.make_event(3, W["seed0"] + 1)
     cfg = dict(W["cluster"], member_cap=128)
-    print(f"bound cfg3 hits {ev.n_hits}", flush=True)
-    got, acc, pk = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], cfg, peak_cap=3000)
-    plain, _, _ = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], cfg, peak_cap=3000,
+    print(f"bound cfg3 hits {ev.n_hits}, every 64th peak", flush=True)
+    got, acc, pk = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], cfg, peak_stride=64)
+    plain, _, _ = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], cfg, peak_stride=64,
                           use_acc=False)
     _same_outputs(got, plain, "bound vs none")
+    g = W["grid"]
+    assert np.unique(pk[:, 0] // (g["n_phi"] * g["n_qpt"])).size == g["n_d0"]
     want = run_oracle(oracle, W["grid"], ev, acc, pk, cfg)
-    compare(got, want, "bound cfg3/3000")
+    compare(got, want, "bound cfg3/stride 64")
     fired = int((_three_cell_votes(acc, pk[:, 0], W["grid"]["n_phi"]) > 128).sum())
     assert fired > pk.shape[0] // 2
     assert want["counts"][4] >= fired
