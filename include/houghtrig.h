@@ -96,7 +96,8 @@ typedef struct {
   float bh_max_isotropy;   /* ... and |mean member direction| at most this */
   float vtx_min_d0;        /* tracks with seed |d0| below this [cm] cast no vertex votes (0: all vote) */
   int32_t fit_kind;        /* refit: 0 Gauss-Newton least squares, 1 extended Kalman filter */
-  int32_t reserved;        /* must be 0 */
+  int32_t vtx_two_branch;  /* 0: vertex votes on the outgoing branch only; 1: also on the
+                              incoming branch (see assoc_cluster) */
 } ht_cluster_cfg;
 
 typedef struct {
@@ -250,6 +251,12 @@ int hough_peaks_noalloc(const ht_grid* grid, const int32_t* acc, int32_t min_vot
  *              and |mean perigee direction| <= bh_max_isotropy; tracks whose seed
  *              circle passes within vtx_min_d0 of the beam line are
  *              features at the interaction point and cast no vertex votes.
+ *              With vtx_two_branch = 1 each track also votes for the cells
+ *              its circle crosses before the perigee (the path of a track
+ *              sent from its vertex towards the beam line, as half of an
+ *              isotropic decay's are), from |d0| to rho_hi; a cell covered
+ *              by both arcs of a row gets one vote, and membership counts
+ *              either arc.
  *   r, phi, layer  [n_hits] hits (layer index increasing with radius)
  *   peaks, n_peaks peak list and device count from hough_peaks (sorted by
  *                  lin, no cell twice); entries beyond min(*n_peaks,

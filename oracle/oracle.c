@@ -987,7 +987,12 @@ static void kf_track(const or_grid* g, const float* r, const float* phi, const i
  * |d0| and the radius of its first owned hit (the vertex cannot lie outside
  * the first hit): in row m the crossing azimuths at the ends of
  * [max(e_m, |d0|), min(e_m+1, r_first)] span an arc of theta bins, all of
- * which get one vote.  A crossing at radius rho solves the circle's line
+ * which get one vote.  With vtx_two_branch the track also votes on its
+ * incoming branch, the part of the circle before the perigee that a track
+ * sent from its vertex towards the beam line follows (an isotropic decay
+ * sends half of its tracks that way): in row m the incoming crossings at the
+ * ends of [max(e_m, |d0|), e_m+1] span a second arc, and each cell of the
+ * union of the two arcs gets one vote.  A crossing at radius rho solves the circle's line
  * equation B x + C y = -(A rho^2 + D) on the circle of radius rho and takes
  * the point ahead of the perigee along the direction of motion; theta comes
  * from the canonical atan2; float64 arithmetic and square roots only.
@@ -996,19 +1001,33 @@ static void kf_track(const or_grid* g, const float* r, const float* phi, const i
  * (section "Physics Motivation": high multiplicity, omnidirectional) when it
  * has at least bh_min_tracks members and the length of the mean member
  * direction (perigee directions) is at most bh_max_isotropy. */
-static double crossing_theta(const cand_t* c, double sn, double rho) {
+static int theta_bin(double th, int nt) {
+  int t = (int)floor((th + OR_PI) / (2.0 * OR_PI / (double)nt));
+  return ((t % nt) + nt) % nt;
+}
+
+/* branch > 0: the crossing ahead of the perigee along the direction of
+ * motion (outgoing branch); branch < 0: the one before it (incoming) */
+static double crossing_theta(const cand_t* c, double sn, double rho, int branch) {
   double c0 = -(c->A * rho * rho + c->D);
   double dl = c0 / sn;
   double hh = (rho - dl) * (rho + dl);
   double h = hh > 0.0 ? sqrt(hh) : 0.0;
+  if (branch < 0) h = -h;
   double px = (dl / sn) * c->B + (h / sn) * (-c->C);
   double py = (dl / sn) * c->C + (h / sn) * c->B;
   return catan2(py, px);
 }
 
-static int theta_bin(double th, int nt) {
-  int t = (int)floor((th + OR_PI) / (2.0 * OR_PI / (double)nt));
-  return ((t % nt) + nt) % nt;
+/* the arc of theta bins between the crossings at radii ra < rb of one
+ * branch: the shorter way round from the bin of one end to the other */
+static void branch_arc(const cand_t* c, double sn, double ra, double rb, int branch, int nt,
+                       int32_t* start, int32_t* len) {
+  int ta = theta_bin(crossing_theta(c, sn, ra, branch), nt);
+  int tb = theta_bin(crossing_theta(c, sn, rb, branch), nt);
+  int d = ((tb - ta) % nt + nt) % nt; /* steps from ta to tb going up */
+  if (d <= nt / 2) { *start = ta; *len = d + 1; }
+  else { *start = tb; *len = nt - d + 1; }
 }
 
 static int is_peak2(const int32_t* v, int nm, int nt, int m, int t, int32_t thr) {
@@ -1055,7 +1074,8 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
       cfg->seed_k < 1 || cfg->seed_k > 64 || cfg->member_cap < 1 || !(cfg->road_sigmas > 0.0f) ||
       !(cfg->box_margin >= 0.0f) || cfg->fit_iters < 0 || cfg->n_rho < 1 || cfg->n_theta < 4 ||
       !(cfg->rho_hi > cfg->rho_lo) || !(cfg->rho_lo > 0.0f) || !(cfg->sigma_rphi > 0.0f) ||
-      !(cfg->vtx_min_d0 >= 0.0f) || cfg->fit_kind < 0 || cfg->fit_kind > 1)
+      !(cfg->vtx_min_d0 >= 0.0f) || cfg->fit_kind < 0 || cfg->fit_kind > 1 ||
+      cfg->vtx_two_branch < 0 || cfg->vtx_two_branch > 1)
     return -1;
   tables tb;
   if (make_tables(g, &tb)) { free_tables(&tb); return -2; }
@@ -1163,9 +1183,13 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
   /* 5. vertex transform over the stored tracks */
   const int nm = cfg->n_rho, nt = cfg->n_theta;
   int32_t* vacc = (int32_t*)calloc((size_t)nm * nt, sizeof(int32_t));
-  /* per (track, row): first bin of the arc and its length (0 = no vote) */
-  int32_t* tv0 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_stored > 0 ? n_stored : 1) * nm);
-  int32_t* tvn = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_stored > 0 ? n_stored : 1) * nm);
+  /* per (track, row): first bin of the arc and its length (0 = no vote), on
+   * the outgoing branch (tv0, tvn) and the incoming one (ti0, tin) */
+  const size_t narc = (size_t)(n_stored > 0 ? n_stored : 1) * nm;
+  int32_t* tv0 = (int32_t*)malloc(sizeof(int32_t) * narc);
+  int32_t* tvn = (int32_t*)malloc(sizeof(int32_t) * narc);
+  int32_t* ti0 = (int32_t*)malloc(sizeof(int32_t) * narc);
+  int32_t* tin = (int32_t*)malloc(sizeof(int32_t) * narc);
   const double rw = ((double)cfg->rho_hi - (double)cfg->rho_lo) / (double)nm;
   for (int32_t t = 0; t < n_stored; ++t) {
     const cand_t* c = &cd[trk_peak[t]];
@@ -1176,22 +1200,26 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
      * the interaction point (the paper's filter near the IP): no votes */
     int votes = !(pca < (double)cfg->vtx_min_d0);
     for (int m = 0; m < nm; ++m) {
-      tv0[(size_t)t * nm + m] = 0;
-      tvn[(size_t)t * nm + m] = 0;
+      const size_t a = (size_t)t * nm + m;
+      tv0[a] = tvn[a] = ti0[a] = tin[a] = 0;
       double e0 = (double)cfg->rho_lo + (double)m * rw;
       double e1 = (double)cfg->rho_lo + (double)(m + 1) * rw;
       double ra = e0 > pca ? e0 : pca;
+      if (!votes) continue;
+      /* outgoing branch: between the perigee and the first hit */
       double rb = e1 < rf ? e1 : rf;
-      if (!votes || !(ra < rb)) continue;
-      int ta = theta_bin(crossing_theta(c, sn, ra), nt);
-      int tb = theta_bin(crossing_theta(c, sn, rb), nt);
-      int d = ((tb - ta) % nt + nt) % nt; /* steps from ta to tb going up */
-      int start, len;
-      if (d <= nt / 2) { start = ta; len = d + 1; }
-      else { start = tb; len = nt - d + 1; }
-      tv0[(size_t)t * nm + m] = start;
-      tvn[(size_t)t * nm + m] = len;
-      for (int q = 0; q < len; ++q) vacc[m * nt + (start + q) % nt] += 1;
+      if (ra < rb) branch_arc(c, sn, ra, rb, +1, nt, &tv0[a], &tvn[a]);
+      /* incoming branch (two-branch vote): the part of the circle before the
+       * perigee, which a track leaving its vertex towards the beam line
+       * follows; anywhere in the row above the perigee radius */
+      if (cfg->vtx_two_branch && ra < e1) branch_arc(c, sn, ra, e1, -1, nt, &ti0[a], &tin[a]);
+      /* one vote per cell of the union of the two arcs */
+      for (int q = 0; q < tvn[a]; ++q) vacc[m * nt + (tv0[a] + q) % nt] += 1;
+      for (int q = 0; q < tin[a]; ++q) {
+        int cc = (ti0[a] + q) % nt;
+        int off = ((cc - tv0[a]) % nt + nt) % nt;
+        if (off >= tvn[a]) vacc[m * nt + cc] += 1;
+      }
     }
   }
   if (vacc_out) memcpy(vacc_out, vacc, sizeof(int32_t) * (size_t)nm * nt);
@@ -1212,12 +1240,14 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
           for (int dm = -1; dm <= 1 && !hit; ++dm) {
             int mm = m + dm;
             if (mm < 0 || mm >= nm) continue;
-            int len = tvn[(size_t)t * nm + mm];
-            if (len == 0) continue;
-            int st = tv0[(size_t)t * nm + mm];
-            /* arc widened by one bin each side contains ti */
-            int off = ((ti - st + 1) % nt + nt) % nt;
-            if (off < len + 2) hit = 1;
+            for (int br = 0; br < 2 && !hit; ++br) {
+              int len = br ? tin[(size_t)t * nm + mm] : tvn[(size_t)t * nm + mm];
+              if (len == 0) continue;
+              int st = br ? ti0[(size_t)t * nm + mm] : tv0[(size_t)t * nm + mm];
+              /* arc widened by one bin each side contains ti */
+              int off = ((ti - st + 1) % nt + nt) % nt;
+              if (off < len + 2) hit = 1;
+            }
           }
           if (!hit) continue;
           const cand_t* c = &cd[trk_peak[t]];
@@ -1261,6 +1291,8 @@ int oracle_assoc_cluster(const or_grid* g, const float* r, const float* phi,
   free(vacc);
   free(tv0);
   free(tvn);
+  free(ti0);
+  free(tin);
   free(hx.x);
   free(hx.y);
   free(hx.q);

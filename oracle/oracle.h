@@ -52,7 +52,7 @@ typedef struct {
   float bh_max_isotropy;   /* ... and |mean member direction| at most this */
   float vtx_min_d0;        /* tracks with seed |d0| below this cast no vertex votes */
   int32_t fit_kind;        /* refit: 0 Gauss-Newton least squares, 1 extended Kalman filter */
-  int32_t reserved;        /* 0 */
+  int32_t vtx_two_branch;  /* 0: vertex votes on the outgoing branch only; 1: also the incoming branch */
 } or_cluster_cfg;
 
 typedef struct {

@@ -43,7 +43,7 @@ class _Cfg(C.Structure):
                 ("rho_lo", C.c_float), ("rho_hi", C.c_float),
                 ("vtx_min_votes", C.c_int32), ("bh_min_tracks", C.c_int32),
                 ("bh_max_isotropy", C.c_float), ("vtx_min_d0", C.c_float),
-                ("fit_kind", C.c_int32), ("reserved", C.c_int32)]
+                ("fit_kind", C.c_int32), ("vtx_two_branch", C.c_int32)]
 
 
 def _grid(g: dict) -> _Grid:
@@ -57,7 +57,8 @@ def _cfg(c: dict) -> _Cfg:
                 float(c["sigma_rphi"]), int(c["fit_iters"]), int(c["n_rho"]),
                 int(c["n_theta"]), float(c["rho_lo"]), float(c["rho_hi"]),
                 int(c["vtx_min_votes"]), int(c["bh_min_tracks"]), float(c["bh_max_isotropy"]),
-                float(c.get("vtx_min_d0", 0.0)), int(c.get("fit_kind", 0)), 0)
+                float(c.get("vtx_min_d0", 0.0)), int(c.get("fit_kind", 0)),
+                int(c.get("vtx_two_branch", 0)))
 
 
 def _p(a):

@@ -46,14 +46,17 @@ double d0_edge(const ht_grid& g, int k) {
   return (double)g.d0_lo + (double)k * ((double)g.d0_hi - (double)g.d0_lo) / (double)g.n_d0;
 }
 
+// device allocation of n elements for the plan; the plan's byte count adds
+// each allocation rounded up to 4 KiB (an upper bound of what it takes)
 template <typename T>
-int dalloc(T** p, size_t n) {
+int dalloc(Plan* plan, T** p, size_t n) {
   *p = nullptr;
   if (n == 0) n = 1;
   if (hipMalloc((void**)p, n * sizeof(T)) != hipSuccess) {
     *p = nullptr;
     return HT_ENOMEM;
   }
+  plan->dev_bytes += (int64_t)((n * sizeof(T) + 4095) / 4096 * 4096);
   return HT_OK;
 }
 
@@ -62,7 +65,7 @@ void free_plan(Plan* p) {
                   p->d_tile_off,  p->d_pbits,     p->d_col_first, p->d_hx,       p->d_hy,
                   p->d_hq,        p->d_hitB,      p->d_mcount,    p->d_mem,      p->d_cstat,
                   p->d_cgeo,      p->d_chit,      p->d_cnl,      p->d_owner_key, p->d_ctile_cnt,
-                  p->d_ctile_off, p->d_trk_peak,  p->d_arc0,     p->d_arcn,      p->d_vacc,
+                  p->d_ctile_off, p->d_trk_peak,  p->d_arc0,     p->d_arcn,     p->d_arci0,    p->d_arcin,      p->d_vacc,
                   p->d_obj_cnt,   p->d_obj_off,   p->d_scalars,  p->d_ckl,       p->d_ckh,
                   p->d_cql,       p->d_ctl,       p->d_cqh,      p->d_cth,      p->d_spread};
   for (void* q : ptrs)
@@ -80,7 +83,7 @@ int check_cluster(const Plan& p, const ht_cluster_cfg& c, int32_t n_hits, int32_
       !(c.rho_lo > 0.0f) || !(c.sigma_rphi > 0.0f) || !isfinite(c.rho_hi) ||
       !isfinite(c.bh_max_isotropy) || !isfinite(c.road_sigmas) || !isfinite(c.box_margin) ||
       !(c.vtx_min_d0 >= 0.0f) || !isfinite(c.vtx_min_d0) || c.fit_kind < 0 || c.fit_kind > 1 ||
-      c.reserved != 0)
+      c.vtx_two_branch < 0 || c.vtx_two_branch > 1)
     return HT_EINVAL;
   if (c.seed_k > 4 || n_hits > p.lim.max_hits || peak_cap > p.lim.max_peaks ||
       c.member_cap > p.lim.max_member_cap || track_cap > p.lim.max_tracks ||
@@ -151,46 +154,48 @@ int ht_plan_create(const ht_grid* grid, const ht_limits* lim, ht_plan** out) {
   const size_t np = (size_t)lim->max_peaks;
   const size_t words = (size_t)p->n_tiles * 8 + 2;
   const int64_t ctiles = ((int64_t)np + 255) / 256;
-  if (rc == HT_OK) rc = dalloc(&p->d_kap, (size_t)g.n_qpt);
-  if (rc == HT_OK) rc = dalloc(&p->d_kapc, (size_t)g.n_qpt);
-  if (rc == HT_OK) rc = dalloc(&p->d_d0c, (size_t)g.n_d0);
-  if (rc == HT_OK) rc = dalloc(&p->d_q, ncol);
-  if (rc == HT_OK) rc = dalloc(&p->d_t, ncol);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_kap, (size_t)g.n_qpt);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_kapc, (size_t)g.n_qpt);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_d0c, (size_t)g.n_d0);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_q, ncol);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_t, ncol);
   // peak ballots: 256 bits per 256-cell tile, or per 1024-cell tile of four-cell lanes
-  if (rc == HT_OK) rc = dalloc(&p->d_bits, (size_t)((p->n_tiles + 3) / 4) * 32 + 2);
-  if (rc == HT_OK) rc = dalloc(&p->d_tile_cnt, (size_t)p->n_tiles);
-  if (rc == HT_OK) rc = dalloc(&p->d_tile_off, (size_t)p->n_tiles);
-  if (rc == HT_OK) rc = dalloc(&p->d_pbits, words);
-  if (rc == HT_OK) rc = dalloc(&p->d_col_first, ncol);
-  if (rc == HT_OK) rc = dalloc(&p->d_hx, nh);
-  if (rc == HT_OK) rc = dalloc(&p->d_hy, nh);
-  if (rc == HT_OK) rc = dalloc(&p->d_hq, nh);
-  if (rc == HT_OK) rc = dalloc(&p->d_hitB, nh);
-  if (rc == HT_OK) rc = dalloc(&p->d_mcount, np);
-  if (rc == HT_OK) rc = dalloc(&p->d_mem, np * (size_t)lim->max_member_cap);
-  if (rc == HT_OK) rc = dalloc(&p->d_cstat, np);
-  if (rc == HT_OK) rc = dalloc(&p->d_cgeo, np * 5);
-  if (rc == HT_OK) rc = dalloc(&p->d_chit, np * HT_MAX_LAYERS);
-  if (rc == HT_OK) rc = dalloc(&p->d_cnl, np);
-  if (rc == HT_OK) rc = dalloc(&p->d_owner_key, nh);
-  if (rc == HT_OK) rc = dalloc(&p->d_ctile_cnt, (size_t)ctiles);
-  if (rc == HT_OK) rc = dalloc(&p->d_ctile_off, (size_t)ctiles);
-  if (rc == HT_OK) rc = dalloc(&p->d_trk_peak, (size_t)lim->max_tracks);
-  if (rc == HT_OK) rc = dalloc(&p->d_arc0, (size_t)lim->max_tracks * lim->max_n_rho);
-  if (rc == HT_OK) rc = dalloc(&p->d_arcn, (size_t)lim->max_tracks * lim->max_n_rho);
-  if (rc == HT_OK) rc = dalloc(&p->d_vacc, (size_t)lim->max_vertex_cells);
-  if (rc == HT_OK) rc = dalloc(&p->d_obj_cnt, (size_t)lim->max_vertex_cells);
-  if (rc == HT_OK) rc = dalloc(&p->d_obj_off, (size_t)lim->max_vertex_cells);
-  if (rc == HT_OK) rc = dalloc(&p->d_scalars, 16);
-  if (rc == HT_OK) rc = dalloc(&p->d_spread, ht::kSpreadWords);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_bits, (size_t)((p->n_tiles + 3) / 4) * 32 + 2);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_tile_cnt, (size_t)p->n_tiles);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_tile_off, (size_t)p->n_tiles);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_pbits, words);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_col_first, ncol);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_hx, nh);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_hy, nh);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_hq, nh);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_hitB, nh);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_mcount, np);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_mem, np * (size_t)lim->max_member_cap);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_cstat, np);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_cgeo, np * 5);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_chit, np * HT_MAX_LAYERS);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_cnl, np);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_owner_key, nh);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_ctile_cnt, (size_t)ctiles);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_ctile_off, (size_t)ctiles);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_trk_peak, (size_t)lim->max_tracks);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_arc0, (size_t)lim->max_tracks * lim->max_n_rho);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_arcn, (size_t)lim->max_tracks * lim->max_n_rho);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_arci0, (size_t)lim->max_tracks * lim->max_n_rho);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_arcin, (size_t)lim->max_tracks * lim->max_n_rho);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_vacc, (size_t)lim->max_vertex_cells);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_obj_cnt, (size_t)lim->max_vertex_cells);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_obj_off, (size_t)lim->max_vertex_cells);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_scalars, 16);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_spread, ht::kSpreadWords);
   // band-vote corner tables: (smallest kappa, lower d0 edge) and (largest
   // kappa, upper d0 edge) of every column
-  if (rc == HT_OK) rc = dalloc(&p->d_ckl, (size_t)g.n_qpt);
-  if (rc == HT_OK) rc = dalloc(&p->d_ckh, (size_t)g.n_qpt);
-  if (rc == HT_OK) rc = dalloc(&p->d_cql, ncol);
-  if (rc == HT_OK) rc = dalloc(&p->d_ctl, ncol);
-  if (rc == HT_OK) rc = dalloc(&p->d_cqh, ncol);
-  if (rc == HT_OK) rc = dalloc(&p->d_cth, ncol);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_ckl, (size_t)g.n_qpt);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_ckh, (size_t)g.n_qpt);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_cql, ncol);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_ctl, ncol);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_cqh, ncol);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_cth, ncol);
   if (rc == HT_OK) {
     std::vector<float> ckl(g.n_qpt), ckh(g.n_qpt), cql(ncol), ctl(ncol), cqh(ncol), cth(ncol);
     const double cb = ht::kCLight * (double)g.bfield;

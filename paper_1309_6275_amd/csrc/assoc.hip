@@ -283,8 +283,10 @@ struct AssocArgs {
   int32_t* ctile_cnt;
   int32_t* ctile_off;
   int32_t* trk_peak;
-  int32_t* arc0;
+  int32_t* arc0;   // vertex arc per (track, row), outgoing branch: first bin, length
   int32_t* arcn;
+  int32_t* arci0;  // the same on the incoming branch (two-branch vote)
+  int32_t* arcin;
   int32_t* vacc;
   int32_t* obj_cnt;
   int32_t* sc;  // device scalars
@@ -1563,12 +1565,15 @@ __global__ __launch_bounds__(64) void kf_kernel(AssocArgs A) {
 }
 
 // ---- second transform --------------------------------------------------------------
+// branch > 0: the crossing at radius rho ahead of the perigee along the
+// direction of motion (outgoing branch); branch < 0: the one before it
 __device__ __forceinline__ double crossing_theta(double cA, double cB, double cC, double cD,
-                                                 double sn, double rho) {
+                                                 double sn, double rho, int branch) {
   const double c0 = -(cA * rho * rho + cD);
   const double dl = c0 / sn;
   const double hh = (rho - dl) * (rho + dl);
-  const double h = hh > 0.0 ? sqrt(hh) : 0.0;
+  double h = hh > 0.0 ? sqrt(hh) : 0.0;
+  if (branch < 0) h = -h;
   const double px = (dl / sn) * cB + (h / sn) * (-cC);
   const double py = (dl / sn) * cC + (h / sn) * cB;
   return catan2(py, px);
@@ -1580,10 +1585,24 @@ __device__ __forceinline__ int theta_bin(double th, int nt) {
   return t < 0 ? t + nt : t;
 }
 
-// One thread per (track, vertex row): the row's two crossings and its arc
-// of votes.  (A thread per track walked its rows in sequence, a chain of
-// float64 square roots and arctangents per row on only as many threads as
-// tracks.)
+// the arc of theta bins between the crossings of one branch at radii ra < rb
+// (the shorter way round)
+__device__ __forceinline__ void branch_arc(double cA, double cB, double cC, double cD,
+                                           double sn, double ra, double rb, int branch, int nt,
+                                           int* start, int* len) {
+  const int ta = theta_bin(crossing_theta(cA, cB, cC, cD, sn, ra, branch), nt);
+  const int tb = theta_bin(crossing_theta(cA, cB, cC, cD, sn, rb, branch), nt);
+  int d = (tb - ta) % nt;
+  if (d < 0) d += nt;
+  if (d <= nt / 2) { *start = ta; *len = d + 1; }
+  else { *start = tb; *len = nt - d + 1; }
+}
+
+// One thread per (track, vertex row): the row's arcs and their votes, one
+// per cell of the union of the outgoing arc (perigee to first hit) and, with
+// the two-branch vote, the incoming arc (perigee radius to the row's top).
+// (A thread per track walked its rows in sequence, a chain of float64
+// square roots and arctangents per row on only as many threads as tracks.)
 __global__ __launch_bounds__(256) void vvote_kernel(AssocArgs A) {
   const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
   const int nm = A.cfg.n_rho, nt = A.cfg.n_theta;
@@ -1600,26 +1619,32 @@ __global__ __launch_bounds__(256) void vvote_kernel(AssocArgs A) {
     const double rf = (double)A.out.tracks[t].r_first;
     // a track passing within vtx_min_d0 of the beam line is an IP feature
     const bool votes = !(pca < (double)A.cfg.vtx_min_d0);
-    int start = 0, len = 0;
+    int start = 0, len = 0, istart = 0, ilen = 0;
     const double e0 = (double)A.cfg.rho_lo + (double)m * rw;
     const double e1 = (double)A.cfg.rho_lo + (double)(m + 1) * rw;
     const double ra = e0 > pca ? e0 : pca;
-    const double rb = e1 < rf ? e1 : rf;
-    if (votes && ra < rb) {
-      const int ta = theta_bin(crossing_theta(cA, cB, cC, cD, sn, ra), nt);
-      const int tb = theta_bin(crossing_theta(cA, cB, cC, cD, sn, rb), nt);
-      int d = (tb - ta) % nt;
-      if (d < 0) d += nt;
-      if (d <= nt / 2) { start = ta; len = d + 1; }
-      else { start = tb; len = nt - d + 1; }
+    if (votes) {
+      const double rb = e1 < rf ? e1 : rf;
+      if (ra < rb) branch_arc(cA, cB, cC, cD, sn, ra, rb, +1, nt, &start, &len);
+      if (A.cfg.vtx_two_branch && ra < e1)
+        branch_arc(cA, cB, cC, cD, sn, ra, e1, -1, nt, &istart, &ilen);
       for (int q = 0; q < len; ++q) {
         int c = start + q;
         if (c >= nt) c -= nt;
         atomicAdd(&A.vacc[m * nt + c], 1);
       }
+      for (int q = 0; q < ilen; ++q) {
+        int c = istart + q;
+        if (c >= nt) c -= nt;
+        int off = (c - start) % nt;
+        if (off < 0) off += nt;
+        if (off >= len) atomicAdd(&A.vacc[m * nt + c], 1);
+      }
     }
     A.arc0[(size_t)t * nm + m] = start;
     A.arcn[(size_t)t * nm + m] = len;
+    A.arci0[(size_t)t * nm + m] = istart;
+    A.arcin[(size_t)t * nm + m] = ilen;
   }
 }
 
@@ -1699,17 +1724,22 @@ __global__ __launch_bounds__(kVThreads) void vpeaks_kernel(AssocArgs A, int n_ze
   if (threadIdx.x == kVThreads - 1) A.sc[S_NOBJ] = o;
 }
 
+// a track is a member of the object at (m, ti) when one of its arcs (either
+// branch) in rows m - 1 .. m + 1, widened by one bin each side, holds ti
 __device__ __forceinline__ bool is_member(const AssocArgs& A, int t, int m, int ti) {
   const int nm = A.cfg.n_rho, nt = A.cfg.n_theta;
   for (int dm = -1; dm <= 1; ++dm) {
     const int mm = m + dm;
     if (mm < 0 || mm >= nm) continue;
-    const int len = A.arcn[(size_t)t * nm + mm];
-    if (len == 0) continue;
-    const int st = A.arc0[(size_t)t * nm + mm];
-    int off = (ti - st + 1) % nt;
-    if (off < 0) off += nt;
-    if (off < len + 2) return true;
+    for (int br = 0; br < 2; ++br) {
+      const size_t a = (size_t)t * nm + mm;
+      const int len = br ? A.arcin[a] : A.arcn[a];
+      if (len == 0) continue;
+      const int st = br ? A.arci0[a] : A.arc0[a];
+      int off = (ti - st + 1) % nt;
+      if (off < 0) off += nt;
+      if (off < len + 2) return true;
+    }
   }
   return false;
 }
@@ -1878,6 +1908,8 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   A.trk_peak = P.d_trk_peak;
   A.arc0 = P.d_arc0;
   A.arcn = P.d_arcn;
+  A.arci0 = P.d_arci0;
+  A.arcin = P.d_arcin;
   A.vacc = out.vacc ? out.vacc : P.d_vacc;
   A.obj_cnt = P.d_obj_cnt;
   A.sc = P.d_scalars;

@@ -32,6 +32,7 @@ struct Plan {
   ht_grid grid;
   ht_limits lim;
   int device;
+  int64_t dev_bytes;  // device bytes the plan allocated (each allocation rounded up to 4 KiB)
   int64_t n_cells;
   float phi_lo, invw;
   float* d_kap;  // [n_qpt]
@@ -71,6 +72,8 @@ struct Plan {
   int32_t* d_trk_peak;   // [max_tracks] peak index of each track
   int32_t* d_arc0;       // [max_tracks * max_n_rho] vertex arc start per row
   int32_t* d_arcn;       // [max_tracks * max_n_rho] vertex arc length per row
+  int32_t* d_arci0;      // the same on the incoming branch (two-branch vote)
+  int32_t* d_arcin;
   int32_t* d_vacc;       // [max_vertex_cells] vertex accumulator
   int32_t* d_obj_cnt;    // [max_vertex_cells] member count per object
   int32_t* d_obj_off;    // [max_vertex_cells] member offset per object

@@ -130,23 +130,6 @@ int host_alloc(T** p, size_t n) {
   return HT_OK;
 }
 
-int64_t plan_bytes(const ht_server_cfg& c, const ht_server_kind& k) {
-  // the device scratch ht_plan_create allocates for these limits, bounded
-  // from above (tables, bitmaps, hit arrays, candidate arrays, member pool)
-  const int64_t cells = (int64_t)k.grid.n_phi * k.grid.n_qpt * k.grid.n_d0;
-  const int64_t np = k.peak_cap;
-  const int64_t nh = c.max_hits;
-  const int64_t vcells = (int64_t)k.cluster.n_rho * k.cluster.n_theta;
-  int64_t b = 0;
-  b += (int64_t)k.grid.n_qpt * 20 + (int64_t)k.grid.n_qpt * k.grid.n_d0 * 8 + k.grid.n_d0 * 8;
-  b += 2 * (cells / 8 + 4096) + 3 * (cells / 256 + 16) * 4 + (int64_t)k.grid.n_qpt * k.grid.n_d0 * 4;
-  b += nh * (3 * 8 + 16 + 8);
-  b += np * (4 + 4 + 4 + 40 + 64) + (np / 256 + 16) * 8;
-  b += np * (int64_t)k.cluster.member_cap * 8;
-  b += (int64_t)c.track_cap * (4 + 8 * k.cluster.n_rho) + vcells * 12 + 64 + (int64_t)ht::kSpreadWords * 8;
-  return b;
-}
-
 void free_slot(Slot& s) {
   for (int k = 0; k < HT_SERVER_MAX_KINDS; ++k) {
     if (s.exec[k]) (void)hipGraphExecDestroy(s.exec[k]);
@@ -228,7 +211,7 @@ int make_slot(const ht_server_cfg& c, Slot& s, int64_t* bytes) {
     lim.max_n_rho = K.cluster.n_rho;
     rc = ht_plan_create(&K.grid, &lim, &s.plan[k]);
     if (rc == HT_OK) rc = ht::check_cluster(*s.plan[k], K.cluster, c.max_hits, K.peak_cap, c.track_cap);
-    *bytes += plan_bytes(c, K);
+    if (s.plan[k]) *bytes += s.plan[k]->dev_bytes;  // what the plan allocated
     const int64_t cells = (int64_t)K.grid.n_phi * K.grid.n_qpt * K.grid.n_d0;
     if (cells > max_cells) max_cells = cells;
     if (K.peak_cap > max_peaks) max_peaks = K.peak_cap;

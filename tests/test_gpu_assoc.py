@@ -271,3 +271,33 @@ def test_assoc_rejects_bad_config(torch, ht):
         with pytest.raises(ht.HoughError) as e:
             ht.assoc_cluster(plan, r, r, layer, peaks, nf, dict(W["cluster"], **bad), bufs)
         assert e.value.code == code, bad
+
+
+@pytest.mark.parametrize("case", ["isotropic", "cfg2", "cfg3"])
+def test_assoc_parity_two_branch_vertex_vote(torch, ht, oracle, case):
+    """vtx_two_branch = 1: the vertex vote also runs along each track's
+    incoming branch (an isotropic decay 10 cm out with noise; a workload-2
+    event; every 64th peak of a 55k-hit event)."""
+    if case == "isotropic":
+        W = CF.WORKLOADS[2]
+        rng = np.random.default_rng(31)
+        psis = np.sort(-1.1 + rng.uniform(-np.pi, np.pi, 60))
+        qpts = rng.choice([-1, 1], 60) * rng.uniform(0.3, 0.9, 60)
+        ev = G.make_vertex_event(10.0, -1.1, psis, qpts, n_noise=300, seed=32)
+        kw = {}
+    elif case == "cfg2":
+        W = CF.WORKLOADS[2]
+        ev = G.make_event(2, W["seed0"] + 11)
+        kw = {}
+    else:
+        W = CF.WORKLOADS[3]
+        ev = G.make_event(3, W["seed0"] + 3)
+        kw = dict(peak_stride=64)
+    cfg = dict(W["cluster"], vtx_two_branch=1)
+    print(f"two-branch {case}: hits {ev.n_hits}", flush=True)
+    got, acc, pk = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], cfg, **kw)
+    want = run_oracle(oracle, W["grid"], ev, acc, pk, cfg)
+    compare(got, want, f"two-branch {case}")
+    if case == "isotropic":
+        obj = want["objects"]
+        assert obj.size and obj["kind"].max() == 1
