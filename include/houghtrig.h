@@ -384,6 +384,15 @@ int ht_cnn_forward(const float* params, const uint16_t* win, const int32_t* n_de
 int ht_cnn_train_step(float* params, float* mom, const uint16_t* win, const float* labels,
                       int32_t n, float lr, float momentum, float pos_weight, float* loss,
                       void* workspace, size_t workspace_bytes, void* stream);
+/* Logits of the first min(*n_peaks, cap) peaks of a peak list of this
+ * plan's grid, with each window built in LDS straight from the accumulator
+ * (the windows of ht_cnn_windows, never written to device memory), in one
+ * launch after the weights' packing.  Same logits as ht_cnn_windows followed
+ * by ht_cnn_forward.  workspace as for ht_cnn_forward (inference);
+ * cap <= the plan's max_peaks. */
+int ht_cnn_score(const ht_plan* plan, const float* params, const int32_t* acc,
+                 const ht_peak* peaks, const int32_t* n_peaks, int32_t cap, float* logits,
+                 void* workspace, size_t workspace_bytes, void* stream);
 /* Ordered compaction: the peaks among the first min(*n_peaks, cap) whose
  * logit is >= threshold, in their order, into out [out_cap]; *n_out (device)
  * receives their full count.  cap <= the plan's max_peaks. */

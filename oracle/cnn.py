@@ -18,8 +18,12 @@ float64, on the precision contract of the device kernels:
     valid) -> ReLU -> linear 16->64 -> ReLU -> linear 64->1, a logit;
   * loss: binary cross-entropy with logits, positives weighted by pos_weight,
     mean over the batch; gradients of the float32 master weights through the
-    same rounded activations (rounding treated as identity); SGD with
-    momentum.
+    same rounded activations (rounding treated as identity); the backward
+    signals of the three hidden layers (dh3, dh2, dh1, after their ReLU
+    masks) are rounded to bfloat16 like the activations before they enter
+    the next contraction, which accumulates wide (the matrix-core training
+    kernels take bfloat16 operands); dz and the last layer's gradients stay
+    wide; SGD with momentum.
 
 Flat parameter vector (float32 masters), in this order:
   W1[16][27] b1[16] W2[16][16][27] b2[16] W3[64][16] b3[64] W4[64] b4[1]
@@ -127,13 +131,14 @@ def loss_and_grad(flat, x, y, pos_weight=1.0, rounding=True):
     g = {}
     g["W4"] = dz @ c["h3"]
     g["b4"] = np.array([dz.sum()])
-    dh3 = np.outer(dz, P["W4"]) * (c["a3"] > 0)
+    rnd = bf16 if rounding else (lambda v: np.asarray(v, np.float64))
+    dh3 = rnd(np.outer(dz, P["W4"]) * (c["a3"] > 0))
     g["W3"] = dh3.T @ c["h2"]
     g["b3"] = dh3.sum(0)
-    dh2 = (dh3 @ P["W3"]) * (c["a2"] > 0)
+    dh2 = rnd((dh3 @ P["W3"]) * (c["a2"] > 0))
     g["W2"] = np.einsum("nd,npc->dcp", dh2, c["h1"])
     g["b2"] = dh2.sum(0)
-    dh1 = np.einsum("nd,dcp->npc", dh2, P["W2"]) * (c["a1"] > 0)
+    dh1 = rnd(np.einsum("nd,dcp->npc", dh2, P["W2"]) * (c["a1"] > 0))
     g["W1"] = np.einsum("npc,npt->ct", dh1, c["X1"])
     g["b1"] = dh1.sum((0, 1))
     return loss, pack(g), z

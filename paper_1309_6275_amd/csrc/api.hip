@@ -386,6 +386,18 @@ int ht_cnn_forward(const float* params, const uint16_t* win, const int32_t* n_de
   return ht::launch_cnn_forward(params, win, n_dev, n_max, logits, ws, (hipStream_t)stream);
 }
 
+int ht_cnn_score(const ht_plan* p, const float* params, const int32_t* acc, const ht_peak* peaks,
+                 const int32_t* n_peaks, int32_t cap, float* logits, void* ws, size_t ws_bytes,
+                 void* stream) {
+  if (!p || !params || !acc || !n_peaks || cap < 0 || (cap > 0 && (!peaks || !logits)) || !ws)
+    return HT_EINVAL;
+  if (ws_bytes < ht::cnn_workspace_bytes(cap, 0)) return HT_EINVAL;
+  if (cap > p->lim.max_peaks) return HT_EUNSUPPORTED;
+  if (cap == 0) return HT_OK;
+  return ht::launch_cnn_score(*p, params, acc, peaks, n_peaks, cap, logits, ws,
+                              (hipStream_t)stream);
+}
+
 int ht_cnn_train_step(float* params, float* mom, const uint16_t* win, const float* labels,
                       int32_t n, float lr, float momentum, float pos_weight, float* loss,
                       void* ws, size_t ws_bytes, void* stream) {

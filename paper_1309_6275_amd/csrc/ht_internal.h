@@ -132,6 +132,8 @@ int launch_cnn_windows(const Plan& p, const int32_t* acc, const ht_peak* peaks, 
                        int32_t cap, uint16_t* win, hipStream_t s);
 int launch_cnn_forward(const float* params, const uint16_t* win, const int32_t* n_dev, int32_t n_max,
                        float* logits, void* ws, hipStream_t s);
+int launch_cnn_score(const Plan& p, const float* params, const int32_t* acc, const ht_peak* peaks,
+                     const int32_t* n_peaks, int32_t cap, float* logits, void* ws, hipStream_t s);
 int launch_cnn_train(float* params, float* mom, const uint16_t* win, const float* labels, int32_t n,
                      float lr, float momentum, float pos_weight, float* loss, void* ws, hipStream_t s);
 int launch_cnn_keep(const Plan& p, const float* logits, const ht_peak* peaks, const int32_t* n_peaks,

@@ -130,6 +130,7 @@ def lib():
         L.ht_cnn_train_step.argtypes = [vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, vp,
                                         vp, C.c_size_t, vp]
         L.ht_cnn_keep.argtypes = [vp, vp, vp, vp, i32, C.c_float, vp, i32, vp, vp]
+        L.ht_cnn_score.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, C.c_size_t, vp]
         L.ht_server_create.argtypes = [vp, vp]
         L.ht_server_destroy.argtypes = [vp]
         L.ht_server_info.argtypes = [vp, vp, vp]
@@ -143,7 +144,7 @@ def lib():
                   "ht_server_create", "ht_server_destroy", "ht_server_info", "ht_server_submit",
                   "ht_server_poll", "ht_cnn_windows", "ht_cnn_forward", "ht_cnn_train_step",
                   "ht_cnn_keep", "hough_vote_cell", "ht_compact_hits", "ht_remap_track_hits",
-                  "hough_vote_n", "assoc_cluster_n", "hough_peaks_noalloc"):
+                  "hough_vote_n", "assoc_cluster_n", "hough_peaks_noalloc", "ht_cnn_score"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -502,6 +503,24 @@ def cnn_forward(params, win, logits, workspace, n_dev=None, stream=None):
                                 _stream(stream)), "ht_cnn_forward")
 
 
+def cnn_score(plan: "Plan", params, acc, peaks, n_peaks, logits, workspace, stream=None):
+    """Logits of the first min(n_peaks, cap) peaks, windows built in LDS from
+    the accumulator (ht_cnn_score)."""
+    torch = _torch()
+    cap = int(peaks.shape[0])
+    _need(tuple(acc.shape) == plan.acc_shape, "acc must have the plan's shape")
+    _need(peaks.dim() == 2 and peaks.shape[1] == 2, "peaks must be int32 [cap, 2]")
+    _need(n_peaks.numel() >= 1, "n_peaks must hold one element")
+    _need(logits.numel() >= cap, "logits holds fewer entries than there are peaks")
+    _need(params.numel() >= CNN_PARAMS, "params must hold HT_CNN_PARAMS floats")
+    _check(lib().ht_cnn_score(plan.handle, _ptr(params, torch.float32, "params"),
+                              _ptr(acc, torch.int32, "acc"), _ptr(peaks, torch.int32, "peaks"),
+                              _ptr(n_peaks, torch.int32, "n_peaks"), cap,
+                              _ptr(logits, torch.float32, "logits"),
+                              _ptr(workspace, torch.uint8, "workspace"), int(workspace.numel()),
+                              _stream(stream)), "ht_cnn_score")
+
+
 def cnn_train_step(params, mom, win, labels, lr, momentum, pos_weight, loss, workspace,
                    stream=None):
     torch = _torch()
@@ -671,4 +690,5 @@ EXPORTS = ("ht_plan_create", "ht_plan_destroy", "ht_strerror", "hough_vote", "ho
            "ht_profile_end", "ht_server_create", "ht_server_destroy", "ht_server_info",
            "ht_server_submit", "ht_server_poll", "ht_cnn_workspace_bytes", "ht_cnn_windows",
            "ht_cnn_forward", "ht_cnn_train_step", "ht_cnn_keep", "ht_compact_hits",
-           "ht_remap_track_hits", "hough_vote_n", "assoc_cluster_n", "hough_peaks_noalloc")
+           "ht_remap_track_hits", "hough_vote_n", "assoc_cluster_n", "hough_peaks_noalloc",
+           "ht_cnn_score")

@@ -1,15 +1,23 @@
 """Train and evaluate the learned peak filter on the device (ht_cnn_*).
 
-Labels (the truth matching of the track metrics): a threshold peak is
-positive when the track that assoc_cluster builds from it survives and
-matches a generated track (at least 75% and at least min_layers of its hits
-from that track); every other peak is negative.  Windows of all peaks come
-from the device; the training set keeps every positive and a stated number
-of random negatives per event.  Training: SGD with momentum on the device,
-positives weighted by the negative/positive ratio.  The threshold keeps a
-stated fraction of the validation positives.  Evaluation on other events:
-track efficiency, fake rate, peaks kept and the time of assoc_cluster with
-and without the filter (the filter's own time included).
+Labels: truth matching of the peak cell against the event generator,
+independent of the refinement.  A threshold peak (i, j, k) is positive when
+a generated track in acceptance (q/pT and d0 inside the grid, at least
+min_layers hits after its perigee) has its true parameters in a cell within
+one bin of it in q/pT and in d0 and within two bins in phi0 (periodic); the
+phi0 tolerance is wider because the vote samples each column at its centre,
+which moves the track's votes by up to about a bin.  Every other peak is
+negative.  The peaks are those of hough_vote and hough_peaks on the device,
+which equal the oracle's bit for bit (the parity tests), so these are the
+oracle Hough's peaks labelled by truth.  The training set keeps every
+positive and a stated number of random negatives per event.  Training: SGD
+with momentum on the device (ht_cnn_train_step), positives weighted by the
+negative/positive ratio.  The threshold keeps a stated fraction of the
+validation positives.  Evaluation on other events: track efficiency and fake
+rate of assoc_cluster (the refinement and its truth matching of tracks, the
+judge of the filter) on all peaks and on the kept peaks, the peaks kept, and
+the time of assoc_cluster with and without the filter (scoring with
+ht_cnn_score and compaction included).
 
 Seeds: training events 5 000 000 + e, validation 5 500 000 + e, test
 5 900 000 + e, all of the 3D displaced-jet composition.
@@ -63,24 +71,43 @@ class Pipeline:
 
     def filter(self, params, thr):
         H = self.H
-        H.cnn_windows(self.plan, self.acc, self.peaks, self.nf, self.win)
-        H.cnn_forward(params, self.win, self.logits, self.ws, n_dev=self.nf)
+        H.cnn_score(self.plan, params, self.acc, self.peaks, self.nf, self.logits, self.ws)
         H.cnn_keep(self.plan, self.logits, self.peaks, self.nf, thr, self.kept, self.nk)
 
 
+def truth_labels(ev, grid, min_layers, lins, dphi=2, dq=1, dd=1):
+    """1 for the peak cells within (dphi, dq, dd) bins of the true cell of a
+    generated track in acceptance, else 0."""
+    nphi, nq, nd = grid["n_phi"], grid["n_qpt"], grid["n_d0"]
+    lins = np.asarray(lins, np.int64)
+    i, col = lins % nphi, lins // nphi
+    j, k = col % nq, col // nq
+    acc = M.in_acceptance(ev, grid, min_layers)
+    qw = (grid["qpt_hi"] - grid["qpt_lo"]) / nq
+    it = np.floor((np.asarray(ev.trk_phi0) + np.pi) * nphi / (2 * np.pi)).astype(np.int64) % nphi
+    jt = np.clip(np.floor((ev.trk_qpt - grid["qpt_lo"]) / qw).astype(np.int64), 0, nq - 1)
+    if nd > 1:
+        dw = (grid["d0_hi"] - grid["d0_lo"]) / nd
+        kt = np.clip(np.floor((ev.trk_d0 - grid["d0_lo"]) / dw).astype(np.int64), 0, nd - 1)
+    else:
+        kt = np.zeros(len(jt), np.int64)
+    y = np.zeros(lins.size, np.float32)
+    for t in np.flatnonzero(acc):
+        di = np.abs(((i - it[t]) + nphi // 2) % nphi - nphi // 2)
+        y[(di <= dphi) & (np.abs(j - jt[t]) <= dq) & (np.abs(k - kt[t]) <= dd)] = 1.0
+    return y
+
+
 def label_event(pl, ev, cl):
-    """Windows (host bf16 bits as int16) and labels of all peaks of one event."""
+    """Windows (host bf16 bits as int16) and truth labels of all peaks of one
+    event."""
     t = pl.torch
     d = pl.upload(ev)
     pl.peaks_of(d)
-    pl.assoc(d, pl.peaks, pl.nf)
     t.cuda.synchronize()
     n = min(int(pl.nf.item()), pl.cap)
-    out = pl.bufs.to_host(ev.n_hits)
-    tm = M.match_tracks(out["tracks"]["hits"], ev.hit_track, cl["min_layers"])
-    y = np.zeros(n, np.float32)
-    good = out["tracks"]["peak"][tm >= 0]
-    y[good[good < n]] = 1.0
+    lins = pl.peaks[:n, 0].cpu().numpy()
+    y = truth_labels(ev, pl.W["grid"], cl["min_layers"], lins)
     pl.H.cnn_windows(pl.plan, pl.acc, pl.peaks, pl.nf, pl.win)
     t.cuda.synchronize()
     return pl.win[:n].view(t.int16).cpu().numpy(), y

@@ -198,3 +198,25 @@ def test_filter_end_to_end_matches_oracle(torch, ht, oracle, event_peaks):
     want = run_oracle(oracle, W["grid"], ev, acc_h, pk_h[keep_o], cl)
     compare(got, want, "filter end to end")
     assert int(want["counts"][1]) > 0
+
+
+def test_score_equals_windows_then_forward(torch, ht, event_peaks):
+    """ht_cnn_score builds the windows in LDS from the accumulator: the same
+    logits, bit for bit, as ht_cnn_windows followed by ht_cnn_forward, over
+    the whole peak list (every d0 plane, clipped edges) with a device count
+    below the capacity."""
+    plan, acc, peaks, nf = event_peaks
+    n = int(nf.item())
+    cap = n + 37
+    pk = peaks[:cap].contiguous()
+    params = torch.from_numpy(cnn.init_params(5)).cuda()
+    win = gpu_windows(torch, ht, plan, acc, pk, cap)
+    ws = ht.cnn_workspace(cap)
+    want = torch.full((cap,), 7.0, dtype=torch.float32, device="cuda")
+    ht.cnn_forward(params, win[:n].contiguous(), want, ws)
+    got = torch.full((cap,), 7.0, dtype=torch.float32, device="cuda")
+    ht.cnn_score(plan, params, acc, pk, nf, got, ws)
+    torch.cuda.synchronize()
+    g, w = got.cpu().numpy(), want.cpu().numpy()
+    assert np.array_equal(g[:n].view(np.uint32), w[:n].view(np.uint32))
+    assert np.all(g[n:] == 7.0)

@@ -92,3 +92,59 @@ def test_sgd_step_closed_form():
     g = np.array([0.25, 1.0])
     p2, m2 = cnn.sgd_step(p, m, g, lr=0.1, momentum=0.9)
     assert np.allclose(m2, [0.7, 1.0]) and np.allclose(p2, [0.93, -2.1])
+
+
+def test_rounded_grad_matches_torch_with_bf16_hooks():
+    """With rounding on, the gradient equals torch's autograd on the same
+    network with every weight, input and activation rounded to bfloat16 on
+    the way forward and the hidden layers' backward signals rounded to
+    bfloat16 on the way back (straight-through roundings, float64
+    elsewhere): the precision contract of the matrix-core training kernels,
+    built from torch's own bfloat16 conversion."""
+    torch = pytest.importorskip("torch")
+
+    def rb(t):  # torch's round to bfloat16, kept in float64
+        return t.to(torch.bfloat16).to(torch.float64)
+
+    class RoundFwd(torch.autograd.Function):  # forward rounding, gradient passes
+        @staticmethod
+        def forward(ctx, t):
+            return rb(t)
+
+        @staticmethod
+        def backward(ctx, g):
+            return g
+
+    class RoundBwd(torch.autograd.Function):  # identity forward, rounded gradient
+        @staticmethod
+        def forward(ctx, t):
+            return t.clone()
+
+        @staticmethod
+        def backward(ctx, g):
+            return rb(g)
+
+    rng = np.random.default_rng(8)
+    flat = cnn.init_params(9)
+    x = rng.integers(0, 30, (10, 5, 5, 5)) / 16.0
+    y = (rng.uniform(size=10) > 0.5).astype(np.float64)
+    loss, g, z = cnn.loss_and_grad(flat, x, y, pos_weight=3.0, rounding=True)
+    P = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True)
+         for k, v in cnn.unpack(flat).items()}
+    W = {k: RoundFwd.apply(v) if k[0] == "W" else v for k, v in P.items()}
+    F = torch.nn.functional
+    xt = rb(torch.tensor(x, dtype=torch.float64).unsqueeze(1))
+    h1 = RoundBwd.apply(RoundFwd.apply(F.relu(F.conv3d(xt, W["W1"].reshape(16, 1, 3, 3, 3), W["b1"]))))
+    h2 = F.relu(F.conv3d(h1, W["W2"].reshape(16, 16, 3, 3, 3), W["b2"])).reshape(-1, 16)
+    h2 = RoundBwd.apply(RoundFwd.apply(h2))
+    h3 = RoundBwd.apply(RoundFwd.apply(F.relu(h2 @ W["W3"].T + W["b3"])))
+    zt = h3 @ W["W4"] + W["b4"]
+    assert np.allclose(z, zt.detach().numpy(), rtol=1e-12, atol=1e-12)
+    w = torch.tensor(np.where(y > 0.5, 3.0, 1.0))
+    lt = (w * F.binary_cross_entropy_with_logits(zt, torch.tensor(y), reduction="none")).mean()
+    lt.backward()
+    gt = np.concatenate([P[name].grad.numpy().reshape(-1) for name, _ in cnn.SHAPES])
+    assert np.allclose(g, gt, rtol=1e-9, atol=1e-14)
+    # and the roundings matter: the unrounded backward differs
+    _, g0, _ = cnn.loss_and_grad(flat, x, y, pos_weight=3.0, rounding=False)
+    assert not np.allclose(g, g0, rtol=1e-6, atol=0)
