@@ -110,7 +110,8 @@ def copy_calibration():
 
 # the sources a kernel's code comes from (plan and launch code excluded)
 KERNEL_SOURCES = {"vote": ("vote.hip", "ht_device.h"),
-                  "refine": ("assoc.hip", "ht_device.h")}
+                  "refine": ("assoc.hip", "ht_device.h"),
+                  "members": ("assoc.hip", "ht_device.h")}
 
 
 def kernel_source_sha(kernel):
@@ -538,9 +539,10 @@ def measure(args, workload, B, steps, warmup, cpu_events, concurrent):
 
     # physics of the outputs (last step) and the seed search's work totals,
     # outside the timed region
-    effs, fakes, n_trk, defined, executed = [], [], 0, [], []
+    effs, fakes, n_trk, defined, executed, cnts = [], [], 0, [], [], []
     for ev, b in zip(events, bufs):
         out = b.to_host(ev.n_hits)
+        cnts.append(out["counts"].astype(np.int64))
         tm = M.track_metrics(ev, g, cl["min_layers"], out["tracks"]["hits"])
         effs.append((tm["n_found"], tm["n_truth_acc"]))
         fakes.append((tm["n_fake"], tm["n_tracks"]))
@@ -599,6 +601,11 @@ def measure(args, workload, B, steps, warmup, cpu_events, concurrent):
         "track_efficiency": eff,
         "fake_rate": fake,
         "tracks_per_event": n_trk / B,
+        # per event: peaks handed to assoc_cluster, refined candidates,
+        # candidates over member_cap, (candidate, member) pairs within it
+        "assoc_counts": {"refined": float(np.mean([c[0] for c in cnts])),
+                         "over_member_cap": float(np.mean([c[4] for c in cnts])),
+                         "member_pairs": float(np.mean([c[5] for c in cnts]))},
         "vote_kernel_votes_per_s": float(np.mean(votes)) / (avg_ms["vote"] / 1e3),
         "stage_ms": {k: avg_ms[k] for k in ("vote", "peaks", "members", "refine", "assoc")},
         "roofline": rl[dominant],
@@ -660,7 +667,7 @@ def main():
                    "mean_hits": r["mean_hits"], "parallelism": r["parallelism"]},
     }
     for k in ("events_per_s", "p50_ms", "p99_ms", "track_efficiency", "fake_rate",
-              "tracks_per_event", "vote_kernel_votes_per_s", "stage_ms", "roofline",
+              "tracks_per_event", "assoc_counts", "vote_kernel_votes_per_s", "stage_ms", "roofline",
               "roofline_vote", "roofline_refine", "cpu_baseline", "concurrent_streams"):
         line[k] = r[k]
     # the displaced-jet workload beside it, where the method reaches its
