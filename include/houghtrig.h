@@ -297,6 +297,38 @@ int assoc_cluster_n(const ht_plan* plan, const float* r, const float* phi, const
                     const int32_t* n_peaks, int32_t peak_cap, const int32_t* acc,
                     const ht_cluster_cfg* cfg, const ht_cluster_out* out, void* stream);
 
+/* ---- Batched launches ----------------------------------------------------
+ * hough_batch -- hough_vote, hough_peaks and assoc_cluster for n_events
+ * (1 .. HT_MAX_BATCH) events of one grid kind, each kernel launched once for
+ * all of them (the event is a grid dimension of every launch), for events
+ * too small to fill the chip alone (the trigger's many small events, section
+ * "Physics Motivation").  Results are exactly those of the three calls made
+ * event by event.  Event b uses its own plan (its scratch); the plans share
+ * the grid; the events share the hit bound n_hits_max, the peak threshold and
+ * capacity, the cluster configuration and the output capacities.
+ *   plan        this event's plan (created for the shared grid)
+ *   r, phi, layer, n_hits_dev   device hits and device hit count (<= n_hits_max)
+ *   acc         device accumulator of the grid (written)
+ *   peaks, n_peaks  device peak list [peak_cap] and count (written)
+ *   out         outputs as for assoc_cluster (the accumulator bound of
+ *               assoc_cluster is used with each event's accumulator)
+ * Returns HT_EINVAL for a null pointer or mismatched plans or capacities,
+ * HT_EUNSUPPORTED for sizes beyond a plan's limits. */
+#define HT_MAX_BATCH 4
+typedef struct {
+  const ht_plan* plan;
+  const float* r;
+  const float* phi;
+  const uint8_t* layer;
+  const int32_t* n_hits_dev;
+  int32_t* acc;
+  ht_peak* peaks;
+  int32_t* n_peaks;
+  ht_cluster_out out;
+} ht_batch_event;
+int hough_batch(int32_t n_events, const ht_batch_event* events, int32_t n_hits_max,
+                int32_t min_votes, int32_t peak_cap, const ht_cluster_cfg* cfg, void* stream);
+
 /* Iterative hit removal (paper, section "Current Tracker and Tracking
  * Algorithm": earlier passes find the easier, prompt tracks, whose hits are
  * then removed so that later passes search for displaced tracks among far

@@ -313,6 +313,54 @@ int assoc_cluster(const ht_plan* p, const float* r, const float* phi, const uint
                           (hipStream_t)stream);
 }
 
+int hough_batch(int32_t nb, const ht_batch_event* ev, int32_t n_hits_max, int32_t min_votes,
+                int32_t peak_cap, const ht_cluster_cfg* cfg, void* stream) {
+  if (!ev || !cfg || nb < 1 || n_hits_max < 0 || peak_cap < 0) return HT_EINVAL;
+  if (nb > HT_MAX_BATCH) return HT_EUNSUPPORTED;
+  if (n_hits_max > 65535) return HT_EUNSUPPORTED;
+  const ht::Plan* plans[HT_MAX_BATCH];
+  const float* r[HT_MAX_BATCH];
+  const float* phi[HT_MAX_BATCH];
+  const int32_t* ndev[HT_MAX_BATCH];
+  int32_t* acc[HT_MAX_BATCH];
+  const int32_t* cacc[HT_MAX_BATCH];
+  ht_peak* out[HT_MAX_BATCH];
+  int32_t* nf[HT_MAX_BATCH];
+  ht::AssocEvent ae[HT_MAX_BATCH];
+  for (int b = 0; b < nb; ++b) {
+    const ht_batch_event& e = ev[b];
+    if (!e.plan || !e.n_hits_dev || !e.acc || !e.n_peaks || (peak_cap > 0 && !e.peaks))
+      return HT_EINVAL;
+    if (n_hits_max > 0 && (!e.r || !e.phi || !e.layer || !e.out.hit_owner)) return HT_EINVAL;
+    if (!e.out.counts || e.out.track_cap != ev[0].out.track_cap ||
+        e.out.object_cap != ev[0].out.object_cap || e.out.member_cap != ev[0].out.member_cap ||
+        e.out.track_cap < 0 || e.out.object_cap < 0 || e.out.member_cap < 0)
+      return HT_EINVAL;
+    if ((e.out.track_cap > 0 && !e.out.tracks) || (e.out.object_cap > 0 && !e.out.objects) ||
+        (e.out.member_cap > 0 && !e.out.members))
+      return HT_EINVAL;
+    if (memcmp(&e.plan->grid, &ev[0].plan->grid, sizeof(ht_grid)) != 0) return HT_EINVAL;
+    if (n_hits_max > e.plan->lim.max_hits) return HT_EUNSUPPORTED;
+    const int rc = ht::check_cluster(*e.plan, *cfg, n_hits_max, peak_cap, e.out.track_cap);
+    if (rc != HT_OK) return rc;
+    plans[b] = e.plan;
+    r[b] = e.r;
+    phi[b] = e.phi;
+    ndev[b] = e.n_hits_dev;
+    acc[b] = e.acc;
+    cacc[b] = e.acc;
+    out[b] = e.peaks;
+    nf[b] = e.n_peaks;
+    ae[b] = ht::AssocEvent{e.plan, e.r, e.phi, e.layer, e.n_hits_dev, e.peaks, e.n_peaks,
+                           e.acc, e.out};
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int rc = ht::launch_vote_batch(*plans[0], nb, r, phi, ndev, n_hits_max, acc, s);
+  if (rc == HT_OK) rc = ht::launch_peaks_batch(nb, plans, cacc, min_votes, out, peak_cap, nf, s);
+  if (rc == HT_OK) rc = ht::launch_assoc_batch(nb, ae, n_hits_max, peak_cap, *cfg, s);
+  return rc;
+}
+
 int ht_compact_hits(const float* r, const float* phi, const uint8_t* layer, int32_t n_hits,
                     const int32_t* hit_owner, float* out_r, float* out_phi, uint8_t* out_layer,
                     int32_t* out_index, int32_t* n_out, void* stream) {

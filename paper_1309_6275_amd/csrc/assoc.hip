@@ -289,11 +289,27 @@ struct AssocArgs {
   int32_t* arcin;
   int32_t* vacc;
   int32_t* obj_cnt;
+  const int32_t* obj_off;  // object member offsets (the scan of obj_cnt)
   int32_t* sc;  // device scalars
   unsigned long long* spread;  // [kSpreadWords] spread counters
   // outputs
   ht_cluster_out out;
 };
+
+// Up to kMaxBatch events in one launch: each kernel takes the arguments of
+// all of them (in the kernel argument segment) and blockIdx.z picks the
+// event (the member sweep splits z into event and hit slice).  One event is
+// the batch of one.
+constexpr int kMaxBatch = 4;
+template <int NB>
+struct AssocBatch {
+  AssocArgs a[NB];
+};
+static_assert(sizeof(AssocBatch<kMaxBatch>) <= 4096, "a batch's arguments fit the kernel argument segment");
+template <int NB>
+__device__ __forceinline__ const AssocArgs& event_args(const AssocBatch<NB>& B) {
+  return B.a[NB == 1 ? 0 : blockIdx.z];
+}
 
 __device__ __forceinline__ int n_cands(const AssocArgs& A) { return A.sc[S_NP]; }
 __device__ __forceinline__ int hits_of(const AssocArgs& A) {
@@ -301,7 +317,9 @@ __device__ __forceinline__ int hits_of(const AssocArgs& A) {
 }
 
 // ---- prep ------------------------------------------------------------------
-__global__ void init_kernel(AssocArgs A, int words) {
+template <int NB>
+__global__ void init_kernel(AssocBatch<NB> AB, int words) {
+  const AssocArgs& A = event_args(AB);
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   if (tid < 16) A.sc[tid] = 0;
@@ -333,7 +351,9 @@ __global__ void init_kernel(AssocArgs A, int words) {
   for (int64_t v = tid; v < ncell_v; v += stride) A.vacc[v] = 0;
 }
 
-__global__ void mark_kernel(AssocArgs A) {
+template <int NB>
+__global__ void mark_kernel(AssocBatch<NB> AB) {
+  const AssocArgs& A = event_args(AB);
   if (A.acc) {
     const int n_hits = hits_of(A);
     for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < n_hits; h += gridDim.x * blockDim.x)
@@ -635,15 +655,18 @@ __device__ void drop_overfull(const AssocArgs& A, SweepShared& S, int k, int j0,
   }
 }
 
-__global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
+template <int NB>
+__global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocBatch<NB> AB) {
   __shared__ SweepShared S;
+  // blockIdx.z = event * slices + slice of the hits (see hit_slices)
+  const int n_slices = gridDim.z / NB;
+  const int slice = (int)blockIdx.z % n_slices;
+  const AssocArgs& A = AB.a[NB == 1 ? 0 : (int)blockIdx.z / n_slices];
   const int j0 = blockIdx.x * kWave;
   const int k = blockIdx.y;
-  // this workgroup's slice of the hits (gridDim.z slices, see hit_slices)
   const int n_all = hits_of(A);
-  const int n_slices = gridDim.z;
   const int chunk = ((n_all + n_slices - 1) / n_slices + kWave - 1) / kWave * kWave;
-  const int h0 = (int)blockIdx.z * chunk;
+  const int h0 = slice * chunk;
   const int h1 = min(n_all, h0 + chunk);
   if (h0 >= h1) return;
   const int n_phi = A.n_phi;
@@ -701,7 +724,7 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocArgs A) {
   }
   __syncthreads();
   uint2* pool = A.pool + (size_t)p_lo * cap;
-  const bool lds_cnt = gridDim.z == 1 && np_wg <= kMaxWgPeaks;
+  const bool lds_cnt = n_slices == 1 && np_wg <= kMaxWgPeaks;
   if (lds_cnt) {
     for (int q = threadIdx.x; q < np_wg; q += kSweepThreads) S.cnt[q] = 0;
     __syncthreads();
@@ -869,9 +892,10 @@ __device__ __forceinline__ int nth_set_bit(unsigned mask, int n) {
   return HT_MAX_LAYERS - 1;
 }
 
-template <int CAP>
+template <int CAP, int NB>
 __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave, RefineShape<CAP>::kMinBlocks) void
-refine_kernel(AssocArgs A) {
+refine_kernel(AssocBatch<NB> AB) {
+  const AssocArgs& A = event_args(AB);
   constexpr int W = RefineShape<CAP>::kWaves;
   // members per chunk of the road loop (registers: 4 per member); the
   // short member lists of caps up to 128 keep one member at a time, which
@@ -1266,7 +1290,9 @@ __device__ __forceinline__ unsigned long long own_key(int n_in, double ss, int p
          (unsigned long long)(0x3ffffff - p);
 }
 
-__global__ void own_kernel(AssocArgs A) {
+template <int NB>
+__global__ void own_kernel(AssocBatch<NB> AB) {
+  const AssocArgs& A = event_args(AB);
   const int np = n_cands(A);
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
     const int st = A.cstat[p];
@@ -1295,7 +1321,9 @@ __device__ __forceinline__ bool survives(const AssocArgs& A, int p, int* own) {
 }
 
 // survivor counts per 256-candidate tile
-__global__ __launch_bounds__(256) void surv_count_kernel(AssocArgs A, int tiles) {
+template <int NB>
+__global__ __launch_bounds__(256) void surv_count_kernel(AssocBatch<NB> AB, int tiles) {
+  const AssocArgs& A = event_args(AB);
   __shared__ int32_t wc[4];
   const int np = n_cands(A);
   for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
@@ -1310,7 +1338,9 @@ __global__ __launch_bounds__(256) void surv_count_kernel(AssocArgs A, int tiles)
   }
 }
 
-__global__ __launch_bounds__(256) void surv_emit_kernel(AssocArgs A, int tiles) {
+template <int NB>
+__global__ __launch_bounds__(256) void surv_emit_kernel(AssocBatch<NB> AB, int tiles) {
+  const AssocArgs& A = event_args(AB);
   __shared__ int32_t wc[4];
   const int np = n_cands(A);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1373,7 +1403,9 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // lane solves the same (at most 3x3) system by Cholesky.  Fixed parameters
 // (one bin in q/pT or d0) get a zero Jacobian column and a unit diagonal, so
 // their step is exactly zero.
-__global__ __launch_bounds__(256) void fit_kernel(AssocArgs A) {
+template <int NB>
+__global__ __launch_bounds__(256) void fit_kernel(AssocBatch<NB> AB) {
+  const AssocArgs& A = event_args(AB);
   const int lane = threadIdx.x & 63;
   const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
   const bool fk = A.n_qpt > 1, fd = A.n_d0 > 1;
@@ -1482,7 +1514,9 @@ __global__ __launch_bounds__(256) void fit_kernel(AssocArgs A) {
 // the covariance, so its gain is zero and it never moves.  Status 1 when a
 // hit has |u| >= 1, 2 when an innovation variance is not positive.  The
 // filter is sequential in the hits, so one thread owns one track.
-__global__ __launch_bounds__(64) void kf_kernel(AssocArgs A) {
+template <int NB>
+__global__ __launch_bounds__(64) void kf_kernel(AssocBatch<NB> AB) {
+  const AssocArgs& A = event_args(AB);
   const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
   const int t = blockIdx.x * 64 + threadIdx.x;
   if (t >= ntrk) return;
@@ -1603,7 +1637,9 @@ __device__ __forceinline__ void branch_arc(double cA, double cB, double cC, doub
 // the two-branch vote, the incoming arc (perigee radius to the row's top).
 // (A thread per track walked its rows in sequence, a chain of float64
 // square roots and arctangents per row on only as many threads as tracks.)
-__global__ __launch_bounds__(256) void vvote_kernel(AssocArgs A) {
+template <int NB>
+__global__ __launch_bounds__(256) void vvote_kernel(AssocBatch<NB> AB) {
+  const AssocArgs& A = event_args(AB);
   const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
   const int nm = A.cfg.n_rho, nt = A.cfg.n_theta;
   const double rw = ((double)A.cfg.rho_hi - (double)A.cfg.rho_lo) / (double)nm;
@@ -1675,7 +1711,9 @@ __device__ __forceinline__ bool vertex_peak(const int32_t* vv, int nm, int nt, i
   return true;
 }
 
-__global__ __launch_bounds__(kVThreads) void vpeaks_kernel(AssocArgs A, int n_zero) {
+template <int NB>
+__global__ __launch_bounds__(kVThreads) void vpeaks_kernel(AssocBatch<NB> AB, int n_zero) {
+  const AssocArgs& A = event_args(AB);
   __shared__ int32_t wsum[kVThreads / kWave];
   __shared__ int32_t sv[kVLds];
   const int nm = A.cfg.n_rho, nt = A.cfg.n_theta;
@@ -1745,7 +1783,9 @@ __device__ __forceinline__ bool is_member(const AssocArgs& A, int t, int m, int 
 }
 
 // pass 1: member count per object (one wave per object)
-__global__ __launch_bounds__(256) void vcount_kernel(AssocArgs A) {
+template <int NB>
+__global__ __launch_bounds__(256) void vcount_kernel(AssocBatch<NB> AB) {
+  const AssocArgs& A = event_args(AB);
   const int nobj = min(A.sc[S_NOBJ], A.out.object_cap);
   const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1762,7 +1802,9 @@ __global__ __launch_bounds__(256) void vcount_kernel(AssocArgs A) {
 }
 
 // pass 2: members in track order, isotropy summed sequentially in that order
-__global__ __launch_bounds__(256) void vmembers_kernel(AssocArgs A, const int32_t* obj_off) {
+template <int NB>
+__global__ __launch_bounds__(256) void vmembers_kernel(AssocBatch<NB> AB) {
+  const AssocArgs& A = event_args(AB);
   const int nobj = min(A.sc[S_NOBJ], A.out.object_cap);
   const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1770,7 +1812,7 @@ __global__ __launch_bounds__(256) void vmembers_kernel(AssocArgs A, const int32_
     ht_object& ob = A.out.objects[o];
     const int c = ob.lin;
     const int m = c / A.cfg.n_theta, ti = c % A.cfg.n_theta;
-    const int begin = obj_off[o];
+    const int begin = A.obj_off[o];
     int cnt = 0;
     double sx = 0.0, sy = 0.0;
     for (int t0 = 0; t0 < ntrk; t0 += 64) {
@@ -1806,7 +1848,9 @@ __global__ __launch_bounds__(256) void vmembers_kernel(AssocArgs A, const int32_
 }
 
 // one wave: lane i reads spread slot i of both counters
-__global__ __launch_bounds__(kWave) void counts_kernel(AssocArgs A) {
+template <int NB>
+__global__ __launch_bounds__(kWave) void counts_kernel(AssocBatch<NB> AB) {
+  const AssocArgs& A = event_args(AB);
   static_assert(kSpread == kWave, "one spread slot per lane");
   int32_t* c = A.out.counts;
   const int lane = threadIdx.x;
@@ -1845,18 +1889,17 @@ int blocks_for(int64_t n, int per) {
   return (int)b;
 }
 
-template <int CAP>
-void launch_refine(const AssocArgs& A, int peak_cap, hipStream_t s) {
+template <int CAP, int NB>
+void launch_refine(const AssocBatch<NB>& AB, int peak_cap, hipStream_t s) {
   constexpr int W = RefineShape<CAP>::kWaves;
-  refine_kernel<CAP><<<blocks_for(peak_cap, W), W * kWave, 0, s>>>(A);
+  refine_kernel<CAP, NB><<<dim3(blocks_for(peak_cap, W), 1, NB), W * kWave, 0, s>>>(AB);
 }
 
-}  // namespace
-
-int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t* layer,
-                 int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks, int32_t peak_cap,
-                 const int32_t* acc, const ht_cluster_cfg& cfg, const ht_cluster_out& out,
-                 hipStream_t s, const int32_t* n_hits_dev) {
+// The arguments of one event's assoc_cluster.
+AssocArgs make_args(const Plan& P, const float* r, const float* phi, const uint8_t* layer,
+                    int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks,
+                    int32_t peak_cap, const int32_t* acc, const ht_cluster_cfg& cfg,
+                    const ht_cluster_out& out, const int32_t* n_hits_dev) {
   const ht_grid& g = P.grid;
   AssocArgs A;
   A.n_phi = g.n_phi;
@@ -1912,74 +1955,142 @@ int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t*
   A.arcin = P.d_arcin;
   A.vacc = out.vacc ? out.vacc : P.d_vacc;
   A.obj_cnt = P.d_obj_cnt;
+  A.obj_off = P.d_obj_off;
   A.sc = P.d_scalars;
   A.spread = P.d_spread;
   A.out = out;
-  if (cfg.member_cap > kMaxMembers) return HT_EUNSUPPORTED;
+  return A;
+}
 
-  const int words = P.n_tiles * 8 + 2;
+// The kernels of assoc_cluster for the NB events of AB, each launch covering
+// all of them (blockIdx.z); P are their plans (the first one's stage timers
+// are marked).  Sizes that set grids (hit bound, peak capacity, output
+// capacities, grid) are the first event's, the same for all.
+template <int NB>
+int assoc_sequence(const AssocBatch<NB>& AB, const Plan* const* P, int32_t n_hits,
+                   int32_t peak_cap, hipStream_t s) {
+  const Plan& P0 = *P[0];
+  const ht_grid& g = P0.grid;
+  const ht_cluster_cfg& cfg = AB.a[0].cfg;
+  const ht_cluster_out& out = AB.a[0].out;
+  if (cfg.member_cap > kMaxMembers) return HT_EUNSUPPORTED;
+  const int words = P0.n_tiles * 8 + 2;
   const int64_t init_n = words > n_hits ? words : n_hits;
-  P.prof_mark(HT_STAGE_ASSOC, 0, s);
-  init_kernel<<<blocks_for(init_n, 256), 256, 0, s>>>(A, words);
+  P0.prof_mark(HT_STAGE_ASSOC, 0, s);
+  init_kernel<NB><<<dim3(blocks_for(init_n, 256), 1, NB), 256, 0, s>>>(AB, words);
   HT_CHECK(hipGetLastError());
-  mark_kernel<<<blocks_for(peak_cap, 256), 256, 0, s>>>(A);
+  mark_kernel<NB><<<dim3(blocks_for(peak_cap, 256), 1, NB), 256, 0, s>>>(AB);
   HT_CHECK(hipGetLastError());
   const int col_tiles = (g.n_qpt + kWave - 1) / kWave;
-  dim3 sweep(col_tiles, g.n_d0, hit_slices(col_tiles * g.n_d0, n_hits));
-  P.prof_mark(HT_STAGE_MEMBERS, 0, s);
-  member_kernel<<<sweep, kSweepThreads, 0, s>>>(A);
+  dim3 sweep(col_tiles, g.n_d0, hit_slices(col_tiles * g.n_d0, n_hits) * NB);
+  P0.prof_mark(HT_STAGE_MEMBERS, 0, s);
+  member_kernel<NB><<<sweep, kSweepThreads, 0, s>>>(AB);
   HT_CHECK(hipGetLastError());
-  P.prof_mark(HT_STAGE_MEMBERS, 1, s);
-  P.prof_mark(HT_STAGE_REFINE, 0, s);
+  P0.prof_mark(HT_STAGE_MEMBERS, 1, s);
+  P0.prof_mark(HT_STAGE_REFINE, 0, s);
   if (cfg.member_cap <= 128)
-    launch_refine<128>(A, peak_cap, s);
+    launch_refine<128, NB>(AB, peak_cap, s);
   else if (cfg.member_cap <= 256)
-    launch_refine<256>(A, peak_cap, s);
+    launch_refine<256, NB>(AB, peak_cap, s);
   else if (cfg.member_cap <= 512)
-    launch_refine<512>(A, peak_cap, s);
+    launch_refine<512, NB>(AB, peak_cap, s);
   else
-    launch_refine<kMaxMembers>(A, peak_cap, s);
+    launch_refine<kMaxMembers, NB>(AB, peak_cap, s);
   HT_CHECK(hipGetLastError());
-  P.prof_mark(HT_STAGE_REFINE, 1, s);
-  own_kernel<<<blocks_for(peak_cap, 256), 256, 0, s>>>(A);
+  P0.prof_mark(HT_STAGE_REFINE, 1, s);
+  own_kernel<NB><<<dim3(blocks_for(peak_cap, 256), 1, NB), 256, 0, s>>>(AB);
   HT_CHECK(hipGetLastError());
   const int tiles = (peak_cap + 255) / 256 > 0 ? (peak_cap + 255) / 256 : 1;
-  surv_count_kernel<<<blocks_for(tiles, 1), 256, 0, s>>>(A, tiles);
+  surv_count_kernel<NB><<<dim3(blocks_for(tiles, 1), 1, NB), 256, 0, s>>>(AB, tiles);
   HT_CHECK(hipGetLastError());
-  int rc = launch_scan(P.d_ctile_cnt, P.d_ctile_off, tiles, P.d_scalars + S_NTRK, s);
+  const int32_t* cnt[NB];
+  int32_t* off[NB];
+  int32_t* tot[NB];
+  for (int b = 0; b < NB; ++b) {
+    cnt[b] = P[b]->d_ctile_cnt;
+    off[b] = P[b]->d_ctile_off;
+    tot[b] = P[b]->d_scalars + S_NTRK;
+  }
+  int rc = NB == 1 ? launch_scan(cnt[0], off[0], tiles, tot[0], s)
+                   : launch_scan_batch(NB, cnt, off, tiles, tot, s);
   if (rc != HT_OK) return rc;
-  surv_emit_kernel<<<blocks_for(tiles, 1), 256, 0, s>>>(A, tiles);
+  surv_emit_kernel<NB><<<dim3(blocks_for(tiles, 1), 1, NB), 256, 0, s>>>(AB, tiles);
   HT_CHECK(hipGetLastError());
   const int tcap = out.track_cap > 0 ? out.track_cap : 1;
   if (out.track_cap > 0) {
     if (cfg.fit_kind == 1)
-      kf_kernel<<<blocks_for(tcap, 64), 64, 0, s>>>(A);
+      kf_kernel<NB><<<dim3(blocks_for(tcap, 64), 1, NB), 64, 0, s>>>(AB);
     else
-      fit_kernel<<<blocks_for(tcap, 4), 256, 0, s>>>(A);
+      fit_kernel<NB><<<dim3(blocks_for(tcap, 4), 1, NB), 256, 0, s>>>(AB);
     HT_CHECK(hipGetLastError());
-    vvote_kernel<<<blocks_for((int64_t)tcap * cfg.n_rho, 256), 256, 0, s>>>(A);
+    vvote_kernel<NB><<<dim3(blocks_for((int64_t)tcap * cfg.n_rho, 256), 1, NB), 256, 0, s>>>(AB);
     HT_CHECK(hipGetLastError());
   }
   const int ocap = out.object_cap > 0 ? out.object_cap : 1;
-  const int ozero = ocap < P.lim.max_vertex_cells ? ocap : P.lim.max_vertex_cells;
-  vpeaks_kernel<<<1, 1024, 0, s>>>(A, ozero);
+  const int ozero = ocap < P0.lim.max_vertex_cells ? ocap : P0.lim.max_vertex_cells;
+  vpeaks_kernel<NB><<<dim3(1, 1, NB), 1024, 0, s>>>(AB, ozero);
   HT_CHECK(hipGetLastError());
   if (out.object_cap > 0) {
-    vcount_kernel<<<blocks_for(ocap, 4), 256, 0, s>>>(A);
+    vcount_kernel<NB><<<dim3(blocks_for(ocap, 4), 1, NB), 256, 0, s>>>(AB);
     HT_CHECK(hipGetLastError());
   }
   // object member offsets, then members and isotropy
-  const int oscan = ocap < P.lim.max_vertex_cells ? ocap : P.lim.max_vertex_cells;
-  rc = launch_scan(P.d_obj_cnt, P.d_obj_off, oscan > 0 ? oscan : 1, P.d_scalars + S_NMEM, s);
+  const int oscan = ocap < P0.lim.max_vertex_cells ? ocap : P0.lim.max_vertex_cells;
+  for (int b = 0; b < NB; ++b) {
+    cnt[b] = P[b]->d_obj_cnt;
+    off[b] = P[b]->d_obj_off;
+    tot[b] = P[b]->d_scalars + S_NMEM;
+  }
+  rc = NB == 1 ? launch_scan(cnt[0], off[0], oscan > 0 ? oscan : 1, tot[0], s)
+               : launch_scan_batch(NB, cnt, off, oscan > 0 ? oscan : 1, tot, s);
   if (rc != HT_OK) return rc;
   if (out.object_cap > 0) {
-    vmembers_kernel<<<blocks_for(ocap, 4), 256, 0, s>>>(A, P.d_obj_off);
+    vmembers_kernel<NB><<<dim3(blocks_for(ocap, 4), 1, NB), 256, 0, s>>>(AB);
     HT_CHECK(hipGetLastError());
   }
-  counts_kernel<<<1, kWave, 0, s>>>(A);
+  counts_kernel<NB><<<dim3(1, 1, NB), kWave, 0, s>>>(AB);
   HT_CHECK(hipGetLastError());
-  P.prof_mark(HT_STAGE_ASSOC, 1, s);
+  P0.prof_mark(HT_STAGE_ASSOC, 1, s);
   return HT_OK;
+}
+
+}  // namespace
+
+int launch_assoc(const Plan& P, const float* r, const float* phi, const uint8_t* layer,
+                 int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks, int32_t peak_cap,
+                 const int32_t* acc, const ht_cluster_cfg& cfg, const ht_cluster_out& out,
+                 hipStream_t s, const int32_t* n_hits_dev) {
+  AssocBatch<1> AB;
+  AB.a[0] = make_args(P, r, phi, layer, n_hits, peaks, n_peaks, peak_cap, acc, cfg, out,
+                      n_hits_dev);
+  const Plan* plans[1] = {&P};
+  return assoc_sequence<1>(AB, plans, n_hits, peak_cap, s);
+}
+
+namespace {
+template <int NB>
+int assoc_batch_nb(const AssocEvent* ev, int32_t n_hits_max, int32_t peak_cap,
+                   const ht_cluster_cfg& cfg, hipStream_t s) {
+  AssocBatch<NB> AB;
+  const Plan* plans[NB];
+  for (int b = 0; b < NB; ++b) {
+    AB.a[b] = make_args(*ev[b].plan, ev[b].r, ev[b].phi, ev[b].layer, n_hits_max, ev[b].peaks,
+                        ev[b].n_peaks, peak_cap, ev[b].acc, cfg, ev[b].out, ev[b].n_hits_dev);
+    plans[b] = ev[b].plan;
+  }
+  return assoc_sequence<NB>(AB, plans, n_hits_max, peak_cap, s);
+}
+}  // namespace
+
+int launch_assoc_batch(int nb, const AssocEvent* ev, int32_t n_hits_max, int32_t peak_cap,
+                       const ht_cluster_cfg& cfg, hipStream_t s) {
+  switch (nb) {
+    case 1: return assoc_batch_nb<1>(ev, n_hits_max, peak_cap, cfg, s);
+    case 2: return assoc_batch_nb<2>(ev, n_hits_max, peak_cap, cfg, s);
+    case 3: return assoc_batch_nb<3>(ev, n_hits_max, peak_cap, cfg, s);
+    case 4: return assoc_batch_nb<4>(ev, n_hits_max, peak_cap, cfg, s);
+    default: return HT_EUNSUPPORTED;
+  }
 }
 
 }  // namespace ht

@@ -103,11 +103,20 @@ namespace ht {
 // which then only bounds it (graph replays of events of any size)
 int launch_vote(const Plan& p, const float* r, const float* phi, int32_t n_hits, int32_t* acc,
                 unsigned long long* n_votes, hipStream_t s, const int32_t* n_hits_dev = nullptr);
+// the vote of nb (<= 4) events in one launch on plan p's grid
+int launch_vote_batch(const Plan& p, int nb, const float* const* r, const float* const* phi,
+                      const int32_t* const* n_dev, int32_t n_hits_max, int32_t* const* acc,
+                      hipStream_t s);
 int launch_cell_vote(const Plan& p, const float* r, const float* phi, int32_t n_hits,
                      int32_t* acc, unsigned long long* n_votes, hipStream_t s);
 int cell_vote_init(int n_phi);
 int launch_peaks(const Plan& p, const int32_t* acc, int32_t min_votes, ht_peak* out,
                  int32_t capacity, int32_t* n_found, hipStream_t s);
+// the peaks of nb (<= 4) events in one launch per kernel, each on its own
+// plan's scratch (plans of one grid)
+int launch_peaks_batch(int nb, const Plan* const* plans, const int32_t* const* acc,
+                       int32_t min_votes, ht_peak* const* out, int32_t capacity,
+                       int32_t* const* n_found, hipStream_t s);
 // hough_peaks on the library's fixed device scratch array (no plan)
 int launch_peaks_noalloc(const ht_grid& g, const int32_t* acc, int32_t min_votes, ht_peak* out,
                          int32_t capacity, int32_t* n_found, hipStream_t s);
@@ -116,9 +125,28 @@ int launch_assoc(const Plan& p, const float* r, const float* phi, const uint8_t*
                  int32_t n_hits, const ht_peak* peaks, const int32_t* n_peaks, int32_t peak_cap,
                  const int32_t* acc, const ht_cluster_cfg& cfg, const ht_cluster_out& out,
                  hipStream_t s, const int32_t* n_hits_dev = nullptr);
+// assoc_cluster over nb events (<= 4) in one launch per kernel: event b has
+// its own plan (scratch), hits, peaks and outputs; the plans share a grid and
+// the events the configuration, hit bound and peak capacity
+struct AssocEvent {
+  const Plan* plan;
+  const float* r;
+  const float* phi;
+  const uint8_t* layer;
+  const int32_t* n_hits_dev;
+  const ht_peak* peaks;
+  const int32_t* n_peaks;
+  const int32_t* acc;
+  ht_cluster_out out;
+};
+int launch_assoc_batch(int nb, const AssocEvent* ev, int32_t n_hits_max, int32_t peak_cap,
+                       const ht_cluster_cfg& cfg, hipStream_t s);
 int launch_asin(const float* u, float* out, int64_t n, hipStream_t s);
 int launch_sqrt(const double* x, double* out, int64_t n, hipStream_t s);
 int launch_scan(const int32_t* cnt, int32_t* off, int n, int32_t* total, hipStream_t s);
+// nb (<= 4) scans of n counts each in one launch
+int launch_scan_batch(int nb, const int32_t* const* cnt, int32_t* const* off, int n,
+                      int32_t* const* total, hipStream_t s);
 int launch_compact(const float* r, const float* phi, const uint8_t* layer, const int32_t* owner,
                    int32_t n, float* out_r, float* out_phi, uint8_t* out_layer,
                    int32_t* out_index, int32_t* n_out, hipStream_t s);

@@ -24,6 +24,21 @@ namespace {
 
 constexpr int kTile = 256;
 
+// The events of one launch (NB of them; blockIdx.y picks one): accumulator,
+// peak ballots, tile counts and offsets, output list and count of each.
+template <int NB>
+struct PeakBatch {
+  const int32_t* acc[NB];
+  void* bits[NB];
+  int32_t* cnt[NB];
+  int32_t* off[NB];
+  ht_peak* out[NB];
+};
+#define HT_PEAK_EVENT(PB)                                                     \
+  const int ev_ = NB == 1 ? 0 : (int)blockIdx.y;                              \
+  const int32_t* __restrict__ acc = (PB).acc[ev_];                            \
+  (void)acc;
+
 __device__ __forceinline__ bool is_peak(const int32_t* __restrict__ acc, int n_phi, int n_qpt,
                                         int n_d0, int k, int j, int i, int32_t thr) {
   const int32_t v = acc[((size_t)k * n_qpt + j) * n_phi + i];
@@ -52,10 +67,12 @@ __device__ __forceinline__ bool is_peak(const int32_t* __restrict__ acc, int n_p
   return true;
 }
 
-__global__ __launch_bounds__(kTile) void flag_kernel(const int32_t* __restrict__ acc, int n_phi,
-                                                     int n_qpt, int n_d0, int64_t n_cells,
-                                                     int32_t thr, uint32_t* __restrict__ bits,
-                                                     int32_t* __restrict__ tile_cnt) {
+template <int NB>
+__global__ __launch_bounds__(kTile) void flag_kernel(PeakBatch<NB> PB, int n_phi, int n_qpt,
+                                                     int n_d0, int64_t n_cells, int32_t thr) {
+  HT_PEAK_EVENT(PB)
+  uint32_t* __restrict__ bits = static_cast<uint32_t*>(PB.bits[ev_]);
+  int32_t* __restrict__ tile_cnt = PB.cnt[ev_];
   __shared__ int32_t wcnt[kTile / kWave];
   const int64_t lin = (int64_t)blockIdx.x * kTile + threadIdx.x;
   bool pk = false;
@@ -83,11 +100,13 @@ __global__ __launch_bounds__(kTile) void flag_kernel(const int32_t* __restrict__
   }
 }
 
-__global__ __launch_bounds__(kTile) void emit_kernel(const int32_t* __restrict__ acc,
-                                                     const uint32_t* __restrict__ bits,
-                                                     const int32_t* __restrict__ tile_off,
-                                                     int64_t n_cells, ht_peak* __restrict__ out,
+template <int NB>
+__global__ __launch_bounds__(kTile) void emit_kernel(PeakBatch<NB> PB, int64_t n_cells,
                                                      int32_t capacity) {
+  HT_PEAK_EVENT(PB)
+  const uint32_t* __restrict__ bits = static_cast<const uint32_t*>(PB.bits[ev_]);
+  const int32_t* __restrict__ tile_off = PB.off[ev_];
+  ht_peak* __restrict__ out = PB.out[ev_];
   __shared__ int32_t wpre[kTile / kWave];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x >> 6;
@@ -137,10 +156,12 @@ __device__ __forceinline__ void load_row6(const int32_t* __restrict__ row, int i
 
 // Ballot words: wave w of tile b writes 4 words at (b * 4 + w) * 4; bit l of
 // word t flags cell b * 1024 + w * 256 + 4 l + t.
-__global__ __launch_bounds__(256) void flag4_kernel(const int32_t* __restrict__ acc, int n_phi,
-                                                    int n_qpt, int n_d0, int64_t n_cells,
-                                                    int32_t thr, uint64_t* __restrict__ bits,
-                                                    int32_t* __restrict__ tile_cnt) {
+template <int NB>
+__global__ __launch_bounds__(256) void flag4_kernel(PeakBatch<NB> PB, int n_phi, int n_qpt,
+                                                    int n_d0, int64_t n_cells, int32_t thr) {
+  HT_PEAK_EVENT(PB)
+  uint64_t* __restrict__ bits = static_cast<uint64_t*>(PB.bits[ev_]);
+  int32_t* __restrict__ tile_cnt = PB.cnt[ev_];
   __shared__ int32_t wcnt[4];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x >> 6;
@@ -224,11 +245,12 @@ __global__ __launch_bounds__(256) void flag4_kernel(const int32_t* __restrict__ 
 // q/pT axis is a multiple of R, so a tile is R whole rows of one d0 plane.
 // The 3 x (R + 2) rows around it are read once, coalesced, instead of nine
 // overlapping row reads per lane from L2.
-template <int R>
-__global__ __launch_bounds__(256) void flag4s_kernel(const int32_t* __restrict__ acc,
-                                                     int n_qpt, int n_d0, int32_t thr,
-                                                     uint64_t* __restrict__ bits,
-                                                     int32_t* __restrict__ tile_cnt) {
+template <int R, int NB>
+__global__ __launch_bounds__(256) void flag4s_kernel(PeakBatch<NB> PB, int n_qpt, int n_d0,
+                                                     int32_t thr) {
+  HT_PEAK_EVENT(PB)
+  uint64_t* __restrict__ bits = static_cast<uint64_t*>(PB.bits[ev_]);
+  int32_t* __restrict__ tile_cnt = PB.cnt[ev_];
   constexpr int NP = kTile4 / R;  // n_phi
   constexpr int ROWS = R + 2;
   __shared__ int32_t sm[3][ROWS][NP];
@@ -323,11 +345,13 @@ __global__ __launch_bounds__(256) void flag4s_kernel(const int32_t* __restrict__
   if (threadIdx.x == 0) tile_cnt[tile] = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
 }
 
-__global__ __launch_bounds__(256) void emit4_kernel(const int32_t* __restrict__ acc,
-                                                    const uint64_t* __restrict__ bits,
-                                                    const int32_t* __restrict__ tile_off,
-                                                    int64_t n_cells, ht_peak* __restrict__ out,
+template <int NB>
+__global__ __launch_bounds__(256) void emit4_kernel(PeakBatch<NB> PB, int64_t n_cells,
                                                     int32_t capacity) {
+  HT_PEAK_EVENT(PB)
+  const uint64_t* __restrict__ bits = static_cast<const uint64_t*>(PB.bits[ev_]);
+  const int32_t* __restrict__ tile_off = PB.off[ev_];
+  ht_peak* __restrict__ out = PB.out[ev_];
   __shared__ int32_t wpre[4];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x >> 6;
@@ -367,36 +391,67 @@ __global__ __launch_bounds__(256) void emit4_kernel(const int32_t* __restrict__ 
 
 int peaks_init(int) { return HT_OK; }
 
-int launch_peaks_core(const ht_grid& g, int64_t n_cells, const int32_t* acc, int32_t min_votes,
-                      ht_peak* out, int32_t capacity, int32_t* n_found, void* bits_v,
-                      int32_t* tile_cnt, int32_t* tile_off, hipStream_t s) {
-  const bool four = (g.n_phi & 3) == 0 && ((uintptr_t)acc & 15) == 0;
+template <int NB>
+int peaks_batch_core(const ht_grid& g, int64_t n_cells, const PeakBatch<NB>& PB, int32_t min_votes,
+                     int32_t capacity, int32_t* const* n_found, hipStream_t s) {
+  bool four = (g.n_phi & 3) == 0;
+  for (int b = 0; b < NB; ++b) four = four && ((uintptr_t)PB.acc[b] & 15) == 0;
   const int tiles = (int)(four ? (n_cells + kTile4 - 1) / kTile4 : (n_cells + kTile - 1) / kTile);
   const int R = four && kTile4 % g.n_phi == 0 ? kTile4 / g.n_phi : 0;
-  uint64_t* bits4 = reinterpret_cast<uint64_t*>(bits_v);
-  uint32_t* bits1 = reinterpret_cast<uint32_t*>(bits_v);
+  const dim3 grid(tiles, NB);
   if (R == 1)
-    flag4s_kernel<1><<<tiles, 256, 0, s>>>(acc, g.n_qpt, g.n_d0, min_votes, bits4, tile_cnt);
+    flag4s_kernel<1, NB><<<grid, 256, 0, s>>>(PB, g.n_qpt, g.n_d0, min_votes);
   else if (R == 2 && g.n_qpt % 2 == 0)
-    flag4s_kernel<2><<<tiles, 256, 0, s>>>(acc, g.n_qpt, g.n_d0, min_votes, bits4, tile_cnt);
+    flag4s_kernel<2, NB><<<grid, 256, 0, s>>>(PB, g.n_qpt, g.n_d0, min_votes);
   else if (R == 4 && g.n_qpt % 4 == 0)
-    flag4s_kernel<4><<<tiles, 256, 0, s>>>(acc, g.n_qpt, g.n_d0, min_votes, bits4, tile_cnt);
+    flag4s_kernel<4, NB><<<grid, 256, 0, s>>>(PB, g.n_qpt, g.n_d0, min_votes);
   else if (four)
-    flag4_kernel<<<tiles, 256, 0, s>>>(acc, g.n_phi, g.n_qpt, g.n_d0, n_cells, min_votes, bits4,
-                                       tile_cnt);
+    flag4_kernel<NB><<<grid, 256, 0, s>>>(PB, g.n_phi, g.n_qpt, g.n_d0, n_cells, min_votes);
   else
-    flag_kernel<<<tiles, kTile, 0, s>>>(acc, g.n_phi, g.n_qpt, g.n_d0, n_cells, min_votes, bits1,
-                                        tile_cnt);
+    flag_kernel<NB><<<grid, kTile, 0, s>>>(PB, g.n_phi, g.n_qpt, g.n_d0, n_cells, min_votes);
   HT_CHECK(hipGetLastError());
-  const int rc = launch_scan(tile_cnt, tile_off, tiles, n_found, s);
+  const int rc = NB == 1 ? launch_scan(PB.cnt[0], PB.off[0], tiles, n_found[0], s)
+                         : launch_scan_batch(NB, PB.cnt, PB.off, tiles, n_found, s);
   if (rc != HT_OK) return rc;
   if (capacity > 0) {
     if (four)
-      emit4_kernel<<<tiles, 256, 0, s>>>(acc, bits4, tile_off, n_cells, out, capacity);
+      emit4_kernel<NB><<<grid, 256, 0, s>>>(PB, n_cells, capacity);
     else
-      emit_kernel<<<tiles, kTile, 0, s>>>(acc, bits1, tile_off, n_cells, out, capacity);
+      emit_kernel<NB><<<grid, kTile, 0, s>>>(PB, n_cells, capacity);
     HT_CHECK(hipGetLastError());
   }
+  return HT_OK;
+}
+
+int launch_peaks_core(const ht_grid& g, int64_t n_cells, const int32_t* acc, int32_t min_votes,
+                      ht_peak* out, int32_t capacity, int32_t* n_found, void* bits_v,
+                      int32_t* tile_cnt, int32_t* tile_off, hipStream_t s) {
+  PeakBatch<1> PB;
+  PB.acc[0] = acc;
+  PB.bits[0] = bits_v;
+  PB.cnt[0] = tile_cnt;
+  PB.off[0] = tile_off;
+  PB.out[0] = out;
+  int32_t* nf[1] = {n_found};
+  return peaks_batch_core<1>(g, n_cells, PB, min_votes, capacity, nf, s);
+}
+
+template <int NB>
+int peaks_batch_nb(const Plan* const* plans, const int32_t* const* acc, int32_t min_votes,
+                   ht_peak* const* out, int32_t capacity, int32_t* const* n_found, hipStream_t s) {
+  PeakBatch<NB> PB;
+  for (int b = 0; b < NB; ++b) {
+    PB.acc[b] = acc[b];
+    PB.bits[b] = plans[b]->d_bits;
+    PB.cnt[b] = plans[b]->d_tile_cnt;
+    PB.off[b] = plans[b]->d_tile_off;
+    PB.out[b] = out[b];
+  }
+  const Plan& p0 = *plans[0];
+  p0.prof_mark(HT_STAGE_PEAKS, 0, s);
+  const int rc = peaks_batch_core<NB>(p0.grid, p0.n_cells, PB, min_votes, capacity, n_found, s);
+  if (rc != HT_OK) return rc;
+  p0.prof_mark(HT_STAGE_PEAKS, 1, s);
   return HT_OK;
 }
 
@@ -408,6 +463,18 @@ int launch_peaks(const Plan& p, const int32_t* acc, int32_t min_votes, ht_peak* 
   if (rc != HT_OK) return rc;
   p.prof_mark(HT_STAGE_PEAKS, 1, s);
   return HT_OK;
+}
+
+int launch_peaks_batch(int nb, const Plan* const* plans, const int32_t* const* acc,
+                       int32_t min_votes, ht_peak* const* out, int32_t capacity,
+                       int32_t* const* n_found, hipStream_t s) {
+  switch (nb) {
+    case 1: return peaks_batch_nb<1>(plans, acc, min_votes, out, capacity, n_found, s);
+    case 2: return peaks_batch_nb<2>(plans, acc, min_votes, out, capacity, n_found, s);
+    case 3: return peaks_batch_nb<3>(plans, acc, min_votes, out, capacity, n_found, s);
+    case 4: return peaks_batch_nb<4>(plans, acc, min_votes, out, capacity, n_found, s);
+    default: return HT_EUNSUPPORTED;
+  }
 }
 
 // Largest accumulator hough_peaks_noalloc takes, and its scratch: the ballot

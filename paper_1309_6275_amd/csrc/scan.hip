@@ -25,9 +25,29 @@ __device__ __forceinline__ int32_t clamp_i32(long long v) {
   return v > 0x7fffffffLL ? 0x7fffffff : (int32_t)v;
 }
 
+// pointers of up to kScanBatch scans run by one launch (one workgroup each)
+constexpr int kScanBatch = 4;
+struct ScanBatch {
+  const int32_t* cnt[kScanBatch];
+  int32_t* off[kScanBatch];
+  int32_t* total[kScanBatch];
+};
+
+__device__ void scan_one(const int32_t* __restrict__ cnt, int32_t* __restrict__ off, int n,
+                         int32_t* __restrict__ total);
+
 __global__ __launch_bounds__(kScanThreads) void scan_kernel(const int32_t* __restrict__ cnt,
                                                             int32_t* __restrict__ off, int n,
                                                             int32_t* __restrict__ total) {
+  scan_one(cnt, off, n, total);
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_batch_kernel(ScanBatch B, int n) {
+  scan_one(B.cnt[blockIdx.x], B.off[blockIdx.x], n, B.total[blockIdx.x]);
+}
+
+__device__ void scan_one(const int32_t* __restrict__ cnt, int32_t* __restrict__ off, int n,
+                         int32_t* __restrict__ total) {
   __shared__ long long wsum[kScanWaves];
   const int t = threadIdx.x;
   const int lane = t & (kWave - 1);
@@ -54,6 +74,20 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(const int32_t* __res
 
 int launch_scan(const int32_t* cnt, int32_t* off, int n, int32_t* total, hipStream_t s) {
   scan_kernel<<<1, kScanThreads, 0, s>>>(cnt, off, n, total);
+  HT_CHECK(hipGetLastError());
+  return HT_OK;
+}
+
+int launch_scan_batch(int nb, const int32_t* const* cnt, int32_t* const* off, int n,
+                      int32_t* const* total, hipStream_t s) {
+  if (nb < 1 || nb > kScanBatch) return HT_EUNSUPPORTED;
+  ScanBatch B = {};
+  for (int b = 0; b < nb; ++b) {
+    B.cnt[b] = cnt[b];
+    B.off[b] = off[b];
+    B.total[b] = total[b];
+  }
+  scan_batch_kernel<<<nb, kScanThreads, 0, s>>>(B, n);
   HT_CHECK(hipGetLastError());
   return HT_OK;
 }

@@ -38,21 +38,40 @@ __device__ __forceinline__ float bcast(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-template <bool POW2, bool WIDE>
+// The events of one launch (a batch of NB events; one event is the batch of
+// one): hits, device hit count (optional), accumulator and vote total
+// (optional) of each.
+template <int NB>
+struct VoteBatch {
+  const float* r[NB];
+  const float* phi[NB];
+  const int32_t* n_dev[NB];
+  int32_t* acc[NB];
+  unsigned long long* n_votes[NB];
+};
+
+template <bool POW2, bool WIDE, int NB>
 __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
-    const float* __restrict__ r, const float* __restrict__ phi, int n_hits_max,
-    const int32_t* __restrict__ n_hits_dev, const float* __restrict__ kap, const float* __restrict__ qt, const float* __restrict__ tt,
-    int n_phi, int n_qpt, float phi_lo, float invw, int stride, int32_t* __restrict__ acc,
-    unsigned long long* __restrict__ n_votes) {
+    VoteBatch<NB> V, int n_hits_max, const float* __restrict__ kap,
+    const float* __restrict__ qt, const float* __restrict__ tt, int n_phi, int n_qpt,
+    float phi_lo, float invw, int stride) {
   extern __shared__ uint32_t lds[];
   __shared__ RadiusSet R;
   __shared__ float s_tab[kMaxRadii][kWave];  // arcsine per (radius, column), NaN: no vote
+  // blockIdx.z = event * slices + slice of the event's hits
+  const int n_slices = gridDim.z / NB;
+  const int ev = NB == 1 ? 0 : (int)blockIdx.z / n_slices;
+  const int slice = (int)blockIdx.z % n_slices;
+  const float* __restrict__ r = V.r[ev];
+  const float* __restrict__ phi = V.phi[ev];
+  const int32_t* __restrict__ n_hits_dev = V.n_dev[ev];
+  int32_t* __restrict__ acc = V.acc[ev];
+  unsigned long long* __restrict__ n_votes = V.n_votes[ev];
   // hits of this event: the device count when given (clamped to the bound the
   // buffers were checked for), else the host count
   const int n_all = n_hits_dev ? min(max(*n_hits_dev, 0), n_hits_max) : n_hits_max;
-  const int n_slices = gridDim.z;
   const int chunk = ((n_all + n_slices - 1) / n_slices + kWave - 1) / kWave * kWave;
-  const int h0 = (int)blockIdx.z * chunk;
+  const int h0 = slice * chunk;
   const int n_hits = min(n_all, h0 + chunk);
   if (n_slices > 1 && h0 >= n_hits) return;  // an empty slice adds nothing
   const int lane = threadIdx.x & (kWave - 1);
@@ -202,46 +221,100 @@ int vote_stride(int n_phi) {
 
 }  // namespace
 
-int vote_init(int n_phi) {
-  const int bytes = kWave * vote_stride(n_phi) * 4;
+namespace {
+template <int NB>
+int vote_init_nb(int bytes) {
   const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
-  HT_CHECK(hipFuncSetAttribute((const void*)vote_kernel<true, true>, at, bytes));
-  HT_CHECK(hipFuncSetAttribute((const void*)vote_kernel<false, true>, at, bytes));
-  HT_CHECK(hipFuncSetAttribute((const void*)vote_kernel<true, false>, at, bytes));
-  HT_CHECK(hipFuncSetAttribute((const void*)vote_kernel<false, false>, at, bytes));
+  HT_CHECK(hipFuncSetAttribute((const void*)vote_kernel<true, true, NB>, at, bytes));
+  HT_CHECK(hipFuncSetAttribute((const void*)vote_kernel<false, true, NB>, at, bytes));
+  HT_CHECK(hipFuncSetAttribute((const void*)vote_kernel<true, false, NB>, at, bytes));
+  HT_CHECK(hipFuncSetAttribute((const void*)vote_kernel<false, false, NB>, at, bytes));
   return HT_OK;
 }
 
-int launch_vote(const Plan& p, const float* r, const float* phi, int32_t n_hits, int32_t* acc,
-                unsigned long long* n_votes, hipStream_t s, const int32_t* n_hits_dev) {
+// The vote of NB events on one plan's grid (the plan gives the tables).
+template <int NB>
+int vote_launch(const Plan& p, const VoteBatch<NB>& V, int32_t n_hits, hipStream_t s) {
   const ht_grid& g = p.grid;
   const int stride = vote_stride(g.n_phi);
   const size_t lds_bytes = (size_t)kWave * stride * 4;
-  if (n_votes) {
-    zero_u64_kernel<<<1, 1, 0, s>>>(n_votes);
-    HT_CHECK(hipGetLastError());
+  for (int b = 0; b < NB; ++b) {
+    if (V.n_votes[b]) {
+      zero_u64_kernel<<<1, 1, 0, s>>>(V.n_votes[b]);
+      HT_CHECK(hipGetLastError());
+    }
   }
   const int tiles = (g.n_qpt + kWave - 1) / kWave * g.n_d0;
   const int slices = hit_slices(tiles, n_hits);
-  dim3 grid((g.n_qpt + kWave - 1) / kWave, g.n_d0, slices);
+  dim3 grid((g.n_qpt + kWave - 1) / kWave, g.n_d0, slices * NB);
   if (slices > 1) {
     // the slices add into the accumulator: clear it first (a kernel, so the
     // sequence can be captured in a graph)
     const int64_t cells = p.n_cells;
     const int64_t blocks = (cells + 1023) / 1024 < 1024 ? (cells + 1023) / 1024 : 1024;
-    zero_i32_kernel<<<(unsigned)blocks, 256, 0, s>>>(acc, cells);
-    HT_CHECK(hipGetLastError());
+    for (int b = 0; b < NB; ++b) {
+      zero_i32_kernel<<<(unsigned)blocks, 256, 0, s>>>(V.acc[b], cells);
+      HT_CHECK(hipGetLastError());
+    }
   }
   const bool pow2 = (g.n_phi & (g.n_phi - 1)) == 0;
   const bool wide = vote_wide(g.n_phi);
-  auto kern = pow2 ? (wide ? vote_kernel<true, true> : vote_kernel<true, false>)
-                   : (wide ? vote_kernel<false, true> : vote_kernel<false, false>);
+  auto kern = pow2 ? (wide ? vote_kernel<true, true, NB> : vote_kernel<true, false, NB>)
+                   : (wide ? vote_kernel<false, true, NB> : vote_kernel<false, false, NB>);
   p.prof_mark(HT_STAGE_VOTE, 0, s);
-  kern<<<grid, kVoteThreads, lds_bytes, s>>>(r, phi, n_hits, n_hits_dev, p.d_kap, p.d_q, p.d_t, g.n_phi,
-                                             g.n_qpt, p.phi_lo, p.invw, stride, acc, n_votes);
+  kern<<<grid, kVoteThreads, lds_bytes, s>>>(V, n_hits, p.d_kap, p.d_q, p.d_t, g.n_phi, g.n_qpt,
+                                             p.phi_lo, p.invw, stride);
   HT_CHECK(hipGetLastError());
   p.prof_mark(HT_STAGE_VOTE, 1, s);
   return HT_OK;
+}
+
+template <int NB>
+int vote_batch_nb(const Plan& p, const float* const* r, const float* const* phi,
+                  const int32_t* const* n_dev, int32_t n_hits_max, int32_t* const* acc,
+                  hipStream_t s) {
+  VoteBatch<NB> V;
+  for (int b = 0; b < NB; ++b) {
+    V.r[b] = r[b];
+    V.phi[b] = phi[b];
+    V.n_dev[b] = n_dev[b];
+    V.acc[b] = acc[b];
+    V.n_votes[b] = nullptr;
+  }
+  return vote_launch<NB>(p, V, n_hits_max, s);
+}
+}  // namespace
+
+int vote_init(int n_phi) {
+  const int bytes = kWave * vote_stride(n_phi) * 4;
+  int rc = vote_init_nb<1>(bytes);
+  if (rc == HT_OK) rc = vote_init_nb<2>(bytes);
+  if (rc == HT_OK) rc = vote_init_nb<3>(bytes);
+  if (rc == HT_OK) rc = vote_init_nb<4>(bytes);
+  return rc;
+}
+
+int launch_vote_batch(const Plan& p, int nb, const float* const* r, const float* const* phi,
+                      const int32_t* const* n_dev, int32_t n_hits_max, int32_t* const* acc,
+                      hipStream_t s) {
+  switch (nb) {
+    case 1: return vote_batch_nb<1>(p, r, phi, n_dev, n_hits_max, acc, s);
+    case 2: return vote_batch_nb<2>(p, r, phi, n_dev, n_hits_max, acc, s);
+    case 3: return vote_batch_nb<3>(p, r, phi, n_dev, n_hits_max, acc, s);
+    case 4: return vote_batch_nb<4>(p, r, phi, n_dev, n_hits_max, acc, s);
+    default: return HT_EUNSUPPORTED;
+  }
+}
+
+int launch_vote(const Plan& p, const float* r, const float* phi, int32_t n_hits, int32_t* acc,
+                unsigned long long* n_votes, hipStream_t s, const int32_t* n_hits_dev) {
+  VoteBatch<1> V;
+  V.r[0] = r;
+  V.phi[0] = phi;
+  V.n_dev[0] = n_hits_dev;
+  V.acc[0] = acc;
+  V.n_votes[0] = n_votes;
+  return vote_launch<1>(p, V, n_hits, s);
 }
 
 int launch_sqrt(const double* x, double* out, int64_t n, hipStream_t s) {

@@ -67,6 +67,13 @@ class ClusterOut(C.Structure):
                 ("vacc", C.c_void_p), ("counts", C.c_void_p), ("work", C.c_void_p)]
 
 
+class BatchEvent(C.Structure):
+    _fields_ = [("plan", C.c_void_p), ("r", C.c_void_p), ("phi", C.c_void_p),
+                ("layer", C.c_void_p), ("n_hits_dev", C.c_void_p), ("acc", C.c_void_p),
+                ("peaks", C.c_void_p), ("n_peaks", C.c_void_p), ("out", ClusterOut)]
+
+
+MAX_BATCH = 4
 SERVER_MAX_KINDS = 4
 HT_EBUSY = -5
 
@@ -131,6 +138,7 @@ def lib():
                                         vp, C.c_size_t, vp]
         L.ht_cnn_keep.argtypes = [vp, vp, vp, vp, i32, C.c_float, vp, i32, vp, vp]
         L.ht_cnn_score.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, C.c_size_t, vp]
+        L.hough_batch.argtypes = [i32, vp, i32, i32, i32, vp, vp]
         L.ht_server_create.argtypes = [vp, vp]
         L.ht_server_destroy.argtypes = [vp]
         L.ht_server_info.argtypes = [vp, vp, vp]
@@ -144,7 +152,8 @@ def lib():
                   "ht_server_create", "ht_server_destroy", "ht_server_info", "ht_server_submit",
                   "ht_server_poll", "ht_cnn_windows", "ht_cnn_forward", "ht_cnn_train_step",
                   "ht_cnn_keep", "hough_vote_cell", "ht_compact_hits", "ht_remap_track_hits",
-                  "hough_vote_n", "assoc_cluster_n", "hough_peaks_noalloc", "ht_cnn_score"):
+                  "hough_vote_n", "assoc_cluster_n", "hough_peaks_noalloc", "ht_cnn_score",
+                  "hough_batch"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -450,6 +459,41 @@ def assoc_cluster_n(plan: Plan, r, phi, layer, n_hits_dev, peaks, n_peaks, cfg: 
            "assoc_cluster_n")
 
 
+def hough_batch(events, n_hits_max: int, min_votes: int, cfg: dict, with_vacc=True,
+                stream=None):
+    """hough_vote, hough_peaks and assoc_cluster for up to MAX_BATCH events in
+    one launch per kernel.  events: list of dicts with plan, r, phi, layer
+    (device tensors holding at least n_hits_max hits), n_dev (int32 [1]
+    device hit count), acc, peaks (int32 [peak_cap, 2]), nf (int32 [1]) and
+    bufs (ClusterBuffers); every peaks tensor has the same capacity."""
+    torch = _torch()
+    nb = len(events)
+    _need(1 <= nb <= MAX_BATCH, "1 .. 4 events")
+    cap = int(events[0]["peaks"].shape[0])
+    arr = (BatchEvent * nb)()
+    keep = []
+    for b, e in enumerate(events):
+        plan = e["plan"]
+        for t in (e["r"], e["phi"], e["layer"]):
+            _need(t.numel() >= n_hits_max, "hits hold fewer entries than n_hits_max")
+        _need(tuple(e["acc"].shape) == plan.acc_shape, "acc must have the plan's shape")
+        _need(e["peaks"].dim() == 2 and e["peaks"].shape == (cap, 2), "peaks must be int32 [cap, 2]")
+        _need(e["n_dev"].numel() >= 1 and e["nf"].numel() >= 1, "counts must hold one element")
+        _check_cluster_args(plan, n_hits_max, e["peaks"], e["nf"], cfg, e["bufs"], with_vacc)
+        o = e["bufs"].struct(with_vacc)
+        keep.append(o)
+        arr[b] = BatchEvent(plan.handle.value, _ptr(e["r"], torch.float32, "r").value,
+                            _ptr(e["phi"], torch.float32, "phi").value,
+                            _ptr(e["layer"], torch.uint8, "layer").value,
+                            _ptr(e["n_dev"], torch.int32, "n_dev").value,
+                            _ptr(e["acc"], torch.int32, "acc").value,
+                            _ptr(e["peaks"], torch.int32, "peaks").value,
+                            _ptr(e["nf"], torch.int32, "nf").value, o)
+    c = cluster_struct(cfg)
+    _check(lib().hough_batch(nb, C.cast(arr, C.c_void_p), int(n_hits_max), int(min_votes), cap,
+                             C.byref(c), _stream(stream)), "hough_batch")
+
+
 def asin_f32(u, out, stream=None):
     torch = _torch()
     _check(lib().ht_asin_f32(_ptr(u, torch.float32, "u"), _ptr(out, torch.float32, "out"),
@@ -691,4 +735,4 @@ EXPORTS = ("ht_plan_create", "ht_plan_destroy", "ht_strerror", "hough_vote", "ho
            "ht_server_submit", "ht_server_poll", "ht_cnn_workspace_bytes", "ht_cnn_windows",
            "ht_cnn_forward", "ht_cnn_train_step", "ht_cnn_keep", "ht_compact_hits",
            "ht_remap_track_hits", "hough_vote_n", "assoc_cluster_n", "hough_peaks_noalloc",
-           "ht_cnn_score")
+           "ht_cnn_score", "hough_batch")
