@@ -190,26 +190,69 @@ def serve_kinds():
                  min_votes=CF.WORKLOADS[2]["min_votes"], peak_cap=1 << 21)]
 
 
+# events of at most this many hits may share a batch in the learned + batched
+# serving configuration
+SERVE_BATCH_HITS = 16384
+SERVE_RATES = (50, 100, 150, 200, 250, 300, 350, 400, 500, 600, 800, 1000)
+
+
+def serve_filter(torch, H, n_train, n_val, keep=0.995):
+    """The 3D kind's learned peak filter, trained on the device on events of
+    the serving stream's 3D kind (seeds apart from the replayed pool's),
+    threshold keeping the fraction keep of the validation events' truth
+    positives."""
+    from paper_1309_6275_amd import configs as CF
+    from paper_1309_6275_amd import eventgen as G
+    from paper_1309_6275_amd import peakfilter as PF
+    W = CF.WORKLOADS[2]
+    t0 = time.perf_counter()
+    pl = PF.Pipeline(torch, H, W, peak_cap=1 << 21)
+    rng = np.random.default_rng(4_200_000)
+    X, Y = PF.training_set(pl, (G.make_serving_event(1, 4_200_001 + 2 * e) for e in range(n_train)),
+                           W["cluster"], rng, 3000)
+    params, losses, _ = PF.train(pl, X, Y, rng)
+    thr = PF.threshold(pl, params, (G.make_serving_event(1, 4_300_001 + 2 * e)
+                                    for e in range(n_val)), W["cluster"], keep)
+    out = params.cpu().numpy()
+    info = dict(train_events=n_train, val_events=n_val, train_windows=int(Y.size),
+                train_positives=int(Y.sum()), epoch_loss=losses, threshold=thr, keep_target=keep,
+                seconds=time.perf_counter() - t0)
+    del pl, X, params
+    torch.cuda.empty_cache()
+    return out, thr, info
+
+
 def serve_bench(args):
     """Real-time replay of Poisson arrivals through the server (host clock:
-    latency = result seen by poll - arrival), several rates; then the 20 kHz
-    stream with a bounded queue; then closed-loop throughput with and
-    without graph replay, and of a 2D-only stream."""
+    latency = result seen by poll - arrival), several rates, for three
+    configurations: the plain serial baseline (one slot: events one after
+    another, no filter), plain (four slots), and learned + batched (four
+    slots, waiting events batched four to a launch, the 3D kind's peaks
+    filtered by the learned filter).  Then the 20 kHz stream with a bounded
+    queue, closed-loop throughput of each configuration and of the two
+    ingredients alone, and the track efficiency and fake rate of each
+    configuration's results on the replayed pool."""
     import torch
+    from paper_1309_6275_amd import configs as CF
     from paper_1309_6275_amd import eventgen as G
     from paper_1309_6275_amd import houghtrig as H
+    from paper_1309_6275_amd import metrics as M
     torch.cuda.set_device(0)
     pool = [(k, G.make_serving_event(k, 4_000_001 + 2 * i + k)) for i in range(16) for k in (0, 1)]
     kinds = serve_kinds()
+    params, thr, filt_info = serve_filter(torch, H, n_train=16, n_val=4)
+    print(json.dumps({"filter": filt_info}), file=sys.stderr, flush=True)
+    learned_kinds = [kinds[0], dict(kinds[1], cnn_params=params, cnn_threshold=thr)]
 
     largest = 65535 * max(k["grid"]["n_qpt"] * k["grid"]["n_d0"] for k in kinds)
     frac = SERVE_WORK_BUDGET if args.work_budget is None else args.work_budget
     work_budget = int(frac * largest)
 
-    def make(use_graphs=True, slots=4, queue=64, budget=work_budget):
+    def make(kinds=kinds, use_graphs=True, slots=4, queue=64, budget=work_budget, batch=0):
         return H.Server(kinds, max_hits=65535, track_cap=4096, object_cap=256, member_cap=4096,
-                        hbm_budget=96 << 30, max_slots=slots, queue_cap=queue,
-                        use_graphs=use_graphs, work_budget=budget)
+                        hbm_budget=128 << 30, max_slots=slots, queue_cap=queue,
+                        use_graphs=use_graphs, work_budget=budget, batch_max=batch,
+                        batch_max_hits=SERVE_BATCH_HITS if batch > 1 else 0)
 
     tags = iter(range(1 << 62))
 
@@ -220,18 +263,25 @@ def serve_bench(args):
         n = max(min_events, int(rate * seconds))
         arrivals = np.cumsum(arng.exponential(1.0 / rate, n))
         picks = arng.integers(0, len(events), n)
-        lat, shed = [], 0
+        lat, shed, batched = [], 0, 0
+
+        def take(done):
+            nonlocal batched
+            for d in done:
+                lat.append(d["t_done"] - d["t_submit"])
+                batched += d["batch"] > 1
         t0 = time.perf_counter()
         for a, p in zip(arrivals, picks):
             while time.perf_counter() - t0 < a:
-                lat += [d["t_done"] - d["t_submit"] for d in srv.poll(wait=False)]
+                take(srv.poll(wait=False))
             k, ev = events[p]
             if not srv.submit(k, ev.r, ev.phi, ev.layer, next(tags), want_outputs=False):
                 shed += 1
-        lat += [d["t_done"] - d["t_submit"] for d in srv.drain()]
+        take(srv.drain())
         wall = time.perf_counter() - t0
         lat = np.array(lat) * 1e3
         return dict(rate=rate, offered=n, done=int(lat.size), shed=shed, wall_s=wall,
+                    batched_fraction=batched / max(1, lat.size),
                     p50_ms=float(np.percentile(lat, 50)) if lat.size else None,
                     p99_ms=float(np.percentile(lat, 99)) if lat.size else None)
 
@@ -248,62 +298,104 @@ def serve_bench(args):
             done += len(srv.poll(wait=True))
         return n / (time.perf_counter() - t0)
 
-    def sweep(srv):
+    def sweep(srv, name):
         """Poisson rates in increasing order until the p99 passes 50 ms; the
         highest rate with nothing shed and a p99 under 10 ms."""
         out = []
-        for rate in (50, 100, 150, 200, 250, 300, 350, 400, 600):
+        for rate in SERVE_RATES:
             r = replay(srv, rate, args.serve_seconds, pool, min_events=400)
             out.append(r)
-            print(json.dumps(r), file=sys.stderr, flush=True)
+            print(json.dumps(dict(r, config=name)), file=sys.stderr, flush=True)
             if r["p99_ms"] is not None and r["p99_ms"] > 50:
                 break
         ok = [r["rate"] for r in out
               if r["shed"] == 0 and r["p99_ms"] is not None and r["p99_ms"] < 10]
         return out, (max(ok) if ok else None)
 
-    srv = make()
-    # warm up every slot and kind
-    closed_loop(srv, pool, 2 * len(pool))
-    rates, best = sweep(srv)
-    hi = replay(srv, 20000, 1.0, pool)
-    tput = closed_loop(srv, pool, 4 * len(pool))
-    srv.close()
-    direct = make(use_graphs=False)
+    def physics(srv):
+        """Track efficiency and fake rate over the pool's events (truth
+        matching of the served tracks), per kind and overall, and the peaks
+        handed to assoc_cluster as a fraction of the threshold peaks."""
+        for i, (k, ev) in enumerate(pool):
+            assert srv.submit(k, ev.r, ev.phi, ev.layer, (1 << 61) + i)
+        got = {d["tag"] - (1 << 61): d for d in srv.drain()}
+        tot = {0: np.zeros(4), 1: np.zeros(4)}
+        peaks = np.zeros(2)
+        for i, (k, ev) in enumerate(pool):
+            d = got[i]
+            K = kinds[k]
+            tm = M.track_metrics(ev, K["grid"], K["cluster"]["min_layers"], d["tracks"]["hits"])
+            tot[k] += [tm["n_found"], tm["n_truth_acc"], tm["n_fake"], tm["n_tracks"]]
+            if k == 1:
+                peaks += [d["n_kept"], d["n_peaks"]]
+        out = {}
+        for k, name in ((0, "2d"), (1, "3d")):
+            f, a, fk, nt = tot[k]
+            out[name] = dict(track_efficiency=f / max(a, 1), fake_rate=fk / max(nt, 1))
+        f, a, fk, nt = tot[0] + tot[1]
+        out.update(track_efficiency=f / max(a, 1), fake_rate=fk / max(nt, 1),
+                   kept_fraction_3d=peaks[0] / max(peaks[1], 1))
+        return out
+
+    def run_config(name, srv, do_sweep=True):
+        closed_loop(srv, pool, 2 * len(pool))  # warm every slot, kind and batch size
+        res = dict(slots=srv.n_slots, slot_bytes=srv.slot_bytes)
+        if do_sweep:
+            res["rates"], res["value"] = sweep(srv, name)
+            best = next((r for r in res["rates"] if r["rate"] == res["value"]), None)
+            res["p50_ms"] = best["p50_ms"] if best else None
+            res["p99_ms"] = best["p99_ms"] if best else None
+            res["at_20kHz"] = replay(srv, 20000, 1.0, pool)
+        res["closed_loop_events_per_s"] = closed_loop(srv, pool, 4 * len(pool))
+        res["physics"] = physics(srv)
+        srv.close()
+        print(json.dumps({name: {k: v for k, v in res.items() if k != "rates"}}), file=sys.stderr,
+              flush=True)
+        return res
+
+    learned = run_config("learned_batched", make(learned_kinds, batch=4))
+    plain = run_config("plain", make())
+    serial = run_config("plain_serial", make(slots=1))
+    batched_only = run_config("batched_no_filter", make(batch=4), do_sweep=False)
+    filter_only = run_config("filter_no_batching", make(learned_kinds), do_sweep=False)
+    direct = make(learned_kinds, use_graphs=False, batch=4)
     closed_loop(direct, pool, len(pool))
     tput_direct = closed_loop(direct, pool, 4 * len(pool))
     direct.close()
     two_d = [e for e in pool if e[0] == 0]
-    srv2 = make()
+    srv2 = make(learned_kinds, batch=4)
     closed_loop(srv2, two_d, len(two_d))
     tput_2d = closed_loop(srv2, two_d, 8 * len(two_d))
-    n_slots, slot_bytes = srv2.n_slots, srv2.slot_bytes
     srv2.close()
-    # the serial per-event baseline: one slot, so events never overlap
-    serial = make(slots=1)
-    closed_loop(serial, pool, len(pool))
-    tput_serial = closed_loop(serial, pool, 2 * len(pool))
-    serial_rates, serial_best = sweep(serial)
-    serial.close()
-    best_r = next((r for r in rates if r["rate"] == best), None)
     line = {
-        "metric": SERVE_METRIC, "value": best, "unit": "events/s", "n_gpus": 1,
-        "higher_is_better": True, "data": "synthetic", "dtype": "f32+f64",
+        "metric": SERVE_METRIC, "value": learned["value"], "unit": "events/s", "n_gpus": 1,
+        "higher_is_better": True, "data": "synthetic", "dtype": "f32+f64+bf16",
         "config": {"workload": "mixed trigger stream: 50% 2D (256x256) / 50% 3D (512x256x64) "
                                "events, hits ~ U[2k, 60k], pool of 32 seeded events",
-                   "slots": n_slots, "slot_bytes": slot_bytes, "queue_cap": 64,
-                   "graphs": True, "work_budget": work_budget,
+                   "form": "learned + batched: 4 slots, up to 4 waiting events of a kind with "
+                           f"<= {SERVE_BATCH_HITS} hits per launch, learned peak filter on the "
+                           "3D kind (keeps 99.5% of validation truth positives)",
+                   "slots": learned["slots"], "slot_bytes": learned["slot_bytes"],
+                   "queue_cap": 64, "graphs": True, "work_budget": work_budget,
                    "work_budget_fraction_of_largest_event": frac},
-        "p50_ms": best_r["p50_ms"] if best_r else None,
-        "p99_ms": best_r["p99_ms"] if best_r else None,
-        "rates": rates,
-        "at_20kHz": hi,
-        "closed_loop_events_per_s": tput,
+        "p50_ms": learned["p50_ms"], "p99_ms": learned["p99_ms"],
+        "track_efficiency": learned["physics"]["track_efficiency"],
+        "fake_rate": learned["physics"]["fake_rate"],
+        "physics": learned["physics"],
+        "rates": learned["rates"],
+        "at_20kHz": learned["at_20kHz"],
+        "closed_loop_events_per_s": learned["closed_loop_events_per_s"],
         "closed_loop_events_per_s_direct_launches": tput_direct,
         "closed_loop_2d_only_events_per_s": tput_2d,
-        "closed_loop_events_per_s_one_slot": tput_serial,
-        "one_slot_value": serial_best,
-        "one_slot_rates": serial_rates,
+        "filter": filt_info,
+        "plain_serial": serial,
+        "plain": plain,
+        "batched_no_filter": batched_only,
+        "filter_no_batching": filter_only,
+        "vs_plain_serial": (learned["value"] / serial["value"]
+                            if learned["value"] and serial["value"] else None),
+        "vs_plain": (learned["value"] / plain["value"]
+                     if learned["value"] and plain["value"] else None),
     }
     print(json.dumps(line), flush=True)
 

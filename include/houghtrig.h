@@ -437,22 +437,34 @@ int ht_cnn_keep(const ht_plan* plan, const float* logits, const ht_peak* peaks,
  * event must be processed within the latency the trigger allows, section
  * "Physics Motivation"; copying the data to the GPU is part of the cost,
  * section "Preliminary Results").  The server owns a fixed set of slots;
- * each slot has its own stream, a plan per grid kind and a resident
- * accumulator, peak list and outputs, and runs one event at a time: copy of
- * the hits to the device, hough_vote, hough_peaks, assoc_cluster, copy of
- * the results to pinned host memory.  With use_graphs the device part of a
- * slot is one HIP graph per kind, captured at creation and replayed for
- * every event (the hit count travels in device memory).  The number of slots
- * is the largest that fits hbm_budget (at most max_slots); events that find
- * every slot busy wait in a FIFO of queue_cap; beyond it ht_server_submit
- * returns HT_EBUSY (the event is shed).  With a work budget, the events in
- * flight share the device by their work (hits times the q/pT x d0 columns
- * of their kind): a waiting event starts, in FIFO order, when a slot is
- * free and the work in flight plus its own stays within work_budget, or
- * when nothing else runs (an event too large for the budget runs alone).
- * Large events then run one after another, each at the speed of the whole
- * device, while small ones overlap.  Results are exactly those of the
- * three calls made one by one for the same event.  Single-threaded: one
+ * each slot has its own stream and room for a batch of up to batch_max
+ * events of one kind: per event a plan per grid kind and a resident
+ * accumulator, peak list and outputs.  A slot runs one batch at a time:
+ * copies of the hits to the device, one launch of the vote, of each peak
+ * finder stage and of each assoc_cluster kernel for the whole batch (the
+ * batched form of hough_batch), copies of the results to pinned host
+ * memory.  A kind may carry the learned peak filter: its parameters
+ * (HT_CNN_PARAMS float32, host memory, copied at creation) and threshold;
+ * then ht_cnn_score and ht_cnn_keep run on each event's threshold peaks and
+ * assoc_cluster refines the kept ones (the peak search improvement the
+ * paper's summary names as future work).  With use_graphs the device part
+ * of a slot is one HIP graph per kind and batch size, captured at creation
+ * and replayed for every batch (hit counts travel in device memory).
+ *
+ * Admission.  The number of slots is the largest that fits hbm_budget (at
+ * most max_slots).  An event submitted while nothing waits and a slot is
+ * free starts at once, alone.  Otherwise it waits in a FIFO of queue_cap
+ * (beyond it ht_server_submit returns HT_EBUSY: the event is shed).  When a
+ * slot frees, the oldest waiting event starts; if it has at most
+ * batch_max_hits hits, up to batch_max - 1 later waiting events of its kind
+ * with at most batch_max_hits hits join it, oldest first (continuous
+ * batching: batches form only while events wait).  With a work budget, the
+ * events in flight share the device by their work (hits times the
+ * q/pT x d0 columns of their kind): a batch starts only while the work in
+ * flight plus its own stays within work_budget, or when nothing else runs
+ * (an event too large for the budget runs alone).  Results are exactly
+ * those of hough_vote, hough_peaks, (ht_cnn_score, ht_cnn_keep,)
+ * assoc_cluster called one by one for the same event.  Single-threaded: one
  * thread calls submit and poll.  Host pointers throughout. */
 #define HT_SERVER_MAX_KINDS 4
 
@@ -461,6 +473,9 @@ typedef struct {
   ht_cluster_cfg cluster;  /* refinement and vertex settings */
   int32_t min_votes;       /* peak threshold */
   int32_t peak_cap;        /* peak-list capacity per event */
+  const float* cnn_params; /* NULL: no filter; else host float32 [HT_CNN_PARAMS] */
+  float cnn_threshold;     /* peaks with a logit >= this are kept */
+  int32_t reserved;        /* 0 */
 } ht_server_kind;
 
 typedef struct {
@@ -471,10 +486,15 @@ typedef struct {
   int32_t object_cap;      /* vertex objects copied back per event */
   int32_t member_cap;      /* object members copied back per event */
   int64_t hbm_budget;      /* device bytes the slots may use */
-  int32_t max_slots;       /* concurrent events at most, >= 1 */
+  int32_t max_slots;       /* concurrent batches at most, >= 1 */
   int32_t queue_cap;       /* events waiting for a slot at most, >= 0 */
-  int32_t use_graphs;      /* 1: replay a captured HIP graph per slot and kind */
+  int32_t use_graphs;      /* 1: replay a captured HIP graph per slot, kind and batch size */
+  int32_t reserved;        /* 0 */
   int64_t work_budget;     /* hit-columns in flight at most, 0: no limit */
+  int32_t batch_max;       /* events per batch at most, 0 or 1 (no batching) .. HT_MAX_BATCH */
+  int32_t batch_max_hits;  /* hits of an event that may share a batch at most, 1 .. max_hits
+                              (ignored without batching); the slot's further event places are
+                              sized for this many hits */
 } ht_server_cfg;
 
 /* Where the results of one event go (host memory, any pointer may be NULL;
@@ -496,7 +516,9 @@ typedef struct {
   int32_t n_peaks;         /* full peak count */
   int32_t counts[8];       /* as assoc_cluster's counts */
   double t_submit, t_start, t_done; /* host steady clock [s]: submitted, on a slot, seen done */
-  double device_ms;        /* device time of the event on its slot (HIP events) */
+  double device_ms;        /* device time of the event's batch on its slot (HIP events) */
+  int32_t n_kept;          /* peaks handed to assoc_cluster (n_peaks without a filter) */
+  int32_t batch;           /* events in the event's batch */
 } ht_server_result;
 
 typedef struct ht_server ht_server;
@@ -515,7 +537,8 @@ int ht_server_info(const ht_server* server, int32_t* n_slots, int64_t* slot_byte
 int ht_server_submit(ht_server* server, int32_t kind, const float* r, const float* phi,
                      const uint8_t* layer, int32_t n_hits, const ht_server_out* out,
                      uint64_t tag);
-/* Collects up to max finished events into results (in completion order),
+/* Collects finished events into results (in completion order, whole
+ * batches: max must be 0 or at least the batch size, else HT_EINVAL),
  * copies their outputs to the places given at submit, starts waiting events
  * on the freed slots.  wait != 0 blocks until at least one event is done or
  * none is pending. */

@@ -80,14 +80,17 @@ HT_EBUSY = -5
 
 class ServerKind(C.Structure):
     _fields_ = [("grid", Grid), ("cluster", ClusterCfg), ("min_votes", C.c_int32),
-                ("peak_cap", C.c_int32)]
+                ("peak_cap", C.c_int32), ("cnn_params", C.c_void_p), ("cnn_threshold", C.c_float),
+                ("reserved", C.c_int32)]
 
 
 class ServerCfg(C.Structure):
     _fields_ = [("n_kinds", C.c_int32), ("kinds", ServerKind * SERVER_MAX_KINDS),
                 ("max_hits", C.c_int32), ("track_cap", C.c_int32), ("object_cap", C.c_int32),
                 ("member_cap", C.c_int32), ("hbm_budget", C.c_int64), ("max_slots", C.c_int32),
-                ("queue_cap", C.c_int32), ("use_graphs", C.c_int32), ("work_budget", C.c_int64)]
+                ("queue_cap", C.c_int32), ("use_graphs", C.c_int32), ("reserved", C.c_int32),
+                ("work_budget", C.c_int64), ("batch_max", C.c_int32),
+                ("batch_max_hits", C.c_int32)]
 
 
 class ServerOut(C.Structure):
@@ -100,7 +103,7 @@ class ServerResult(C.Structure):
     _fields_ = [("tag", C.c_uint64), ("kind", C.c_int32), ("n_hits", C.c_int32),
                 ("status", C.c_int32), ("n_peaks", C.c_int32), ("counts", C.c_int32 * 8),
                 ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
-                ("device_ms", C.c_double)]
+                ("device_ms", C.c_double), ("n_kept", C.c_int32), ("batch", C.c_int32)]
 
 
 _lib = None
@@ -627,29 +630,41 @@ class Server:
     """The trigger serving loop (ht_server_*): events of several grid kinds,
     submitted one by one from host arrays, processed on device-resident
     slots; results come back through poll().  kinds: list of dicts with
-    grid, cluster, min_votes, peak_cap."""
+    grid, cluster, min_votes, peak_cap, and optionally the learned filter:
+    cnn_params (host float32 [CNN_PARAMS]) and cnn_threshold.  batch_max > 1
+    lets up to that many waiting events of one kind with at most
+    batch_max_hits hits share a batch."""
 
     def __init__(self, kinds, max_hits=65535, track_cap=4096, object_cap=256, member_cap=4096,
                  hbm_budget=64 << 30, max_slots=4, queue_cap=256, use_graphs=True,
-                 work_budget=0):
+                 work_budget=0, batch_max=0, batch_max_hits=0):
         if not 1 <= len(kinds) <= SERVER_MAX_KINDS:
             raise ValueError("1..4 kinds")
         _torch()  # a GPU must be there
         cfg = ServerCfg()
         cfg.n_kinds = len(kinds)
+        params = []  # held until the server has copied them
         for i, k in enumerate(kinds):
             cfg.kinds[i].grid = grid_struct(k["grid"])
             cfg.kinds[i].cluster = cluster_struct(k["cluster"])
             cfg.kinds[i].min_votes = int(k["min_votes"])
             cfg.kinds[i].peak_cap = int(k["peak_cap"])
+            if k.get("cnn_params") is not None:
+                w = np.ascontiguousarray(k["cnn_params"], np.float32).reshape(-1)
+                _need(w.size == CNN_PARAMS, f"cnn_params needs {CNN_PARAMS} floats")
+                params.append(w)
+                cfg.kinds[i].cnn_params = w.ctypes.data
+                cfg.kinds[i].cnn_threshold = float(k["cnn_threshold"])
         cfg.max_hits, cfg.track_cap = int(max_hits), int(track_cap)
         cfg.object_cap, cfg.member_cap = int(object_cap), int(member_cap)
         cfg.hbm_budget, cfg.max_slots = int(hbm_budget), int(max_slots)
         cfg.queue_cap, cfg.use_graphs = int(queue_cap), int(bool(use_graphs))
         cfg.work_budget = int(work_budget)
+        cfg.batch_max, cfg.batch_max_hits = int(batch_max), int(batch_max_hits)
         self.cfg = cfg
         h = C.c_void_p()
         _check(lib().ht_server_create(C.byref(cfg), C.byref(h)), "ht_server_create")
+        del params
         self._h = h
         self._keep = {}
         n, b = C.c_int32(), C.c_int64()
@@ -697,7 +712,7 @@ class Server:
             d = dict(tag=int(x.tag), kind=int(x.kind), n_hits=int(x.n_hits), status=int(x.status),
                      n_peaks=int(x.n_peaks), counts=np.array(x.counts[:], np.int32),
                      t_submit=x.t_submit, t_start=x.t_start, t_done=x.t_done,
-                     device_ms=x.device_ms)
+                     device_ms=x.device_ms, n_kept=int(x.n_kept), batch=int(x.batch))
             if bufs is not None:
                 c = d["counts"]
                 d["tracks"] = bufs["tracks"][:min(c[1], self.cfg.track_cap)].copy()

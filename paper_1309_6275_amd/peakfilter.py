@@ -77,40 +77,95 @@ class Pipeline:
 
 def truth_labels(ev, grid, min_layers, lins, dphi=2, dq=1, dd=1):
     """1 for the peak cells within (dphi, dq, dd) bins of the true cell of a
-    generated track in acceptance, else 0."""
+    generated track in acceptance (phi0 periodic, the others clipped to the
+    grid), else 0.  The cells near the truth are listed once per track and
+    offset, then looked up: linear in tracks plus peaks."""
     nphi, nq, nd = grid["n_phi"], grid["n_qpt"], grid["n_d0"]
     lins = np.asarray(lins, np.int64)
-    i, col = lins % nphi, lins // nphi
-    j, k = col % nq, col // nq
     acc = M.in_acceptance(ev, grid, min_layers)
+    t = np.flatnonzero(acc)
     qw = (grid["qpt_hi"] - grid["qpt_lo"]) / nq
-    it = np.floor((np.asarray(ev.trk_phi0) + np.pi) * nphi / (2 * np.pi)).astype(np.int64) % nphi
-    jt = np.clip(np.floor((ev.trk_qpt - grid["qpt_lo"]) / qw).astype(np.int64), 0, nq - 1)
+    it = np.floor((np.asarray(ev.trk_phi0)[t] + np.pi) * nphi / (2 * np.pi)).astype(np.int64) % nphi
+    jt = np.clip(np.floor((np.asarray(ev.trk_qpt)[t] - grid["qpt_lo"]) / qw).astype(np.int64),
+                 0, nq - 1)
     if nd > 1:
         dw = (grid["d0_hi"] - grid["d0_lo"]) / nd
-        kt = np.clip(np.floor((ev.trk_d0 - grid["d0_lo"]) / dw).astype(np.int64), 0, nd - 1)
+        kt = np.clip(np.floor((np.asarray(ev.trk_d0)[t] - grid["d0_lo"]) / dw).astype(np.int64),
+                     0, nd - 1)
     else:
-        kt = np.zeros(len(jt), np.int64)
-    y = np.zeros(lins.size, np.float32)
-    for t in np.flatnonzero(acc):
-        di = np.abs(((i - it[t]) + nphi // 2) % nphi - nphi // 2)
-        y[(di <= dphi) & (np.abs(j - jt[t]) <= dq) & (np.abs(k - kt[t]) <= dd)] = 1.0
-    return y
+        kt = np.zeros(t.size, np.int64)
+    di, dj, dk = np.meshgrid(np.arange(-dphi, dphi + 1), np.arange(-dq, dq + 1),
+                             np.arange(-dd, dd + 1), indexing="ij")
+    ii = (it[:, None] + di.reshape(-1)[None, :]) % nphi
+    jj = jt[:, None] + dj.reshape(-1)[None, :]
+    kk = kt[:, None] + dk.reshape(-1)[None, :]
+    ok = (jj >= 0) & (jj < nq) & (kk >= 0) & (kk < nd)
+    near = np.unique(((kk * nq + jj) * nphi + ii)[ok])
+    return np.isin(lins, near).astype(np.float32)
 
 
-def label_event(pl, ev, cl):
-    """Windows (host bf16 bits as int16) and truth labels of all peaks of one
-    event."""
-    t = pl.torch
-    d = pl.upload(ev)
-    pl.peaks_of(d)
-    t.cuda.synchronize()
-    n = min(int(pl.nf.item()), pl.cap)
-    lins = pl.peaks[:n, 0].cpu().numpy()
-    y = truth_labels(ev, pl.W["grid"], cl["min_layers"], lins)
-    pl.H.cnn_windows(pl.plan, pl.acc, pl.peaks, pl.nf, pl.win)
-    t.cuda.synchronize()
-    return pl.win[:n].view(t.int16).cpu().numpy(), y
+def training_set(pl, events, cl, rng, neg_per_event):
+    """Windows (device bfloat16) and truth labels of every positive peak and
+    up to neg_per_event random negative peaks of each event."""
+    t, H = pl.torch, pl.H
+    xs, ys = [], []
+    for ev in events:
+        d = pl.upload(ev)
+        pl.peaks_of(d)
+        H.cnn_windows(pl.plan, pl.acc, pl.peaks, pl.nf, pl.win)
+        t.cuda.synchronize()
+        n = min(int(pl.nf.item()), pl.cap)
+        y = truth_labels(ev, pl.W["grid"], cl["min_layers"], pl.peaks[:n, 0].cpu().numpy())
+        pos = np.flatnonzero(y > 0.5)
+        neg = np.flatnonzero(y < 0.5)
+        neg = rng.choice(neg, min(neg_per_event, neg.size), replace=False)
+        sel = np.concatenate([pos, neg])
+        xs.append(pl.win[t.from_numpy(sel).cuda()].clone())
+        ys.append(y[sel])
+    return t.cat(xs), np.concatenate(ys).astype(np.float32)
+
+
+def train(pl, X, Y, rng, epochs=6, batch=4096, lr=0.05, seed=7):
+    """SGD with momentum on the device, positives weighted by the
+    negative/positive ratio.  Returns the device parameters and the mean
+    loss of each epoch."""
+    t, H = pl.torch, pl.H
+    n_pos = int(Y.sum())
+    pos_weight = (Y.size - n_pos) / max(n_pos, 1)
+    params = t.from_numpy(init_params(seed)).cuda()
+    mom = t.zeros_like(params)
+    loss = t.zeros(1, dtype=t.float32, device="cuda")
+    Yd = t.from_numpy(Y).cuda()
+    ws = H.cnn_workspace(batch, training=True)
+    losses = []
+    for ep in range(epochs):
+        perm = t.from_numpy(rng.permutation(Y.size)).cuda()
+        ep_loss = []
+        for b in range(0, Y.size - batch + 1, batch):
+            idx = perm[b:b + batch]
+            H.cnn_train_step(params, mom, X[idx].contiguous(), Yd[idx].contiguous(), lr, 0.9,
+                             pos_weight, loss, ws)
+            ep_loss.append(loss.clone())
+        t.cuda.synchronize()
+        losses.append(float(t.cat(ep_loss).mean().item()) if ep_loss else float("nan"))
+    return params, losses, pos_weight
+
+
+def threshold(pl, params, events, cl, keep):
+    """The logit threshold that keeps the fraction keep of the truth-positive
+    peaks of the events (scored with ht_cnn_score)."""
+    t, H = pl.torch, pl.H
+    pos_logits = []
+    for ev in events:
+        d = pl.upload(ev)
+        pl.peaks_of(d)
+        H.cnn_score(pl.plan, params, pl.acc, pl.peaks, pl.nf, pl.logits, pl.ws)
+        t.cuda.synchronize()
+        n = min(int(pl.nf.item()), pl.cap)
+        y = truth_labels(ev, pl.W["grid"], cl["min_layers"], pl.peaks[:n, 0].cpu().numpy())
+        pos_logits.append(pl.logits[:n].cpu().numpy()[y > 0.5])
+    pos_logits = np.concatenate(pos_logits)
+    return float(np.quantile(pos_logits, 1.0 - keep)) if pos_logits.size else 0.0
 
 
 def main(argv=None):
@@ -132,58 +187,17 @@ def main(argv=None):
     pl = Pipeline(torch, H, W)
     rng = np.random.default_rng(5_000_000)
 
-    # training set
     t0 = time.perf_counter()
-    xs, ys = [], []
-    for e in range(args.train_events):
-        win, y = label_event(pl, G.make_event(2, 5_000_000 + e), cl)
-        pos = np.flatnonzero(y > 0.5)
-        neg = np.flatnonzero(y < 0.5)
-        neg = rng.choice(neg, min(args.neg_per_event, neg.size), replace=False)
-        sel = np.concatenate([pos, neg])
-        xs.append(win[sel])
-        ys.append(y[sel])
-    X = np.concatenate(xs)
-    Y = np.concatenate(ys)
+    X, Y = training_set(pl, (G.make_event(2, 5_000_000 + e) for e in range(args.train_events)),
+                        cl, rng, args.neg_per_event)
     n_pos = int(Y.sum())
     t_data = time.perf_counter() - t0
-    pos_weight = (Y.size - n_pos) / max(n_pos, 1)
-
-    # training on the device
-    params = torch.from_numpy(init_params(7)).cuda()
-    mom = torch.zeros_like(params)
-    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-    Xd = torch.from_numpy(X).cuda().view(torch.bfloat16)
-    Yd = torch.from_numpy(Y).cuda()
-    ws = H.cnn_workspace(args.batch, training=True)
-    losses = []
     t0 = time.perf_counter()
-    steps = 0
-    for ep in range(args.epochs):
-        perm = torch.from_numpy(rng.permutation(Y.size)).cuda()
-        ep_loss = []
-        for b in range(0, Y.size - args.batch + 1, args.batch):
-            idx = perm[b:b + args.batch]
-            H.cnn_train_step(params, mom, Xd[idx].contiguous(), Yd[idx].contiguous(), args.lr, 0.9,
-                             pos_weight, loss, ws)
-            ep_loss.append(loss.clone())
-            steps += 1
-        torch.cuda.synchronize()
-        losses.append(float(torch.cat(ep_loss).mean().item()))
+    params, losses, pos_weight = train(pl, X, Y, rng, args.epochs, args.batch, args.lr)
     t_train = time.perf_counter() - t0
-
-    # threshold on validation events: keep the requested fraction of positives
-    pos_logits = []
-    for e in range(args.val_events):
-        ev = G.make_event(2, 5_500_000 + e)
-        win, y = label_event(pl, ev, cl)
-        n = y.size
-        ws_i = pl.ws
-        H.cnn_forward(params, pl.win[:n].contiguous(), pl.logits[:n], ws_i)
-        torch.cuda.synchronize()
-        pos_logits.append(pl.logits[:n].cpu().numpy()[y > 0.5])
-    pos_logits = np.concatenate(pos_logits)
-    thr = float(np.quantile(pos_logits, 1.0 - args.keep)) if pos_logits.size else 0.0
+    steps = args.epochs * (Y.size // args.batch)
+    thr = threshold(pl, params, (G.make_event(2, 5_500_000 + e) for e in range(args.val_events)),
+                    cl, args.keep)
 
     # evaluation: the same events with all peaks and with the kept peaks
     rows = []

@@ -51,10 +51,10 @@ def test_struct_sizes_match_header_layout():
     assert H.TRACK_DTYPE.itemsize == 13 * 4 + 16 * 4
     assert H.OBJECT_DTYPE.itemsize == 8 * 4
     # serving loop structs (static_asserts on the C side hold the same sizes)
-    assert ctypes.sizeof(H.ServerKind) == 112
-    assert ctypes.sizeof(H.ServerCfg) == 504
+    assert ctypes.sizeof(H.ServerKind) == 128
+    assert ctypes.sizeof(H.ServerCfg) == 576
     assert ctypes.sizeof(H.ServerOut) == 56
-    assert ctypes.sizeof(H.ServerResult) == 88
+    assert ctypes.sizeof(H.ServerResult) == 96
 
 
 def test_strerror_without_gpu(libpath):
@@ -80,3 +80,43 @@ def test_bench_refuses_more_than_one_gpu():
                          capture_output=True, text=True, timeout=120)
     assert res.returncode == 2
     assert "one GPU" in res.stderr and res.stdout == ""
+
+
+def test_server_rejects_bad_configuration_before_the_device(libpath):
+    """ht_server_create checks its configuration before any device call:
+    each broken field alone gives HT_EINVAL, here without a GPU."""
+    from paper_1309_6275_amd import configs as CF
+    from paper_1309_6275_amd import houghtrig as H
+    lib = ctypes.CDLL(libpath)
+    lib.ht_server_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.ht_server_create.restype = ctypes.c_int
+    params = (ctypes.c_float * H.CNN_PARAMS)()
+
+    def base():
+        c = H.ServerCfg()
+        c.n_kinds = 1
+        k = c.kinds[0]
+        k.grid = H.grid_struct(CF.WORKLOADS[1]["grid"])
+        k.cluster = H.cluster_struct(CF.WORKLOADS[1]["cluster"])
+        k.min_votes, k.peak_cap = 7, 1024
+        k.cnn_params = ctypes.cast(params, ctypes.c_void_p)
+        k.cnn_threshold = 0.5
+        c.max_hits, c.track_cap, c.object_cap, c.member_cap = 4096, 64, 8, 64
+        c.hbm_budget, c.max_slots, c.queue_cap = 1 << 30, 1, 4
+        c.batch_max, c.batch_max_hits = 4, 1000
+        return c
+
+    breaks = [("batch_max", 5), ("batch_max", -1), ("batch_max_hits", 0),
+              ("batch_max_hits", 4097), ("reserved", 1), ("max_hits", 65536),
+              ("work_budget", -1), ("n_kinds", 0)]
+    for field, value in breaks:
+        c = base()
+        setattr(c, field, value)
+        h = ctypes.c_void_p()
+        assert lib.ht_server_create(ctypes.byref(c), ctypes.byref(h)) == H.HT_EINVAL, field
+        assert not h.value
+    for field, value in [("reserved", 2), ("cnn_threshold", float("nan")), ("peak_cap", 0)]:
+        c = base()
+        setattr(c.kinds[0], field, value)
+        h = ctypes.c_void_p()
+        assert lib.ht_server_create(ctypes.byref(c), ctypes.byref(h)) == H.HT_EINVAL, field
