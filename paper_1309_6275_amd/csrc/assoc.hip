@@ -901,6 +901,9 @@ refine_kernel(AssocBatch<NB> AB) {
   // short member lists of caps up to 128 keep one member at a time, which
   // leaves the registers for a fifth wave per SIMD
   constexpr int kChunk = CAP <= 128 ? 1 : 8;
+  // passing members per lane and layer whose float64 distances wait for the
+  // end of the layer (chunked path)
+  constexpr int kDefer = 4;
   __shared__ WaveMem<CAP> MW[W];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x >> 6;
@@ -1200,26 +1203,61 @@ refine_kernel(AssocBatch<NB> AB) {
           if (!(dist <= road)) continue;
           if (bh < 0 || dist < bd || (dist == bd && hh < bh)) { bh = hh; bd = dist; }
         }
-      } else for (int e0 = st; e0 < en; e0 += kChunk) {
-        Mem4 v[kChunk];
+      } else {
+        // The float64 distances of the members that pass are deferred to the
+        // end of the layer, where the loads of their float64 coordinates
+        // (L2 gathers) are issued together: one round trip per layer instead
+        // of one per chunk with a pass.  A lane with more than kDefer passes
+        // in the layer takes the others at once.
+        int q[kDefer];
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) v[u] = M.mem[min(e0 + u, en - 1)];
-        unsigned pass = 0;
+        for (int t = 0; t < kDefer; ++t) q[t] = -1;
+        int nq = 0;
+        for (int e0 = st; e0 < en; e0 += kChunk) {
+          Mem4 v[kChunk];
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-          const float f32 =
-              __builtin_fmaf(Af, v[u].q, __builtin_fmaf(Bf, v[u].x, __builtin_fmaf(Cf, v[u].y, Df)));
-          pass |= (fabsf(f32) <= thr ? 1u : 0u) << u;
+          for (int u = 0; u < kChunk; ++u) v[u] = M.mem[min(e0 + u, en - 1)];
+          unsigned pass = 0;
+#pragma unroll
+          for (int u = 0; u < kChunk; ++u) {
+            const float f32 = __builtin_fmaf(Af, v[u].q,
+                                             __builtin_fmaf(Bf, v[u].x, __builtin_fmaf(Cf, v[u].y, Df)));
+            pass |= (fabsf(f32) <= thr ? 1u : 0u) << u;
+          }
+          const int left = en - e0;
+          if (!active) pass = 0;
+          if (left < kChunk) pass &= (1u << left) - 1u;
+          while (pass) {
+            const int u = __builtin_ctz(pass);
+            pass &= pass - 1u;
+            const int hh = M.mem[e0 + u].h;
+            ++exec;
+            if (nq < kDefer) {
+#pragma unroll
+              for (int t = 0; t < kDefer; ++t) q[t] = nq == t ? hh : q[t];
+              ++nq;
+              continue;
+            }
+            const double dist = fabs(circle_dist(cA, cB, cC, cD, A.hx[hh], A.hy[hh], A.hq[hh]));
+            if (!(dist <= road)) continue;
+            if (bh < 0 || dist < bd || (dist == bd && hh < bh)) { bh = hh; bd = dist; }
+          }
         }
-        const int left = en - e0;
-        if (!active) pass = 0;
-        if (left < kChunk) pass &= (1u << left) - 1u;
-        while (pass) {
-          const int u = __builtin_ctz(pass);
-          pass &= pass - 1u;
-          const int hh = M.mem[e0 + u].h;
-          ++exec;
-          const double dist = fabs(circle_dist(cA, cB, cC, cD, A.hx[hh], A.hy[hh], A.hq[hh]));
+        double qx[kDefer], qy[kDefer], qq[kDefer];
+#pragma unroll
+        for (int t = 0; t < kDefer; ++t) {
+          qx[t] = qy[t] = qq[t] = 0.0;
+          if (q[t] >= 0) {
+            qx[t] = A.hx[q[t]];
+            qy[t] = A.hy[q[t]];
+            qq[t] = A.hq[q[t]];
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < kDefer; ++t) {
+          if (q[t] < 0) continue;
+          const int hh = q[t];
+          const double dist = fabs(circle_dist(cA, cB, cC, cD, qx[t], qy[t], qq[t]));
           if (!(dist <= road)) continue;
           if (bh < 0 || dist < bd || (dist == bd && hh < bh)) { bh = hh; bd = dist; }
         }
