@@ -780,17 +780,178 @@ struct RawMembers {  // members in pool order, before grouping
   int8_t L[CAP];
 };
 
+// Angle bins of a layer's members (caps above 128).  Within each layer the
+// members are grouped by kNB bins of their azimuth (relative to the cell's
+// phi0 centre), between the smallest and largest azimuth of the layer.  When
+// every member of a layer has the same radius r, a seed circle's points at r
+// within the road lie on two arcs that follow from the circle's equation, and
+// a lane tests only the members of the bins those arcs reach.
+constexpr int kNB = 32;
+constexpr int kBinKeys = HT_MAX_LAYERS * kNB;
+constexpr float kPiF = 3.14159265358979f;
+constexpr float k2PiF = 6.28318530717959f;
+// padding of every computed angle (radians): far above the float32 rounding
+// of the azimuths, of the circle's direction and of the arc half-widths
+constexpr float kAngPad = 1e-5f;
+
+template <bool ON>
+struct LayerBins {};
+template <>
+struct LayerBins<true> {
+  // group counts, then group starts (entry kBinKeys: the member count), as
+  // 16-bit entries two to a word (counts and starts are at most 1024)
+  uint32_t bpack[kBinKeys / 2 + 1];
+  __device__ __forceinline__ int start(int key) const {
+    return (int)((bpack[key >> 1] >> ((key & 1) * 16)) & 0xffffu);
+  }
+  float lr[HT_MAX_LAYERS];    // the layer's radius when all its members share it, else 0
+  float lmn[HT_MAX_LAYERS], lmx[HT_MAX_LAYERS];  // azimuth range of the layer's members
+  float linv[HT_MAX_LAYERS];  // bins per radian
+};
+
+// a layer's radius and azimuth ranges while the members are loaded
+struct LayerStats {
+  int32_t rlo[HT_MAX_LAYERS], rhi[HT_MAX_LAYERS];  // members' radius bits, smallest and largest
+  int32_t alo[HT_MAX_LAYERS], ahi[HT_MAX_LAYERS];  // members' azimuth (ordered bits)
+};
+
+// float bits in an order that int comparisons follow
+__device__ __forceinline__ int32_t ord_bits(float f) {
+  const int32_t b = __float_as_int(f);
+  return b >= 0 ? b : b ^ 0x7fffffff;
+}
+__device__ __forceinline__ float ord_float(int32_t b) {
+  return __int_as_float(b >= 0 ? b : b ^ 0x7fffffff);
+}
+
+// azimuth relative to ref, in [-pi, pi) (azimuths of valid hits lie in [-4, 4])
+__device__ __forceinline__ float rel_angle(float ph, float ref) {
+  float d = ph - ref;
+  if (d >= kPiF) d -= k2PiF;
+  if (d >= kPiF) d -= k2PiF;
+  if (d < -kPiF) d += k2PiF;
+  if (d < -kPiF) d += k2PiF;
+  return d;
+}
+
+// bin of a relative azimuth: monotone in rel, clamped to [0, kNB - 1]
+__device__ __forceinline__ int angle_bin(float rel, float mn, float inv) {
+  const float t = (rel - mn) * inv;
+  return t < 1.0f ? 0 : (t >= (float)(kNB - 1) ? kNB - 1 : (int)t);
+}
+
+// the bins holding every member whose relative azimuth lies in [a, b]
+__device__ __forceinline__ unsigned bin_span(float a, float b, float mn, float mx, float inv) {
+  if (!(b >= mn) || !(a <= mx) || !(a <= b)) return 0u;
+  const int ba = angle_bin(a, mn, inv), bb = angle_bin(b, mn, inv);
+  return ((2u << bb) - 1u) & ~((1u << ba) - 1u);
+}
+
+// Bins of a layer of radius r that can hold a member within the road of the
+// circle f = A q + B x + C y + D (float32 coefficients; R = |(B, C)|, phB the
+// direction of (B, C)): a point (r, phi) has f = A r^2 + D + r R cos(phi - phB),
+// so |f| <= thr needs cos(phi - phB) in [lo, hi], i.e. phi - phB within
+// [acos(hi), acos(lo)] of 0 on either side.  The cosine interval is widened
+// by far more than the float32 rounding of its terms, and the arcs by
+// kAngPad, so no member that the float64 road test keeps is left out.
+__device__ __forceinline__ unsigned road_bins(float r, float Af, float Df, float Rf, float phB,
+                                              float thr, float ref, float mn, float mx,
+                                              float inv) {
+  constexpr unsigned kAll = kNB == 32 ? ~0u : (1u << (kNB & 31)) - 1u;
+  const float r2 = r * r;
+  const float den = r * Rf;
+  if (!(den > 1e-30f) || !(thr < 1e30f)) return kAll;
+  const float base = Af * r2 + Df;
+  const float mag = fabsf(Af) * r2 + fabsf(Df) + thr;
+  const float epsc = 1e-5f * (mag / den) + 1e-6f;
+  const float hi = (thr - base) / den + epsc;
+  const float lo = (-thr - base) / den - epsc;
+  if (hi < -1.0f || lo > 1.0f) return 0u;  // no point of radius r comes within the road
+  if (!(hi == hi) || !(lo == lo)) return kAll;
+  const float a1 = hi >= 1.0f ? 0.0f : fmaxf(acosf(hi) - kAngPad, 0.0f);
+  const float a2 = lo <= -1.0f ? kPiF + kAngPad : acosf(lo) + kAngPad;
+  const float c = rel_angle(phB, ref);
+  unsigned m = 0u;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const float u = side ? c + a1 - kAngPad : c - a2 - kAngPad;
+    const float v = side ? c + a2 + kAngPad : c - a1 + kAngPad;
+    m |= bin_span(u, v, mn, mx, inv);
+    if (v > kPiF - kAngPad) m |= bin_span(u - k2PiF, v - k2PiF, mn, mx, inv);
+    if (u < -kPiF + kAngPad) m |= bin_span(u + k2PiF, v + k2PiF, mn, mx, inv);
+  }
+  return m;
+}
+
+// each lane's inlier hit per layer: a row in LDS (caps up to 128), or eight
+// registers of two 16-bit entries (larger caps, whose LDS limits residency)
+template <bool REG>
+struct InlierRow {
+  uint16_t* row;
+  __device__ __forceinline__ void init(uint16_t* r) {
+    row = r;
+    for (int L = 0; L < HT_MAX_LAYERS; ++L) row[L] = kNoHit;
+  }
+  __device__ __forceinline__ void set(int L, uint16_t v) { row[L] = v; }
+  __device__ __forceinline__ int get(int L) const { return row[L]; }
+};
+template <>
+struct InlierRow<true> {
+  uint32_t w[HT_MAX_LAYERS / 2];
+  __device__ __forceinline__ void init(uint16_t*) {
+#pragma unroll
+    for (int i = 0; i < HT_MAX_LAYERS / 2; ++i) w[i] = 0xffffffffu;
+  }
+  __device__ __forceinline__ void set(int L, uint16_t v) {
+    const int sh = (L & 1) * 16;
+#pragma unroll
+    for (int i = 0; i < HT_MAX_LAYERS / 2; ++i)
+      if (i == (L >> 1)) w[i] = (w[i] & ~(0xffffu << sh)) | ((uint32_t)v << sh);
+  }
+  __device__ __forceinline__ int get(int L) const {
+    uint32_t x = w[0];
+#pragma unroll
+    for (int i = 1; i < HT_MAX_LAYERS / 2; ++i)
+      if (i == (L >> 1)) x = w[i];
+    return (int)((x >> ((L & 1) * 16)) & 0xffffu);
+  }
+  // lane win's entry for layer L (called by every lane)
+  __device__ __forceinline__ int of_lane(int win, int L) const {
+    uint32_t x = 0;
+#pragma unroll
+    for (int i = 0; i < HT_MAX_LAYERS / 2; ++i) {
+      const uint32_t y = (uint32_t)__builtin_amdgcn_readlane((int)w[i], win);
+      if (i == ((L >> 1) & (HT_MAX_LAYERS / 2 - 1))) x = y;
+    }
+    return (int)((x >> ((L & 1) * 16)) & 0xffffu);
+  }
+};
+
+__device__ __forceinline__ int wave_incl_scan_i32(int v, int lane) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int o = __shfl_up(v, d, kWave);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
 template <int CAP>
 struct WaveMem {
-  Mem4 mem[CAP];   // grouped by layer
-  float adx[CAP];  // |x - cell centre| of the grouped members
+  Mem4 mem[CAP];   // grouped by layer (and by azimuth bin within a layer for caps above 128)
+  float adx[CAP];  // |x - cell centre| of the grouped members (above cap 128, before the
+                   // grouping: each member's relative azimuth in pool order)
   union {
     // members in pool order before grouping, staged in LDS for CAP <= 128;
     // larger caps stage them in registers (LDS, not registers, limits their
     // occupancy)
     RawMembers<(CAP <= 128 ? CAP : 1)> raw;
-    uint16_t hit[kWave][HT_MAX_LAYERS + 2];  // each lane's inlier per layer, kNoHit if none
+    LayerStats st;  // caps above 128, until the bins are set
+    // each lane's inlier per layer, kNoHit if none (caps up to 128; larger
+    // caps keep them in registers)
+    uint16_t hit[CAP <= 128 ? kWave : 1][HT_MAX_LAYERS + 2];
   } u;
+  LayerBins<(CAP > 128)> lb;
   int32_t lstart[HT_MAX_LAYERS + 1];
   int32_t lcnt[HT_MAX_LAYERS + 1];
   int32_t seed[3][4];
@@ -804,9 +965,10 @@ template <int CAP>
 struct RefineShape {
   static constexpr int kWaves = CAP <= 128 ? 4 : (CAP <= 256 ? 2 : 1);
   // workgroups per CU the register budget is set for: six waves per SIMD
-  // for caps up to 128 (the LDS of six workgroups fits), else left to the
-  // compiler (LDS allows no more)
-  static constexpr int kMinBlocks = CAP <= 128 ? 6 : 1;
+  // for caps up to 128 (the LDS of six workgroups fits); two one-wave
+  // workgroups per SIMD at cap 1024 (at most 256 registers, so that the six
+  // workgroups the LDS allows can all be resident); else left to the compiler
+  static constexpr int kMinBlocks = CAP <= 128 ? 6 : (CAP >= 1024 ? 8 : 1);
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -939,11 +1101,13 @@ refine_kernel(AssocBatch<NB> AB) {
     const int k = col / A.n_qpt;
     const double kapc = A.kapc[j], d0c = A.d0c[k];  // issued early, used by the box check
     const size_t moff = (size_t)p * cap;
+    // azimuth origin of the angle bins: the cell's phi0 centre
+    const float ref = -kPiF + ((float)(lin - col * A.n_phi) + 0.5f) * (k2PiF / (float)A.n_phi);
     constexpr bool kRawLds = CAP <= 128;
     constexpr int RM = kRawLds ? 1 : CAP / kWave;
     Mem4 rec[RM];
     float radx[RM];
-    int rL[RM], rslot[RM];
+    int rL[RM];
     unsigned lmask = 0;
     float qmax = 0.0f;
     if constexpr (kRawLds) {
@@ -965,6 +1129,17 @@ refine_kernel(AssocBatch<NB> AB) {
         qmax = fmaxf(qmax, hb.z);
       }
     } else {
+      // the layers' radius and azimuth ranges start empty; the group counts at 0
+      if constexpr (!kRawLds) {
+        if (lane < HT_MAX_LAYERS) {
+          M.u.st.rlo[lane] = 0x7fffffff;
+          M.u.st.rhi[lane] = 0;
+          M.u.st.alo[lane] = 0x7fffffff;
+          M.u.st.ahi[lane] = (int32_t)0x80000000;
+        }
+        for (int e = lane; e <= kBinKeys / 2; e += kWave) M.lb.bpack[e] = 0u;
+      }
+      wave_sync();
       // load members in pool order into registers: member lane + 64 t is
       // entry t of the lane (n <= cap <= CAP)
 #pragma unroll
@@ -986,6 +1161,21 @@ refine_kernel(AssocBatch<NB> AB) {
           qmax = fmaxf(qmax, hb.z);
         }
       }
+      // each member's radius and azimuth (the hit's inputs) widen its
+      // layer's ranges (a loop of its own: the loads of these two inputs
+      // need not be in flight with the member records)
+#pragma unroll
+      for (int t = 0; t < RM; ++t) {
+        if (rL[t] < 0) continue;
+        const int h = rec[t].h, L = rL[t];
+        const float hr = A.r[h];
+        const float rel = rel_angle(A.phi[h], ref);
+        M.adx[lane + t * kWave] = rel;
+        atomicMin(&M.u.st.rlo[L], __float_as_int(hr));
+        atomicMax(&M.u.st.rhi[L], __float_as_int(hr));
+        atomicMin(&M.u.st.alo[L], ord_bits(rel));
+        atomicMax(&M.u.st.ahi[L], ord_bits(rel));
+      }
     }
     lmask = wave_or(lmask);
     qmax = wave_max_nonneg(qmax);
@@ -996,41 +1186,84 @@ refine_kernel(AssocBatch<NB> AB) {
       wave_sync();
       continue;
     }
-    // group members by layer: counting sort with LDS atomics (order within a
-    // layer does not matter, every selection breaks ties on the hit index)
-    if (lane <= HT_MAX_LAYERS) M.lcnt[lane] = 0;
-    wave_sync();
+    // group members by layer (and, above cap 128, by azimuth bin within the
+    // layer): counting sort with LDS atomics (order within a group does not
+    // matter, every selection breaks ties on the hit index)
+    int ls;  // lane L < 16: start of layer L; lane 16: the member count
     if constexpr (kRawLds) {
+      if (lane <= HT_MAX_LAYERS) M.lcnt[lane] = 0;
+      wave_sync();
       for (int m = lane; m < n; m += kWave)
         M.u.raw.slot[m] = (int16_t)atomicAdd(&M.lcnt[M.u.raw.L[m]], 1);
-    } else {
-#pragma unroll
-      for (int t = 0; t < RM; ++t)
-        if (rL[t] >= 0) rslot[t] = atomicAdd(&M.lcnt[rL[t]], 1);
-    }
-    wave_sync();
-    // layer starts: exclusive scan of the 16 layer counts in the first row
-    // of lanes; lane 16 holds the total
-    int ls;
-    {
-      const int c = lane < HT_MAX_LAYERS ? M.lcnt[lane] : 0;
-      const int incl = row_scan_incl(c);
-      const int total = __builtin_amdgcn_readlane(incl, HT_MAX_LAYERS - 1);
-      ls = lane < HT_MAX_LAYERS ? incl - c : total;
-      if (lane <= HT_MAX_LAYERS) M.lstart[lane] = ls;
-    }
-    wave_sync();
-    if constexpr (kRawLds) {
+      wave_sync();
+      // layer starts: exclusive scan of the 16 layer counts in the first row
+      // of lanes; lane 16 holds the total
+      {
+        const int c = lane < HT_MAX_LAYERS ? M.lcnt[lane] : 0;
+        const int incl = row_scan_incl(c);
+        const int total = __builtin_amdgcn_readlane(incl, HT_MAX_LAYERS - 1);
+        ls = lane < HT_MAX_LAYERS ? incl - c : total;
+        if (lane <= HT_MAX_LAYERS) M.lstart[lane] = ls;
+      }
+      wave_sync();
       for (int m = lane; m < n; m += kWave) {
         const int e = M.lstart[M.u.raw.L[m]] + M.u.raw.slot[m];
         M.mem[e] = M.u.raw.mem[m];
         M.adx[e] = M.u.raw.adx[m];
       }
     } else {
+      wave_sync();
+      // the layers' bin parameters
+      if (lane < HT_MAX_LAYERS) {
+        const float mn = ord_float(M.u.st.alo[lane]), mx = ord_float(M.u.st.ahi[lane]);
+        M.lb.lr[lane] = M.u.st.rlo[lane] == M.u.st.rhi[lane] ? __int_as_float(M.u.st.rlo[lane]) : 0.0f;
+        M.lb.lmn[lane] = mn;
+        M.lb.lmx[lane] = mx;
+        const float span = mx - mn;
+        M.lb.linv[lane] = span > 1e-30f ? (float)kNB / span : 0.0f;
+      }
+      wave_sync();
 #pragma unroll
       for (int t = 0; t < RM; ++t) {
         if (rL[t] < 0) continue;
-        const int e = M.lstart[rL[t]] + rslot[t];
+        const int L = rL[t];
+        const int key = L * kNB + angle_bin(M.adx[lane + t * kWave], M.lb.lmn[L], M.lb.linv[L]);
+        // group and slot in one register (key < 512, slot < 1024)
+        const int sh = (key & 1) * 16;
+        const uint32_t old = atomicAdd(&M.lb.bpack[key >> 1], 1u << sh);
+        rL[t] = key | ((int)((old >> sh) & 0xffffu) << 10);
+      }
+      wave_sync();
+      // group starts: exclusive scan of the kBinKeys counts, lane l owning
+      // groups G l .. G l + G - 1
+      {
+        constexpr int G = kBinKeys / kWave;  // groups per lane, G / 2 words
+        static_assert(kBinKeys == G * kWave && G % 2 == 0, "whole words per lane");
+        uint32_t c[G / 2];
+        int sum = 0;
+#pragma unroll
+        for (int i = 0; i < G / 2; ++i) {
+          c[i] = M.lb.bpack[(G / 2) * lane + i];
+          sum += (int)(c[i] & 0xffffu) + (int)(c[i] >> 16);
+        }
+        const int incl = wave_incl_scan_i32(sum, lane);
+        int run = incl - sum;
+#pragma unroll
+        for (int i = 0; i < G / 2; ++i) {
+          const int lo = run;
+          run += (int)(c[i] & 0xffffu);
+          M.lb.bpack[(G / 2) * lane + i] = (uint32_t)lo | ((uint32_t)run << 16);
+          run += (int)(c[i] >> 16);
+        }
+        if (lane == kWave - 1) M.lb.bpack[kBinKeys / 2] = (uint32_t)incl;
+      }
+      wave_sync();
+      ls = M.lb.start(lane < HT_MAX_LAYERS ? lane * kNB : kBinKeys);
+      if (lane <= HT_MAX_LAYERS) M.lstart[lane] = ls;
+#pragma unroll
+      for (int t = 0; t < RM; ++t) {
+        if (rL[t] < 0) continue;
+        const int e = M.lb.start(rL[t] & 0x3ff) + (rL[t] >> 10);
         M.mem[e] = rec[t];
         M.adx[e] = radx[t];
       }
@@ -1097,9 +1330,9 @@ refine_kernel(AssocBatch<NB> AB) {
       }
     }
     // the grouped raw records are dead from here on; the union holds the
-    // per-lane inlier rows
-    uint16_t* hitL = M.u.hit[lane];
-    for (int L = 0; L < HT_MAX_LAYERS; ++L) hitL[L] = kNoHit;
+    // per-lane inlier rows (caps up to 128)
+    InlierRow<(kChunk > 1)> hitL;
+    hitL.init(M.u.hit[kChunk > 1 ? 0 : lane]);
     wave_sync();
     if (A.origin_seed) ns[0] = 1;
     // one combination per lane: lane = 16 a + 4 b + c (seed_k <= 4), which
@@ -1132,6 +1365,7 @@ refine_kernel(AssocBatch<NB> AB) {
     // can move f (< 5e-7 of that bound), so it never drops a member the
     // float64 test keeps.
     float Af = 0.0f, Bf = 0.0f, Cf = 0.0f, Df = 0.0f, thr = -1.0f;
+    float Rf = 0.0f, phB = 0.0f;  // |(B, C)| and its direction (angle bins)
     if (ok) {
       const double ra = road * fabs(cA);
       const float pre = ra <= 0.5 ? (float)(road * (1.0 + 2.0 * ra) * 1.000001) : __builtin_inff();
@@ -1141,6 +1375,10 @@ refine_kernel(AssocBatch<NB> AB) {
       Df = (float)cD;
       const float mag = fabsf(Af) * qmax + (fabsf(Bf) + fabsf(Cf)) * rmax + fabsf(Df);
       thr = pre + mag * 1e-6f;
+      if constexpr (kChunk > 1) {
+        Rf = __builtin_sqrtf(Bf * Bf + Cf * Cf);
+        phB = atan2f(Cf, Bf);
+      }
     }
     // road tests the method defines for this candidate: every member
     // against every admissible seed circle
@@ -1213,34 +1451,74 @@ refine_kernel(AssocBatch<NB> AB) {
 #pragma unroll
         for (int t = 0; t < kDefer; ++t) q[t] = -1;
         int nq = 0;
-        for (int e0 = st; e0 < en; e0 += kChunk) {
-          Mem4 v[kChunk];
+        auto take = [&](int hh) {
+          ++exec;
+          if (nq < kDefer) {
 #pragma unroll
-          for (int u = 0; u < kChunk; ++u) v[u] = M.mem[min(e0 + u, en - 1)];
-          unsigned pass = 0;
-#pragma unroll
-          for (int u = 0; u < kChunk; ++u) {
-            const float f32 = __builtin_fmaf(Af, v[u].q,
-                                             __builtin_fmaf(Bf, v[u].x, __builtin_fmaf(Cf, v[u].y, Df)));
-            pass |= (fabsf(f32) <= thr ? 1u : 0u) << u;
+            for (int t = 0; t < kDefer; ++t) q[t] = nq == t ? hh : q[t];
+            ++nq;
+            return;
           }
-          const int left = en - e0;
-          if (!active) pass = 0;
-          if (left < kChunk) pass &= (1u << left) - 1u;
-          while (pass) {
-            const int u = __builtin_ctz(pass);
-            pass &= pass - 1u;
-            const int hh = M.mem[e0 + u].h;
-            ++exec;
-            if (nq < kDefer) {
-#pragma unroll
-              for (int t = 0; t < kDefer; ++t) q[t] = nq == t ? hh : q[t];
-              ++nq;
-              continue;
+          const double dist = fabs(circle_dist(cA, cB, cC, cD, A.hx[hh], A.hy[hh], A.hq[hh]));
+          if (!(dist <= road)) return;
+          if (bh < 0 || dist < bd || (dist == bd && hh < bh)) { bh = hh; bd = dist; }
+        };
+        const float lr = M.lb.lr[L];
+        if (lr > 0.0f) {
+          // every member of the layer has radius lr: each lane reads only the
+          // members of the azimuth bins its road reaches
+          unsigned bm = active ? road_bins(lr, Af, Df, Rf, phB, thr, ref, M.lb.lmn[L],
+                                           M.lb.lmx[L], M.lb.linv[L])
+                               : 0u;
+          const int kb = L * kNB;
+          int e = 0, eend = 0;
+          for (;;) {
+            while (e >= eend && bm) {
+              const int b0 = __builtin_ctz(bm);
+              int b1 = b0;  // adjacent bins are one contiguous run
+              while (b1 + 1 < kNB && ((bm >> (b1 + 1)) & 1u)) ++b1;
+              bm &= ~(((2u << b1) - 1u) & ~((1u << b0) - 1u));
+              e = M.lb.start(kb + b0);
+              eend = M.lb.start(kb + b1 + 1);
             }
-            const double dist = fabs(circle_dist(cA, cB, cC, cD, A.hx[hh], A.hy[hh], A.hq[hh]));
-            if (!(dist <= road)) continue;
-            if (bh < 0 || dist < bd || (dist == bd && hh < bh)) { bh = hh; bd = dist; }
+            const bool has = e < eend;
+            if (__ballot(has) == 0ull) break;
+            if (has) {
+              // up to four members of the run at once (their reads in flight together)
+              constexpr int kW = 4;
+              Mem4 v[kW];
+#pragma unroll
+              for (int u = 0; u < kW; ++u) v[u] = M.mem[min(e + u, eend - 1)];
+              const int cnt = min(kW, eend - e);
+              e += cnt;
+#pragma unroll
+              for (int u = 0; u < kW; ++u) {
+                const float f32 = __builtin_fmaf(
+                    Af, v[u].q, __builtin_fmaf(Bf, v[u].x, __builtin_fmaf(Cf, v[u].y, Df)));
+                if (u < cnt && fabsf(f32) <= thr) take(v[u].h);
+              }
+            }
+          }
+        } else {
+          for (int e0 = st; e0 < en; e0 += kChunk) {
+            Mem4 v[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) v[u] = M.mem[min(e0 + u, en - 1)];
+            unsigned pass = 0;
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+              const float f32 = __builtin_fmaf(
+                  Af, v[u].q, __builtin_fmaf(Bf, v[u].x, __builtin_fmaf(Cf, v[u].y, Df)));
+              pass |= (fabsf(f32) <= thr ? 1u : 0u) << u;
+            }
+            const int left = en - e0;
+            if (!active) pass = 0;
+            if (left < kChunk) pass &= (1u << left) - 1u;
+            while (pass) {
+              const int u = __builtin_ctz(pass);
+              pass &= pass - 1u;
+              take(M.mem[e0 + u].h);
+            }
           }
         }
         double qx[kDefer], qy[kDefer], qq[kDefer];
@@ -1263,7 +1541,7 @@ refine_kernel(AssocBatch<NB> AB) {
         }
       }
       if (active) {
-        hitL[L] = bh < 0 ? kNoHit : (uint16_t)bh;
+        hitL.set(L, bh < 0 ? kNoHit : (uint16_t)bh);
         if (bh >= 0) ++n_in;
       }
     }
@@ -1277,7 +1555,7 @@ refine_kernel(AssocBatch<NB> AB) {
     double ss = 0.0;
     if (n_in == best_n) {
       for (unsigned lm = lmask; lm; lm &= lm - 1u) {
-        const int hh = hitL[__builtin_ctz(lm)];
+        const int hh = hitL.get(__builtin_ctz(lm));
         if (hh == kNoHit) continue;
         ++exec;
         const double d = fabs(circle_dist(cA, cB, cC, cD, A.hx[hh], A.hy[hh], A.hq[hh]));
@@ -1297,10 +1575,13 @@ refine_kernel(AssocBatch<NB> AB) {
     }
     ++ncand;
     wave_sync();
-    if (lane < HT_MAX_LAYERS) {
-      const int hh = M.u.hit[win][lane];
-      A.chit[(size_t)p * HT_MAX_LAYERS + lane] = hh == kNoHit ? -1 : hh;
-    }
+    int whh;
+    if constexpr (kChunk > 1)
+      whh = hitL.of_lane(win, lane);
+    else
+      whh = lane < HT_MAX_LAYERS ? (int)M.u.hit[win][lane] : 0;
+    if (lane < HT_MAX_LAYERS)
+      A.chit[(size_t)p * HT_MAX_LAYERS + lane] = whh == kNoHit ? -1 : whh;
     wave_sync();
   }
   // the workgroup's totals, one atomic per counter from lanes 0-4 of wave 0

@@ -301,3 +301,27 @@ def test_assoc_parity_two_branch_vertex_vote(torch, ht, oracle, case):
     if case == "isotropic":
         obj = want["objects"]
         assert obj.size and obj["kind"].max() == 1
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_assoc_parity_angle_bins(torch, ht, oracle, mixed):
+    """Above member_cap 128 the seed search groups each layer's members by
+    azimuth bins; when all members of a layer share one radius, a seed
+    circle is tested only against the bins its road can reach.  Workload-2
+    events at member_cap 256 (every layer on the binned path), and the same
+    events with the radii of half of one layer's hits moved by one float32
+    step (that layer is scanned whole, the others binned)."""
+    W = CF.WORKLOADS[2]
+    cfg = dict(W["cluster"], member_cap=256)
+    for s in range(2):
+        ev = G.make_event(2, W["seed0"] + 50 + s)
+        if mixed:
+            r = ev.r.copy()
+            sel = np.flatnonzero(ev.layer == 4)[::2]
+            r[sel] = np.nextafter(r[sel], np.float32(200.0))
+            ev = SimpleNamespace(r=r, phi=ev.phi, layer=ev.layer, n_hits=ev.n_hits)
+        print(f"angle bins: seed {W['seed0'] + 50 + s}, mixed radii {mixed}", flush=True)
+        got, acc, pk = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], cfg)
+        want = run_oracle(oracle, W["grid"], ev, acc, pk, cfg)
+        compare(got, want, f"angle bins {s} mixed {mixed}")
+        assert int(got["counts"][1]) > 100
