@@ -67,7 +67,9 @@ void free_plan(Plan* p) {
                   p->d_cgeo,      p->d_chit,      p->d_cnl,      p->d_owner_key, p->d_ctile_cnt,
                   p->d_ctile_off, p->d_trk_peak,  p->d_arc0,     p->d_arcn,     p->d_arci0,    p->d_arcin,      p->d_vacc,
                   p->d_obj_cnt,   p->d_obj_off,   p->d_scalars,  p->d_ckl,       p->d_ckh,
-                  p->d_cql,       p->d_ctl,       p->d_cqh,      p->d_cth,      p->d_spread};
+                  p->d_cql,       p->d_ctl,       p->d_cqh,      p->d_cth,      p->d_spread,
+                  p->d_cls,       p->d_bkt,       p->d_bkt_off,  p->d_hkey,     p->d_shit,
+                  p->d_sphi};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -188,6 +190,12 @@ int ht_plan_create(const ht_grid* grid, const ht_limits* lim, ht_plan** out) {
   if (rc == HT_OK) rc = dalloc(p, &p->d_obj_off, (size_t)lim->max_vertex_cells);
   if (rc == HT_OK) rc = dalloc(p, &p->d_scalars, 16);
   if (rc == HT_OK) rc = dalloc(p, &p->d_spread, ht::kSpreadWords);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_cls, (size_t)ht::kClsSlots);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_bkt, (size_t)ht::kBucketKeys);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_bkt_off, (size_t)ht::kBucketKeys + 1);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_hkey, nh);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_shit, nh);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_sphi, nh);
   // band-vote corner tables: (smallest kappa, lower d0 edge) and (largest
   // kappa, upper d0 edge) of every column
   if (rc == HT_OK) rc = dalloc(p, &p->d_ckl, (size_t)g.n_qpt);

@@ -53,7 +53,12 @@ constexpr int kMaxMembers = 1024; // largest member_cap (LDS slots per wave in r
 constexpr int kGridCap = 8192;    // grid-stride launches use at most this many blocks
 
 // S_NBAD: valid hits whose layer is HT_MAX_LAYERS or more (they vote but are no members)
-enum { S_NP = 0, S_NBAD = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5 };
+constexpr float kPiF = 3.14159265358979f;
+constexpr float k2PiF = 6.28318530717959f;
+
+// S_MODE: 1 when the member lists are built by candidate (see cls_kernel);
+// S_COVER: set when the hits have more distinct radii than the hash holds
+enum { S_NP = 0, S_NBAD = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5, S_MODE = 6, S_COVER = 7 };
 // The seed search's totals (road tests, refined candidates, candidates over
 // member_cap, (candidate, member) pairs within it) are summed per workgroup
 // and added to kSpread counters in separate 128-byte lines, chosen by
@@ -292,6 +297,13 @@ struct AssocArgs {
   const int32_t* obj_off;  // object member offsets (the scan of obj_cnt)
   int32_t* sc;  // device scalars
   unsigned long long* spread;  // [kSpreadWords] spread counters
+  // member lists by candidate
+  uint32_t* cls;       // hash of the radii
+  int32_t* bkt;        // hits per (class, bucket)
+  int32_t* bkt_off;    // bucket starts
+  int32_t* hkey;       // each hit's bucket key | slot << 14, or -1
+  int32_t* shit;       // hits in bucket order
+  float* sphi;         // their azimuths
   // outputs
   ht_cluster_out out;
 };
@@ -330,6 +342,8 @@ __global__ void init_kernel(AssocBatch<NB> AB, int words) {
     A.sc[S_NP] = np;
   }
   for (int64_t w = tid; w < words; w += stride) A.pbits[w] = 0u;
+  for (int64_t w = tid; w < kClsSlots; w += stride) A.cls[w] = kRadEmpty;
+  for (int64_t w = tid; w < kBucketKeys; w += stride) A.bkt[w] = 0;
   const int n_hits = hits_of(A);
   for (int64_t h = tid; h < n_hits; h += stride) {
     const float r = A.r[h], ph = A.phi[h];
@@ -372,6 +386,244 @@ __global__ void mark_kernel(AssocBatch<NB> AB) {
       first = pl < 0 || pl >= A.n_cells || pl / A.n_phi != col;
     }
     if (first) A.col_first[col] = p;
+  }
+}
+
+// ---- member lists by candidate -------------------------------------------------
+// A hit of radius r is a member of the candidate at cell (i, j, k) when the
+// float32 coordinate x = ((phi - s) - phi_lo) invw of the vote (s the arcsine
+// of column (j, k) at radius r) lies within the member window w(r, j, k) of
+// the cell centre, on the periodic image of x nearest the cell.  x is a
+// monotone function of the azimuth, so a candidate's members of one radius
+// are the hits of that radius in one interval of azimuth (periodic).  When
+// the event's member-eligible hits (valid, layer below HT_MAX_LAYERS) have at
+// most kMaxClasses distinct radii, they are bucketed by (radius class,
+// azimuth bucket) and one wave per candidate tests, for each radius, only
+// the hits of the buckets its interval reaches (one bucket of margin on each
+// side, far above every rounding), with the very operations of the sweep
+// below, and writes its member list contiguously.  Otherwise the sweep runs.
+
+// insert float bits k into a linear-probing hash of kClsSlots (LDS or
+// global); false when the hash is full
+__device__ __forceinline__ bool hash_insert(uint32_t* key, uint32_t k) {
+  uint32_t slot = rad_hash(k);
+  for (int p = 0; p < kClsSlots; ++p) {
+    const uint32_t v = __hip_atomic_load(&key[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v == k) return true;
+    if (v == kRadEmpty) {
+      const uint32_t old = atomicCAS(&key[slot], kRadEmpty, k);
+      if (old == kRadEmpty || old == k) return true;
+    }
+    slot = (slot + 1) & (kClsSlots - 1);
+  }
+  return false;
+}
+
+// azimuth in [-pi, pi) (up to rounding) and its bucket, the same function for
+// hits and interval ends (monotone in the wrapped azimuth)
+__device__ __forceinline__ float wrap_pi_f(float a) {
+  return a - k2PiF * floorf((a + kPiF) * (1.0f / k2PiF));
+}
+__device__ __forceinline__ float bucket_coord(float aw) {
+  return (aw + kPiF) * ((float)kBuckets / k2PiF);
+}
+__device__ __forceinline__ int bucket_of(float aw) {
+  const float t = bucket_coord(aw);
+  return t < 1.0f ? 0 : (t >= (float)(kBuckets - 1) ? kBuckets - 1 : (int)t);
+}
+
+// the event's distinct radii (each workgroup's, then merged into the event's hash)
+template <int NB>
+__global__ __launch_bounds__(256) void cls_kernel(AssocBatch<NB> AB) {
+  const AssocArgs& A = event_args(AB);
+  __shared__ uint32_t key[kClsSlots];
+  __shared__ int over;
+  if (threadIdx.x < kClsSlots) key[threadIdx.x] = kRadEmpty;
+  if (threadIdx.x == 0) over = 0;
+  __syncthreads();
+  const int n = hits_of(A);
+  uint32_t last = kRadEmpty;
+  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < n; h += gridDim.x * blockDim.x) {
+    const float rv = A.r[h];
+    if (!hit_ok(rv, A.phi[h]) || A.layer[h] >= HT_MAX_LAYERS) continue;
+    const uint32_t k = __float_as_uint(rv);
+    if (k == last) continue;
+    last = k;
+    if (!hash_insert(key, k)) over = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x < kClsSlots) {
+    const uint32_t k = key[threadIdx.x];
+    if (k != kRadEmpty && !hash_insert(A.cls, k)) over = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && over) atomicOr(&A.sc[S_COVER], 1);
+}
+
+// class index of each hash slot (rank among the filled slots, the same in
+// every workgroup); returns the class count, or -1 when the lists are built
+// by the sweep.  Whole workgroup; ends with a barrier.
+__device__ __forceinline__ int class_table(const AssocArgs& A, int32_t* idx, float* cr) {
+  __shared__ int ncls;
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    static_assert(kClsSlots == kWave, "one hash slot per lane");
+    const uint32_t k = A.cls[lane];
+    const bool full = k != kRadEmpty;
+    const uint64_t m = __ballot(full);
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    const int n = __popcll(m);
+    const bool on = n <= kMaxClasses && A.sc[S_COVER] == 0;
+    idx[lane] = full && on ? rank : -1;
+    if (full && on) cr[rank] = __uint_as_float(k);
+    if (lane == 0) ncls = on ? n : -1;
+  }
+  __syncthreads();
+  return ncls;
+}
+
+__device__ __forceinline__ int class_of(const AssocArgs& A, const int32_t* idx, uint32_t k) {
+  uint32_t slot = rad_hash(k);
+  for (int p = 0; p < kClsSlots; ++p) {
+    const uint32_t v = A.cls[slot];
+    if (v == k) return idx[slot];
+    if (v == kRadEmpty) return -1;
+    slot = (slot + 1) & (kClsSlots - 1);
+  }
+  return -1;
+}
+
+// each member-eligible hit's bucket and slot in it
+template <int NB>
+__global__ __launch_bounds__(256) void bcount_kernel(AssocBatch<NB> AB) {
+  const AssocArgs& A = event_args(AB);
+  __shared__ int32_t idx[kClsSlots];
+  __shared__ float cr[kMaxClasses];
+  const int ncls = class_table(A, idx, cr);
+  if (blockIdx.x == 0 && threadIdx.x == 0) A.sc[S_MODE] = ncls >= 0 ? 1 : 0;
+  if (ncls < 0) return;
+  const int n = hits_of(A);
+  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < n; h += gridDim.x * blockDim.x) {
+    const float rv = A.r[h], ph = A.phi[h];
+    int key = -1;
+    if (hit_ok(rv, ph) && A.layer[h] < HT_MAX_LAYERS) {
+      const int c = class_of(A, idx, __float_as_uint(rv));
+      if (c >= 0) {
+        const int b = c * kBuckets + bucket_of(wrap_pi_f(ph));
+        key = b | (atomicAdd(&A.bkt[b], 1) << 14);
+      }
+    }
+    A.hkey[h] = key;
+  }
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void bscatter_kernel(AssocBatch<NB> AB) {
+  const AssocArgs& A = event_args(AB);
+  if (A.sc[S_MODE] == 0) return;
+  const int n = hits_of(A);
+  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < n; h += gridDim.x * blockDim.x) {
+    const int key = A.hkey[h];
+    if (key < 0) continue;
+    const int e = A.bkt_off[key & (kBucketKeys - 1)] + (key >> 14);
+    A.shit[e] = h;
+    A.sphi[e] = A.phi[h];
+  }
+}
+
+// One wave per candidate: lane c < the class count works out class c's
+// arcsine, window and bucket ranges, then the wave tests the hits of each
+// class's ranges, 64 at a time, and appends the members (ballot prefix).
+template <int NB>
+__global__ __launch_bounds__(256) void mcand_kernel(AssocBatch<NB> AB) {
+  const AssocArgs& A = event_args(AB);
+  __shared__ int32_t idx[kClsSlots];
+  __shared__ float cr[kMaxClasses];
+  const int ncls = class_table(A, idx, cr);
+  if (ncls < 0) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int waves = (int)(blockDim.x / kWave);
+  const int np = n_cands(A);
+  const int cap = A.cfg.member_cap;
+  const int n_phi = A.n_phi;
+  const float wbase = 0.5f + (float)A.cfg.win_bins;
+  for (int p = blockIdx.x * waves + (int)(threadIdx.x / kWave); p < np; p += gridDim.x * waves) {
+    const int lin = A.peaks[p].lin;
+    if (lin < 0 || lin >= A.n_cells) continue;  // no members (mark_kernel set the count to 0)
+    const int col = lin / n_phi;
+    const int i = lin - col * n_phi;
+    const int j = col % A.n_qpt;
+    const int k = col / A.n_qpt;
+    float s = __builtin_nanf(""), w = 0.0f;
+    int st0 = 0, en0 = 0, st1 = 0, en1 = 0;
+    if (lane < ncls) {
+      const float rv = cr[lane];
+      const float ir = 1.0f / rv;
+      float x = 0.0f, u = 0.0f;
+      const bool ok = phi0_coord(rv * rv, ir, 0.0f, A.kap[j], A.qt[(size_t)k * A.n_qpt + j],
+                                 A.tt[(size_t)k * A.n_qpt + j], A.phi_lo, A.invw, &x, &u);
+      if (ok) {
+        s = asin_f(u);
+        w = member_window(member_e5(rv, ir, A.hd0, A.hk, A.invw), u, wbase);
+        // azimuths whose x lies within w of the cell centre, as bucket
+        // coordinates: [lo, lo + len] (periodic), one bucket of margin
+        const float xc = (float)i + 0.5f;
+        const float a = ((xc - w) / A.invw + A.phi_lo) + s;
+        const float lo = bucket_coord(wrap_pi_f(a)) - 1.0f;
+        const float len = 2.0f * w / A.invw * ((float)kBuckets / k2PiF) + 2.0f;
+        const int base = lane * kBuckets;
+        if (!(len < (float)(kBuckets - 2)) || !(lo == lo)) {
+          st0 = A.bkt_off[base];
+          en0 = A.bkt_off[base + kBuckets];
+        } else {
+          const int b0 = (int)floorf(lo);
+          const int b1 = (int)floorf(lo + len) + 1;  // one past the last bucket
+          // b0 in [-2, kBuckets], b1 - b0 < kBuckets
+          const int c0 = b0 < 0 ? b0 + kBuckets : (b0 >= kBuckets ? b0 - kBuckets : b0);
+          const int c1 = c0 + (b1 - b0);
+          if (c1 <= kBuckets) {
+            st0 = A.bkt_off[base + c0];
+            en0 = A.bkt_off[base + c1];
+          } else {
+            st0 = A.bkt_off[base + c0];
+            en0 = A.bkt_off[base + kBuckets];
+            st1 = A.bkt_off[base];
+            en1 = A.bkt_off[base + c1 - kBuckets];
+          }
+        }
+      }
+    }
+    int cnt = 0;
+    uint2* pool = A.pool + (size_t)p * cap;
+    for (int c = 0; c < ncls; ++c) {
+      const float sc = bcastf(s, c);
+      if (!(sc == sc)) continue;
+      const float wc = bcastf(w, c);
+#pragma unroll
+      for (int part = 0; part < 2; ++part) {
+        const int st = bcasti(part ? st1 : st0, c);
+        const int en = bcasti(part ? en1 : en0, c);
+        for (int e0 = st; e0 < en; e0 += kWave) {
+          const int e = e0 + lane;
+          bool mem = false;
+          int h = 0;
+          float adx = 0.0f;
+          if (e < en) {
+            h = A.shit[e];
+            const float x = ((A.sphi[e] - sc) - A.phi_lo) * A.invw;
+            adx = cell_adx(x, i, n_phi);
+            mem = adx <= wc;
+          }
+          const uint64_t m = __ballot(mem);
+          if (mem) {
+            const int slot = cnt + __popcll(m & ((1ull << lane) - 1ull));
+            if (slot < cap) pool[slot] = make_uint2((unsigned)h, __float_as_uint(adx));
+          }
+          cnt += __popcll(m);
+        }
+      }
+    }
+    if (lane == 0) A.mcount[p] = cnt;
   }
 }
 
@@ -662,6 +914,7 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocBatch<NB> AB
   const int n_slices = gridDim.z / NB;
   const int slice = (int)blockIdx.z % n_slices;
   const AssocArgs& A = AB.a[NB == 1 ? 0 : (int)blockIdx.z / n_slices];
+  if (A.sc[S_MODE] != 0) return;  // the lists are built by candidate
   const int j0 = blockIdx.x * kWave;
   const int k = blockIdx.y;
   const int n_all = hits_of(A);
@@ -788,8 +1041,6 @@ struct RawMembers {  // members in pool order, before grouping
 // a lane tests only the members of the bins those arcs reach.
 constexpr int kNB = 32;
 constexpr int kBinKeys = HT_MAX_LAYERS * kNB;
-constexpr float kPiF = 3.14159265358979f;
-constexpr float k2PiF = 6.28318530717959f;
 // padding of every computed angle (radians): far above the float32 rounding
 // of the azimuths, of the circle's direction and of the arc half-widths
 constexpr float kAngPad = 1e-5f;
@@ -2277,6 +2528,12 @@ AssocArgs make_args(const Plan& P, const float* r, const float* phi, const uint8
   A.obj_off = P.d_obj_off;
   A.sc = P.d_scalars;
   A.spread = P.d_spread;
+  A.cls = P.d_cls;
+  A.bkt = P.d_bkt;
+  A.bkt_off = P.d_bkt_off;
+  A.hkey = P.d_hkey;
+  A.shit = P.d_shit;
+  A.sphi = P.d_sphi;
   A.out = out;
   return A;
 }
@@ -2303,6 +2560,28 @@ int assoc_sequence(const AssocBatch<NB>& AB, const Plan* const* P, int32_t n_hit
   const int col_tiles = (g.n_qpt + kWave - 1) / kWave;
   dim3 sweep(col_tiles, g.n_d0, hit_slices(col_tiles * g.n_d0, n_hits) * NB);
   P0.prof_mark(HT_STAGE_MEMBERS, 0, s);
+  {
+    const dim3 hgrid(blocks_for(n_hits, 256) < 256 ? blocks_for(n_hits, 256) : 256, 1, NB);
+    cls_kernel<NB><<<hgrid, 256, 0, s>>>(AB);
+    HT_CHECK(hipGetLastError());
+    bcount_kernel<NB><<<hgrid, 256, 0, s>>>(AB);
+    HT_CHECK(hipGetLastError());
+    const int32_t* bc[NB];
+    int32_t* bo[NB];
+    int32_t* bt[NB];
+    for (int b = 0; b < NB; ++b) {
+      bc[b] = P[b]->d_bkt;
+      bo[b] = P[b]->d_bkt_off;
+      bt[b] = P[b]->d_bkt_off + kBucketKeys;
+    }
+    const int brc = NB == 1 ? launch_scan(bc[0], bo[0], kBucketKeys, bt[0], s)
+                            : launch_scan_batch(NB, bc, bo, kBucketKeys, bt, s);
+    if (brc != HT_OK) return brc;
+    bscatter_kernel<NB><<<hgrid, 256, 0, s>>>(AB);
+    HT_CHECK(hipGetLastError());
+    mcand_kernel<NB><<<dim3(blocks_for(peak_cap, 4), 1, NB), 256, 0, s>>>(AB);
+    HT_CHECK(hipGetLastError());
+  }
   member_kernel<NB><<<sweep, kSweepThreads, 0, s>>>(AB);
   HT_CHECK(hipGetLastError());
   P0.prof_mark(HT_STAGE_MEMBERS, 1, s);

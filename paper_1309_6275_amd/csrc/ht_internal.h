@@ -14,6 +14,14 @@ namespace ht {
 // five groups of 64 counters, one 128-byte line each (the seed search's totals)
 constexpr int kSpreadWords = 5 * 64 * 16;
 
+// member lists by candidate: the distinct radii of an event's member-eligible
+// hits go into a hash of kClsSlots; with at most kMaxClasses of them the hits
+// are bucketed by (radius class, one of kBuckets azimuth buckets)
+constexpr int kClsSlots = 64;
+constexpr int kMaxClasses = 16;
+constexpr int kBuckets = 1024;
+constexpr int kBucketKeys = kMaxClasses * kBuckets;
+
 // Hit slices for launches of one workgroup per 64-column tile: grids with
 // fewer than 128 tiles also split the hits, so that about 256 workgroups run,
 // with slices of at least 1024 hits of the bound the buffers were checked
@@ -79,6 +87,13 @@ struct Plan {
   int32_t* d_obj_off;    // [max_vertex_cells] member offset per object
   int32_t* d_scalars;    // [16] device counters
   unsigned long long* d_spread;  // [kSpreadWords] counters spread over 128-byte lines
+  // member lists by candidate
+  uint32_t* d_cls;      // [kClsSlots] hash of the hits' radii (float bits)
+  int32_t* d_bkt;       // [kBucketKeys] hits per (class, bucket)
+  int32_t* d_bkt_off;   // [kBucketKeys + 1] bucket starts; the bucketed hit count last
+  int32_t* d_hkey;      // [max_hits] bucket key | slot << 14 of each hit, -1 if none
+  int32_t* d_shit;      // [max_hits] hits in bucket order
+  float* d_sphi;        // [max_hits] their azimuths
   // stage timing (ht_profile_*): HIP events recorded around the stages of
   // later calls; plan calls are ordered, so the counters need no locking
   mutable int32_t prof_depth;          // 0: off
