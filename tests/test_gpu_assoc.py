@@ -325,3 +325,26 @@ def test_assoc_parity_angle_bins(torch, ht, oracle, mixed):
         want = run_oracle(oracle, W["grid"], ev, acc, pk, cfg)
         compare(got, want, f"angle bins {s} mixed {mixed}")
         assert int(got["counts"][1]) > 100
+
+
+@pytest.mark.parametrize("extra_radii", [6, 7])
+def test_assoc_parity_member_lists_both_paths(torch, ht, oracle, extra_radii):
+    """Member lists are built by candidate (hits bucketed by radius and
+    azimuth) when the member-eligible hits have at most 16 distinct radii,
+    else by the sweep over (hit, column) pairs.  A workload-2 event (10
+    radii) plus one hit on each of 6 new radii takes the first path, plus 7
+    the second; both equal the oracle."""
+    W = CF.WORKLOADS[2]
+    ev = G.make_event(2, W["seed0"] + 90)
+    rng = np.random.default_rng(90)
+    new_r = np.float32(rng.uniform(12.0, 100.0, extra_radii))
+    r = np.concatenate([ev.r, new_r]).astype(np.float32)
+    phi = np.concatenate([ev.phi, rng.uniform(-np.pi, np.pi, extra_radii)]).astype(np.float32)
+    layer = np.concatenate([ev.layer, rng.integers(0, 10, extra_radii)]).astype(np.uint8)
+    ev2 = SimpleNamespace(r=r, phi=phi, layer=layer, n_hits=int(r.size))
+    assert np.unique(r).size == 10 + extra_radii
+    print(f"member lists: {10 + extra_radii} radii", flush=True)
+    got, acc, pk = run_gpu(torch, ht, W["grid"], ev2, W["min_votes"], W["cluster"])
+    want = run_oracle(oracle, W["grid"], ev2, acc, pk, W["cluster"])
+    compare(got, want, f"{10 + extra_radii} radii")
+    assert int(got["counts"][1]) > 100
