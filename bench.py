@@ -193,7 +193,7 @@ def serve_kinds():
 # events of at most this many hits may share a batch in the learned + batched
 # serving configuration
 SERVE_BATCH_HITS = 16384
-SERVE_RATES = (50, 100, 150, 200, 250, 300, 350, 400, 500, 600, 800, 1000)
+SERVE_RATES = (50, 100, 200, 300, 400, 600, 800, 1000, 1200, 1400, 1600, 2000, 2500, 3000)
 
 
 def serve_filter(torch, H, n_train, n_val, keep=0.995):

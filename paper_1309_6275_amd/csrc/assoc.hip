@@ -403,6 +403,16 @@ __global__ void mark_kernel(AssocBatch<NB> AB) {
 // side, far above every rounding), with the very operations of the sweep
 // below, and writes its member list contiguously.  Otherwise the sweep runs.
 
+// inclusive prefix sum over the wave
+__device__ __forceinline__ int wave_incl_scan_i32(int v, int lane) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int o = __shfl_up(v, d, kWave);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
 // insert float bits k into a linear-probing hash of kClsSlots (LDS or
 // global); false when the hash is full
 __device__ __forceinline__ bool hash_insert(uint32_t* key, uint32_t k) {
@@ -593,35 +603,59 @@ __global__ __launch_bounds__(256) void mcand_kernel(AssocBatch<NB> AB) {
         }
       }
     }
+    // The classes' ranges, range q = 2 c + part held by lane q, laid end to
+    // end: a sparse event's candidate (a few hits per class) reads them 64
+    // hits at a time whatever their lengths.
+    const int nr = 2 * ncls;
+    const int qc = lane >> 1;
+    const int rst0 = __shfl(st0, qc, kWave), ren0 = __shfl(en0, qc, kWave);
+    const int rst1 = __shfl(st1, qc, kWave), ren1 = __shfl(en1, qc, kWave);
+    const float rs = __shfl(s, qc, kWave);
+    const int rst = (lane & 1) ? rst1 : rst0;
+    const int rlen = lane < nr && rs == rs ? ((lane & 1) ? ren1 - rst1 : ren0 - rst0) : 0;
+    const int rend = wave_incl_scan_i32(rlen, lane);  // end of range q in the laid-out order
+    const int total = __builtin_amdgcn_readlane(rend, kWave - 1);
     int cnt = 0;
     uint2* pool = A.pool + (size_t)p * cap;
-    for (int c = 0; c < ncls; ++c) {
-      const float sc = bcastf(s, c);
-      if (!(sc == sc)) continue;
-      const float wc = bcastf(w, c);
+    auto test = [&](int e, bool in, float sc, float wc) {
+      bool mem = false;
+      int h = 0;
+      float adx = 0.0f;
+      if (in) {
+        h = A.shit[e];
+        const float x = ((A.sphi[e] - sc) - A.phi_lo) * A.invw;
+        adx = cell_adx(x, i, n_phi);
+        mem = adx <= wc;
+      }
+      const uint64_t m = __ballot(mem);
+      if (mem) {
+        const int slot = cnt + __popcll(m & ((1ull << lane) - 1ull));
+        if (slot < cap) pool[slot] = make_uint2((unsigned)h, __float_as_uint(adx));
+      }
+      cnt += __popcll(m);
+    };
+    if (total > 3 * kWave) {
+      // dense: class by class (the lookup of a hit's range costs more than
+      // the partly filled last pass of each range)
+      for (int c = 0; c < ncls; ++c) {
+        const float sc = bcastf(s, c);
+        if (!(sc == sc)) continue;
+        const float wc = bcastf(w, c);
 #pragma unroll
-      for (int part = 0; part < 2; ++part) {
-        const int st = bcasti(part ? st1 : st0, c);
-        const int en = bcasti(part ? en1 : en0, c);
-        for (int e0 = st; e0 < en; e0 += kWave) {
-          const int e = e0 + lane;
-          bool mem = false;
-          int h = 0;
-          float adx = 0.0f;
-          if (e < en) {
-            h = A.shit[e];
-            const float x = ((A.sphi[e] - sc) - A.phi_lo) * A.invw;
-            adx = cell_adx(x, i, n_phi);
-            mem = adx <= wc;
-          }
-          const uint64_t m = __ballot(mem);
-          if (mem) {
-            const int slot = cnt + __popcll(m & ((1ull << lane) - 1ull));
-            if (slot < cap) pool[slot] = make_uint2((unsigned)h, __float_as_uint(adx));
-          }
-          cnt += __popcll(m);
+        for (int part = 0; part < 2; ++part) {
+          const int st = bcasti(part ? st1 : st0, c);
+          const int en = bcasti(part ? en1 : en0, c);
+          for (int e0 = st; e0 < en; e0 += kWave) test(e0 + lane, e0 + lane < en, sc, wc);
         }
       }
+    } else for (int t0 = 0; t0 < total; t0 += kWave) {
+      const int t = t0 + lane;
+      // range of t: the number of ranges that end at or before it
+      int q = 0;
+      for (int u = 0; u < nr; ++u) q += t >= __builtin_amdgcn_readlane(rend, u) ? 1 : 0;
+      const int qs = q < kWave ? q : kWave - 1;
+      const int e = __shfl(rst, qs, kWave) + (t - (__shfl(rend, qs, kWave) - __shfl(rlen, qs, kWave)));
+      test(e, t < total, __shfl(s, qs >> 1, kWave), __shfl(w, qs >> 1, kWave));
     }
     if (lane == 0) A.mcount[p] = cnt;
   }
@@ -1178,14 +1212,6 @@ struct InlierRow<true> {
   }
 };
 
-__device__ __forceinline__ int wave_incl_scan_i32(int v, int lane) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int o = __shfl_up(v, d, kWave);
-    if (lane >= d) v += o;
-  }
-  return v;
-}
 
 template <int CAP>
 struct WaveMem {
