@@ -87,6 +87,9 @@ def parse():
                          "largest event (max_hits x the most q/pT x d0 columns); 0: no limit")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="seconds of arrivals per Poisson rate in --serve")
+    ap.add_argument("--serve-batch-hits", type=int, default=SERVE_BATCH_HITS,
+                    help="--serve: events of at most this many hits may share a batch in the "
+                         "learned + batched configuration")
     ap.add_argument("--two-pass", action="store_true",
                     help="benchmark iterative hit removal instead: prompt pass on the 2D grid, "
                          "removal of its hits, displaced pass on the 3D grid, against the "
@@ -252,7 +255,7 @@ def serve_bench(args):
         return H.Server(kinds, max_hits=65535, track_cap=4096, object_cap=256, member_cap=4096,
                         hbm_budget=128 << 30, max_slots=slots, queue_cap=queue,
                         use_graphs=use_graphs, work_budget=budget, batch_max=batch,
-                        batch_max_hits=SERVE_BATCH_HITS if batch > 1 else 0)
+                        batch_max_hits=args.serve_batch_hits if batch > 1 else 0)
 
     tags = iter(range(1 << 62))
 
@@ -373,7 +376,7 @@ def serve_bench(args):
         "config": {"workload": "mixed trigger stream: 50% 2D (256x256) / 50% 3D (512x256x64) "
                                "events, hits ~ U[2k, 60k], pool of 32 seeded events",
                    "form": "learned + batched: 4 slots, up to 4 waiting events of a kind with "
-                           f"<= {SERVE_BATCH_HITS} hits per launch, learned peak filter on the "
+                           f"<= {args.serve_batch_hits} hits per launch, learned peak filter on the "
                            "3D kind (keeps 99.5% of validation truth positives)",
                    "slots": learned["slots"], "slot_bytes": learned["slot_bytes"],
                    "queue_cap": 64, "graphs": True, "work_budget": work_budget,
