@@ -348,3 +348,38 @@ def test_assoc_parity_member_lists_both_paths(torch, ht, oracle, extra_radii):
     want = run_oracle(oracle, W["grid"], ev2, acc, pk, W["cluster"])
     compare(got, want, f"{10 + extra_radii} radii")
     assert int(got["counts"][1]) > 100
+
+
+@pytest.mark.parametrize("case", ["phi_beyond_pi", "odd_grid_2d", "odd_grid_3d"])
+def test_assoc_parity_member_lists_edges(torch, ht, oracle, case):
+    """Member lists by candidate on inputs that stress the azimuth buckets:
+    azimuths outside [-pi, pi) (valid hits reach |phi| <= 4; the buckets use
+    the wrapped azimuth, the member test the raw one), and grids whose phi0
+    axis is not a power of two."""
+    if case == "phi_beyond_pi":
+        W = CF.WORKLOADS[2]
+        grid, cfg = W["grid"], W["cluster"]
+        ev = G.make_event(2, W["seed0"] + 91)
+        phi = ev.phi.astype(np.float64)
+        phi = np.where(phi > np.pi - 0.85, phi - 2 * np.pi, phi)
+        phi = np.where(phi < -np.pi + 0.85, phi + 2 * np.pi, phi)
+        ev = SimpleNamespace(r=ev.r, phi=phi.astype(np.float32), layer=ev.layer, n_hits=ev.n_hits)
+        assert np.abs(ev.phi).max() > np.pi and np.abs(ev.phi).max() <= 4.0
+        min_votes = W["min_votes"]
+    elif case == "odd_grid_2d":
+        W = CF.WORKLOADS[1]
+        grid = dict(W["grid"], n_phi=250, n_qpt=200)
+        cfg = W["cluster"]
+        ev = G.make_event(1, W["seed0"] + 91, n_prompt=80, n_noise=200)
+        min_votes = W["min_votes"]
+    else:
+        W = CF.WORKLOADS[2]
+        grid = dict(W["grid"], n_phi=500, n_qpt=120, n_d0=24)
+        cfg = dict(W["cluster"], member_cap=256)
+        ev = G.make_event(2, W["seed0"] + 91)
+        min_votes = W["min_votes"]
+    print(f"member list edges: {case}", flush=True)
+    got, acc, pk = run_gpu(torch, ht, grid, ev, min_votes, cfg)
+    want = run_oracle(oracle, grid, ev, acc, pk, cfg)
+    compare(got, want, case)
+    assert int(got["counts"][1]) > 10
