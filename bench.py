@@ -79,6 +79,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=-1,
                     help="events of the CPU oracle baseline (0 skips it; -1: 2 events of "
                          "workload 3, 16 of workload 2)")
+    ap.add_argument("--serving-probe", type=int, default=1,
+                    help="1: also replay the mixed trigger stream at 1 kHz through the plain "
+                         "server and report arrival-to-result latency as serving_1kHz")
     ap.add_argument("--serve", action="store_true",
                     help="benchmark the trigger serving loop instead: Poisson arrivals of a mixed "
                          "2D/3D event stream, p50/p99 latency, shedding, closed-loop throughput")
@@ -225,6 +228,70 @@ def serve_filter(torch, H, n_train, n_val, keep=0.995):
     return out, thr, info
 
 
+def serve_replay(srv, rate, seconds, events, tags, min_events=1):
+    """Real-time replay of Poisson arrivals (seeded by the rate, so every
+    server configuration sees the same sequence at a given rate) through a
+    server; latency = result seen by poll - arrival (host clock)."""
+    arng = np.random.default_rng(4_100_000 + int(rate))
+    n = max(min_events, int(rate * seconds))
+    arrivals = np.cumsum(arng.exponential(1.0 / rate, n))
+    picks = arng.integers(0, len(events), n)
+    lat, shed, batched = [], 0, 0
+
+    def take(done):
+        nonlocal batched
+        for d in done:
+            lat.append(d["t_done"] - d["t_submit"])
+            batched += d["batch"] > 1
+    t0 = time.perf_counter()
+    for a, p in zip(arrivals, picks):
+        while time.perf_counter() - t0 < a:
+            take(srv.poll(wait=False))
+        k, ev = events[p]
+        if not srv.submit(k, ev.r, ev.phi, ev.layer, next(tags), want_outputs=False):
+            shed += 1
+    take(srv.drain())
+    wall = time.perf_counter() - t0
+    lat = np.array(lat) * 1e3
+    return dict(rate=rate, offered=n, done=int(lat.size), shed=shed, wall_s=wall,
+                batched_fraction=batched / max(1, lat.size),
+                p50_ms=float(np.percentile(lat, 50)) if lat.size else None,
+                p99_ms=float(np.percentile(lat, 99)) if lat.size else None)
+
+
+def serve_closed_loop(srv, events, n, tags):
+    """n events back to back, the queue kept full; events/s."""
+    t0 = time.perf_counter()
+    sent = done = 0
+    while done < n:
+        while sent < n:
+            k, ev = events[sent % len(events)]
+            if not srv.submit(k, ev.r, ev.phi, ev.layer, next(tags), want_outputs=False):
+                break
+            sent += 1
+        done += len(srv.poll(wait=True))
+    return n / (time.perf_counter() - t0)
+
+
+def serving_probe():
+    """Arrival-to-result latency for the default line: the plain server (4
+    slots) on the mixed trigger stream at 1 kHz for 2 s, and its closed-loop
+    rate (the full comparison is bench.py --serve)."""
+    from paper_1309_6275_amd import eventgen as G
+    from paper_1309_6275_amd import houghtrig as H
+    pool = [(k, G.make_serving_event(k, 4_000_001 + 2 * i + k)) for i in range(16) for k in (0, 1)]
+    tags = iter(range(1 << 62))
+    srv = H.Server(serve_kinds(), max_hits=65535, track_cap=4096, object_cap=256,
+                   member_cap=4096, hbm_budget=96 << 30, max_slots=4, queue_cap=64)
+    serve_closed_loop(srv, pool, 2 * len(pool), tags)  # warm every slot and kind
+    r = serve_replay(srv, 1000, 2.0, pool, tags)
+    r["closed_loop_events_per_s"] = serve_closed_loop(srv, pool, 4 * len(pool), tags)
+    srv.close()
+    r["stream"] = ("50% 2D (256x256) / 50% 3D (512x256x64) events, hits ~ U[2k, 60k], "
+                   "Poisson arrivals replayed in real time, plain server with 4 slots")
+    return r
+
+
 def serve_bench(args):
     """Real-time replay of Poisson arrivals through the server (host clock:
     latency = result seen by poll - arrival), several rates, for three
@@ -260,46 +327,10 @@ def serve_bench(args):
     tags = iter(range(1 << 62))
 
     def replay(srv, rate, seconds, events, min_events=1):
-        # arrivals and picks seeded by the rate: every server configuration
-        # sees the same sequence at a given rate
-        arng = np.random.default_rng(4_100_000 + int(rate))
-        n = max(min_events, int(rate * seconds))
-        arrivals = np.cumsum(arng.exponential(1.0 / rate, n))
-        picks = arng.integers(0, len(events), n)
-        lat, shed, batched = [], 0, 0
-
-        def take(done):
-            nonlocal batched
-            for d in done:
-                lat.append(d["t_done"] - d["t_submit"])
-                batched += d["batch"] > 1
-        t0 = time.perf_counter()
-        for a, p in zip(arrivals, picks):
-            while time.perf_counter() - t0 < a:
-                take(srv.poll(wait=False))
-            k, ev = events[p]
-            if not srv.submit(k, ev.r, ev.phi, ev.layer, next(tags), want_outputs=False):
-                shed += 1
-        take(srv.drain())
-        wall = time.perf_counter() - t0
-        lat = np.array(lat) * 1e3
-        return dict(rate=rate, offered=n, done=int(lat.size), shed=shed, wall_s=wall,
-                    batched_fraction=batched / max(1, lat.size),
-                    p50_ms=float(np.percentile(lat, 50)) if lat.size else None,
-                    p99_ms=float(np.percentile(lat, 99)) if lat.size else None)
+        return serve_replay(srv, rate, seconds, events, tags, min_events)
 
     def closed_loop(srv, events, n):
-        """n events back to back, the queue kept full; events/s."""
-        t0 = time.perf_counter()
-        sent = done = 0
-        while done < n:
-            while sent < n:
-                k, ev = events[sent % len(events)]
-                if not srv.submit(k, ev.r, ev.phi, ev.layer, next(tags), want_outputs=False):
-                    break
-                sent += 1
-            done += len(srv.poll(wait=True))
-        return n / (time.perf_counter() - t0)
+        return serve_closed_loop(srv, events, n, tags)
 
     def sweep(srv, name):
         """Poisson rates in increasing order until the p99 passes 50 ms; the
@@ -774,6 +805,8 @@ def main():
             "workload", "events_per_step", "mean_hits", "votes_per_s", "events_per_s",
             "ms_per_step", "p50_ms", "p99_ms", "track_efficiency", "fake_rate",
             "tracks_per_event", "stage_ms", "roofline", "roofline_vote", "roofline_refine")}
+    if args.serving_probe:
+        line["serving_1kHz"] = serving_probe()
     print(json.dumps(line), flush=True)
 
 
