@@ -1054,15 +1054,19 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocBatch<NB> AB
 // hit indices are < 65535 (at most 65535 hits), so 0xffff marks "no hit"
 constexpr uint16_t kNoHit = 0xffff;
 
+// a member: float32 x, y of the hit, its |x - cell centre| in the column
+// (the seed ranking key) and the hit index; the float32 x^2 + y^2 of the
+// pre-filter is recomputed from x and y
 struct alignas(16) Mem4 {
-  float x, y, q;
+  float x, y, adx;
   int32_t h;
 };
+
+__device__ __forceinline__ float mem_q(const Mem4& v) { return __builtin_fmaf(v.x, v.x, v.y * v.y); }
 
 template <int CAP>
 struct RawMembers {  // members in pool order, before grouping
   Mem4 mem[CAP];
-  float adx[CAP];
   int16_t slot[CAP];
   int8_t L[CAP];
 };
@@ -1215,9 +1219,10 @@ struct InlierRow<true> {
 
 template <int CAP>
 struct WaveMem {
-  Mem4 mem[CAP];   // grouped by layer (and by azimuth bin within a layer for caps above 128)
-  float adx[CAP];  // |x - cell centre| of the grouped members (above cap 128, before the
-                   // grouping: each member's relative azimuth in pool order)
+  // grouped by layer (and by azimuth bin within a layer for caps above 128);
+  // above cap 128, before the grouping, its first CAP floats hold each
+  // member's relative azimuth in pool order
+  Mem4 mem[CAP];
   union {
     // members in pool order before grouping, staged in LDS for CAP <= 128;
     // larger caps stage them in registers (LDS, not registers, limits their
@@ -1383,7 +1388,6 @@ refine_kernel(AssocBatch<NB> AB) {
     constexpr bool kRawLds = CAP <= 128;
     constexpr int RM = kRawLds ? 1 : CAP / kWave;
     Mem4 rec[RM];
-    float radx[RM];
     int rL[RM];
     unsigned lmask = 0;
     float qmax = 0.0f;
@@ -1397,10 +1401,9 @@ refine_kernel(AssocBatch<NB> AB) {
         Mem4 r4;
         r4.x = hb.x;
         r4.y = hb.y;
-        r4.q = hb.z;
+        r4.adx = __uint_as_float(pe.y);
         r4.h = h;
         M.u.raw.mem[m] = r4;
-        M.u.raw.adx[m] = __uint_as_float(pe.y);
         M.u.raw.L[m] = (int8_t)L;
         lmask |= 1u << L;
         qmax = fmaxf(qmax, hb.z);
@@ -1430,9 +1433,8 @@ refine_kernel(AssocBatch<NB> AB) {
           const int L = (int)hb.w;
           rec[t].x = hb.x;
           rec[t].y = hb.y;
-          rec[t].q = hb.z;
+          rec[t].adx = __uint_as_float(pe.y);
           rec[t].h = h;
-          radx[t] = __uint_as_float(pe.y);
           rL[t] = L;
           lmask |= 1u << L;
           qmax = fmaxf(qmax, hb.z);
@@ -1447,7 +1449,7 @@ refine_kernel(AssocBatch<NB> AB) {
         const int h = rec[t].h, L = rL[t];
         const float hr = A.r[h];
         const float rel = rel_angle(A.phi[h], ref);
-        M.adx[lane + t * kWave] = rel;
+        reinterpret_cast<float*>(M.mem)[lane + t * kWave] = rel;
         atomicMin(&M.u.st.rlo[L], __float_as_int(hr));
         atomicMax(&M.u.st.rhi[L], __float_as_int(hr));
         atomicMin(&M.u.st.alo[L], ord_bits(rel));
@@ -1486,7 +1488,6 @@ refine_kernel(AssocBatch<NB> AB) {
       for (int m = lane; m < n; m += kWave) {
         const int e = M.lstart[M.u.raw.L[m]] + M.u.raw.slot[m];
         M.mem[e] = M.u.raw.mem[m];
-        M.adx[e] = M.u.raw.adx[m];
       }
     } else {
       wave_sync();
@@ -1504,7 +1505,8 @@ refine_kernel(AssocBatch<NB> AB) {
       for (int t = 0; t < RM; ++t) {
         if (rL[t] < 0) continue;
         const int L = rL[t];
-        const int key = L * kNB + angle_bin(M.adx[lane + t * kWave], M.lb.lmn[L], M.lb.linv[L]);
+        const int key = L * kNB + angle_bin(reinterpret_cast<const float*>(M.mem)[lane + t * kWave],
+                                            M.lb.lmn[L], M.lb.linv[L]);
         // group and slot in one register (key < 512, slot < 1024)
         const int sh = (key & 1) * 16;
         const uint32_t old = atomicAdd(&M.lb.bpack[key >> 1], 1u << sh);
@@ -1542,7 +1544,6 @@ refine_kernel(AssocBatch<NB> AB) {
         if (rL[t] < 0) continue;
         const int e = M.lb.start(rL[t] & 0x3ff) + (rL[t] >> 10);
         M.mem[e] = rec[t];
-        M.adx[e] = radx[t];
       }
     }
     wave_sync();
@@ -1568,14 +1569,14 @@ refine_kernel(AssocBatch<NB> AB) {
       else if (lane < n0 + n1 + n2) { s = 2; st = sst[2]; en = sen[2]; }
       const int e = st + lane - (s == 1 ? n0 : (s == 2 ? n0 + n1 : 0));
       unsigned long long key = 0;
-      if (s >= 0) key = ((unsigned long long)__float_as_uint(M.adx[e]) << 32) | (unsigned)M.mem[e].h;
+      if (s >= 0) key = ((unsigned long long)__float_as_uint(M.mem[e].adx) << 32) | (unsigned)M.mem[e].h;
       const int nmax = max(n0, max(n1, n2));
       int rank = 0;
       for (int t = 0; t < nmax; ++t) {
         const int e2 = st + t;
         if (s >= 0 && e2 < en) {
           const unsigned long long k2 =
-              ((unsigned long long)__float_as_uint(M.adx[e2]) << 32) | (unsigned)M.mem[e2].h;
+              ((unsigned long long)__float_as_uint(M.mem[e2].adx) << 32) | (unsigned)M.mem[e2].h;
           rank += k2 < key;
         }
       }
@@ -1595,7 +1596,7 @@ refine_kernel(AssocBatch<NB> AB) {
           for (int e = st + lane, t = 0; e < en; e += kWave, ++t) {
             if ((taken >> t) & 1ull) continue;
             const unsigned long long key =
-                ((unsigned long long)__float_as_uint(M.adx[e]) << 32) | (unsigned)M.mem[e].h;
+                ((unsigned long long)__float_as_uint(M.mem[e].adx) << 32) | (unsigned)M.mem[e].h;
             if (key < mine) { mine = key; arg = t; }
           }
           const unsigned long long best = wave_min_u64(mine);
@@ -1635,12 +1636,12 @@ refine_kernel(AssocBatch<NB> AB) {
     }
     // |dist| >= |f| / (1 + |A||f|): a member with |f| > road / (1 - road |A|)
     // cannot be within the road, and road / (1 - x) <= road (1 + 2x) for
-    // x <= 1/2, a bound without a division.  The float32 test allows a margin of 1e-6
+    // x <= 1/2, a bound without a division.  The float32 test allows a margin of 2e-6
     // of a bound on the magnitudes of the terms and partial sums over all
     // members (|x|, |y| <= rmax, q <= qmax), far above what the rounding of
-    // the coefficients, of the coordinates and of three fused multiply-adds
-    // can move f (< 5e-7 of that bound), so it never drops a member the
-    // float64 test keeps.
+    // the coefficients, of the coordinates, of q = x^2 + y^2 recomputed in
+    // float32 and of three fused multiply-adds can move f (< 8e-7 of that
+    // bound), so it never drops a member the float64 test keeps.
     float Af = 0.0f, Bf = 0.0f, Cf = 0.0f, Df = 0.0f, thr = -1.0f;
     float Rf = 0.0f, phB = 0.0f;  // |(B, C)| and its direction (angle bins)
     if (ok) {
@@ -1651,7 +1652,7 @@ refine_kernel(AssocBatch<NB> AB) {
       Cf = (float)cC;
       Df = (float)cD;
       const float mag = fabsf(Af) * qmax + (fabsf(Bf) + fabsf(Cf)) * rmax + fabsf(Df);
-      thr = pre + mag * 1e-6f;
+      thr = pre + mag * 2e-6f;
       if constexpr (kChunk > 1) {
         Rf = __builtin_sqrtf(Bf * Bf + Cf * Cf);
         phB = atan2f(Cf, Bf);
@@ -1710,7 +1711,7 @@ refine_kernel(AssocBatch<NB> AB) {
         for (int e = st; e < en; ++e) {
           const Mem4 v = M.mem[e];
           const float f32 =
-              __builtin_fmaf(Af, v.q, __builtin_fmaf(Bf, v.x, __builtin_fmaf(Cf, v.y, Df)));
+              __builtin_fmaf(Af, mem_q(v), __builtin_fmaf(Bf, v.x, __builtin_fmaf(Cf, v.y, Df)));
           if (!(active && fabsf(f32) <= thr)) continue;
           const int hh = v.h;
           ++exec;
@@ -1771,7 +1772,7 @@ refine_kernel(AssocBatch<NB> AB) {
 #pragma unroll
               for (int u = 0; u < kW; ++u) {
                 const float f32 = __builtin_fmaf(
-                    Af, v[u].q, __builtin_fmaf(Bf, v[u].x, __builtin_fmaf(Cf, v[u].y, Df)));
+                    Af, mem_q(v[u]), __builtin_fmaf(Bf, v[u].x, __builtin_fmaf(Cf, v[u].y, Df)));
                 if (u < cnt && fabsf(f32) <= thr) take(v[u].h);
               }
             }
@@ -1785,7 +1786,7 @@ refine_kernel(AssocBatch<NB> AB) {
 #pragma unroll
             for (int u = 0; u < kChunk; ++u) {
               const float f32 = __builtin_fmaf(
-                  Af, v[u].q, __builtin_fmaf(Bf, v[u].x, __builtin_fmaf(Cf, v[u].y, Df)));
+                  Af, mem_q(v[u]), __builtin_fmaf(Bf, v[u].x, __builtin_fmaf(Cf, v[u].y, Df)));
               pass |= (fabsf(f32) <= thr ? 1u : 0u) << u;
             }
             const int left = en - e0;
