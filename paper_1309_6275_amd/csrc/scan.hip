@@ -55,17 +55,43 @@ __device__ void scan_one(const int32_t* __restrict__ cnt, int32_t* __restrict__ 
   const int per = (n + kScanThreads - 1) / kScanThreads;
   const int b = (int)min((long long)n, (long long)t * per);
   const int e = min(n, b + per);
+  // whole 16-byte vectors per thread when the runs and the arrays allow
+  const bool vec = (per & 3) == 0 && (n & 3) == 0 && ((uintptr_t)cnt & 15) == 0 &&
+                   ((uintptr_t)off & 15) == 0;
   long long s = 0;
-  for (int x = b; x < e; ++x) s += cnt[x];
+  if (vec) {
+    for (int x = b; x < e; x += 4) {
+      const int4 c = *reinterpret_cast<const int4*>(cnt + x);
+      s += (long long)c.x + c.y + c.z + c.w;
+    }
+  } else {
+    for (int x = b; x < e; ++x) s += cnt[x];
+  }
   const long long incl = wave_incl_scan(s, lane);
   if (lane == kWave - 1) wsum[wave] = incl;
   __syncthreads();
   long long base = 0;
   for (int w = 0; w < wave; ++w) base += wsum[w];
   long long run = base + incl - s;
-  for (int x = b; x < e; ++x) {
-    off[x] = clamp_i32(run);
-    run += cnt[x];
+  if (vec) {
+    for (int x = b; x < e; x += 4) {
+      const int4 c = *reinterpret_cast<const int4*>(cnt + x);
+      int4 o;
+      o.x = clamp_i32(run);
+      run += c.x;
+      o.y = clamp_i32(run);
+      run += c.y;
+      o.z = clamp_i32(run);
+      run += c.z;
+      o.w = clamp_i32(run);
+      run += c.w;
+      *reinterpret_cast<int4*>(off + x) = o;
+    }
+  } else {
+    for (int x = b; x < e; ++x) {
+      off[x] = clamp_i32(run);
+      run += cnt[x];
+    }
   }
   if (t == kScanThreads - 1 && total) *total = clamp_i32(base + incl);
 }
