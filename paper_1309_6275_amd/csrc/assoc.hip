@@ -1186,32 +1186,57 @@ struct InlierRow {
 };
 template <>
 struct InlierRow<true> {
-  uint32_t w[HT_MAX_LAYERS / 2];
+  // eight words of two 16-bit entries, layer L in word L / 2 (named
+  // registers selected by a switch on the wave-uniform layer: an indexed
+  // array would be placed in scratch memory)
+  uint32_t w0, w1, w2, w3, w4, w5, w6, w7;
   __device__ __forceinline__ void init(uint16_t*) {
-#pragma unroll
-    for (int i = 0; i < HT_MAX_LAYERS / 2; ++i) w[i] = 0xffffffffu;
+    w0 = w1 = w2 = w3 = w4 = w5 = w6 = w7 = 0xffffffffu;
   }
+  // L must be the same in every lane
   __device__ __forceinline__ void set(int L, uint16_t v) {
-    const int sh = (L & 1) * 16;
-#pragma unroll
-    for (int i = 0; i < HT_MAX_LAYERS / 2; ++i)
-      if (i == (L >> 1)) w[i] = (w[i] & ~(0xffffu << sh)) | ((uint32_t)v << sh);
-  }
-  __device__ __forceinline__ int get(int L) const {
-    uint32_t x = w[0];
-#pragma unroll
-    for (int i = 1; i < HT_MAX_LAYERS / 2; ++i)
-      if (i == (L >> 1)) x = w[i];
-    return (int)((x >> ((L & 1) * 16)) & 0xffffu);
-  }
-  // lane win's entry for layer L (called by every lane)
-  __device__ __forceinline__ int of_lane(int win, int L) const {
-    uint32_t x = 0;
-#pragma unroll
-    for (int i = 0; i < HT_MAX_LAYERS / 2; ++i) {
-      const uint32_t y = (uint32_t)__builtin_amdgcn_readlane((int)w[i], win);
-      if (i == ((L >> 1) & (HT_MAX_LAYERS / 2 - 1))) x = y;
+    const int Lu = __builtin_amdgcn_readfirstlane(L);
+    const uint32_t sh = (uint32_t)(Lu & 1) * 16u;
+    const uint32_t keep = ~(0xffffu << sh);
+    const uint32_t val = (uint32_t)v << sh;
+    switch (Lu >> 1) {
+      case 0: w0 = (w0 & keep) | val; break;
+      case 1: w1 = (w1 & keep) | val; break;
+      case 2: w2 = (w2 & keep) | val; break;
+      case 3: w3 = (w3 & keep) | val; break;
+      case 4: w4 = (w4 & keep) | val; break;
+      case 5: w5 = (w5 & keep) | val; break;
+      case 6: w6 = (w6 & keep) | val; break;
+      default: w7 = (w7 & keep) | val; break;
     }
+  }
+  // L must be the same in every lane
+  __device__ __forceinline__ int get(int L) const {
+    const int Lu = __builtin_amdgcn_readfirstlane(L);
+    uint32_t x;
+    switch (Lu >> 1) {
+      case 0: x = w0; break;
+      case 1: x = w1; break;
+      case 2: x = w2; break;
+      case 3: x = w3; break;
+      case 4: x = w4; break;
+      case 5: x = w5; break;
+      case 6: x = w6; break;
+      default: x = w7; break;
+    }
+    return (int)((x >> ((Lu & 1) * 16)) & 0xffffu);
+  }
+  // lane win's entry for layer L (L may differ between lanes; every lane calls it)
+  __device__ __forceinline__ int of_lane(int win, int L) const {
+    const int i = (L >> 1) & 7;
+    uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)w0, win);
+    x = i == 1 ? (uint32_t)__builtin_amdgcn_readlane((int)w1, win) : x;
+    x = i == 2 ? (uint32_t)__builtin_amdgcn_readlane((int)w2, win) : x;
+    x = i == 3 ? (uint32_t)__builtin_amdgcn_readlane((int)w3, win) : x;
+    x = i == 4 ? (uint32_t)__builtin_amdgcn_readlane((int)w4, win) : x;
+    x = i == 5 ? (uint32_t)__builtin_amdgcn_readlane((int)w5, win) : x;
+    x = i == 6 ? (uint32_t)__builtin_amdgcn_readlane((int)w6, win) : x;
+    x = i == 7 ? (uint32_t)__builtin_amdgcn_readlane((int)w7, win) : x;
     return (int)((x >> ((L & 1) * 16)) & 0xffffu);
   }
 };
