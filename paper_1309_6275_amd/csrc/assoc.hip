@@ -1271,11 +1271,12 @@ struct WaveMem {
 template <int CAP>
 struct RefineShape {
   static constexpr int kWaves = CAP <= 128 ? 4 : (CAP <= 256 ? 2 : 1);
-  // workgroups per CU the register budget is set for: six waves per SIMD
-  // for caps up to 128 (the LDS of six workgroups fits); two one-wave
-  // workgroups per SIMD at cap 1024 (at most 256 registers, so that the six
-  // workgroups the LDS allows can all be resident); else left to the compiler
-  static constexpr int kMinBlocks = CAP <= 128 ? 6 : (CAP >= 1024 ? 8 : 1);
+  // waves per SIMD the register budget is set for (the second launch bound
+  // of HIP): six for caps up to 128 (80 registers; the LDS of six
+  // workgroups fits); two at cap 1024 (at most 256 registers, so that the
+  // eight one-wave workgroups the LDS allows can all be resident); else left
+  // to the compiler
+  static constexpr int kMinWavesPerSimd = CAP <= 128 ? 6 : (CAP >= 1024 ? 2 : 1);
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -1362,7 +1363,7 @@ __device__ __forceinline__ int nth_set_bit(unsigned mask, int n) {
 }
 
 template <int CAP, int NB>
-__global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave, RefineShape<CAP>::kMinBlocks) void
+__global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave, RefineShape<CAP>::kMinWavesPerSimd) void
 refine_kernel(AssocBatch<NB> AB) {
   const AssocArgs& A = event_args(AB);
   constexpr int W = RefineShape<CAP>::kWaves;
