@@ -266,7 +266,7 @@ struct AssocArgs {
   double* hx;
   double* hy;
   double* hq;
-  float4* hitB;  // x, y, x^2+y^2 (float32), layer
+  float4* hitB;  // x, y (float32), the input radius and azimuth
   // the point-vote accumulator of these hits, or null (no member-count bound)
   const int32_t* acc;
   // peaks
@@ -279,7 +279,8 @@ struct AssocArgs {
   uint32_t* pbits;
   int32_t* col_first;
   int32_t* mcount;
-  uint2* pool;   // member_cap slots per candidate: hit, |x - cell centre| bits
+  // member_cap slots per candidate: hit | layer << 16, |x - cell centre| bits
+  uint2* pool;
   int32_t* cstat;
   int32_t* cnl;
   double* cgeo;
@@ -302,7 +303,7 @@ struct AssocArgs {
   int32_t* bkt;        // hits per (class, bucket)
   int32_t* bkt_off;    // bucket starts
   int32_t* hkey;       // each hit's bucket key | slot << 14, or -1
-  int32_t* shit;       // hits in bucket order
+  int32_t* shit;       // hits in bucket order (hit | layer << 16)
   float* sphi;         // their azimuths
   // outputs
   ht_cluster_out out;
@@ -321,6 +322,11 @@ static_assert(sizeof(AssocBatch<kMaxBatch>) <= 4096, "a batch's arguments fit th
 template <int NB>
 __device__ __forceinline__ const AssocArgs& event_args(const AssocBatch<NB>& B) {
   return B.a[NB == 1 ? 0 : blockIdx.z];
+}
+
+// first word of a member entry: the hit (< 65536) and its layer (< 16)
+__device__ __forceinline__ unsigned member_word(const AssocArgs& A, int h) {
+  return (unsigned)h | ((unsigned)A.layer[h] << 16);
 }
 
 __device__ __forceinline__ int n_cands(const AssocArgs& A) { return A.sc[S_NP]; }
@@ -357,7 +363,7 @@ __global__ void init_kernel(AssocBatch<NB> AB, int words) {
     A.hx[h] = x;
     A.hy[h] = y;
     A.hq[h] = q;
-    A.hitB[h] = make_float4((float)x, (float)y, (float)q, (float)A.layer[h]);
+    A.hitB[h] = make_float4((float)x, (float)y, r, ph);
     A.owner_key[h] = 0ull;
     A.out.hit_owner[h] = -1;
   }
@@ -536,7 +542,7 @@ __global__ __launch_bounds__(256) void bscatter_kernel(AssocBatch<NB> AB) {
     const int key = A.hkey[h];
     if (key < 0) continue;
     const int e = A.bkt_off[key & (kBucketKeys - 1)] + (key >> 14);
-    A.shit[e] = h;
+    A.shit[e] = h | ((int)A.layer[h] << 16);  // a member entry's first word
     A.sphi[e] = A.phi[h];
   }
 }
@@ -1023,7 +1029,8 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocBatch<NB> AB
   if (lds_cnt) {
     sweep_members(A, S, k, j0, h0, h1, [&](int q, int hh, float adx) {
       const int slot = atomicAdd(&S.cnt[q], 1);
-      if (slot < cap) pool[(size_t)q * cap + slot] = make_uint2((unsigned)hh, __float_as_uint(adx));
+      if (slot < cap)
+        pool[(size_t)q * cap + slot] = make_uint2(member_word(A, hh), __float_as_uint(adx));
       return slot == cap;
     });
     __syncthreads();
@@ -1034,7 +1041,8 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocBatch<NB> AB
     int32_t* cnt = A.mcount + p_lo;
     sweep_members(A, S, k, j0, h0, h1, [&](int q, int hh, float adx) {
       const int slot = atomicAdd(&cnt[q], 1);
-      if (slot < cap) pool[(size_t)q * cap + slot] = make_uint2((unsigned)hh, __float_as_uint(adx));
+      if (slot < cap)
+        pool[(size_t)q * cap + slot] = make_uint2(member_word(A, hh), __float_as_uint(adx));
       return slot >= cap;
     });
   }
@@ -1421,9 +1429,9 @@ refine_kernel(AssocBatch<NB> AB) {
       // load members in pool order
       for (int m = lane; m < n; m += kWave) {
         const uint2 pe = A.pool[moff + m];
-        const int h = (int)pe.x;
+        const int h = (int)(pe.x & 0xffffu);
+        const int L = (int)(pe.x >> 16);
         const float4 hb = A.hitB[h];
-        const int L = (int)hb.w;
         Mem4 r4;
         r4.x = hb.x;
         r4.y = hb.y;
@@ -1432,7 +1440,7 @@ refine_kernel(AssocBatch<NB> AB) {
         M.u.raw.mem[m] = r4;
         M.u.raw.L[m] = (int8_t)L;
         lmask |= 1u << L;
-        qmax = fmaxf(qmax, hb.z);
+        qmax = fmaxf(qmax, mem_q(r4));
       }
     } else {
       // the layers' radius and azimuth ranges start empty; the group counts at 0
@@ -1447,39 +1455,31 @@ refine_kernel(AssocBatch<NB> AB) {
       }
       wave_sync();
       // load members in pool order into registers: member lane + 64 t is
-      // entry t of the lane (n <= cap <= CAP)
+      // entry t of the lane (n <= cap <= CAP); each member's radius and
+      // azimuth (the hit's inputs) widen its layer's ranges
 #pragma unroll
       for (int t = 0; t < RM; ++t) {
         const int m = lane + t * kWave;
         rL[t] = -1;
         if (m < n) {
           const uint2 pe = A.pool[moff + m];
-          const int h = (int)pe.x;
+          const int h = (int)(pe.x & 0xffffu);
+          const int L = (int)(pe.x >> 16);
           const float4 hb = A.hitB[h];
-          const int L = (int)hb.w;
           rec[t].x = hb.x;
           rec[t].y = hb.y;
           rec[t].adx = __uint_as_float(pe.y);
           rec[t].h = h;
           rL[t] = L;
           lmask |= 1u << L;
-          qmax = fmaxf(qmax, hb.z);
+          qmax = fmaxf(qmax, mem_q(rec[t]));
+          const float rel = rel_angle(hb.w, ref);
+          reinterpret_cast<float*>(M.mem)[m] = rel;
+          atomicMin(&M.u.st.rlo[L], __float_as_int(hb.z));
+          atomicMax(&M.u.st.rhi[L], __float_as_int(hb.z));
+          atomicMin(&M.u.st.alo[L], ord_bits(rel));
+          atomicMax(&M.u.st.ahi[L], ord_bits(rel));
         }
-      }
-      // each member's radius and azimuth (the hit's inputs) widen its
-      // layer's ranges (a loop of its own: the loads of these two inputs
-      // need not be in flight with the member records)
-#pragma unroll
-      for (int t = 0; t < RM; ++t) {
-        if (rL[t] < 0) continue;
-        const int h = rec[t].h, L = rL[t];
-        const float hr = A.r[h];
-        const float rel = rel_angle(A.phi[h], ref);
-        reinterpret_cast<float*>(M.mem)[lane + t * kWave] = rel;
-        atomicMin(&M.u.st.rlo[L], __float_as_int(hr));
-        atomicMax(&M.u.st.rhi[L], __float_as_int(hr));
-        atomicMin(&M.u.st.alo[L], ord_bits(rel));
-        atomicMax(&M.u.st.ahi[L], ord_bits(rel));
       }
     }
     lmask = wave_or(lmask);

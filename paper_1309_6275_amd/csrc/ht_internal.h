@@ -67,7 +67,7 @@ struct Plan {
   double* d_hx;          // [max_hits] hit x, y, x^2+y^2
   double* d_hy;
   double* d_hq;
-  float4* d_hitB;        // [max_hits] x, y, x^2+y^2 (float32), layer
+  float4* d_hitB;        // [max_hits] x, y (float32), the input radius and azimuth
   int32_t* d_mcount;     // [max_peaks] member counts
   uint2* d_mem;          // member pool: (hit, |x - cell centre| bits), member_cap slots per candidate
   int32_t* d_cstat;      // [max_peaks] candidate status / inlier count
@@ -92,7 +92,7 @@ struct Plan {
   int32_t* d_bkt;       // [kBucketKeys] hits per (class, bucket)
   int32_t* d_bkt_off;   // [kBucketKeys + 1] bucket starts; the bucketed hit count last
   int32_t* d_hkey;      // [max_hits] bucket key | slot << 14 of each hit, -1 if none
-  int32_t* d_shit;      // [max_hits] hits in bucket order
+  int32_t* d_shit;      // [max_hits] hits in bucket order (hit | layer << 16)
   float* d_sphi;        // [max_hits] their azimuths
   // stage timing (ht_profile_*): HIP events recorded around the stages of
   // later calls; plan calls are ordered, so the counters need no locking
