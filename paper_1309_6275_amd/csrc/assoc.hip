@@ -293,9 +293,9 @@ struct AssocArgs {
   int32_t* arcn;
   int32_t* arci0;  // the same on the incoming branch (two-branch vote)
   int32_t* arcin;
+  double2* tunit;  // per track: (-C, B) / |(B, C)| of its seed circle
   int32_t* vacc;
   int32_t* obj_cnt;
-  const int32_t* obj_off;  // object member offsets (the scan of obj_cnt)
   int32_t* sc;  // device scalars
   unsigned long long* spread;  // [kSpreadWords] spread counters
   // member lists by candidate
@@ -1049,6 +1049,15 @@ __global__ __launch_bounds__(kSweepThreads) void member_kernel(AssocBatch<NB> AB
 }
 
 // ---- refine: one wave per candidate ------------------------------------------
+// Ownership key of a refined candidate's inlier hits: most inlier layers,
+// then the smallest float32 seed sum of squared distances, then the lowest
+// candidate index; each hit keeps the largest key offered to it.
+__device__ __forceinline__ unsigned long long own_key(int n_in, double ss, int p) {
+  const uint32_t sb = __float_as_uint((float)ss);
+  return ((unsigned long long)n_in << 58) | ((unsigned long long)(0xffffffffu - sb) << 26) |
+         (unsigned long long)(0x3ffffff - p);
+}
+
 // Members are grouped by layer in LDS as (x, y, x^2+y^2) in float32 plus the
 // hit index, one 16-byte record each, for a conservative float32 pre-filter;
 // the float64 coordinates of the seeds and of the few members that pass are
@@ -1884,8 +1893,11 @@ refine_kernel(AssocBatch<NB> AB) {
       whh = hitL.of_lane(win, lane);
     else
       whh = lane < HT_MAX_LAYERS ? (int)M.u.hit[win][lane] : 0;
-    if (lane < HT_MAX_LAYERS)
+    if (lane < HT_MAX_LAYERS) {
       A.chit[(size_t)p * HT_MAX_LAYERS + lane] = whh == kNoHit ? -1 : whh;
+      if (whh != kNoHit)
+        atomicMax(&A.owner_key[whh], own_key(best_n, __longlong_as_double((long long)best_ss), p));
+    }
     wave_sync();
   }
   // the workgroup's totals, one atomic per counter from lanes 0-4 of wave 0
@@ -1907,27 +1919,7 @@ refine_kernel(AssocBatch<NB> AB) {
 }
 
 // ---- ownership -----------------------------------------------------------------
-__device__ __forceinline__ unsigned long long own_key(int n_in, double ss, int p) {
-  const uint32_t sb = __float_as_uint((float)ss);
-  return ((unsigned long long)n_in << 58) | ((unsigned long long)(0xffffffffu - sb) << 26) |
-         (unsigned long long)(0x3ffffff - p);
-}
-
-template <int NB>
-__global__ void own_kernel(AssocBatch<NB> AB) {
-  const AssocArgs& A = event_args(AB);
-  const int np = n_cands(A);
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
-    const int st = A.cstat[p];
-    if (st < 0) continue;
-    const unsigned long long key = own_key(st, A.cgeo[(size_t)p * 5], p);
-    for (int L = 0; L < HT_MAX_LAYERS; ++L) {
-      const int h = A.chit[(size_t)p * HT_MAX_LAYERS + L];
-      if (h >= 0) atomicMax(&A.owner_key[h], key);
-    }
-  }
-}
-
+// (the seed search offers each inlier hit its candidate's key, own_key)
 __device__ __forceinline__ int owned_count(const AssocArgs& A, int p) {
   int own = 0;
   for (int L = 0; L < HT_MAX_LAYERS; ++L) {
@@ -2026,13 +2018,11 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // lane solves the same (at most 3x3) system by Cholesky.  Fixed parameters
 // (one bin in q/pT or d0) get a zero Jacobian column and a unit diagonal, so
 // their step is exactly zero.
-template <int NB>
-__global__ __launch_bounds__(256) void fit_kernel(AssocBatch<NB> AB) {
-  const AssocArgs& A = event_args(AB);
+__device__ void fit_tracks(const AssocArgs& A, int bid, int nblk) {
   const int lane = threadIdx.x & 63;
   const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
   const bool fk = A.n_qpt > 1, fd = A.n_d0 > 1;
-  for (int t = blockIdx.x * 4 + (threadIdx.x >> 6); t < ntrk; t += gridDim.x * 4) {
+  for (int t = bid * 4 + (threadIdx.x >> 6); t < ntrk; t += nblk * 4) {
     ht_track& tr = A.out.tracks[t];
     const int p = A.trk_peak[t];
     const double* g = A.cgeo + (size_t)p * 5;
@@ -2260,15 +2250,13 @@ __device__ __forceinline__ void branch_arc(double cA, double cB, double cC, doub
 // the two-branch vote, the incoming arc (perigee radius to the row's top).
 // (A thread per track walked its rows in sequence, a chain of float64
 // square roots and arctangents per row on only as many threads as tracks.)
-template <int NB>
-__global__ __launch_bounds__(256) void vvote_kernel(AssocBatch<NB> AB) {
-  const AssocArgs& A = event_args(AB);
+__device__ void vote_rows(const AssocArgs& A, int bid, int nblk) {
   const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
   const int nm = A.cfg.n_rho, nt = A.cfg.n_theta;
   const double rw = ((double)A.cfg.rho_hi - (double)A.cfg.rho_lo) / (double)nm;
   const int64_t work = (int64_t)ntrk * nm;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < work;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = (int64_t)bid * blockDim.x + threadIdx.x; e < work;
+       e += (int64_t)nblk * blockDim.x) {
     const int t = (int)(e / nm), m = (int)(e - (int64_t)t * nm);
     const int p = A.trk_peak[t];
     const double* g = A.cgeo + (size_t)p * 5;
@@ -2300,11 +2288,30 @@ __global__ __launch_bounds__(256) void vvote_kernel(AssocBatch<NB> AB) {
         if (off >= len) atomicAdd(&A.vacc[m * nt + c], 1);
       }
     }
+    if (m == 0) A.tunit[t] = make_double2(-cC / sn, cB / sn);
     A.arc0[(size_t)t * nm + m] = start;
     A.arcn[(size_t)t * nm + m] = len;
     A.arci0[(size_t)t * nm + m] = istart;
     A.arcin[(size_t)t * nm + m] = ilen;
   }
+}
+
+// the vertex votes after the Kalman filter (kf_kernel)
+template <int NB>
+__global__ __launch_bounds__(256) void vvote_kernel(AssocBatch<NB> AB) {
+  vote_rows(event_args(AB), blockIdx.x, gridDim.x);
+}
+
+// the refit (workgroups below fit_blocks) and the vertex votes (the rest) in
+// one launch: the votes read the tracks' seed circles and first radii, which
+// the refit does not change
+template <int NB>
+__global__ __launch_bounds__(256) void fit_vote_kernel(AssocBatch<NB> AB, int fit_blocks) {
+  const AssocArgs& A = event_args(AB);
+  if ((int)blockIdx.x < fit_blocks)
+    fit_tracks(A, blockIdx.x, fit_blocks);
+  else
+    vote_rows(A, blockIdx.x - fit_blocks, gridDim.x - fit_blocks);
 }
 
 // vertex peaks in cell order, by one workgroup: thread t tests a run of
@@ -2386,79 +2393,98 @@ __global__ __launch_bounds__(kVThreads) void vpeaks_kernel(AssocBatch<NB> AB, in
 }
 
 // a track is a member of the object at (m, ti) when one of its arcs (either
-// branch) in rows m - 1 .. m + 1, widened by one bin each side, holds ti
+// branch) in rows m - 1 .. m + 1, widened by one bin each side, holds ti.
+// t < the track count; the twelve loads do not depend on each other.
 __device__ __forceinline__ bool is_member(const AssocArgs& A, int t, int m, int ti) {
   const int nm = A.cfg.n_rho, nt = A.cfg.n_theta;
+  bool in = false;
+#pragma unroll
   for (int dm = -1; dm <= 1; ++dm) {
     const int mm = m + dm;
-    if (mm < 0 || mm >= nm) continue;
-    for (int br = 0; br < 2; ++br) {
-      const size_t a = (size_t)t * nm + mm;
-      const int len = br ? A.arcin[a] : A.arcn[a];
-      if (len == 0) continue;
-      const int st = br ? A.arci0[a] : A.arc0[a];
-      int off = (ti - st + 1) % nt;
-      if (off < 0) off += nt;
-      if (off < len + 2) return true;
-    }
+    const bool row = mm >= 0 && mm < nm;
+    const size_t a = (size_t)t * nm + (row ? mm : m);
+    const int len = A.arcn[a], st = A.arc0[a], ilen = A.arcin[a], ist = A.arci0[a];
+    int off = (ti - st + 1) % nt;
+    if (off < 0) off += nt;
+    int ioff = (ti - ist + 1) % nt;
+    if (ioff < 0) ioff += nt;
+    in = in || (row && ((len > 0 && off < len + 2) || (ilen > 0 && ioff < ilen + 2)));
   }
-  return false;
+  return in;
 }
 
-// pass 1: member count per object (one wave per object)
+// pass 1: member count per object, one wave per (object, 64 tracks)
 template <int NB>
 __global__ __launch_bounds__(256) void vcount_kernel(AssocBatch<NB> AB) {
   const AssocArgs& A = event_args(AB);
   const int nobj = min(A.sc[S_NOBJ], A.out.object_cap);
   const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
+  const int nch = (ntrk + kWave - 1) / kWave;
+  const int64_t pairs = (int64_t)nobj * nch;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int o = blockIdx.x * 4 + wave; o < nobj; o += gridDim.x * 4) {
+  for (int64_t q = (int64_t)blockIdx.x * 4 + wave; q < pairs; q += (int64_t)gridDim.x * 4) {
+    const int o = (int)(q / nch), ch = (int)(q - (int64_t)o * nch);
     const int c = A.out.objects[o].lin;
     const int m = c / A.cfg.n_theta, ti = c % A.cfg.n_theta;
-    int cnt = 0;
-    for (int t0 = 0; t0 < ntrk; t0 += 64) {
-      const int t = t0 + lane;
-      cnt += __popcll(__ballot(t < ntrk && is_member(A, t, m, ti)));
-    }
-    if (lane == 0) A.obj_cnt[o] = cnt;
+    const int t = ch * kWave + lane;
+    const int cnt = __popcll(__ballot(is_member(A, min(t, ntrk - 1), m, ti) && t < ntrk));
+    if (lane == 0 && cnt) atomicAdd(&A.obj_cnt[o], cnt);
   }
 }
 
-// pass 2: members in track order, isotropy summed sequentially in that order
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// pass 2: members in track order and the isotropy, one wave per object.  An
+// object's members start after those of the objects before it (the wave sums
+// their counts).  The tracks are tested kVGroup chunks of 64 at a time (their
+// loads in flight together); the direction sums then take the members one by
+// one in track order from the lanes' registers, the order that defines them.
+constexpr int kVGroup = 4;
 template <int NB>
 __global__ __launch_bounds__(256) void vmembers_kernel(AssocBatch<NB> AB) {
   const AssocArgs& A = event_args(AB);
   const int nobj = min(A.sc[S_NOBJ], A.out.object_cap);
   const int ntrk = min(A.sc[S_NTRK], A.out.track_cap);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t below = lane ? ((1ull << lane) - 1ull) : 0ull;
   for (int o = blockIdx.x * 4 + wave; o < nobj; o += gridDim.x * 4) {
     ht_object& ob = A.out.objects[o];
     const int c = ob.lin;
     const int m = c / A.cfg.n_theta, ti = c % A.cfg.n_theta;
-    const int begin = A.obj_off[o];
+    int begin = 0;
+    for (int q = lane; q < o; q += kWave) begin += A.obj_cnt[q];
+    for (int off = kWave / 2; off > 0; off >>= 1) begin += __shfl_xor(begin, off);
     int cnt = 0;
     double sx = 0.0, sy = 0.0;
-    for (int t0 = 0; t0 < ntrk; t0 += 64) {
-      const int t = t0 + lane;
-      const bool mem = t < ntrk && is_member(A, t, m, ti);
-      const uint64_t msk = __ballot(mem);
-      if (mem) {
-        const uint64_t lower = lane ? (msk & ((1ull << lane) - 1ull)) : 0ull;
-        const int idx = begin + cnt + __popcll(lower);
-        if (idx < A.out.member_cap) A.out.members[idx] = t;
+    for (int t0 = 0; t0 < ntrk; t0 += kVGroup * kWave) {
+      bool mem[kVGroup];
+      double2 u[kVGroup];
+#pragma unroll
+      for (int g = 0; g < kVGroup; ++g) {
+        const int t = t0 + g * kWave + lane;
+        const int tl = min(t, ntrk - 1);
+        mem[g] = is_member(A, tl, m, ti) && t < ntrk;
+        u[g] = A.tunit[tl];
       }
-      if (lane == 0) {
-        uint64_t b = msk;
-        while (b) {
-          const int l = __builtin_ctzll(b);
-          b &= b - 1;
-          const double* g = A.cgeo + (size_t)A.trk_peak[t0 + l] * 5;
-          const double sn = sqrt(g[2] * g[2] + g[3] * g[3]);
-          sx += -g[3] / sn;
-          sy += g[2] / sn;
+#pragma unroll
+      for (int g = 0; g < kVGroup; ++g) {
+        const uint64_t msk = __ballot(mem[g]);
+        if (mem[g]) {
+          const int idx = begin + cnt + __popcll(msk & below);
+          if (idx < A.out.member_cap) A.out.members[idx] = t0 + g * kWave + lane;
         }
+        for (uint64_t b = msk; b; b &= b - 1) {
+          const int l = __builtin_ctzll(b);
+          sx += readlane_d(u[g].x, l);
+          sy += readlane_d(u[g].y, l);
+        }
+        cnt += __popcll(msk);
       }
-      cnt += __popcll(msk);
     }
     if (lane == 0) {
       const double R = cnt > 0 ? sqrt(sx * sx + sy * sy) / (double)cnt : 0.0;
@@ -2466,11 +2492,12 @@ __global__ __launch_bounds__(256) void vmembers_kernel(AssocBatch<NB> AB) {
       ob.member_begin = begin;
       ob.isotropy = (float)R;
       ob.kind = (cnt >= A.cfg.bh_min_tracks && R <= (double)A.cfg.bh_max_isotropy) ? 1 : 0;
+      if (o == nobj - 1) A.sc[S_NMEM] = begin + cnt;
     }
   }
 }
 
-// one wave: lane i reads spread slot i of both counters
+// one wave: lane i reads spread slot i of each counter
 template <int NB>
 __global__ __launch_bounds__(kWave) void counts_kernel(AssocBatch<NB> AB) {
   const AssocArgs& A = event_args(AB);
@@ -2503,6 +2530,7 @@ __global__ __launch_bounds__(kWave) void counts_kernel(AssocBatch<NB> AB) {
   c[6] = tests > 0x7fffffffull ? 0x7fffffff : (int32_t)tests;
   c[7] = 0;
 }
+
 
 
 int blocks_for(int64_t n, int per) {
@@ -2576,9 +2604,9 @@ AssocArgs make_args(const Plan& P, const float* r, const float* phi, const uint8
   A.arcn = P.d_arcn;
   A.arci0 = P.d_arci0;
   A.arcin = P.d_arcin;
+  A.tunit = P.d_tunit;
   A.vacc = out.vacc ? out.vacc : P.d_vacc;
   A.obj_cnt = P.d_obj_cnt;
-  A.obj_off = P.d_obj_off;
   A.sc = P.d_scalars;
   A.spread = P.d_spread;
   A.cls = P.d_cls;
@@ -2649,8 +2677,6 @@ int assoc_sequence(const AssocBatch<NB>& AB, const Plan* const* P, int32_t n_hit
     launch_refine<kMaxMembers, NB>(AB, peak_cap, s);
   HT_CHECK(hipGetLastError());
   P0.prof_mark(HT_STAGE_REFINE, 1, s);
-  own_kernel<NB><<<dim3(blocks_for(peak_cap, 256), 1, NB), 256, 0, s>>>(AB);
-  HT_CHECK(hipGetLastError());
   const int tiles = (peak_cap + 255) / 256 > 0 ? (peak_cap + 255) / 256 : 1;
   surv_count_kernel<NB><<<dim3(blocks_for(tiles, 1), 1, NB), 256, 0, s>>>(AB, tiles);
   HT_CHECK(hipGetLastError());
@@ -2662,19 +2688,22 @@ int assoc_sequence(const AssocBatch<NB>& AB, const Plan* const* P, int32_t n_hit
     off[b] = P[b]->d_ctile_off;
     tot[b] = P[b]->d_scalars + S_NTRK;
   }
-  int rc = NB == 1 ? launch_scan(cnt[0], off[0], tiles, tot[0], s)
-                   : launch_scan_batch(NB, cnt, off, tiles, tot, s);
+  const int rc = NB == 1 ? launch_scan(cnt[0], off[0], tiles, tot[0], s)
+                         : launch_scan_batch(NB, cnt, off, tiles, tot, s);
   if (rc != HT_OK) return rc;
   surv_emit_kernel<NB><<<dim3(blocks_for(tiles, 1), 1, NB), 256, 0, s>>>(AB, tiles);
   HT_CHECK(hipGetLastError());
   const int tcap = out.track_cap > 0 ? out.track_cap : 1;
   if (out.track_cap > 0) {
-    if (cfg.fit_kind == 1)
+    const int vblocks = blocks_for((int64_t)tcap * cfg.n_rho, 256);
+    if (cfg.fit_kind == 1) {
       kf_kernel<NB><<<dim3(blocks_for(tcap, 64), 1, NB), 64, 0, s>>>(AB);
-    else
-      fit_kernel<NB><<<dim3(blocks_for(tcap, 4), 1, NB), 256, 0, s>>>(AB);
-    HT_CHECK(hipGetLastError());
-    vvote_kernel<NB><<<dim3(blocks_for((int64_t)tcap * cfg.n_rho, 256), 1, NB), 256, 0, s>>>(AB);
+      HT_CHECK(hipGetLastError());
+      vvote_kernel<NB><<<dim3(vblocks, 1, NB), 256, 0, s>>>(AB);
+    } else {
+      const int fblocks = blocks_for(tcap, 4);
+      fit_vote_kernel<NB><<<dim3(fblocks + vblocks, 1, NB), 256, 0, s>>>(AB, fblocks);
+    }
     HT_CHECK(hipGetLastError());
   }
   const int ocap = out.object_cap > 0 ? out.object_cap : 1;
@@ -2682,19 +2711,10 @@ int assoc_sequence(const AssocBatch<NB>& AB, const Plan* const* P, int32_t n_hit
   vpeaks_kernel<NB><<<dim3(1, 1, NB), 1024, 0, s>>>(AB, ozero);
   HT_CHECK(hipGetLastError());
   if (out.object_cap > 0) {
-    vcount_kernel<NB><<<dim3(blocks_for(ocap, 4), 1, NB), 256, 0, s>>>(AB);
+    vcount_kernel<NB><<<dim3(blocks_for((int64_t)ocap * ((tcap + kWave - 1) / kWave), 4), 1, NB),
+                        256, 0, s>>>(AB);
     HT_CHECK(hipGetLastError());
   }
-  // object member offsets, then members and isotropy
-  const int oscan = ocap < P0.lim.max_vertex_cells ? ocap : P0.lim.max_vertex_cells;
-  for (int b = 0; b < NB; ++b) {
-    cnt[b] = P[b]->d_obj_cnt;
-    off[b] = P[b]->d_obj_off;
-    tot[b] = P[b]->d_scalars + S_NMEM;
-  }
-  rc = NB == 1 ? launch_scan(cnt[0], off[0], oscan > 0 ? oscan : 1, tot[0], s)
-               : launch_scan_batch(NB, cnt, off, oscan > 0 ? oscan : 1, tot, s);
-  if (rc != HT_OK) return rc;
   if (out.object_cap > 0) {
     vmembers_kernel<NB><<<dim3(blocks_for(ocap, 4), 1, NB), 256, 0, s>>>(AB);
     HT_CHECK(hipGetLastError());

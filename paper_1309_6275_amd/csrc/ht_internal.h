@@ -82,9 +82,9 @@ struct Plan {
   int32_t* d_arcn;       // [max_tracks * max_n_rho] vertex arc length per row
   int32_t* d_arci0;      // the same on the incoming branch (two-branch vote)
   int32_t* d_arcin;
+  double2* d_tunit;      // [max_tracks] (-C, B) / |(B, C)| of each track's seed circle (isotropy)
   int32_t* d_vacc;       // [max_vertex_cells] vertex accumulator
   int32_t* d_obj_cnt;    // [max_vertex_cells] member count per object
-  int32_t* d_obj_off;    // [max_vertex_cells] member offset per object
   int32_t* d_scalars;    // [16] device counters
   unsigned long long* d_spread;  // [kSpreadWords] counters spread over 128-byte lines
   // member lists by candidate
