@@ -731,7 +731,9 @@ def measure(args, workload, B, steps, warmup, cpu_events, concurrent):
         # candidates over member_cap, (candidate, member) pairs within it
         "assoc_counts": {"refined": float(np.mean([c[0] for c in cnts])),
                          "over_member_cap": float(np.mean([c[4] for c in cnts])),
-                         "member_pairs": float(np.mean([c[5] for c in cnts]))},
+                         "member_pairs": float(np.mean([c[5] for c in cnts])),
+                         "objects": float(np.mean([c[2] for c in cnts])),
+                         "object_members": float(np.mean([c[3] for c in cnts]))},
         "vote_kernel_votes_per_s": float(np.mean(votes)) / (avg_ms["vote"] / 1e3),
         "stage_ms": {k: avg_ms[k] for k in ("vote", "peaks", "members", "refine", "assoc")},
         "roofline": rl[dominant],

@@ -66,7 +66,7 @@ void free_plan(Plan* p) {
                   p->d_hq,        p->d_hitB,      p->d_mcount,    p->d_mem,      p->d_cstat,
                   p->d_cgeo,      p->d_chit,      p->d_cnl,      p->d_owner_key, p->d_ctile_cnt,
                   p->d_ctile_off, p->d_trk_peak,  p->d_arc0,     p->d_arcn,     p->d_arci0,    p->d_arcin,      p->d_tunit,      p->d_vacc,
-                  p->d_obj_cnt,   p->d_scalars,  p->d_ckl,       p->d_ckh,
+                  p->d_obj_cnt,   p->d_vtile,     p->d_scalars,  p->d_ckl,       p->d_ckh,
                   p->d_cql,       p->d_ctl,       p->d_cqh,      p->d_cth,      p->d_spread,
                   p->d_cls,       p->d_bkt,       p->d_bkt_off,  p->d_hkey,     p->d_shit,
                   p->d_sphi};
@@ -188,6 +188,7 @@ int ht_plan_create(const ht_grid* grid, const ht_limits* lim, ht_plan** out) {
   if (rc == HT_OK) rc = dalloc(p, &p->d_tunit, (size_t)lim->max_tracks);
   if (rc == HT_OK) rc = dalloc(p, &p->d_vacc, (size_t)lim->max_vertex_cells);
   if (rc == HT_OK) rc = dalloc(p, &p->d_obj_cnt, (size_t)lim->max_vertex_cells);
+  if (rc == HT_OK) rc = dalloc(p, &p->d_vtile, (size_t)lim->max_vertex_cells / 1024 + 1);
   if (rc == HT_OK) rc = dalloc(p, &p->d_scalars, 16);
   if (rc == HT_OK) rc = dalloc(p, &p->d_spread, ht::kSpreadWords);
   if (rc == HT_OK) rc = dalloc(p, &p->d_cls, (size_t)ht::kClsSlots);

@@ -5,36 +5,35 @@
 //
 // Launch sequence (all on the caller's stream, no host synchronisation; the
 // device peak count bounds every per-candidate loop):
-//   prep      per hit: float64 Cartesian coordinates (canonical sincos),
-//             ownership keys cleared; counters and the vertex accumulator
-//             zeroed;
+//   prep      per hit: float64 Cartesian coordinates (canonical sincos) and
+//             a float32 record; ownership keys cleared; counters and the
+//             vertex accumulator zeroed;
 //   mark      peak bitmap and the first peak index of every column (and,
 //             with an accumulator, the count of hits beyond the layer
 //             range);
-//   members   a sweep shaped like the vote (workgroup = 64 columns of one
-//             d0, lane = column, hits broadcast through SGPRs; grids with
-//             few tiles also split the hits) that re-evaluates each hit's
-//             phi0 coordinate, from per-radius tables where the hit's radius
-//             is shared, and appends it to every peak of the column whose
-//             member window holds it; candidates past member_cap, or proved
-//             past it by the accumulator, leave the sweep;
+//   members   by candidate: the hits grouped by (radius class, azimuth
+//             bucket) with a counting sort (cls, bcount, scan, bscatter),
+//             then one wave per candidate tests the hits of the buckets its
+//             member window reaches for each class (mcand); events with
+//             more distinct radii than the classes hold use a sweep shaped
+//             like the vote instead (member_kernel);
 //   refine    one wave per candidate: member layers, seed layers, the
 //             seed_k nearest members of each seed layer by rank, then one
 //             seed combination per lane (<= 64) scored against the members
 //             in LDS, smallest non-seed layers first; the best lane wins by
-//             (inliers, sum, index); totals go to spread counters;
-//   own       per candidate, 64-bit atomicMax of (inliers, -sum, -index) on
-//             each inlier hit;
+//             (inliers, sum, index) and offers each inlier hit its 64-bit
+//             ownership key (atomicMax); totals go to spread counters;
 //   survive   ordered compaction of the candidates owning >= min_layers
 //             hits into the track list (tile counts, scan, emit);
-//   fit       float64 Gauss-Newton, one wave per track (lanes = hits), or
-//             the Kalman filter, one thread per track;
-//   vvote     one thread per (track, vertex row): crossing arc, atomic votes
-//             into the vertex accumulator;
-//   vpeaks    one workgroup: vertex local maxima in cell order;
-//   vcount,   member counts per object, their scan, then one wave per
-//   vmembers  object: member tracks by ballot, written in order, isotropy
-//             summed in track order;
+//   fit+vvote one launch: float64 Gauss-Newton, one wave per track (lanes =
+//             hits), beside one thread per (track, vertex row) voting its
+//             crossing arcs into the vertex accumulator (the Kalman filter,
+//             one thread per track, runs as a launch of its own first);
+//   vpeaks    vertex local maxima in cell order: counts per 1024-cell tile,
+//             then each tile places its own (vpcount, vpemit);
+//   vcount,   member counts, one wave per (object, 64 tracks), then one
+//   vmembers  wave per object: member tracks by ballot, written in order,
+//             isotropy summed in track order;
 //   counts    the output counts (the spread counters summed).
 // Every decision that selects an integer result uses float32 vote
 // arithmetic or float64 arithmetic and square roots in a fixed order, so the
@@ -296,6 +295,7 @@ struct AssocArgs {
   double2* tunit;  // per track: (-C, B) / |(B, C)| of its seed circle
   int32_t* vacc;
   int32_t* obj_cnt;
+  int32_t* vtile;  // vertex peaks per 1024-cell tile
   int32_t* sc;  // device scalars
   unsigned long long* spread;  // [kSpreadWords] spread counters
   // member lists by candidate
@@ -2314,14 +2314,12 @@ __global__ __launch_bounds__(256) void fit_vote_kernel(AssocBatch<NB> AB, int fi
     vote_rows(A, blockIdx.x - fit_blocks, gridDim.x - fit_blocks);
 }
 
-// vertex peaks in cell order, by one workgroup: thread t tests a run of
-// consecutive cells (a vertex accumulator of up to kVLds cells is first read
-// into LDS, coalesced; larger ones are read from global memory), a scan of
-// the per-thread counts places each run's objects, and every thread writes
-// its own in cell order.  It also clears the first n_zero object member
-// counts (the input of the member-offset scan).
-constexpr int kVLds = 16384;
-constexpr int kVThreads = 1024;
+// Vertex peaks in cell order, in two launches over 1024-cell tiles (thread t
+// of a tile tests cells 4t .. 4t + 3): vpcount counts each tile's peaks (and
+// clears the first n_zero object member counts, the input of vcount), then
+// vpemit places each tile's peaks after those of the tiles before it (it sums
+// their counts) and writes them in cell order; the last tile writes the count.
+constexpr int kVTile = 1024;
 __device__ __forceinline__ bool vertex_peak(const int32_t* vv, int nm, int nt, int c, int thr) {
   const int m = c / nt, ti = c - m * nt;
   const int v = vv[c];
@@ -2341,55 +2339,75 @@ __device__ __forceinline__ bool vertex_peak(const int32_t* vv, int nm, int nt, i
   return true;
 }
 
+// the tile's peak flags of this thread's four cells, as bits
+__device__ __forceinline__ unsigned vertex_flags(const AssocArgs& A, int tile) {
+  const int nm = A.cfg.n_rho, nt = A.cfg.n_theta, ncell = nm * nt;
+  const int c0 = tile * kVTile + (int)threadIdx.x * 4;
+  unsigned f = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (c0 + u < ncell && vertex_peak(A.vacc, nm, nt, c0 + u, A.cfg.vtx_min_votes)) f |= 1u << u;
+  return f;
+}
+
 template <int NB>
-__global__ __launch_bounds__(kVThreads) void vpeaks_kernel(AssocBatch<NB> AB, int n_zero) {
+__global__ __launch_bounds__(256) void vpcount_kernel(AssocBatch<NB> AB, int n_zero) {
   const AssocArgs& A = event_args(AB);
-  __shared__ int32_t wsum[kVThreads / kWave];
-  __shared__ int32_t sv[kVLds];
-  const int nm = A.cfg.n_rho, nt = A.cfg.n_theta;
-  const int ncell = nm * nt;
-  const int thr = A.cfg.vtx_min_votes;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
-  const double rw = ((double)A.cfg.rho_hi - (double)A.cfg.rho_lo) / (double)nm;
-  const bool staged = ncell <= kVLds;
-  for (int c = threadIdx.x; c < n_zero; c += kVThreads) A.obj_cnt[c] = 0;
-  if (staged)
-    for (int c = threadIdx.x; c < ncell; c += kVThreads) sv[c] = A.vacc[c];
+  __shared__ int32_t wc[4];
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < n_zero; c += gridDim.x * 256) A.obj_cnt[c] = 0;
+  const int cnt = __popc(vertex_flags(A, blockIdx.x));
+  int x = cnt;
+  for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = x;
   __syncthreads();
-  const int32_t* vv = staged ? sv : A.vacc;
-  const int run = (ncell + kVThreads - 1) / kVThreads;
-  const int c0 = min(threadIdx.x * run, ncell), c1 = min(c0 + run, ncell);
-  int cnt = 0;
-  for (int c = c0; c < c1; ++c) cnt += vertex_peak(vv, nm, nt, c, thr) ? 1 : 0;
-  int x = cnt;  // inclusive scan over the wave, then over the 16 wave totals
+  if (threadIdx.x == 0) A.vtile[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void vpemit_kernel(AssocBatch<NB> AB) {
+  const AssocArgs& A = event_args(AB);
+  __shared__ int32_t wsum[4];
+  __shared__ int32_t base_s;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nm = A.cfg.n_rho, nt = A.cfg.n_theta;
+  const double rw = ((double)A.cfg.rho_hi - (double)A.cfg.rho_lo) / (double)nm;
+  if (wave == 0) {  // peaks of the tiles before this one
+    int b = 0;
+    for (int q = lane; q < (int)blockIdx.x; q += kWave) b += A.vtile[q];
+    for (int off = kWave / 2; off > 0; off >>= 1) b += __shfl_xor(b, off);
+    if (lane == 0) base_s = b;
+  }
+  const unsigned f = vertex_flags(A, blockIdx.x);
+  const int cnt = __popc(f);
+  int x = cnt;  // inclusive scan over the wave, then over the four wave totals
   for (int d = 1; d < kWave; d <<= 1) {
     const int y = __shfl_up(x, d, kWave);
     if (lane >= d) x += y;
   }
   if (lane == kWave - 1) wsum[wave] = x;
   __syncthreads();
-  int o = x - cnt;
+  int o = base_s + x - cnt;
   for (int w = 0; w < wave; ++w) o += wsum[w];
-  if (cnt) {
-    for (int c = c0; c < c1; ++c) {
-      if (!vertex_peak(vv, nm, nt, c, thr)) continue;
-      if (o < A.out.object_cap) {
-        const int m = c / nt, ti = c - m * nt;
-        ht_object ob;
-        ob.lin = c;
-        ob.votes = vv[c];
-        ob.n_tracks = 0;
-        ob.kind = 0;
-        ob.rho = (float)((double)A.cfg.rho_lo + ((double)m + 0.5) * rw);
-        ob.theta = (float)(-kPi + ((double)ti + 0.5) * (2.0 * kPi / (double)nt));
-        ob.isotropy = 0.0f;
-        ob.member_begin = 0;
-        A.out.objects[o] = ob;
-      }
-      ++o;
+  const int c0 = (int)blockIdx.x * kVTile + (int)threadIdx.x * 4;
+  for (unsigned b = f; b; b &= b - 1) {
+    const int c = c0 + __builtin_ctz(b);
+    if (o < A.out.object_cap) {
+      const int m = c / nt, ti = c - m * nt;
+      ht_object ob;
+      ob.lin = c;
+      ob.votes = A.vacc[c];
+      ob.n_tracks = 0;
+      ob.kind = 0;
+      ob.rho = (float)((double)A.cfg.rho_lo + ((double)m + 0.5) * rw);
+      ob.theta = (float)(-kPi + ((double)ti + 0.5) * (2.0 * kPi / (double)nt));
+      ob.isotropy = 0.0f;
+      ob.member_begin = 0;
+      A.out.objects[o] = ob;
     }
+    ++o;
   }
-  if (threadIdx.x == kVThreads - 1) A.sc[S_NOBJ] = o;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255)
+    A.sc[S_NOBJ] = base_s + wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
 // a track is a member of the object at (m, ti) when one of its arcs (either
@@ -2607,6 +2625,7 @@ AssocArgs make_args(const Plan& P, const float* r, const float* phi, const uint8
   A.tunit = P.d_tunit;
   A.vacc = out.vacc ? out.vacc : P.d_vacc;
   A.obj_cnt = P.d_obj_cnt;
+  A.vtile = P.d_vtile;
   A.sc = P.d_scalars;
   A.spread = P.d_spread;
   A.cls = P.d_cls;
@@ -2708,8 +2727,13 @@ int assoc_sequence(const AssocBatch<NB>& AB, const Plan* const* P, int32_t n_hit
   }
   const int ocap = out.object_cap > 0 ? out.object_cap : 1;
   const int ozero = ocap < P0.lim.max_vertex_cells ? ocap : P0.lim.max_vertex_cells;
-  vpeaks_kernel<NB><<<dim3(1, 1, NB), 1024, 0, s>>>(AB, ozero);
-  HT_CHECK(hipGetLastError());
+  {
+    const int vt = (cfg.n_rho * cfg.n_theta + kVTile - 1) / kVTile;
+    vpcount_kernel<NB><<<dim3(vt, 1, NB), 256, 0, s>>>(AB, ozero);
+    HT_CHECK(hipGetLastError());
+    vpemit_kernel<NB><<<dim3(vt, 1, NB), 256, 0, s>>>(AB);
+    HT_CHECK(hipGetLastError());
+  }
   if (out.object_cap > 0) {
     vcount_kernel<NB><<<dim3(blocks_for((int64_t)ocap * ((tcap + kWave - 1) / kWave), 4), 1, NB),
                         256, 0, s>>>(AB);

@@ -85,6 +85,7 @@ struct Plan {
   double2* d_tunit;      // [max_tracks] (-C, B) / |(B, C)| of each track's seed circle (isotropy)
   int32_t* d_vacc;       // [max_vertex_cells] vertex accumulator
   int32_t* d_obj_cnt;    // [max_vertex_cells] member count per object
+  int32_t* d_vtile;      // [max_vertex_cells / 1024 + 1] vertex peaks per 1024-cell tile
   int32_t* d_scalars;    // [16] device counters
   unsigned long long* d_spread;  // [kSpreadWords] counters spread over 128-byte lines
   // member lists by candidate
