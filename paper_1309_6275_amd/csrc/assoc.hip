@@ -12,9 +12,10 @@
 //             with an accumulator, the count of hits beyond the layer
 //             range);
 //   members   by candidate: the hits grouped by (radius class, azimuth
-//             bucket) with a counting sort (cls, bcount, scan, bscatter),
-//             then one wave per candidate tests the hits of the buckets its
-//             member window reaches for each class (mcand); events with
+//             bucket) with a counting sort (the classes in the mark launch,
+//             then bcount, scan, bscatter), then one wave per candidate
+//             tests the hits of the buckets its member window reaches for
+//             each class (mcand); events with
 //             more distinct radii than the classes hold use a sweep shaped
 //             like the vote instead (member_kernel);
 //   refine    one wave per candidate: member layers, seed layers, the
@@ -55,7 +56,7 @@ constexpr int kGridCap = 8192;    // grid-stride launches use at most this many 
 constexpr float kPiF = 3.14159265358979f;
 constexpr float k2PiF = 6.28318530717959f;
 
-// S_MODE: 1 when the member lists are built by candidate (see cls_kernel);
+// S_MODE: 1 when the member lists are built by candidate (see radius_classes);
 // S_COVER: set when the hits have more distinct radii than the hash holds
 enum { S_NP = 0, S_NBAD = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5, S_MODE = 6, S_COVER = 7 };
 // The seed search's totals (road tests, refined candidates, candidates over
@@ -371,16 +372,14 @@ __global__ void init_kernel(AssocBatch<NB> AB, int words) {
   for (int64_t v = tid; v < ncell_v; v += stride) A.vacc[v] = 0;
 }
 
-template <int NB>
-__global__ void mark_kernel(AssocBatch<NB> AB) {
-  const AssocArgs& A = event_args(AB);
+__device__ void mark_peaks(const AssocArgs& A, int bid, int nblk) {
   if (A.acc) {
     const int n_hits = hits_of(A);
-    for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < n_hits; h += gridDim.x * blockDim.x)
+    for (int h = bid * blockDim.x + threadIdx.x; h < n_hits; h += nblk * blockDim.x)
       if (A.layer[h] >= HT_MAX_LAYERS && hit_ok(A.r[h], A.phi[h])) atomicAdd(&A.sc[S_NBAD], 1);
   }
   const int np = n_cands(A);
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
+  for (int p = bid * blockDim.x + threadIdx.x; p < np; p += nblk * blockDim.x) {
     A.mcount[p] = 0;
     const int lin = A.peaks[p].lin;
     if (lin < 0 || lin >= A.n_cells) continue;
@@ -449,9 +448,7 @@ __device__ __forceinline__ int bucket_of(float aw) {
 }
 
 // the event's distinct radii (each workgroup's, then merged into the event's hash)
-template <int NB>
-__global__ __launch_bounds__(256) void cls_kernel(AssocBatch<NB> AB) {
-  const AssocArgs& A = event_args(AB);
+__device__ void radius_classes(const AssocArgs& A, int bid, int nblk) {
   __shared__ uint32_t key[kClsSlots];
   __shared__ int over;
   if (threadIdx.x < kClsSlots) key[threadIdx.x] = kRadEmpty;
@@ -459,7 +456,7 @@ __global__ __launch_bounds__(256) void cls_kernel(AssocBatch<NB> AB) {
   __syncthreads();
   const int n = hits_of(A);
   uint32_t last = kRadEmpty;
-  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < n; h += gridDim.x * blockDim.x) {
+  for (int h = bid * blockDim.x + threadIdx.x; h < n; h += nblk * blockDim.x) {
     const float rv = A.r[h];
     if (!hit_ok(rv, A.phi[h]) || A.layer[h] >= HT_MAX_LAYERS) continue;
     const uint32_t k = __float_as_uint(rv);
@@ -474,6 +471,17 @@ __global__ __launch_bounds__(256) void cls_kernel(AssocBatch<NB> AB) {
   }
   __syncthreads();
   if (threadIdx.x == 0 && over) atomicOr(&A.sc[S_COVER], 1);
+}
+
+// the peak marks (workgroups below mark_blocks, 256 threads) and the radius
+// classes (the rest) in one launch
+template <int NB>
+__global__ __launch_bounds__(256) void mark_kernel(AssocBatch<NB> AB, int mark_blocks) {
+  const AssocArgs& A = event_args(AB);
+  if ((int)blockIdx.x < mark_blocks)
+    mark_peaks(A, blockIdx.x, mark_blocks);
+  else
+    radius_classes(A, blockIdx.x - mark_blocks, gridDim.x - mark_blocks);
 }
 
 // class index of each hash slot (rank among the filled slots, the same in
@@ -2655,15 +2663,17 @@ int assoc_sequence(const AssocBatch<NB>& AB, const Plan* const* P, int32_t n_hit
   P0.prof_mark(HT_STAGE_ASSOC, 0, s);
   init_kernel<NB><<<dim3(blocks_for(init_n, 256), 1, NB), 256, 0, s>>>(AB, words);
   HT_CHECK(hipGetLastError());
-  mark_kernel<NB><<<dim3(blocks_for(peak_cap, 256), 1, NB), 256, 0, s>>>(AB);
-  HT_CHECK(hipGetLastError());
+  const int hblocks = blocks_for(n_hits, 256) < 256 ? blocks_for(n_hits, 256) : 256;
+  {
+    const int mblocks = blocks_for(peak_cap, 256);
+    mark_kernel<NB><<<dim3(mblocks + hblocks, 1, NB), 256, 0, s>>>(AB, mblocks);
+    HT_CHECK(hipGetLastError());
+  }
   const int col_tiles = (g.n_qpt + kWave - 1) / kWave;
   dim3 sweep(col_tiles, g.n_d0, hit_slices(col_tiles * g.n_d0, n_hits) * NB);
   P0.prof_mark(HT_STAGE_MEMBERS, 0, s);
   {
-    const dim3 hgrid(blocks_for(n_hits, 256) < 256 ? blocks_for(n_hits, 256) : 256, 1, NB);
-    cls_kernel<NB><<<hgrid, 256, 0, s>>>(AB);
-    HT_CHECK(hipGetLastError());
+    const dim3 hgrid(hblocks, 1, NB);
     bcount_kernel<NB><<<hgrid, 256, 0, s>>>(AB);
     HT_CHECK(hipGetLastError());
     const int32_t* bc[NB];
