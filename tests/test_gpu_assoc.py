@@ -221,6 +221,23 @@ def test_assoc_parity_vertex_events(torch, ht, oracle, kind):
     assert want["counts"][2] >= 1
 
 
+@pytest.mark.parametrize("n_rho,n_theta", [(9, 150), (3, 101), (40, 333)])
+def test_assoc_parity_vertex_grid_tiles(torch, ht, oracle, n_rho, n_theta):
+    """Vertex grids that do not fill whole 1024-cell tiles (the vertex peaks
+    are counted and placed per tile): one partial tile, two tiles with a
+    ragged tail, and thirteen tiles on an odd theta axis."""
+    W = CF.WORKLOADS[2]
+    rng = np.random.default_rng(33)
+    psis = -0.4 + rng.uniform(-1.45, 1.45, 60)
+    qpts = rng.choice([-1, 1], 60) * rng.uniform(0.3, 0.9, 60)
+    ev = G.make_vertex_event(7.0, -0.4, psis, qpts, n_noise=300, seed=6)
+    cfg = dict(W["cluster"], member_cap=512, n_rho=n_rho, n_theta=n_theta)
+    got, acc, pk = run_gpu(torch, ht, W["grid"], ev, W["min_votes"], cfg)
+    want = run_oracle(oracle, W["grid"], ev, acc, pk, cfg)
+    compare(got, want, f"vertex grid {n_rho}x{n_theta}")
+    assert want["counts"][2] >= 1
+
+
 def test_assoc_capacities_and_overflow(torch, ht, oracle):
     """Small track/object/member capacities truncate in order with full
     counts; a small member_cap drops candidates identically."""
