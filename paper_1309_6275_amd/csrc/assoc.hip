@@ -25,7 +25,8 @@
 //             (inliers, sum, index) and offers each inlier hit its 64-bit
 //             ownership key (atomicMax); totals go to spread counters;
 //   survive   ordered compaction of the candidates owning >= min_layers
-//             hits into the track list (tile counts, scan, emit);
+//             hits into the track list (tile counts and their sums per 64
+//             tiles, then each tile places its survivors);
 //   fit+vvote one launch: float64 Gauss-Newton, one wave per track (lanes =
 //             hits), beside one thread per (track, vertex row) voting its
 //             crossing arcs into the vertex accumulator (the Kalman filter,
@@ -35,7 +36,8 @@
 //   vcount,   member counts, one wave per (object, 64 tracks), then one
 //   vmembers  wave per object: member tracks by ballot, written in order,
 //             isotropy summed in track order;
-//   counts    the output counts (the spread counters summed).
+//   counts    the output counts (the spread counters summed), by the wave
+//             of the last object in the member pass.
 // Every decision that selects an integer result uses float32 vote
 // arithmetic or float64 arithmetic and square roots in a fixed order, so the
 // results match the CPU reference bit for bit; the refit uses the device
@@ -64,7 +66,7 @@ enum { S_NP = 0, S_NBAD = 2, S_NTRK = 3, S_NOBJ = 4, S_NMEM = 5, S_MODE = 6, S_C
 // and added to kSpread counters in separate 128-byte lines, chosen by
 // workgroup: tens of thousands of waves adding into one address serialise in
 // one L2 channel (about a fifth of the kernel's time when measured, and most
-// of it on events where every candidate overflows); counts_kernel sums the
+// of it on events where every candidate overflows); write_counts sums the
 // slots.
 constexpr int kSpread = 64;
 constexpr int kSpreadStride = 16;  // 64-bit words: one 128-byte line per slot
@@ -286,8 +288,8 @@ struct AssocArgs {
   double* cgeo;
   int32_t* chit;
   unsigned long long* owner_key;
-  int32_t* ctile_cnt;
-  int32_t* ctile_off;
+  int32_t* ctile_cnt;  // survivors per 256-candidate tile
+  int32_t* ctile_off;  // their sums per group of 64 tiles
   int32_t* trk_peak;
   int32_t* arc0;   // vertex arc per (track, row), outgoing branch: first bin, length
   int32_t* arcn;
@@ -337,7 +339,7 @@ __device__ __forceinline__ int hits_of(const AssocArgs& A) {
 
 // ---- prep ------------------------------------------------------------------
 template <int NB>
-__global__ void init_kernel(AssocBatch<NB> AB, int words) {
+__global__ void init_kernel(AssocBatch<NB> AB, int words, int surv_groups) {
   const AssocArgs& A = event_args(AB);
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -351,6 +353,7 @@ __global__ void init_kernel(AssocBatch<NB> AB, int words) {
   for (int64_t w = tid; w < words; w += stride) A.pbits[w] = 0u;
   for (int64_t w = tid; w < kClsSlots; w += stride) A.cls[w] = kRadEmpty;
   for (int64_t w = tid; w < kBucketKeys; w += stride) A.bkt[w] = 0;
+  for (int64_t w = tid; w < surv_groups; w += stride) A.ctile_off[w] = 0;
   const int n_hits = hits_of(A);
   for (int64_t h = tid; h < n_hits; h += stride) {
     const float r = A.r[h], ph = A.phi[h];
@@ -1943,7 +1946,8 @@ __device__ __forceinline__ bool survives(const AssocArgs& A, int p, int* own) {
   return *own >= A.cfg.min_layers;
 }
 
-// survivor counts per 256-candidate tile
+// survivor counts per 256-candidate tile, and their sums per group of 64
+// tiles (zeroed by init_kernel)
 template <int NB>
 __global__ __launch_bounds__(256) void surv_count_kernel(AssocBatch<NB> AB, int tiles) {
   const AssocArgs& A = event_args(AB);
@@ -1956,29 +1960,47 @@ __global__ __launch_bounds__(256) void surv_count_kernel(AssocBatch<NB> AB, int 
     const uint64_t m = __ballot(s);
     if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = __popcll(m);
     __syncthreads();
-    if (threadIdx.x == 0) A.ctile_cnt[tile] = wc[0] + wc[1] + wc[2] + wc[3];
+    if (threadIdx.x == 0) {
+      const int c = wc[0] + wc[1] + wc[2] + wc[3];
+      A.ctile_cnt[tile] = c;
+      if (c) atomicAdd(&A.ctile_off[tile >> 6], c);
+    }
     __syncthreads();
   }
 }
 
+// The survivors as tracks, in candidate order: a tile's first track index is
+// the sum of the group sums before its group and of the tile counts before
+// it in its group (wave 0 reads both, 64 at a time); the last tile writes
+// the track count.
 template <int NB>
 __global__ __launch_bounds__(256) void surv_emit_kernel(AssocBatch<NB> AB, int tiles) {
   const AssocArgs& A = event_args(AB);
   __shared__ int32_t wc[4];
+  __shared__ int32_t base_s;
   const int np = n_cands(A);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    if (wave == 0) {
+      const int g = tile >> 6;
+      int b = 0;
+      for (int q = lane; q < g; q += kWave) b += A.ctile_off[q];
+      if (g * 64 + lane < tile) b += A.ctile_cnt[g * 64 + lane];
+      for (int off = kWave / 2; off > 0; off >>= 1) b += __shfl_xor(b, off);
+      if (lane == 0) base_s = b;
+    }
     const int p = tile * 256 + threadIdx.x;
     int own = 0;
     const bool s = p < np && survives(A, p, &own);
     const uint64_t m = __ballot(s);
     if (lane == 0) wc[wave] = __popcll(m);
     __syncthreads();
+    if (tile == tiles - 1 && threadIdx.x == 0) A.sc[S_NTRK] = base_s + wc[0] + wc[1] + wc[2] + wc[3];
     int before = 0;
     for (int w = 0; w < wave; ++w) before += wc[w];
     if (s) {
       const uint64_t lower = lane ? (m & ((1ull << lane) - 1ull)) : 0ull;
-      const int t = A.ctile_off[tile] + before + __popcll(lower);
+      const int t = base_s + before + __popcll(lower);
       if (t < A.out.track_cap) {
         ht_track tr;
         tr.peak = p;
@@ -2458,6 +2480,39 @@ __global__ __launch_bounds__(256) void vcount_kernel(AssocBatch<NB> AB) {
   }
 }
 
+// the event's counts, by one wave (uniform control): lane i reads spread
+// slot i of each counter; n_mem is the object members' total
+__device__ void write_counts(const AssocArgs& A, int n_mem) {
+  static_assert(kSpread == kWave, "one spread slot per lane");
+  int32_t* c = A.out.counts;
+  const int lane = threadIdx.x & (kWave - 1);
+  unsigned long long ncand = A.spread[(size_t)(SP_NCAND + lane) * kSpreadStride];
+  unsigned long long tests = A.spread[(size_t)(SP_TESTS + lane) * kSpreadStride];
+  unsigned long long nover = A.spread[(size_t)(SP_NOVER + lane) * kSpreadStride];
+  unsigned long long pairs = A.spread[(size_t)(SP_PAIRS + lane) * kSpreadStride];
+  unsigned long long exec = A.spread[(size_t)(SP_EXEC + lane) * kSpreadStride];
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    ncand += __shfl_xor(ncand, off);
+    tests += __shfl_xor(tests, off);
+    nover += __shfl_xor(nover, off);
+    pairs += __shfl_xor(pairs, off);
+    exec += __shfl_xor(exec, off);
+  }
+  if (lane != 0) return;
+  if (A.out.work) {
+    A.out.work[0] = tests;
+    A.out.work[1] = exec;
+  }
+  c[0] = (int32_t)ncand;
+  c[1] = A.sc[S_NTRK];
+  c[2] = A.sc[S_NOBJ];
+  c[3] = n_mem;
+  c[4] = (int32_t)nover;
+  c[5] = pairs > 0x7fffffffull ? 0x7fffffff : (int32_t)pairs;
+  c[6] = tests > 0x7fffffffull ? 0x7fffffff : (int32_t)tests;
+  c[7] = 0;
+}
+
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
@@ -2520,42 +2575,11 @@ __global__ __launch_bounds__(256) void vmembers_kernel(AssocBatch<NB> AB) {
       ob.kind = (cnt >= A.cfg.bh_min_tracks && R <= (double)A.cfg.bh_max_isotropy) ? 1 : 0;
       if (o == nobj - 1) A.sc[S_NMEM] = begin + cnt;
     }
+    if (o == nobj - 1) write_counts(A, begin + cnt);
   }
+  if (nobj == 0 && blockIdx.x == 0 && wave == 0) write_counts(A, 0);
 }
 
-// one wave: lane i reads spread slot i of each counter
-template <int NB>
-__global__ __launch_bounds__(kWave) void counts_kernel(AssocBatch<NB> AB) {
-  const AssocArgs& A = event_args(AB);
-  static_assert(kSpread == kWave, "one spread slot per lane");
-  int32_t* c = A.out.counts;
-  const int lane = threadIdx.x;
-  unsigned long long ncand = A.spread[(size_t)(SP_NCAND + lane) * kSpreadStride];
-  unsigned long long tests = A.spread[(size_t)(SP_TESTS + lane) * kSpreadStride];
-  unsigned long long nover = A.spread[(size_t)(SP_NOVER + lane) * kSpreadStride];
-  unsigned long long pairs = A.spread[(size_t)(SP_PAIRS + lane) * kSpreadStride];
-  unsigned long long exec = A.spread[(size_t)(SP_EXEC + lane) * kSpreadStride];
-  for (int off = kWave / 2; off > 0; off >>= 1) {
-    ncand += __shfl_xor(ncand, off);
-    tests += __shfl_xor(tests, off);
-    nover += __shfl_xor(nover, off);
-    pairs += __shfl_xor(pairs, off);
-    exec += __shfl_xor(exec, off);
-  }
-  if (lane != 0) return;
-  if (A.out.work) {
-    A.out.work[0] = tests;
-    A.out.work[1] = exec;
-  }
-  c[0] = (int32_t)ncand;
-  c[1] = A.sc[S_NTRK];
-  c[2] = A.sc[S_NOBJ];
-  c[3] = A.sc[S_NMEM];
-  c[4] = (int32_t)nover;
-  c[5] = pairs > 0x7fffffffull ? 0x7fffffff : (int32_t)pairs;
-  c[6] = tests > 0x7fffffffull ? 0x7fffffff : (int32_t)tests;
-  c[7] = 0;
-}
 
 
 
@@ -2661,7 +2685,9 @@ int assoc_sequence(const AssocBatch<NB>& AB, const Plan* const* P, int32_t n_hit
   const int words = P0.n_tiles * 8 + 2;
   const int64_t init_n = words > n_hits ? words : n_hits;
   P0.prof_mark(HT_STAGE_ASSOC, 0, s);
-  init_kernel<NB><<<dim3(blocks_for(init_n, 256), 1, NB), 256, 0, s>>>(AB, words);
+  const int surv_tiles = (peak_cap + 255) / 256 > 0 ? (peak_cap + 255) / 256 : 1;
+  init_kernel<NB><<<dim3(blocks_for(init_n, 256), 1, NB), 256, 0, s>>>(AB, words,
+                                                                      (surv_tiles + 63) / 64);
   HT_CHECK(hipGetLastError());
   const int hblocks = blocks_for(n_hits, 256) < 256 ? blocks_for(n_hits, 256) : 256;
   {
@@ -2706,20 +2732,9 @@ int assoc_sequence(const AssocBatch<NB>& AB, const Plan* const* P, int32_t n_hit
     launch_refine<kMaxMembers, NB>(AB, peak_cap, s);
   HT_CHECK(hipGetLastError());
   P0.prof_mark(HT_STAGE_REFINE, 1, s);
-  const int tiles = (peak_cap + 255) / 256 > 0 ? (peak_cap + 255) / 256 : 1;
+  const int tiles = surv_tiles;
   surv_count_kernel<NB><<<dim3(blocks_for(tiles, 1), 1, NB), 256, 0, s>>>(AB, tiles);
   HT_CHECK(hipGetLastError());
-  const int32_t* cnt[NB];
-  int32_t* off[NB];
-  int32_t* tot[NB];
-  for (int b = 0; b < NB; ++b) {
-    cnt[b] = P[b]->d_ctile_cnt;
-    off[b] = P[b]->d_ctile_off;
-    tot[b] = P[b]->d_scalars + S_NTRK;
-  }
-  const int rc = NB == 1 ? launch_scan(cnt[0], off[0], tiles, tot[0], s)
-                         : launch_scan_batch(NB, cnt, off, tiles, tot, s);
-  if (rc != HT_OK) return rc;
   surv_emit_kernel<NB><<<dim3(blocks_for(tiles, 1), 1, NB), 256, 0, s>>>(AB, tiles);
   HT_CHECK(hipGetLastError());
   const int tcap = out.track_cap > 0 ? out.track_cap : 1;
@@ -2749,11 +2764,9 @@ int assoc_sequence(const AssocBatch<NB>& AB, const Plan* const* P, int32_t n_hit
                         256, 0, s>>>(AB);
     HT_CHECK(hipGetLastError());
   }
-  if (out.object_cap > 0) {
-    vmembers_kernel<NB><<<dim3(blocks_for(ocap, 4), 1, NB), 256, 0, s>>>(AB);
-    HT_CHECK(hipGetLastError());
-  }
-  counts_kernel<NB><<<dim3(1, 1, NB), kWave, 0, s>>>(AB);
+  // members and isotropy; the wave of the last object (block 0 when there
+  // are none) writes the counts, whose other inputs are final by now
+  vmembers_kernel<NB><<<dim3(blocks_for(ocap, 4), 1, NB), 256, 0, s>>>(AB);
   HT_CHECK(hipGetLastError());
   P0.prof_mark(HT_STAGE_ASSOC, 1, s);
   return HT_OK;
