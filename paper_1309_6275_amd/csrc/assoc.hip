@@ -566,14 +566,24 @@ __global__ __launch_bounds__(256) void mcand_kernel(AssocBatch<NB> AB) {
   const AssocArgs& A = event_args(AB);
   __shared__ int32_t idx[kClsSlots];
   __shared__ float cr[kMaxClasses];
+  __shared__ float cir[kMaxClasses], ce5[kMaxClasses];  // 1 / r and the window's hit part
   const int ncls = class_table(A, idx, cr);
   if (ncls < 0) return;
+  if ((int)threadIdx.x < ncls) {
+    const float ir = 1.0f / cr[threadIdx.x];
+    cir[threadIdx.x] = ir;
+    ce5[threadIdx.x] = member_e5(cr[threadIdx.x], ir, A.hd0, A.hk, A.invw);
+  }
+  __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int waves = (int)(blockDim.x / kWave);
   const int np = n_cands(A);
   const int cap = A.cfg.member_cap;
   const int n_phi = A.n_phi;
   const float wbase = 0.5f + (float)A.cfg.win_bins;
+  // bin width for the bucket ranges only (their margin is a whole bucket,
+  // far above this product's rounding)
+  const float binw = 1.0f / A.invw;
   for (int p = blockIdx.x * waves + (int)(threadIdx.x / kWave); p < np; p += gridDim.x * waves) {
     const int lin = A.peaks[p].lin;
     if (lin < 0 || lin >= A.n_cells) continue;  // no members (mark_kernel set the count to 0)
@@ -585,19 +595,19 @@ __global__ __launch_bounds__(256) void mcand_kernel(AssocBatch<NB> AB) {
     int st0 = 0, en0 = 0, st1 = 0, en1 = 0;
     if (lane < ncls) {
       const float rv = cr[lane];
-      const float ir = 1.0f / rv;
+      const float ir = cir[lane];
       float x = 0.0f, u = 0.0f;
       const bool ok = phi0_coord(rv * rv, ir, 0.0f, A.kap[j], A.qt[(size_t)k * A.n_qpt + j],
                                  A.tt[(size_t)k * A.n_qpt + j], A.phi_lo, A.invw, &x, &u);
       if (ok) {
         s = asin_f(u);
-        w = member_window(member_e5(rv, ir, A.hd0, A.hk, A.invw), u, wbase);
+        w = member_window(ce5[lane], u, wbase);
         // azimuths whose x lies within w of the cell centre, as bucket
         // coordinates: [lo, lo + len] (periodic), one bucket of margin
         const float xc = (float)i + 0.5f;
-        const float a = ((xc - w) / A.invw + A.phi_lo) + s;
+        const float a = ((xc - w) * binw + A.phi_lo) + s;
         const float lo = bucket_coord(wrap_pi_f(a)) - 1.0f;
-        const float len = 2.0f * w / A.invw * ((float)kBuckets / k2PiF) + 2.0f;
+        const float len = 2.0f * w * binw * ((float)kBuckets / k2PiF) + 2.0f;
         const int base = lane * kBuckets;
         if (!(len < (float)(kBuckets - 2)) || !(lo == lo)) {
           st0 = A.bkt_off[base];
@@ -631,6 +641,7 @@ __global__ __launch_bounds__(256) void mcand_kernel(AssocBatch<NB> AB) {
     const int rst = (lane & 1) ? rst1 : rst0;
     const int rlen = lane < nr && rs == rs ? ((lane & 1) ? ren1 - rst1 : ren0 - rst0) : 0;
     const int rend = wave_incl_scan_i32(rlen, lane);  // end of range q in the laid-out order
+    const int rbase = rst - (rend - rlen);  // position t of range q is hit rbase + t
     const int total = __builtin_amdgcn_readlane(rend, kWave - 1);
     int cnt = 0;
     uint2* pool = A.pool + (size_t)p * cap;
@@ -667,11 +678,17 @@ __global__ __launch_bounds__(256) void mcand_kernel(AssocBatch<NB> AB) {
       }
     } else for (int t0 = 0; t0 < total; t0 += kWave) {
       const int t = t0 + lane;
-      // range of t: the number of ranges that end at or before it
+      // range of t: the number of ranges that end at or before it, by a
+      // binary search over the ends (non-decreasing in q, nr <= 32)
       int q = 0;
-      for (int u = 0; u < nr; ++u) q += t >= __builtin_amdgcn_readlane(rend, u) ? 1 : 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1) {
+        // every lane reads (a lane's value can only be read while it is active)
+        const int end = __shfl(rend, min(q + step - 1, kWave - 1), kWave);
+        if (q + step <= nr && end <= t) q += step;
+      }
       const int qs = q < kWave ? q : kWave - 1;
-      const int e = __shfl(rst, qs, kWave) + (t - (__shfl(rend, qs, kWave) - __shfl(rlen, qs, kWave)));
+      const int e = __shfl(rbase, qs, kWave) + t;
       test(e, t < total, __shfl(s, qs >> 1, kWave), __shfl(w, qs >> 1, kWave));
     }
     if (lane == 0) A.mcount[p] = cnt;

@@ -112,7 +112,6 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
   for (int a = 0; a < kMaxRadii; ++a) sreg[a] = a < R.n ? s_tab[a][lane] : __builtin_nanf("");
 
   uint32_t* col = lds + lane * stride;
-  uint32_t votes = 0;
   for (int base = h0 + wave * kWave; base < n_hits; base += kVoteThreads) {
     const int h = base + lane;
     float hr = 1.0f, hp = 0.0f;
@@ -151,7 +150,10 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
       const float x = d * invw;
       // x lies in [-n_phi, 2 n_phi) (|phi| <= 4, |asin| <= pi/2): one
       // period of correction is enough; a power of two wraps with a mask
-      int i = (int)floorf(x);
+      // floor and conversion in one instruction (x is finite and in range
+      // whenever the vote counts)
+      int i;
+      asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(i) : "v"(x));
       if (POW2) {
         i &= n_phi - 1;
       } else {
@@ -163,7 +165,6 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
           atomicAdd(&col[i], 1u);
         else
           atomicAdd(&col[i >> 1], (i & 1) ? 65536u : 1u);
-        ++votes;
       }
     }
   }
@@ -180,12 +181,20 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
     const uint32_t w = lds[cj * stride + (i >> 1)];
     return (int32_t)((i & 1) ? (w >> 16) : (w & 0xFFFFu));
   };
+  // the vote count, when asked for, is the sum of the tile's counters (the
+  // loop above keeps no count of its own)
+  uint32_t votes = 0;
   if (n_slices == 1) {
-    for (int e = threadIdx.x; e < total; e += kVoteThreads) out[e] = tile(e);
+    for (int e = threadIdx.x; e < total; e += kVoteThreads) {
+      const int32_t v = tile(e);
+      out[e] = v;
+      votes += (uint32_t)v;
+    }
   } else {
     for (int e = threadIdx.x; e < total; e += kVoteThreads) {
       const int32_t v = tile(e);
       if (v) atomicAdd(&out[e], v);
+      votes += (uint32_t)v;
     }
   }
 
