@@ -1740,10 +1740,9 @@ refine_kernel(AssocBatch<NB> AB) {
       const int key = mine ? (((nxt - ls) << 4) | lane) : 0x7fffffff;
       int rank = 0;
       for (int t = 0; t < HT_MAX_LAYERS; ++t) rank += __shfl(key, t, kWave) < key ? 1 : 0;
-      for (int t = 0; t < HT_MAX_LAYERS; ++t) {
-        const int rt = __shfl(rank, t, kWave);
-        if (((nsm >> t) & 1u) && rt == lane) orderv = t;
-      }
+      // lane rank receives the layer of that rank (a forward permute; the
+      // other lanes send to lane 63, whose value is never read)
+      orderv = __builtin_amdgcn_ds_permute((mine ? rank : kWave - 1) * 4, lane);
     }
     unsigned sseq = smask;
     int remaining = nS;
