@@ -1635,13 +1635,16 @@ refine_kernel(AssocBatch<NB> AB) {
       if (s >= 0) key = ((unsigned long long)__float_as_uint(M.mem[e].adx) << 32) | (unsigned)M.mem[e].h;
       const int nmax = max(n0, max(n1, n2));
       int rank = 0;
+      // every lane reads every round (the reads of four rounds in flight
+      // together); rounds past the lane's own layer read a record inside the
+      // member list and do not count
+#pragma unroll 4
       for (int t = 0; t < nmax; ++t) {
         const int e2 = st + t;
-        if (s >= 0 && e2 < en) {
-          const unsigned long long k2 =
-              ((unsigned long long)__float_as_uint(M.mem[e2].adx) << 32) | (unsigned)M.mem[e2].h;
-          rank += k2 < key;
-        }
+        const Mem4 m2 = M.mem[e2 < n ? e2 : n - 1];
+        const unsigned long long k2 =
+            ((unsigned long long)__float_as_uint(m2.adx) << 32) | (unsigned)m2.h;
+        rank += (s >= 0 && e2 < en && k2 < key) ? 1 : 0;
       }
       if (s >= 0 && rank < kk) M.seed[s][rank] = e;
     } else {
@@ -1652,6 +1655,20 @@ refine_kernel(AssocBatch<NB> AB) {
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
         const int st = sst[s], en = sen[s];
+        if (en - st <= kWave) {
+          // a layer of at most 64 members: each lane's key is read once
+          const int e = st + lane;
+          unsigned long long key = ~0ull;
+          if (e < en) key = ((unsigned long long)__float_as_uint(M.mem[e].adx) << 32) | (unsigned)M.mem[e].h;
+          for (int r = 0; r < ns[s]; ++r) {
+            const unsigned long long best = wave_min_u64(key);
+            if (e < en && key == best) {
+              M.seed[s][r] = e;
+              key = ~0ull;
+            }
+          }
+          continue;
+        }
         unsigned long long taken = 0;
         for (int r = 0; r < ns[s]; ++r) {
           unsigned long long mine = ~0ull;
