@@ -1910,13 +1910,43 @@ refine_kernel(AssocBatch<NB> AB) {
       continue;
     }
     double ss = 0.0;
-    if (n_in == best_n) {
+    if (kChunk == 1 && n_in == best_n) {
       for (unsigned lm = lmask; lm; lm &= lm - 1u) {
         const int hh = hitL.get(__builtin_ctz(lm));
         if (hh == kNoHit) continue;
         ++exec;
         const double d = fabs(circle_dist(cA, cB, cC, cD, A.hx[hh], A.hy[hh], A.hq[hh]));
         ss += d * d;
+      }
+    } else if (n_in == best_n) {
+      // above cap 128: four layers at a time, their coordinate loads in
+      // flight together, then the sum in layer order (at cap 128 the
+      // registers would cost the kernel its occupancy)
+      for (unsigned lm = lmask; lm;) {
+        int hq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          hq[u] = kNoHit;
+          if (lm) {
+            hq[u] = hitL.get(__builtin_ctz(lm));
+            lm &= lm - 1u;
+          }
+        }
+        double X[4], Y[4], Q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int h = hq[u] == kNoHit ? 0 : hq[u];
+          X[u] = A.hx[h];
+          Y[u] = A.hy[h];
+          Q[u] = A.hq[h];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (hq[u] == kNoHit) continue;
+          ++exec;
+          const double d = fabs(circle_dist(cA, cB, cC, cD, X[u], Y[u], Q[u]));
+          ss += d * d;
+        }
       }
     }
     unsigned long long key = ~0ull;
