@@ -1437,9 +1437,23 @@ refine_kernel(AssocBatch<NB> AB) {
   }
   unsigned long long tests = 0, ncand = 0;
   uint32_t exec = 0;  // this lane's float64 circle distances
-  for (int p = blockIdx.x * W + wave; p < np; p += gridDim.x * W) {
-    const int lin = A.peaks[p].lin;
-    const int n = A.mcount[p];
+  // above cap 128 the next candidate's cell and member count are requested
+  // while this one is worked on (two registers; at cap 128 they would cost
+  // the kernel its occupancy)
+  constexpr bool kAhead = CAP > 128;
+  const int pstep = gridDim.x * W;
+  int lin_a = -1, n_a = 0;
+  if (kAhead && blockIdx.x * W + wave < np) {
+    lin_a = A.peaks[blockIdx.x * W + wave].lin;
+    n_a = A.mcount[blockIdx.x * W + wave];
+  }
+  for (int p = blockIdx.x * W + wave; p < np; p += pstep) {
+    const int lin = kAhead ? lin_a : A.peaks[p].lin;
+    const int n = kAhead ? n_a : A.mcount[p];
+    if (kAhead && p + pstep < np) {
+      lin_a = A.peaks[p + pstep].lin;
+      n_a = A.mcount[p + pstep];
+    }
     if (lin < 0 || lin >= A.n_cells) {
       if (lane == 0) { A.cstat[p] = -1; A.cnl[p] = 0; }
       continue;
