@@ -6,9 +6,12 @@
 // at one d0 (lane = column), so a tile's accumulator rows are one contiguous
 // block of the output.  The tile's counters live in LDS: 32-bit counters
 // when 64 rows fit in the 160 KiB of a gfx950 CU (n_phi <= 639), otherwise
-// packed 16-bit pairs (a column holds at most n_hits <= 65535 votes per bin,
-// so a ds_add_u32 of 1 or 1 << 16 never carries across the pair).  The row
-// stride is odd in dwords so neighbouring columns fall in different banks.  Waves of
+// 16-bit halves of 32 rows, column c in the low half of row c and column
+// c + 32 in the high half (a column holds at most n_hits <= 65535 votes per
+// bin, so a ds_add_u32 of 1 or 1 << 16 never carries across the halves; a
+// lane's row and increment are fixed, so a vote costs the same instructions
+// as with 32-bit counters).  The row stride is odd in dwords so neighbouring
+// columns fall in different banks.  Waves of
 // the workgroup split the hits: each wave loads 64 hits with one coalesced
 // load, keeps them in VGPRs and broadcasts them one at a time through SGPRs
 // (v_readlane), so the per-evaluation work is pure VALU with scalar hit
@@ -84,7 +87,8 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
   const int j = j0 + lane;
   const bool col_ok = j < n_qpt;
 
-  for (int w = threadIdx.x; w < kWave * stride; w += kVoteThreads) lds[w] = 0u;
+  constexpr int kRows = WIDE ? kWave : kWave / 2;
+  for (int w = threadIdx.x; w < kRows * stride; w += kVoteThreads) lds[w] = 0u;
   float ck = 0.0f, cq = 0.0f, ct = 0.0f;
   if (col_ok) {
     ck = kap[j];
@@ -111,7 +115,8 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
 #pragma unroll
   for (int a = 0; a < kMaxRadii; ++a) sreg[a] = a < R.n ? s_tab[a][lane] : __builtin_nanf("");
 
-  uint32_t* col = lds + lane * stride;
+  uint32_t* col = lds + (lane % kRows) * stride;
+  const uint32_t inc = WIDE || lane < kRows ? 1u : 65536u;
   for (int base = h0 + wave * kWave; base < n_hits; base += kVoteThreads) {
     const int h = base + lane;
     float hr = 1.0f, hp = 0.0f;
@@ -161,10 +166,7 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
         i = i >= n_phi ? i - n_phi : i;
       }
       if (ok) {
-        if (WIDE)
-          atomicAdd(&col[i], 1u);
-        else
-          atomicAdd(&col[i >> 1], (i & 1) ? 65536u : 1u);
+        atomicAdd(&col[i], inc);
       }
     }
   }
@@ -178,8 +180,8 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(
     const int cj = e / n_phi;
     const int i = e - cj * n_phi;
     if (WIDE) return (int32_t)lds[cj * stride + i];
-    const uint32_t w = lds[cj * stride + (i >> 1)];
-    return (int32_t)((i & 1) ? (w >> 16) : (w & 0xFFFFu));
+    const uint32_t w = lds[(cj % kRows) * stride + i];
+    return (int32_t)(cj >= kRows ? (w >> 16) : (w & 0xFFFFu));
   };
   // the vote count, when asked for, is the sum of the tile's counters (the
   // loop above keeps no count of its own)
@@ -226,9 +228,10 @@ __global__ void zero_i32_kernel(int32_t* __restrict__ p, int64_t n) {
 // LDS of a CU less the kernel's static arrays (radius set and table)
 constexpr int kLdsBytes = 160 * 1024 - (int)sizeof(RadiusSet) - kMaxRadii * kWave * 4;
 bool vote_wide(int n_phi) { return (size_t)kWave * (size_t)(n_phi | 1) * 4 <= (size_t)kLdsBytes; }
-int vote_stride(int n_phi, bool wide) {
-  const int words = wide ? n_phi : (n_phi + 1) / 2;
-  return words | 1;  // odd dword stride
+int vote_stride(int n_phi) { return n_phi | 1; }  // odd dword stride
+// LDS bytes of a tile: 64 rows of 32-bit counters, or 32 rows of 16-bit pairs
+size_t vote_lds_bytes(int n_phi, bool wide) {
+  return (size_t)(wide ? kWave : kWave / 2) * vote_stride(n_phi) * 4;
 }
 
 }  // namespace
@@ -265,8 +268,8 @@ int vote_launch(const Plan& p, const VoteBatch<NB>& V, int32_t n_hits, hipStream
     slices = 2;
     wide = false;
   }
-  const int stride = vote_stride(g.n_phi, wide);
-  const size_t lds_bytes = (size_t)kWave * stride * 4;
+  const int stride = vote_stride(g.n_phi);
+  const size_t lds_bytes = vote_lds_bytes(g.n_phi, wide);
   dim3 grid((g.n_qpt + kWave - 1) / kWave, g.n_d0, slices * NB);
   if (slices > 1) {
     // the slices add into the accumulator: clear it first (a kernel, so the
@@ -306,7 +309,7 @@ int vote_batch_nb(const Plan& p, const float* const* r, const float* const* phi,
 }  // namespace
 
 int vote_init(int n_phi) {
-  const int bytes = kWave * vote_stride(n_phi, vote_wide(n_phi)) * 4;
+  const int bytes = (int)vote_lds_bytes(n_phi, vote_wide(n_phi));
   int rc = vote_init_nb<1>(bytes);
   if (rc == HT_OK) rc = vote_init_nb<2>(bytes);
   if (rc == HT_OK) rc = vote_init_nb<3>(bytes);
