@@ -1318,10 +1318,12 @@ struct RefineShape {
   static constexpr int kWaves = CAP <= 128 ? 4 : (CAP <= 256 ? 2 : 1);
   // waves per SIMD the register budget is set for (the second launch bound
   // of HIP): six for caps up to 128 (80 registers; the LDS of six
-  // workgroups fits); two at cap 1024 (at most 256 registers, so that the
-  // eight one-wave workgroups the LDS allows can all be resident); else left
-  // to the compiler
-  static constexpr int kMinWavesPerSimd = CAP <= 128 ? 6 : (CAP >= 1024 ? 2 : 1);
+  // workgroups fits); three at cap 512 (168 registers; twelve one-wave
+  // workgroups of 10 KB fit the LDS); two at cap 1024 (at most 256
+  // registers, so that the eight one-wave workgroups the LDS allows can all
+  // be resident); else left to the compiler
+  static constexpr int kMinWavesPerSimd =
+      CAP <= 128 ? 6 : (CAP >= 1024 ? 2 : (CAP == 512 ? 3 : 1));
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -1409,7 +1411,7 @@ __device__ __forceinline__ int nth_set_bit(unsigned mask, int n) {
 
 template <int CAP, int NB>
 __global__ __launch_bounds__(RefineShape<CAP>::kWaves * kWave, RefineShape<CAP>::kMinWavesPerSimd) void
-refine_kernel(AssocBatch<NB> AB) {
+refine_kernel(AssocBatch<NB> AB, int n_lo, int n_hi) {
   const AssocArgs& A = event_args(AB);
   constexpr int W = RefineShape<CAP>::kWaves;
   // members per chunk of the road loop (registers: 4 per member); the
@@ -1454,6 +1456,9 @@ refine_kernel(AssocBatch<NB> AB) {
       lin_a = A.peaks[p + pstep].lin;
       n_a = A.mcount[p + pstep];
     }
+    // a launch takes the candidates with n_lo <= n <= n_hi (the others are
+    // another launch's)
+    if (n < n_lo || n > n_hi) continue;
     if (lin < 0 || lin >= A.n_cells) {
       if (lane == 0) { A.cstat[p] = -1; A.cnl[p] = 0; }
       continue;
@@ -2668,9 +2673,10 @@ int blocks_for(int64_t n, int per) {
 }
 
 template <int CAP, int NB>
-void launch_refine(const AssocBatch<NB>& AB, int peak_cap, hipStream_t s) {
+void launch_refine(const AssocBatch<NB>& AB, int peak_cap, hipStream_t s, int n_lo = 0,
+                   int n_hi = 0x7fffffff) {
   constexpr int W = RefineShape<CAP>::kWaves;
-  refine_kernel<CAP, NB><<<dim3(blocks_for(peak_cap, W), 1, NB), W * kWave, 0, s>>>(AB);
+  refine_kernel<CAP, NB><<<dim3(blocks_for(peak_cap, W), 1, NB), W * kWave, 0, s>>>(AB, n_lo, n_hi);
 }
 
 // The arguments of one event's assoc_cluster.
@@ -2805,8 +2811,14 @@ int assoc_sequence(const AssocBatch<NB>& AB, const Plan* const* P, int32_t n_hit
     launch_refine<256, NB>(AB, peak_cap, s);
   else if (cfg.member_cap <= 512)
     launch_refine<512, NB>(AB, peak_cap, s);
-  else
-    launch_refine<kMaxMembers, NB>(AB, peak_cap, s);
+  else {
+    // caps above 512: the candidates with at most 512 members take the
+    // cap-512 kernel (fewer registers and LDS per wave: three waves per SIMD
+    // instead of two), the others the cap-1024 kernel
+    launch_refine<512, NB>(AB, peak_cap, s, 0, 512);
+    HT_CHECK(hipGetLastError());
+    launch_refine<kMaxMembers, NB>(AB, peak_cap, s, 513);
+  }
   HT_CHECK(hipGetLastError());
   P0.prof_mark(HT_STAGE_REFINE, 1, s);
   const int tiles = surv_tiles;
