@@ -1318,12 +1318,13 @@ struct RefineShape {
   static constexpr int kWaves = CAP <= 128 ? 4 : (CAP <= 256 ? 2 : 1);
   // waves per SIMD the register budget is set for (the second launch bound
   // of HIP): six for caps up to 128 (80 registers; the LDS of six
-  // workgroups fits); three at cap 512 (168 registers; twelve one-wave
-  // workgroups of 10 KB fit the LDS); two at cap 1024 (at most 256
+  // workgroups fits); four at cap 512 (128 registers, a few spilled; sixteen
+  // one-wave workgroups of 10 KB fit the LDS; 4% faster than three waves
+  // with no spill on the 55k-hit workload); two at cap 1024 (at most 256
   // registers, so that the eight one-wave workgroups the LDS allows can all
   // be resident); else left to the compiler
   static constexpr int kMinWavesPerSimd =
-      CAP <= 128 ? 6 : (CAP >= 1024 ? 2 : (CAP == 512 ? 3 : 1));
+      CAP <= 128 ? 6 : (CAP >= 1024 ? 2 : (CAP == 512 ? 4 : 1));
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -2813,7 +2814,7 @@ int assoc_sequence(const AssocBatch<NB>& AB, const Plan* const* P, int32_t n_hit
     launch_refine<512, NB>(AB, peak_cap, s);
   else {
     // caps above 512: the candidates with at most 512 members take the
-    // cap-512 kernel (fewer registers and LDS per wave: three waves per SIMD
+    // cap-512 kernel (fewer registers and LDS per wave: four waves per SIMD
     // instead of two), the others the cap-1024 kernel
     launch_refine<512, NB>(AB, peak_cap, s, 0, 512);
     HT_CHECK(hipGetLastError());
