@@ -1317,14 +1317,15 @@ template <int CAP>
 struct RefineShape {
   static constexpr int kWaves = CAP <= 128 ? 4 : (CAP <= 256 ? 2 : 1);
   // waves per SIMD the register budget is set for (the second launch bound
-  // of HIP): six for caps up to 128 (80 registers; the LDS of six
-  // workgroups fits); four at cap 512 (128 registers, a few spilled; sixteen
+  // of HIP): seven for caps up to 128 (72 registers, a few spilled; the LDS
+  // of seven four-wave workgroups fits; 4% faster than six waves without the
+  // spill on the displaced-jet workload); four at cap 512 (128 registers, a few spilled; sixteen
   // one-wave workgroups of 10 KB fit the LDS; 4% faster than three waves
   // with no spill on the 55k-hit workload); two at cap 1024 (at most 256
   // registers, so that the eight one-wave workgroups the LDS allows can all
   // be resident); else left to the compiler
   static constexpr int kMinWavesPerSimd =
-      CAP <= 128 ? 6 : (CAP >= 1024 ? 2 : (CAP == 512 ? 4 : 1));
+      CAP <= 128 ? 7 : (CAP >= 1024 ? 2 : (CAP == 512 ? 4 : 1));
 };
 
 __device__ __forceinline__ void wave_sync() {
